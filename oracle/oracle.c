@@ -1,0 +1,381 @@
+/*
+ * oracle.c -- plain, slow, sequential CPU reference for graph trimming.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library links, includes or
+ * calls this file; only the test-suite, the smoke check and the CPU baseline
+ * of the benchmark use it.  It shares no code with the GPU path.
+ *
+ * Paper: "Efficient Parallel Graph Trimming by Arc-Consistency"
+ * (arXiv 2107.12720).  Section references below are to that paper.
+ *
+ * Conventions: status LIVE = 1 / DEAD = 0 (stored in `live`), levels are
+ * 1-based peeling steps (0 for vertices that stay live).
+ *
+ *   or_peel        the trimmed graph (Def. Trimmed Graph, Section 2) and the
+ *                  peeling step of every removed vertex (Def. of alpha,
+ *                  Section 2.4), by out-degree counters over G^T as in the
+ *                  sequential AC-4-based algorithm (Section 5.1), with the
+ *                  counters taken from CSR offsets (AC4Trim*, Section 9.3),
+ *                  processing one peeling step after the other (FIFO).
+ *   or_ac6_seq     the sequential AC-6-based algorithm (Section 6.1) run
+ *                  literally, counting every status check of a successor.
+ *   or_ac3_jacobi  the AC-3-based algorithm (Section 4.1) with the
+ *                  edge_index cursor of Section 8, statuses read as they were
+ *                  at the start of each repetition (round).
+ *   or_ac3_inplace the same with statuses updated in place during a sweep
+ *                  (the literal sequential schedule, vertices in id order).
+ *   or_counts      closed forms of the traversed-edge totals for AC-6,
+ *                  AC-4 (with and without the * initialisation) and AC-3.
+ *   or_implicit_csr  materialises the hash-generated graph (Section 2.1,
+ *                  implicit graphs) with this file's own SplitMix64.
+ *   or_batch_peel  or_peel on every graph of a packed batch, one graph per
+ *                  thread.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ----------------------------------------------------------------- peel */
+/*
+ * Removes, one peeling step after the other, every vertex whose live
+ * out-degree is zero.  cnt[v] starts at |v.post| (CSR offsets, duplicates and
+ * self-loops included).  A removed w decrements cnt[u] once per edge u->w,
+ * found through this function's own transposed graph.  A self-loop keeps
+ * cnt[v] >= 1, so such a v is never removed.
+ *
+ * Outputs: live[v] (1 LIVE, 0 DEAD), level[v] (peeling step, 0 if live),
+ * order[0 .. n_dead) (removal order: non-decreasing level).
+ * stats[0] = alpha (max level), stats[1] = n_live, stats[2] = reverse edges
+ * traversed during propagation.  Returns n_dead, or -1 on allocation failure.
+ */
+int64_t or_peel(int32_t n, const int32_t *row_off, const int32_t *col, uint8_t *live,
+                int32_t *level, int32_t *order, int64_t *stats) {
+    int64_t m = row_off[n];
+    int64_t *pre_off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *pre = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int64_t *fill = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *cnt = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!pre_off || !pre || !fill || !cnt) {
+        free(pre_off); free(pre); free(fill); free(cnt);
+        return -1;
+    }
+    /* G^T by counting the in-degree of every vertex */
+    for (int64_t e = 0; e < m; ++e) pre_off[col[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) pre_off[v + 1] += pre_off[v];
+    memcpy(fill, pre_off, ((size_t)n + 1) * sizeof(int64_t));
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_off[u]; e < row_off[u + 1]; ++e) pre[fill[col[e]]++] = u;
+
+    int64_t qh = 0, qt = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        cnt[v] = row_off[v + 1] - row_off[v];
+        live[v] = 1;
+        level[v] = 0;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (cnt[v] == 0) {
+            live[v] = 0;
+            level[v] = 1;
+            order[qt++] = v;
+        }
+    }
+    int64_t rev = 0;
+    int32_t alpha = qt > 0 ? 1 : 0;
+    while (qh < qt) {
+        int32_t w = order[qh++];
+        for (int64_t k = pre_off[w]; k < pre_off[w + 1]; ++k) {
+            int32_t u = pre[k];
+            ++rev;
+            cnt[u] -= 1;
+            if (cnt[u] == 0 && live[u]) {
+                live[u] = 0;
+                level[u] = level[w] + 1;
+                if (level[u] > alpha) alpha = level[u];
+                order[qt++] = u;
+            }
+        }
+    }
+    stats[0] = alpha;
+    stats[1] = n - qt;
+    stats[2] = rev;
+    free(pre_off); free(pre); free(fill); free(cnt);
+    return qt;
+}
+
+/* ------------------------------------------------------------ AC-6 (seq) */
+/*
+ * Sequential AC-6-based trimming (Section 6.1).  Each vertex keeps a cursor
+ * into its successor list; DoPost(v) checks successors from the cursor on,
+ * and the first LIVE one w becomes v's support: v joins w.S and the cursor
+ * moves past w (the edge is removed from v.post).  With no LIVE successor v
+ * becomes DEAD and enters Q; each w taken from Q hands every member of w.S
+ * back to DoPost.  Every status check of a successor counts as one traversed
+ * edge.  S sets are singly linked lists (sh = head, sn = next).
+ *
+ * stats[0] = traversed edges, stats[1] = n_live, stats[2] = |Q| high-water.
+ */
+static int64_t ac6_dopost(int32_t v, const int32_t *row_off, const int32_t *col, uint8_t *live,
+                          int64_t *cur, int32_t *sh, int32_t *sn, int32_t *Q, int64_t *qt) {
+    int64_t checked = 0;
+    int64_t end = row_off[v + 1];
+    while (cur[v] < end) {
+        int32_t w = col[cur[v]];
+        cur[v] += 1;
+        checked += 1;
+        if (live[w]) {
+            sn[v] = sh[w];
+            sh[w] = v;
+            return checked;
+        }
+    }
+    live[v] = 0;
+    Q[(*qt)++] = v;
+    return checked;
+}
+
+int64_t or_ac6_seq(int32_t n, const int32_t *row_off, const int32_t *col, uint8_t *live,
+                   int64_t *stats) {
+    int64_t *cur = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int32_t *sh = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *sn = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *Q = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    if (!cur || !sh || !sn || !Q) {
+        free(cur); free(sh); free(sn); free(Q);
+        return -1;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        live[v] = 1;
+        sh[v] = -1;
+        cur[v] = row_off[v];
+    }
+    int64_t edges = 0, hw = 0, n_dead = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t qh = 0, qt = 0;
+        edges += ac6_dopost(v, row_off, col, live, cur, sh, sn, Q, &qt);
+        while (qh < qt) {
+            if (qt - qh > hw) hw = qt - qh;
+            int32_t w = Q[qh++];
+            n_dead += 1;
+            while (sh[w] >= 0) {
+                int32_t u = sh[w];
+                sh[w] = sn[u];               /* w.S := w.S \ {u} */
+                edges += ac6_dopost(u, row_off, col, live, cur, sh, sn, Q, &qt);
+            }
+        }
+    }
+    stats[0] = edges;
+    stats[1] = n - n_dead;
+    stats[2] = hw;
+    free(cur); free(sh); free(sn); free(Q);
+    return edges;
+}
+
+/* ------------------------------------------------------------ AC-3 (seq) */
+/*
+ * AC-3-based trimming (Section 4.1) with the edge_index cursor (Section 8):
+ * repeat rounds until no vertex changes.  In a round every LIVE vertex v
+ * scans from its cursor; a successor that is DEAD is skipped for good (the
+ * cursor moves past it), the first non-DEAD successor ends the scan and is
+ * checked again next round.  A vertex whose scan reaches the end becomes
+ * DEAD.  Every successor check counts as one traversed edge.
+ *
+ * or_ac3_jacobi reads the status every vertex had at the start of the round
+ * (dround[w] < r means "removed in an earlier round"), or_ac3_inplace reads
+ * the current status (vertices in id order, removals visible at once).
+ * stats[0] = traversed edges, stats[1] = rounds, stats[2] = n_live.
+ */
+static int64_t ac3_run(int32_t n, const int32_t *row_off, const int32_t *col, uint8_t *live,
+                       int64_t *stats, int jacobi) {
+    int64_t *cur = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *dround = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!cur || !dround) { free(cur); free(dround); return -1; }
+    const int64_t NEVER = INT64_MAX;
+    for (int32_t v = 0; v < n; ++v) {
+        live[v] = 1;
+        cur[v] = row_off[v];
+        dround[v] = NEVER;
+    }
+    int64_t edges = 0, rounds = 0, n_live = n;
+    int change = 1;
+    while (change) {
+        change = 0;
+        rounds += 1;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!live[v]) continue;
+            int64_t end = row_off[v + 1];
+            int found = 0;
+            while (cur[v] < end) {
+                int32_t w = col[cur[v]];
+                edges += 1;
+                int dead = jacobi ? (dround[w] < rounds) : !live[w];
+                if (!dead) { found = 1; break; }
+                cur[v] += 1;
+            }
+            if (!found) {
+                live[v] = 0;
+                dround[v] = rounds;
+                n_live -= 1;
+                change = 1;
+            }
+        }
+    }
+    stats[0] = edges;
+    stats[1] = rounds;
+    stats[2] = n_live;
+    free(cur); free(dround);
+    return edges;
+}
+int64_t or_ac3_jacobi(int32_t n, const int32_t *row_off, const int32_t *col, uint8_t *live,
+                      int64_t *stats) {
+    return ac3_run(n, row_off, col, live, stats, 1);
+}
+int64_t or_ac3_inplace(int32_t n, const int32_t *row_off, const int32_t *col, uint8_t *live,
+                       int64_t *stats) {
+    return ac3_run(n, row_off, col, live, stats, 0);
+}
+
+/* --------------------------------------------------------- closed forms */
+/*
+ * Traversed-edge totals from the final live set and the peeling levels
+ * (alpha = max level).  fl(v) = index of the first LIVE successor of a live v.
+ *   out[0] T6   = sum_dead deg(v) + sum_live (fl(v) + 1)
+ *   out[1] T4*  = sum_dead indeg(w)          (propagation over G^T)
+ *   out[2] T4   = m + T4*                    (counters found by traversal)
+ *   out[3] T3J  = sum_dead (deg(v) + level(v) - 1) + sum_live (fl(v) + alpha + 1)
+ *   out[4] rounds of the Jacobi AC-3 = alpha + 1
+ *   out[5] T6min = sum_dead deg(v) + n_live  (no successor order does better)
+ *   out[6] m, out[7] n_live
+ * Returns 0, or -(v+1) for a live vertex without a live successor.
+ */
+int64_t or_counts(int32_t n, const int32_t *row_off, const int32_t *col, const uint8_t *live,
+                  const int32_t *level, int32_t alpha, int64_t *out) {
+    int64_t m = row_off[n];
+    int64_t *indeg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!indeg) return -1;
+    for (int64_t e = 0; e < m; ++e) indeg[col[e]]++;
+    int64_t t6 = 0, t4s = 0, t3 = 0, t6min = 0, n_live = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t b = row_off[v], e = row_off[v + 1], deg = e - b;
+        if (live[v]) {
+            int64_t fl = -1;
+            for (int64_t k = b; k < e; ++k)
+                if (live[col[k]]) { fl = k - b; break; }
+            if (fl < 0) { free(indeg); return -((int64_t)v + 1); }
+            t6 += fl + 1;
+            t3 += fl + (int64_t)alpha + 1;
+            t6min += 1;
+            n_live += 1;
+        } else {
+            t6 += deg;
+            t4s += indeg[v];
+            t3 += deg + (int64_t)level[v] - 1;
+            t6min += deg;
+        }
+    }
+    out[0] = t6;
+    out[1] = t4s;
+    out[2] = m + t4s;
+    out[3] = t3;
+    out[4] = (int64_t)alpha + 1;
+    out[5] = t6min;
+    out[6] = m;
+    out[7] = n_live;
+    free(indeg);
+    return 0;
+}
+
+/* ------------------------------------------------------ implicit graphs */
+/*
+ * The hash-generated graph G = (V, POST): n = 2^log2n, fin() is the
+ * SplitMix64 finalizer (Steele, Lea, Flood, OOPSLA 2014).
+ *   deg(v) = 0                       if fin(seed ^ TZ ^ (v<<8)) < zero_thr
+ *          = 1 + #{j<255 : fin(seed ^ TD ^ (v<<8)) >= table[j]}   otherwise
+ *   POST(v)[i] = fin(seed ^ TN ^ ((v<<8) | i)) & (n-1),  0 <= i < deg(v)
+ * Pass col == NULL to fill row_off only.  Returns m.
+ */
+static inline uint64_t or_fin(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ULL;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return z;
+}
+uint64_t or_fin64(uint64_t z) { return or_fin(z); }
+
+#define OR_TZ 0x5A45524F00000000ULL
+#define OR_TD 0x4445470000000000ULL
+#define OR_TN 0x4E42520000000000ULL
+
+int32_t or_implicit_deg(uint64_t seed, uint64_t zero_thr, const uint64_t *table, uint64_t v) {
+    if (or_fin(seed ^ OR_TZ ^ (v << 8)) < zero_thr) return 0;
+    uint64_t u = or_fin(seed ^ OR_TD ^ (v << 8));
+    int32_t d = 1;
+    for (int j = 0; j < 255; ++j)
+        if (u >= table[j]) d += 1;
+    return d;
+}
+int32_t or_implicit_nbr(uint64_t seed, int log2n, uint64_t v, uint64_t i) {
+    uint64_t mask = (log2n >= 64) ? ~0ULL : ((1ULL << log2n) - 1);
+    return (int32_t)(or_fin(seed ^ OR_TN ^ ((v << 8) | i)) & mask);
+}
+
+int64_t or_implicit_csr(int log2n, uint64_t seed, uint64_t zero_thr, const uint64_t *table,
+                        int32_t *row_off, int32_t *col) {
+    int64_t n = (int64_t)1 << log2n;
+    int64_t e = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        int32_t d = or_implicit_deg(seed, zero_thr, table, (uint64_t)v);
+        row_off[v] = (int32_t)e;
+        if (col)
+            for (int32_t i = 0; i < d; ++i) col[e + i] = or_implicit_nbr(seed, log2n, (uint64_t)v, (uint64_t)i);
+        e += d;
+    }
+    row_off[n] = (int32_t)e;
+    return e;
+}
+
+/* --------------------------------------------------------------- batches */
+/*
+ * or_peel on each graph of a packed batch: graph g owns vertices
+ * [vbase[g], vbase[g+1]); row_off is absolute into col; col holds graph-local
+ * ids.  live is indexed by global vertex id.  out[g] = n_live of graph g,
+ * out[G + g] = alpha of graph g.  One graph per thread.
+ */
+int64_t or_batch_peel(int64_t G, const int64_t *vbase, const int32_t *row_off, const int32_t *col,
+                      uint8_t *live, int64_t *out, int nthreads) {
+    int64_t fail = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    (void)nthreads;
+#endif
+    #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(+ : fail)
+    for (int64_t g = 0; g < G; ++g) {
+        int32_t n = (int32_t)(vbase[g + 1] - vbase[g]);
+        const int32_t *ro = row_off + vbase[g];
+        int32_t e0 = ro[0];
+        int32_t *lro = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+        int32_t *lv = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+        int32_t *ord = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+        if (!lro || !lv || !ord) { fail += 1; free(lro); free(lv); free(ord); continue; }
+        for (int32_t v = 0; v <= n; ++v) lro[v] = ro[v] - e0;
+        int64_t st[3];
+        if (or_peel(n, lro, col + e0, live + vbase[g], lv, ord, st) < 0) fail += 1;
+        out[g] = st[1];
+        out[G + g] = st[0];
+        free(lro); free(lv); free(ord);
+    }
+    return fail ? -1 : 0;
+}
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,320 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each checks it against an
+independent definition (greatest fixed point by subset search, the peeling of
+Def. alpha done by whole steps, the reach-a-cycle characterisation through a
+library SCC routine), a worked example printed in the paper, closed forms of
+a graph family, or a published test vector.
+"""
+import os
+import itertools
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def parse_golden(path):
+    adj, fields, in_graph = [], {}, False
+    for line in open(path):
+        line = line.split("#", 1)[0].strip()
+        if not line:
+            continue
+        if line == "graph":
+            in_graph = True
+            continue
+        if line == "end":
+            in_graph = False
+            continue
+        if in_graph:
+            _, rest = line.split(":", 1)
+            adj.append([int(x) for x in rest.split()])
+        else:
+            k, *vals = line.split()
+            fields[k] = [int(x) for x in vals]
+    return adj, fields
+
+
+# ------------------------------------------------------------ independent refs
+def jacobi_peel(adj):
+    """Def. alpha written out: each step removes, all at once, every remaining
+    vertex without a remaining successor.  Returns (live, level)."""
+    n = len(adj)
+    alive = [True] * n
+    level = [0] * n
+    step = 0
+    while True:
+        step += 1
+        rm = [v for v in range(n) if alive[v] and not any(alive[w] for w in adj[v])]
+        if not rm:
+            break
+        for v in rm:
+            alive[v] = False
+            level[v] = step
+    return alive, level
+
+
+def greatest_by_subsets(n, adj_masks):
+    """Union of every vertex subset S with: each v in S has a successor in S
+    (Def. Trimmed Graph); the union of such sets is such a set, so this is the
+    greatest one."""
+    best = 0
+    for S in range(1 << n):
+        ok = True
+        for v in range(n):
+            if (S >> v) & 1 and not (adj_masks[v] & S):
+                ok = False
+                break
+        if ok:
+            best |= S
+    return best
+
+
+def reaches_cycle(g):
+    """v is live iff v reaches a directed cycle (a self-loop counts): nontrivial
+    strongly connected components from scipy, then reverse reachability."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components, breadth_first_order
+    n = g.n
+    src = np.repeat(np.arange(n), np.diff(g.row_off))
+    A = sp.csr_matrix((np.ones(g.m), (src, g.col)), shape=(n, n))
+    ncomp, lab = connected_components(A, directed=True, connection="strong")
+    size = np.bincount(lab, minlength=ncomp)
+    cyclic = size[lab] > 1
+    cyclic[src[src == g.col]] = True
+    # reverse reachability from every cyclic vertex via an extra super-source
+    R = sp.csr_matrix((np.ones(g.m), (g.col, src)), shape=(n + 1, n + 1)).tolil()
+    for v in np.nonzero(cyclic)[0]:
+        R[n, v] = 1
+    order = breadth_first_order(R.tocsr(), n, directed=True, return_predecessors=False)
+    out = np.zeros(n, bool)
+    out[order[order < n]] = True
+    return out
+
+
+def check_certificate(g, live, level):
+    """Soundness (each LIVE vertex has a LIVE successor) plus a removal
+    certificate (each DEAD vertex has only DEAD successors, all removed at a
+    strictly earlier step, and its step is one more than their latest step).
+    The certificate proves the live set greatest: no removed vertex can be in
+    any self-supporting set, by induction on the step."""
+    ro, col = g.row_off, g.col
+    for v in range(g.n):
+        succ = col[ro[v]:ro[v + 1]]
+        if live[v]:
+            assert level[v] == 0
+            assert live[succ].any(), f"live {v} without live successor"
+        else:
+            assert not live[succ].any(), f"dead {v} with live successor"
+            mx = level[succ].max() if succ.size else 0
+            assert level[v] == mx + 1, f"level of {v}"
+
+
+# ------------------------------------------------------------------ tests
+def test_worked_example(orc, gen):
+    adj, f = parse_golden(os.path.join(GOLDEN, "worked_example.txt"))
+    g = gen.from_adjacency(adj)
+    r = orc.peel(g)
+    assert list(r.live) == f["live"]
+    assert list(r.level) == f["levels"]
+    assert r.alpha == f["alpha"][0]
+    # removal order by steps: {v2, v5}, v4, v3, v1
+    assert sorted(r.order[:2]) == [1, 4] and list(r.order[2:]) == [3, 2, 0]
+    c = orc.counts(g, r)
+    assert (c.T6, c.T4s, c.T4, c.T3J, c.rounds3) == (
+        f["T6"][0], f["T4s"][0], f["T4"][0], f["T3J"][0], f["rounds3"][0])
+    live6, t6, _ = orc.ac6_seq(g)
+    assert t6 == f["T6"][0] and not live6.any()
+    live3, t3, rounds = orc.ac3(g)
+    assert (t3, rounds) == (f["T3J"][0], f["rounds3"][0]) and not live3.any()
+    assert r.rev_edges == f["T4s"][0]
+
+
+def test_splitmix64_reference_vector(orc, gen):
+    # SplitMix64 from state 0 (Steele, Lea, Flood 2014; reference C by Vigna):
+    # outputs are fin(k * golden) for k = 1, 2, 3, 4.
+    golden = 0x9E3779B97F4A7C15
+    expect = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F, 0xF88BB8A8724C81EC]
+    for k, e in enumerate(expect, 1):
+        z = (golden * k) & ((1 << 64) - 1)
+        assert orc.fin64(z) == e
+        assert gen.fin64(z) == e
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_vs_stepwise_peel(orc, gen, seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 300))
+    m = int(rng.integers(0, 4 * n))
+    g = gen.uniform(n, m, seed=seed, drop_self=bool(seed % 2))
+    adj = [list(g.col[g.row_off[v]:g.row_off[v + 1]]) for v in range(n)]
+    alive, level = jacobi_peel(adj)
+    r = orc.peel(g)
+    assert list(r.live.astype(bool)) == alive
+    assert list(r.level) == level
+    assert r.alpha == max(level + [0])
+    check_certificate(g, r.live.astype(bool), r.level)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_simulations_equal_closed_forms(orc, gen, seed):
+    """The sequential AC-6 and AC-3 runs, counting every successor check, agree
+    with the closed forms, and T6 <= T3(in place) <= T3J (Section 8: each edge
+    at most once for AC-6; AC-3 re-checks its cursor edge every repetition)."""
+    for n, m in ((50, 60), (400, 800), (2000, 2500), (3000, 9000)):
+        g = gen.uniform(n, m, seed=100 + seed, drop_self=False)
+        r = orc.peel(g)
+        c = orc.counts(g, r)
+        live6, t6, _ = orc.ac6_seq(g)
+        live3, t3, rounds = orc.ac3(g, jacobi=True)
+        live3i, t3i, rounds_i = orc.ac3(g, jacobi=False)
+        assert (live6 == r.live).all() and (live3 == r.live).all() and (live3i == r.live).all()
+        assert t6 == c.T6
+        assert t3 == c.T3J and rounds == c.rounds3 == r.alpha + 1
+        assert c.T6 <= t3i <= c.T3J and rounds_i <= rounds
+        assert r.rev_edges == c.T4s and c.T4 == c.T4s + g.m
+        assert c.T6min <= c.T6 <= g.m
+
+
+def test_exhaustive_four_vertices(orc, gen):
+    """All 2^16 digraphs on 4 vertices (self-loops included) against the
+    greatest self-supporting subset found by enumeration."""
+    n = 4
+    for code in range(1 << (n * n)):
+        masks = [(code >> (n * v)) & 0xF for v in range(n)]
+        adj = [[w for w in range(n) if (masks[v] >> w) & 1] for v in range(n)]
+        g = gen.from_adjacency(adj)
+        r = orc.peel(g)
+        got = sum(1 << v for v in range(n) if r.live[v])
+        assert got == greatest_by_subsets(n, masks), (code, adj)
+
+
+def test_exhaustive_three_vertices_all_algorithms(orc, gen):
+    n = 3
+    for code in range(1 << (n * n)):
+        masks = [(code >> (n * v)) & 0x7 for v in range(n)]
+        adj = [[w for w in range(n) if (masks[v] >> w) & 1] for v in range(n)]
+        g = gen.from_adjacency(adj)
+        want = greatest_by_subsets(n, masks)
+        for live in (orc.peel(g).live, orc.ac6_seq(g)[0], orc.ac3(g)[0], orc.ac3(g, False)[0]):
+            assert sum(1 << v for v in range(n) if live[v]) == want
+
+
+def test_duplicates_and_self_loops_special_cases(orc, gen):
+    # a self-loop keeps its vertex and everything that reaches it
+    g = gen.from_adjacency([[1], [2], [2], [0], []])
+    r = orc.peel(g)
+    assert list(r.live) == [1, 1, 1, 1, 0]
+    # duplicate edges to a dying vertex: removed once, counted per edge
+    g = gen.from_adjacency([[1, 1, 1], []])
+    r = orc.peel(g)
+    c = orc.counts(g, r)
+    assert list(r.live) == [0, 0] and c.T6 == 3 and c.T4s == 3 and r.alpha == 2
+    # a 2-cycle survives; a chain into it survives; a chain out of it dies
+    g = gen.from_adjacency([[1], [0], [0], [4], []])
+    assert list(orc.peel(g).live) == [1, 1, 1, 0, 0]
+    # empty graph and edgeless graph
+    g = gen.from_adjacency([])
+    r = orc.peel(g)
+    assert r.n_live == 0 and r.alpha == 0
+    g = gen.from_adjacency([[], [], []])
+    r = orc.peel(g)
+    assert r.alpha == 1 and r.n_live == 0
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_reach_cycle_characterisation(orc, gen, seed):
+    for n, m in ((1000, 900), (5000, 6000), (20000, 30000)):
+        g = gen.uniform(n, m, seed=seed * 7 + 1, drop_self=bool(seed % 2))
+        r = orc.peel(g)
+        assert (r.live.astype(bool) == reaches_cycle(g)).all()
+
+
+def test_chain_long():
+    import graphgen as gen
+    import oracle as orc
+    n = 100000
+    adj_src = np.arange(n - 1, dtype=np.int32)
+    g = gen.from_edges(n, adj_src, adj_src + 1)
+    r = orc.peel(g)
+    assert r.alpha == n and r.n_live == 0
+    assert r.level[0] == n and r.level[n - 1] == 1
+    c = orc.counts(g, r)
+    assert c.T6 == n - 1 and c.T3J == sum(1 + (n - v) - 1 for v in range(n - 1))
+
+
+def test_config0_closed_form(orc, gen):
+    """Core + tail: every core vertex keeps a core successor (8 uniform draws,
+    self-loops dropped) and every tail vertex only points to higher tail ids,
+    which end in sinks.  So the live set is the core exactly, T6 = n_core +
+    E_tail, T4* = E_tail, T4 = m + E_tail."""
+    g = gen.config0()
+    n_core = g.meta["n_core"]
+    assert (g.n, n_core, g.meta["n_sink"]) == (65536, 45875, 655)
+    r = orc.peel(g)
+    assert r.live[:n_core].all() and not r.live[n_core:].any()
+    e_tail = int(g.row_off[-1] - g.row_off[n_core])
+    c = orc.counts(g, r)
+    assert c.T6 == n_core + e_tail
+    assert c.T4s == e_tail and c.T4 == g.m + e_tail
+    deg = g.degrees()
+    assert c.T3J == int((deg[n_core:] + r.level[n_core:] - 1).sum()) + n_core * (r.alpha + 1)
+    check_certificate(g, r.live.astype(bool), r.level)
+    live6, t6, _ = orc.ac6_seq(g)
+    assert t6 == c.T6
+
+
+def test_rmat_chain_depth(orc, gen):
+    """A planted chain of L vertices ending in a sink forces alpha >= L and
+    c_i removed at step >= L - i."""
+    g = gen.rmat(14, 8, seed=3, chain=3000)
+    r = orc.peel(g)
+    ch = g.meta["chain_ids"]
+    assert r.alpha >= 3000
+    assert (r.level[ch] >= 3000 - np.arange(3000)).all()
+    check_certificate(g, r.live.astype(bool), r.level)
+    live6, t6, _ = orc.ac6_seq(g)
+    assert (live6 == r.live).all() and t6 == orc.counts(g, r).T6
+
+
+def test_implicit_generator_two_implementations(orc, gen):
+    """The oracle's POST against the workload definition recomputed here from
+    the graphgen finalizer (two separate SplitMix64 implementations), plus the
+    zero-degree fraction and Zipf mean as statistical sanity checks."""
+    imp = gen.implicit(log2n=16, seed=5)
+    M = (1 << 64) - 1
+    for v in (0, 1, 2, 77, 4095, 65535):
+        z = gen.fin64(imp.seed ^ gen.IMPLICIT_TAG_ZERO ^ (v << 8))
+        if z < imp.zero_thr:
+            d = 0
+        else:
+            u = gen.fin64(imp.seed ^ gen.IMPLICIT_TAG_DEG ^ (v << 8))
+            d = 1 + int(np.sum(np.uint64(u) >= imp.table[:255]))
+        assert orc.implicit_deg(imp, v) == d
+        for i in range(min(d, 5)):
+            w = gen.fin64((imp.seed ^ gen.IMPLICIT_TAG_NBR ^ ((v << 8) | i)) & M) & (imp.n - 1)
+            assert orc.implicit_nbr(imp, v, i) == w
+    ro, col = orc.implicit_csr(imp)
+    deg = np.diff(ro)
+    assert abs((deg == 0).mean() - 0.2) < 0.01
+    # E[min(Zipf(2.1), 256)] = sum_{k<256} k p_k + 256 P(K >= 256) ~= 3.44
+    assert abs(deg[deg > 0].mean() - 3.44) < 0.15
+    assert deg.max() <= 256 and col.max() < imp.n
+
+
+def test_batch_oracle_per_graph(orc, gen):
+    b = gen.batch(12, seed=1, n_range=(100, 3000))
+    live, nl, al = orc.batch_peel(b)
+    for g in range(b.G):
+        r = orc.peel(b.graph(g))
+        v0, v1 = b.vbase[g], b.vbase[g + 1]
+        assert (live[v0:v1] == r.live).all() and nl[g] == r.n_live and al[g] == r.alpha
+
+
+def test_bitmap_layout(orc):
+    live = np.zeros(70, np.uint8)
+    live[[0, 5, 31, 32, 69]] = 1
+    bm = orc.bitmap(live)
+    assert bm.dtype == np.uint32 and bm.shape == (3,)
+    assert bm[0] == (1 | (1 << 5) | (1 << 31)) and bm[1] == 1 and bm[2] == (1 << 5)
