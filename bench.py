@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the trimming hot path on one MI355X.
+
+One step = one complete AC-6 trim (init, first sweep, propagation, bitmap)
+of the R-MAT scale-22 graph with a planted 100,000-vertex chain, with the
+graph resident in HBM.  The value is input edges per second (m / step time).
+The live bitmap and the traversed-edge total are checked against the CPU
+oracle in the same run.
+
+Also reported on the same JSON line:
+  roofline      the dominant kernel's algorithmic bytes / its average event-timed
+                duration, against the 8 TB/s HBM peak (plus HBM traffic measured by
+                rocprofv3 counters when a summary for the current kernel source is
+                committed under profiles/);
+  cpu_baseline  the oracle (sequential peel) timed on this host on the same graph;
+  breakdown     every kernel's average duration;
+  baselines     AC-4 and AC-3 on the same graph (one or a few runs each);
+  depth         alpha times the measured per-step latency of a bare chain.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-baselines]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "edges/s + graphs/s: batched/learned-order AC-6 vs plain AC-6, bit-exact live set"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("ac6.hip", "ac4.hip", "ac3.hip", "trim_device.h", "trim_api.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2107_12720_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def prop_bytes(st, t6):
+    """Algorithmic bytes of one ac6_propagate launch: 8 B per successor check
+    (target id + target status), 16 B per close (two list-head exchanges),
+    16 B per join (record store + head CAS), 8 B per list member handed back
+    (its record)."""
+    return (8 * (t6 - st["edges_sweep"]) + 16 * st["closes"] + 16 * st["joins"]
+            + 8 * st["visited"])
+
+
+def sweep_counts(g):
+    """(checks, joins, casualties) of the first sweep.  Only out-degree-0
+    vertices are removed while it runs, so v joins the list of its first
+    successor with out-degree > 0, or is queued for removal if it has none."""
+    import numpy as np
+    deg = np.diff(g.row_off.astype(np.int64))
+    ok = np.flatnonzero(deg[g.col] > 0)
+    start = g.row_off[:-1].astype(np.int64)
+    j = np.searchsorted(ok, start)
+    first = np.where(j < ok.size, ok[np.minimum(j, ok.size - 1)], -1)
+    has = (deg > 0) & (first >= start) & (first < g.row_off[1:])
+    checks = np.where(has, first - start + 1, deg).sum()
+    return int(checks), int(has.sum()), int(((deg > 0) & ~has).sum())
+
+
+def sweep_bytes(g, checks, joins, casualties):
+    """Algorithmic bytes of one ac6_sweep launch: 4 B of offsets per vertex, 8 B
+    per successor check (target id + target status), 16 B per join (head
+    exchange + record store), 4 B per queued casualty."""
+    return 4 * (g.n + 1) + 8 * checks + 16 * joins + 4 * casualties
+
+
+def time_gpu(ctx, fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ktimes = {}
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        res = fn()
+        for name, ms in ctx.kernel_times():
+            ktimes.setdefault(name, []).append(ms)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps, ktimes, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-baselines", action="store_true", help="skip AC-4 / AC-3 / chain runs")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs "
+                                   "are not part of this build", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    import paper_2107_12720_amd as T
+
+    log("generating R-MAT scale 22, edge factor 16, chain 100000 ...")
+    g = gg.config1()
+    n, m = g.n, g.m
+    ctx = T.Context(0)
+    ctx.set_timing(True)
+    ro, col = T.to_device(g.row_off), T.to_device(g.col)
+    P = ctx.num_workers(T.AC6)
+    bm = torch.empty((n + 31) // 32, dtype=torch.int32, device="cuda")
+    we = torch.empty(P, dtype=torch.int64, device="cuda")
+    st_t = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
+
+    def step():
+        return ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=bm, worker_edges=we, stats=st_t)
+
+    log(f"AC-6: warmup {args.warmup}, timed {args.steps} steps")
+    ms, ktimes, res = time_gpu(ctx, step, args.steps, args.warmup)
+    st = res.stats_dict()
+    value = m / (ms / 1e3)
+
+    # parity against the oracle (bit-exact bitmap, exact traversed-edge total)
+    import oracle
+    t_or = time.perf_counter()
+    r = oracle.peel(g)
+    t_or = time.perf_counter() - t_or
+    c = oracle.counts(g, r)
+    parity = bool(np.array_equal(res.bitmap_numpy(), oracle.bitmap(r.live))
+                  and st["edges_total"] == c.T6 and int(we.sum().item()) == c.T6)
+    log(f"AC-6 {ms:.3f} ms/step, {value:.3e} edges/s, parity={parity}")
+
+    kavg = {k: float(np.mean(v)) for k, v in ktimes.items()}
+    dom = max(kavg, key=kavg.get)
+    b_prop = prop_bytes(st, c.T6)
+    sw_checks, sw_joins, sw_cas = sweep_counts(g)
+    if sw_checks != st["edges_sweep"]:
+        log(f"warning: sweep checks {st['edges_sweep']} != host count {sw_checks}")
+        parity = False
+    b_sweep = sweep_bytes(g, sw_checks, sw_joins, sw_cas)
+    algo_bytes = {"ac6_propagate": b_prop, "ac6_sweep": b_sweep,
+                  "ac6_init": 8 * (n + 1) + 8 * n, "ac6_pack": 8 * n + n // 8}
+    ach = algo_bytes[dom] / (kavg[dom] / 1e3) / 1e9
+    traffic = measured_traffic(dom, "rmat22_chain")
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes": int(algo_bytes[dom]), "avg_ms": kavg[dom]}
+    breakdown = {k: {"avg_ms": kavg[k],
+                     "algorithmic_bytes": int(algo_bytes.get(k, 0)),
+                     "achieved_GBs": algo_bytes.get(k, 0) / (kavg[k] / 1e3) / 1e9}
+                 for k in kavg}
+    path_bytes = 8 * c.T6 + 20 * n + n // 8
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "rmat22_ef16_chain100k", "algo": "ac6", "n": n, "m": m,
+                   "alpha": r.alpha, "n_live": r.n_live, "T6": c.T6, "T6min": c.T6min,
+                   "workers": P, "block": 256, "chunk": 4096},
+        "parity": parity,
+        "roofline": roofline,
+        "breakdown": breakdown,
+        "path": {"algorithmic_bytes": path_bytes,
+                 "GBs": path_bytes / (ms / 1e3) / 1e9,
+                 "frac": path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+        "stats": st,
+    }
+
+    if not args.no_baselines:
+        # depth floor: a bare 100,000-vertex chain costs alpha dependent steps
+        s = np.arange(99999, dtype=np.int32)
+        gc = gg.from_edges(100000, s, s + 1)
+        rc_, cc_ = T.to_device(gc.row_off), T.to_device(gc.col)
+        ms_chain, _, _ = time_gpu(ctx, lambda: ctx.trim_csr(T.AC6, gc.n, rc_, cc_), 3, 1)
+        hop_us = ms_chain * 1e3 / 100000
+        out["depth"] = {"alpha": r.alpha, "chain_hop_us": hop_us,
+                        "floor_ms": r.alpha * hop_us / 1e3}
+        a, b = gg.transpose(g)
+        rro, rcl = T.to_device(a), T.to_device(b)
+        ms4, kt4, res4 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC4, n, ro, col, rro, rcl), 3, 1)
+        st4 = res4.stats_dict()
+        ok4 = bool(np.array_equal(res4.bitmap_numpy(), oracle.bitmap(r.live))
+                   and st4["edges_total"] == c.T4s)
+        log(f"AC-4 {ms4:.3f} ms, parity={ok4}")
+        ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC3, n, ro, col), 1, 0)
+        st3 = res3.stats_dict()
+        ok3 = bool(np.array_equal(res3.bitmap_numpy(), oracle.bitmap(r.live))
+                   and st3["edges_total"] == c.T3J and st3["rounds"] == c.rounds3)
+        log(f"AC-3 {ms3:.3f} ms, parity={ok3}")
+        out["baselines"] = {
+            "ac4": {"ms": ms4, "edges_per_s": m / (ms4 / 1e3), "traversed": st4["edges_total"],
+                    "T4star": c.T4s, "T4": c.T4, "parity": ok4,
+                    "kernels_ms": {k: float(np.mean(v)) for k, v in kt4.items()}},
+            "ac3": {"ms": ms3, "edges_per_s": m / (ms3 / 1e3), "traversed": st3["edges_total"],
+                    "rounds": st3["rounds"], "T3J": c.T3J, "parity": ok3,
+                    "kernels_ms": {k: float(np.mean(v)) for k, v in kt3.items()}},
+            "ac6_speedup_vs_ac4": ms4 / ms, "ac6_speedup_vs_ac3": ms3 / ms,
+        }
+
+    if not args.no_cpu:
+        # the oracle as it stands, single-threaded, repeated up to ~cpu_seconds
+        times = [t_or]
+        while sum(times) < args.cpu_seconds and len(times) < 20:
+            t = time.perf_counter()
+            oracle.peel(g)
+            times.append(time.perf_counter() - t)
+        tm = float(np.mean(times))
+        out["cpu_baseline"] = {"value": m / tm, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                               "sample": f"full rmat22_ef16_chain100k graph, {len(times)} runs "
+                                         f"of the sequential peel, mean {tm:.3f} s",
+                               "host_cores": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

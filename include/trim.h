@@ -1,0 +1,183 @@
+/*
+ * trim.h -- C ABI of libtrim, parallel graph trimming on one MI355X (gfx950).
+ *
+ * Graph trimming (Def. Trimmed Graph, Section 2 of "Efficient Parallel Graph
+ * Trimming by Arc-Consistency", arXiv 2107.12720) removes, until a fixed
+ * point, every vertex that has no live successor.  The result is the greatest
+ * vertex set in which every vertex keeps a successor inside the set.  Three
+ * algorithms compute it:
+ *
+ *   TRIM_AC6  the AC-6-based algorithm (Section 6, Alg. par-ac-6-trim): each
+ *             live vertex keeps one support, the first live successor found
+ *             from its cursor; a removed vertex hands back only the vertices
+ *             it supported.  Each edge is examined at most once.
+ *   TRIM_AC4  the AC-4-based algorithm (Section 5, Alg. par-ac4trim): live
+ *             out-degree counters, decremented over the transposed graph.
+ *             Counters start from CSR offsets (AC4Trim*, Section 9.3).
+ *   TRIM_AC3  the AC-3-based algorithm (Section 4, Alg. TraditionalTrim):
+ *             repeated sweeps with the edge_index cursor of Section 8.  A
+ *             sweep reads the statuses of its start (one sweep = one round),
+ *             so the round count is alpha + 1 (Def. of alpha, Section 2.4).
+ *
+ * Conventions for every call:
+ *  - Pointers marked (device) are device memory owned by the caller.  The
+ *    library never frees or keeps them beyond the call's stream work.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls
+ *    only enqueue work on it and return; results are valid after the caller
+ *    synchronises the stream.
+ *  - Every call returns a trim_status_t.  Argument errors are detected on the
+ *    host before anything is enqueued; trim_last_error() then returns a
+ *    message for the calling thread.  Nothing aborts or throws across the ABI.
+ *  - Outputs: live_bitmap has ceil(n/32) uint32 words; bit (v % 32) of word
+ *    v / 32 is set iff v is LIVE.  Bits at positions >= n in the last word are
+ *    zero.  worker_edges[p] receives the successor checks made by worker p
+ *    (Section 9.3 counts traversed edges per worker); only their sum is a
+ *    deterministic quantity.  All outputs are overwritten, never accumulated.
+ *  - A trim_ctx owns the call's working memory and must not be used by two
+ *    host threads or on two streams at the same time.
+ */
+#ifndef TRIM_H
+#define TRIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRIM_ABI_VERSION 1
+
+typedef enum { TRIM_AC3 = 3, TRIM_AC4 = 4, TRIM_AC6 = 6 } trim_algo_t;
+
+typedef enum {
+    TRIM_OK = 0,
+    TRIM_E_INVAL = -1,        /* bad argument (null pointer, size out of range) */
+    TRIM_E_NOMEM = -2,        /* device working memory could not be allocated */
+    TRIM_E_HIP = -3,          /* a HIP runtime call failed */
+    TRIM_E_UNSUPPORTED = -4,  /* e.g. AC-4 on an implicit graph (no G^T) */
+    TRIM_E_BADGRAPH = -5,     /* validate=1 found non-monotone offsets or bad targets */
+    TRIM_E_STALLED = -6       /* reserved: a watchdog bound was exceeded */
+} trim_status_t;
+
+typedef struct trim_ctx trim_ctx;
+
+/* Explicit graph G = (V, E) in CSR (Section 2.1), plus G^T for AC-4. */
+typedef struct {
+    int32_t n;                /* vertices, 0 <= n <= 2^30 */
+    int64_t m;                /* edges, == row_off[n], 0 <= m < 2^31 */
+    const int32_t *row_off;   /* (device) n+1 non-decreasing offsets, row_off[0] == 0 */
+    const int32_t *col;       /* (device) m targets in [0, n); successor order = array order */
+    const int32_t *rrow_off;  /* (device) G^T offsets, n+1; AC-4 only, else NULL */
+    const int32_t *rcol;      /* (device) G^T sources, m; AC-4 only, else NULL */
+} trim_csr_t;
+
+/*
+ * Implicit graph G = (V, POST) (Section 2.1, on-the-fly property Section
+ * 1.3): successors are computed when needed, nothing is stored.  With
+ * fin() the SplitMix64 finalizer, n = 2^log2n:
+ *   deg(v) = 0                              if fin(seed ^ TZ ^ (v<<8)) < zero_thr
+ *          = 1 + #{j < 255 : fin(seed ^ TD ^ (v<<8)) >= deg_table[j]}   otherwise
+ *   POST(v)[i] = fin(seed ^ TN ^ ((v<<8) | i)) & (n-1),   0 <= i < deg(v)
+ * with TZ = 0x5A45524F00000000, TD = 0x4445470000000000,
+ * TN = 0x4E42520000000000.  deg_table holds inverse-CDF thresholds, so
+ * deg(v) <= 256.
+ */
+typedef struct {
+    int32_t log2n;              /* 1 .. 30 */
+    uint64_t seed;
+    uint64_t zero_thr;
+    const uint64_t *deg_table;  /* (device) 256 non-decreasing thresholds */
+} trim_implicit_t;
+
+/* Launch options; zero-initialise for defaults. */
+typedef struct {
+    int32_t block;      /* threads per workgroup of the sweep kernels (64..1024, 0 = 256) */
+    int32_t workers;    /* persistent workgroups P (0 = sized from occupancy) */
+    int32_t chunk;      /* AC-6: vertices claimed per dynamic work chunk of the first
+                           sweep (Section 8, schedule(dynamic, s)); rounded up to a
+                           multiple of block; 0 = 4096 */
+    int32_t validate;   /* 1 = check offsets/targets on the device first (synchronises) */
+    int32_t graph;      /* trim_batch only: 1 = capture the launch sequence into a HIP
+                           graph on the first call and replay it while every argument
+                           is unchanged (needs a non-NULL stream) */
+    int32_t reserved[3];
+} trim_opts_t;
+
+/* Per-call statistics, written to device memory. */
+typedef struct {
+    uint64_t edges_total;  /* sum of worker_edges: successor checks (AC-6, AC-3) or
+                              reverse edges traversed (AC-4) */
+    uint64_t n_live;       /* popcount of the live bitmap */
+    uint64_t n_dead;       /* vertices removed */
+    uint64_t rounds;       /* AC-3: sweeps run (alpha + 1); 0 otherwise */
+    uint64_t queued;       /* AC-6/AC-4: work items that went through the shared queue */
+    uint64_t edges_sweep;  /* AC-6: successor checks made by the first sweep */
+    uint64_t closes;       /* AC-6: removed vertices whose support lists were closed
+                              after the first sweep */
+    uint64_t joins;        /* AC-6: support-list joins after the first sweep */
+    uint64_t visited;      /* AC-6: support-list members handed back */
+    uint64_t reserved[3];
+} trim_stats_t;
+
+/*
+ * Per-kernel timing of the last call made on `ctx` (for benchmarks).  With
+ * trim_ctx_set_timing(ctx, 1), every launch sequence records HIP events
+ * around each kernel on the call's stream.  trim_ctx_kernel_times waits for
+ * the last call to finish and writes up to `max` entries: names[i] (a static
+ * string) and ms[i] (elapsed milliseconds).  Returns the number of kernels.
+ */
+int trim_ctx_set_timing(trim_ctx *ctx, int enable);
+int trim_ctx_kernel_times(trim_ctx *ctx, int max, const char **names, float *ms);
+
+int trim_version(void);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *trim_last_error(void);
+
+/* Create a context bound to HIP device `device`.  *out is NULL on failure. */
+int trim_ctx_create(trim_ctx **out, int device);
+/* Free a context and its working memory (NULL is ignored). */
+int trim_ctx_destroy(trim_ctx *ctx);
+
+/* Number of workers P for `algo` with `opts` (NULL = defaults); size of worker_edges. */
+int trim_num_workers(trim_ctx *ctx, int algo, const trim_opts_t *opts, int32_t *P);
+
+/*
+ * Trim an explicit graph with `algo`.  Output live_bitmap (device,
+ * ceil(n/32) words), worker_edges (device, P entries from trim_num_workers),
+ * stats (device, may be NULL).  AC-4 needs g->rrow_off and g->rcol
+ * (TRIM_E_INVAL without them).  Self-loops keep their vertex; duplicate edges
+ * are allowed and counted as separate edges.
+ */
+int trim_csr(trim_ctx *ctx, int algo, const trim_csr_t *g, const trim_opts_t *opts,
+             uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats, void *stream);
+
+/*
+ * Trim an implicit graph (AC-6 or AC-3 only; AC-4 needs G^T and returns
+ * TRIM_E_UNSUPPORTED, Table trim: AC-4 lacks the on-the-fly property).
+ * Outputs as for trim_csr with n = 2^log2n.
+ */
+int trim_implicit(trim_ctx *ctx, int algo, const trim_implicit_t *g, const trim_opts_t *opts,
+                  uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats,
+                  void *stream);
+
+/*
+ * AC-6 on G independent graphs packed into one CSR, in one launch sequence.
+ * Graph g owns vertices [vbase[g], vbase[g+1]) and their out-edges;
+ * row_off (device, vbase[G]+1 entries) is absolute into col; col (device)
+ * holds graph-local target ids in [0, vbase[g+1]-vbase[g]).  vbase and
+ * bitmap_base are device int64 arrays of G+1 entries; graph g's bitmap starts
+ * at word bitmap_base[g] of live_bitmaps and covers its n_g vertices
+ * (bitmap_base[g+1] - bitmap_base[g] >= ceil(n_g/32)).  graph_edges (device,
+ * G entries) receives each graph's successor checks.  total_n = vbase[G] and
+ * total_m = row_off[total_n] are passed by value.
+ */
+int trim_batch(trim_ctx *ctx, int32_t G, const int64_t *vbase, const int32_t *row_off,
+               const int32_t *col, int64_t total_n, int64_t total_m, const int64_t *bitmap_base,
+               const trim_opts_t *opts, uint32_t *live_bitmaps, uint64_t *graph_edges,
+               trim_stats_t *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRIM_H */

@@ -1,0 +1,256 @@
+"""Python binding of libtrim: parallel graph trimming on MI355X (gfx950).
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+kernels of ``libtrim.so`` (built from ``csrc/`` by ``build.py``); PyTorch is
+used only for device memory and streams.  There is no fallback: if the
+library is missing or no GPU is present, calls raise :class:`TrimError`.
+
+The functions mirror the C ABI in ``include/trim.h``:
+
+* :meth:`Context.trim_csr`      -- AC-6 / AC-4 / AC-3 on an explicit CSR graph;
+* :meth:`Context.trim_implicit` -- AC-6 / AC-3 on the hash-generated graph;
+* :meth:`Context.trim_batch`    -- AC-6 on many packed graphs in one launch
+  sequence (optionally replayed from a captured HIP graph);
+* :meth:`Context.num_workers`   -- the worker count P (size of worker_edges).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrim.so")
+
+AC3, AC4, AC6 = 3, 4, 6
+ALGOS = {"ac3": AC3, "ac4": AC4, "ac6": AC6}
+STATUS = {0: "TRIM_OK", -1: "TRIM_E_INVAL", -2: "TRIM_E_NOMEM", -3: "TRIM_E_HIP",
+          -4: "TRIM_E_UNSUPPORTED", -5: "TRIM_E_BADGRAPH", -6: "TRIM_E_STALLED"}
+EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destroy",
+           "trim_num_workers", "trim_csr", "trim_implicit", "trim_batch",
+           "trim_ctx_set_timing", "trim_ctx_kernel_times")
+STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
+                "joins", "visited")
+STATS_WORDS = 12
+
+
+class TrimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("workers", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class CsrDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("row_off", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("rrow_off", ctypes.c_void_p), ("rcol", ctypes.c_void_p)]
+
+
+class ImplicitDesc(ctypes.Structure):
+    _fields_ = [("log2n", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("zero_thr", ctypes.c_uint64), ("deg_table", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtrim.so (raises TrimError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TrimError(-3, f"{LIB_PATH} is missing; build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        L.trim_version.restype = ctypes.c_int
+        L.trim_last_error.restype = ctypes.c_char_p
+        L.trim_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.trim_ctx_destroy.argtypes = [vp]
+        L.trim_num_workers.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Opts),
+                                       ctypes.POINTER(i32)]
+        L.trim_csr.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(Opts),
+                               vp, vp, vp, vp]
+        L.trim_implicit.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ImplicitDesc),
+                                    ctypes.POINTER(Opts), vp, vp, vp, vp]
+        L.trim_batch.argtypes = [vp, i32, vp, vp, vp, ctypes.c_int64, ctypes.c_int64, vp,
+                                 ctypes.POINTER(Opts), vp, vp, vp, vp]
+        L.trim_ctx_set_timing.argtypes = [vp, ctypes.c_int]
+        L.trim_ctx_kernel_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
+                                            ctypes.POINTER(ctypes.c_float)]
+        for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_num_workers", "trim_csr",
+                  "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().trim_last_error().decode()
+
+
+def _check(code: int):
+    if code != 0:
+        raise TrimError(code, last_error())
+
+
+def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False) -> Opts:
+    return Opts(block, workers, chunk, int(bool(validate)), int(bool(graph)), (0, 0, 0))
+
+
+def _dev_ptr(t, dtype, name, allow_none=False):
+    import torch
+    if t is None:
+        if allow_none:
+            return None
+        raise TrimError(-1, f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TrimError(-1, f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TrimError(-1, f"{name} must be a contiguous {dtype} tensor")
+    return t.data_ptr()
+
+
+def _stream_handle(stream, device):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class TrimResult:
+    live_bitmap: "object"    # torch.int32 tensor of ceil(n/32) words (uint32 bit patterns)
+    worker_edges: "object"   # torch.int64 tensor of P counts (or per-graph counts)
+    stats: "object"          # torch.int64 tensor of 12 words (trim_stats_t)
+
+    def stats_dict(self) -> dict:
+        s = self.stats.cpu().numpy().view(np.uint64)
+        return {k: int(s[i]) for i, k in enumerate(STATS_FIELDS)}
+
+    def bitmap_numpy(self) -> np.ndarray:
+        return self.live_bitmap.cpu().numpy().view(np.uint32)
+
+
+class Context:
+    """A libtrim context bound to one GPU; owns the call's working memory."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise TrimError(-3, "no GPU available; libtrim has no CPU path")
+        self.device = device
+        self._h = ctypes.c_void_p()
+        _check(lib().trim_ctx_create(ctypes.byref(self._h), device))
+
+    def close(self):
+        if self._h:
+            lib().trim_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, enable: bool = True):
+        """Record HIP events around each kernel of later calls (same stream)."""
+        _check(lib().trim_ctx_set_timing(self._h, int(bool(enable))))
+
+    def kernel_times(self) -> list:
+        """[(kernel name, ms)] of the last call; waits for it to finish."""
+        names = (ctypes.c_char_p * 16)()
+        ms = (ctypes.c_float * 16)()
+        k = lib().trim_ctx_kernel_times(self._h, 16, names, ms)
+        if k < 0:
+            raise TrimError(k, last_error())
+        return [(names[i].decode(), float(ms[i])) for i in range(k)]
+
+    def num_workers(self, algo: int = AC6, opts: Opts | None = None) -> int:
+        P = ctypes.c_int32()
+        _check(lib().trim_num_workers(self._h, int(algo), ctypes.byref(opts or Opts()),
+                                      ctypes.byref(P)))
+        return P.value
+
+    def _outputs(self, n_words, P, live_bitmap, worker_edges, stats):
+        import torch
+        dev = torch.device("cuda", self.device)
+        if live_bitmap is None:
+            live_bitmap = torch.empty(max(n_words, 1), dtype=torch.int32, device=dev)
+        if worker_edges is None:
+            worker_edges = torch.empty(max(P, 1), dtype=torch.int64, device=dev)
+        if stats is None:
+            stats = torch.empty(STATS_WORDS, dtype=torch.int64, device=dev)
+        return live_bitmap, worker_edges, stats
+
+    def trim_csr(self, algo, n, row_off, col, rrow_off=None, rcol=None, *, live_bitmap=None,
+                 worker_edges=None, stats=None, opts: Opts | None = None,
+                 stream=None) -> TrimResult:
+        """Trim the CSR graph (row_off, col: int32 device tensors) with algo 3/4/6."""
+        import torch
+        algo = ALGOS.get(algo, algo)
+        opts = opts or Opts()
+        m = int(col.numel()) if col is not None else 0
+        d = CsrDesc(int(n), m, _dev_ptr(row_off, torch.int32, "row_off"),
+                    _dev_ptr(col, torch.int32, "col") if m else None,
+                    _dev_ptr(rrow_off, torch.int32, "rrow_off", allow_none=True),
+                    _dev_ptr(rcol, torch.int32, "rcol", allow_none=True) if m else None)
+        P = self.num_workers(algo, opts)
+        lb, we, st = self._outputs((int(n) + 31) // 32, P, live_bitmap, worker_edges, stats)
+        _check(lib().trim_csr(self._h, int(algo), ctypes.byref(d), ctypes.byref(opts),
+                              ctypes.c_void_p(lb.data_ptr()), ctypes.c_void_p(we.data_ptr()),
+                              ctypes.c_void_p(st.data_ptr()), _stream_handle(stream, self.device)))
+        return TrimResult(lb, we, st)
+
+    def trim_implicit(self, algo, log2n, seed, zero_thr, deg_table, *, live_bitmap=None,
+                      worker_edges=None, stats=None, opts: Opts | None = None,
+                      stream=None) -> TrimResult:
+        """Trim the hash-generated graph G = (V, POST) with n = 2^log2n (algo 3 or 6)."""
+        import torch
+        algo = ALGOS.get(algo, algo)
+        opts = opts or Opts()
+        d = ImplicitDesc(int(log2n), int(seed) & (2 ** 64 - 1), int(zero_thr) & (2 ** 64 - 1),
+                         _dev_ptr(deg_table, torch.int64, "deg_table"))
+        P = self.num_workers(algo, opts) if algo in (AC3, AC6) else 1
+        lb, we, st = self._outputs(((1 << int(log2n)) + 31) // 32, P, live_bitmap, worker_edges,
+                                   stats)
+        _check(lib().trim_implicit(self._h, int(algo), ctypes.byref(d), ctypes.byref(opts),
+                                   ctypes.c_void_p(lb.data_ptr()), ctypes.c_void_p(we.data_ptr()),
+                                   ctypes.c_void_p(st.data_ptr()),
+                                   _stream_handle(stream, self.device)))
+        return TrimResult(lb, we, st)
+
+    def trim_batch(self, vbase, row_off, col, bitmap_base, total_n, total_m, *, live_bitmaps=None,
+                   graph_edges=None, stats=None, opts: Opts | None = None,
+                   stream=None) -> TrimResult:
+        """AC-6 on the packed batch (vbase, bitmap_base: int64 device tensors of G+1)."""
+        import torch
+        opts = opts or Opts()
+        G = int(vbase.numel()) - 1
+        if live_bitmaps is None:
+            raise TrimError(-1, "live_bitmaps must be preallocated (bitmap_base[G] words)")
+        lb, ge, st = self._outputs(0, G, live_bitmaps, graph_edges, stats)
+        _check(lib().trim_batch(self._h, G, _dev_ptr(vbase, torch.int64, "vbase"),
+                                _dev_ptr(row_off, torch.int32, "row_off"),
+                                _dev_ptr(col, torch.int32, "col") if total_m else None,
+                                int(total_n), int(total_m),
+                                _dev_ptr(bitmap_base, torch.int64, "bitmap_base"),
+                                ctypes.byref(opts), ctypes.c_void_p(lb.data_ptr()),
+                                ctypes.c_void_p(ge.data_ptr()), ctypes.c_void_p(st.data_ptr()),
+                                _stream_handle(stream, self.device)))
+        return TrimResult(lb, ge, st)
+
+
+def to_device(a: np.ndarray, device: int = 0):
+    """numpy array -> contiguous device tensor (int32/int64 views kept)."""
+    import torch
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda", device))

@@ -1,0 +1,198 @@
+// ac3.hip -- AC-3-based graph trimming on gfx950 (Section 4.1, Alg. TraditionalTrim).
+//
+// Repetitions ("rounds") of a sweep over the live vertices, until a round
+// removes nothing.  Each vertex keeps the edge_index cursor of Section 8:
+// successors found DEAD are passed for good, the first successor that is not
+// DEAD ends the scan and is checked again in the next round.
+//
+// A round reads the statuses as they were at its start: dround[w] holds the
+// round in which w was removed (INT_MAX while live), and w counts as DEAD in
+// round r iff dround[w] < r.  A removal in round r is therefore seen from
+// round r+1 on, whatever the lane order, which makes the result of every round
+// and the number of rounds (alpha + 1, Def. of alpha) deterministic.
+//
+// All rounds run inside one cooperative launch: the live vertices of round r
+// sit in a compacted list, survivors are appended (wavefront-aggregated) to
+// the list of round r+1, and a grid barrier separates rounds.  List sizes
+// rotate over three counter slots so that resetting the slot of round r+2
+// never races with readers of rounds r and r+1.
+#include <climits>
+
+#include "trim_device.h"
+#include "trim_internal.h"
+
+namespace trim {
+
+namespace {
+
+template <class View>
+struct Stage3 {
+    static constexpr int kWords = 1;
+    __device__ static void apply(View&, uint64_t*) {}
+};
+template <>
+struct Stage3<ImplicitView> {
+    static constexpr int kWords = 256;
+    __device__ static void apply(ImplicitView& g, uint64_t* lds) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) lds[i] = g.table[i];
+        __syncthreads();
+        g.table = lds;
+    }
+};
+
+template <class View>
+__global__ void ac3_init(View g, int n, int* ptr, int* dround, int* list1, int* ctr,
+                         uint64_t* worker_edges, int P, trim_stats_t* stats) {
+    __shared__ uint64_t lds[Stage3<View>::kWords];
+    Stage3<View>::apply(g, lds);
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < kCtrInts) ctr[tid] = (tid == kCnt0 + 1) ? n : 0;
+    for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
+    if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
+    for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
+        ptr[v] = g.begin(v);
+        dround[v] = INT_MAX;
+        list1[v] = v;
+    }
+}
+
+// Sense-free grid barrier: arrivals counted in *count, the last arrival resets
+// it and bumps *gen.  Agent-scope fences make every block's writes of the
+// round visible to every other block (and XCD) after the barrier.
+__device__ __forceinline__ void grid_barrier(int* count, int* gen) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int g0 = ld_dev(gen);
+        __threadfence();
+        if (add_dev(count, 1) == (int)gridDim.x - 1) {
+            st_dev(count, 0);
+            __threadfence();
+            add_dev(gen, 1);
+        } else {
+            while (ld_dev(gen) == g0) __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <class View>
+__global__ __launch_bounds__(256) void ac3_rounds(View g, int* ptr, int* dround, int* list0,
+                                                  int* list1, int* ctr, uint64_t* worker_edges,
+                                                  trim_stats_t* stats) {
+    __shared__ uint64_t lds[Stage3<View>::kWords];
+    Stage3<View>::apply(g, lds);
+    uint64_t edges = 0;
+    int r = 1;
+    for (;; ++r) {
+        const int* in = (r & 1) ? list1 : list0;
+        int* out = (r & 1) ? list0 : list1;
+        const int cnt_in = ld_dev(ctr + kCnt0 + r % 3);
+        int* cnt_out = ctr + kCnt0 + (r + 1) % 3;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
+        for (int base = blockIdx.x * blockDim.x; base < cnt_in; base += gridDim.x * blockDim.x) {
+            const int i = base + threadIdx.x;
+            bool keep = false;
+            int v = 0;
+            if (i < cnt_in) {
+                v = in[i];
+                const int p0 = ptr[v];
+                const int e = g.end(v);
+                const int ctx = g.vctx(v);
+                int p = p0;
+                for (; p < e; ++p)
+                    if (dround[g.target(v, p, ctx)] >= r) break;
+                if (p < e) {
+                    edges += (uint64_t)(p - p0 + 1);
+                    if (p != p0) ptr[v] = p;
+                    keep = true;
+                } else {
+                    edges += (uint64_t)(e - p0);
+                    dround[v] = r;
+                }
+            }
+            const int slot = wave_append_slot(keep, cnt_out, nullptr);
+            if (keep) out[slot] = v;
+        }
+        grid_barrier(ctr + kBarCount, ctr + kBarGen);
+        if (ld_dev(cnt_out) == cnt_in) break;   // no removal in round r
+    }
+    edges = wave_sum(edges);
+    if (lane_id() == 0 && edges) add_dev(worker_edges + blockIdx.x, edges);
+    if (stats && blockIdx.x == 0 && threadIdx.x == 0) stats->rounds = (uint64_t)r;
+}
+
+struct Ac3Live {
+    const int* dround;
+    __device__ __forceinline__ bool operator()(int v) const { return dround[v] == INT_MAX; }
+};
+
+inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
+    long long b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (int)b;
+}
+
+template <class View>
+hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats) {
+    const int P = lc.workers;
+    int pack_blocks = 0;
+    int* ptr = w.a;
+    int* dround = w.c;
+    int* list1 = w.d;
+    int* list0 = reinterpret_cast<int*>(w.b);
+    {
+        Timed t(lc, "ac3_init");
+        hipLaunchKernelGGL(ac3_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
+                           lc.stream, g, n, ptr, dround, list1, w.ctr, worker_edges, P, stats);
+    }
+    if (n > 0) {
+        void* args[] = {&g, &ptr, &dround, &list0, &list1, (void*)&w.ctr, &worker_edges, &stats};
+        {
+            Timed t(lc, "ac3_rounds");
+            hipError_t e = hipLaunchCooperativeKernel((const void*)ac3_rounds<View>, dim3(P),
+                                                      dim3(256), args, 0, lc.stream);
+            if (e != hipSuccess) return e;
+        }
+        Timed t(lc, "ac3_pack");
+        pack_blocks = grid_for(n, 256, lc.cus * 4);
+        hipLaunchKernelGGL(pack_bitmap<Ac3Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
+                           Ac3Live{dround}, n, bitmap, w.part);
+    }
+    // an empty graph still runs the repeat-until loop once
+    if (stats)
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
+                           pack_blocks, worker_edges, w.part, w.ctr, stats, 1);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t ac3_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats) {
+    ExplicitView v{g.row_off, g.col};
+    return ac3_run(v, g.n, w, lc, bitmap, worker_edges, stats);
+}
+
+hipError_t ac3_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
+                        uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats) {
+    const int n = 1 << g.log2n;
+    ImplicitView v{g.seed, g.zero_thr, g.deg_table, (uint32_t)(n - 1)};
+    return ac3_run(v, n, w, lc, bitmap, worker_edges, stats);
+}
+
+int ac3_max_workers_per_cu(int) {
+    int nb = 0, nb2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ac3_rounds<ExplicitView>, 256, 0) !=
+        hipSuccess)
+        return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, ac3_rounds<ImplicitView>, 256, 0) ==
+            hipSuccess &&
+        nb2 < nb)
+        nb = nb2;
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace trim

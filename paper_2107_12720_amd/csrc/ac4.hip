@@ -1,0 +1,142 @@
+// ac4.hip -- AC-4-based graph trimming on gfx950 (Section 5.2, Alg. par-ac4trim).
+//
+// cnt[v] is the live out-degree counter, initialised from CSR offsets
+// (AC4Trim*, Section 9.3: no edge is traversed to find it).  A removed vertex
+// w decrements cnt[u] once for every edge u -> w, walking w's predecessors in
+// the transposed graph.  The paper takes CAS(status, LIVE, DEAD) to enqueue a
+// vertex once; here the fetch-and-add that brings cnt[u] from 1 to 0 returns
+// 1 to exactly one lane, which makes that lane u's unique remover, so the
+// status is simply cnt[u] == 0.
+//
+// Kernels: ac4_init (counters), ac4_seed (out-degree-0 vertices queued),
+// ac4_propagate (persistent workers on per-wavefront LDS rings, WaveQueue;
+// a lane walks the predecessors of its removed vertex eight at a time, with
+// the eight decrements in flight together), ac4_pack (bitmap from cnt > 0).
+#include "trim_device.h"
+#include "trim_internal.h"
+
+namespace trim {
+
+namespace {
+
+__global__ void ac4_init(const int* row_off, int n, int* cnt, int* ctr, uint64_t* worker_edges,
+                         int P, trim_stats_t* stats) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < kCtrInts) ctr[tid] = 0;
+    for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
+    if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
+    for (int v = tid; v < n; v += gridDim.x * blockDim.x) cnt[v] = row_off[v + 1] - row_off[v];
+}
+
+__global__ void ac4_seed(const int* cnt, int n, uint32_t* q, int* ctr) {
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int v = base + threadIdx.x;
+        const bool dead = v < n && cnt[v] == 0;
+        const int slot = wave_append_slot(dead, ctr + kQTail, ctr + kPending);
+        if (dead) q[slot] = make_item(0, v);
+    }
+}
+
+constexpr int kBatch = 8;
+
+__global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const int* rcol,
+                                                     int* cnt, uint32_t* q, int* ctr,
+                                                     uint64_t* worker_edges) {
+    __shared__ uint32_t rings[256 / kWave][kLocalQ];
+    __shared__ int ring_tail[256 / kWave];
+    WaveQueue wq;
+    const int wv = threadIdx.x / kWave;
+    wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending);
+    uint32_t item = kNone;
+    int k = 0, e = 0;
+    bool started = false;
+    uint64_t edges = 0;
+    while (wq.acquire(item)) {
+        uint32_t out[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) out[j] = kNone;
+        if (item != kNone) {
+            if (!started) {
+                const int w = item_vertex(item);
+                k = rrow_off[w];
+                e = rrow_off[w + 1];
+                started = true;
+                edges += (uint64_t)(e - k);
+            }
+            const int nb = min(kBatch, e - k);
+            int u[kBatch], old[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (j < nb) u[j] = rcol[k + j];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (j < nb) old[j] = add_dev(cnt + u[j], -1);
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j)
+                if (j < nb && old[j] == 1) out[j] = make_item(0, u[j]);   // u's last live successor
+            k += nb;
+            if (k >= e) {
+                item = kNone;
+                started = false;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; j += 2) wq.push(out[j], out[j + 1]);
+    }
+    edges = wave_sum(edges);
+    if (lane_id() == 0 && edges) add_dev(worker_edges + blockIdx.x, edges);
+}
+
+struct Ac4Live {
+    const int* cnt;
+    __device__ __forceinline__ bool operator()(int v) const { return cnt[v] > 0; }
+};
+
+inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
+    long long b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (int)b;
+}
+
+}  // namespace
+
+hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats) {
+    const int n = g.n, P = lc.workers, B = lc.block;
+    int pack_blocks = 0;
+    {
+        Timed t(lc, "ac4_init");
+        hipLaunchKernelGGL(ac4_init, dim3(grid_for(n, 256, 16384)), dim3(256), 0, lc.stream,
+                           g.row_off, n, w.a, w.ctr, worker_edges, P, stats);
+    }
+    if (n > 0) {
+        {
+            Timed t(lc, "ac4_seed");
+            hipLaunchKernelGGL(ac4_seed, dim3(grid_for(n, B, lc.cus * 8)), dim3(B), 0, lc.stream,
+                               w.a, n, w.q, w.ctr);
+        }
+        {
+            Timed t(lc, "ac4_propagate");
+            hipLaunchKernelGGL(ac4_propagate, dim3(P), dim3(256), 0, lc.stream, g.rrow_off,
+                               g.rcol, w.a, w.q, w.ctr, worker_edges);
+        }
+        Timed t(lc, "ac4_pack");
+        pack_blocks = grid_for(n, 256, lc.cus * 4);
+        hipLaunchKernelGGL(pack_bitmap<Ac4Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
+                           Ac4Live{w.a}, n, bitmap, w.part);
+    }
+    if (stats)
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
+                           pack_blocks, worker_edges, w.part, w.ctr, stats, 0);
+    return hipGetLastError();
+}
+
+int ac4_max_workers_per_cu(int) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ac4_propagate, 256, 0) != hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace trim

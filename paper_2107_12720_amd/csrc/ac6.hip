@@ -1,0 +1,402 @@
+// ac6.hip -- AC-6-based graph trimming on gfx950 (Section 6.2, Alg. par-ac-6-trim).
+//
+// State per vertex v:
+//   head[2v], head[2v+1]  the supporting set S(v) (Def. Supporting Set), split
+//            in two intrusive linked lists: S_more(v) holds supporters with
+//            successors left after v, S_last(v) those for which v is the last
+//            successor.  Each head is kEmpty, the id of the last vertex that
+//            joined, or kDead once v is removed; kDead closes the list.
+//   rec[v]   (next, cursor): the next member of the list v is in, and the
+//            position of v's current support in its successor list.
+//
+// The split matters for depth: when v is removed, every member of S_last(v)
+// is removed too, with no successor left to check.  The closer learns the
+// first of them from its own exchange and closes it at once, so each step of
+// a peeling chain costs one atomic round trip instead of a list walk plus a
+// record load.
+//
+// The paper's Lock(w)/recheck/add and Lock(v)/DEAD/Unlock become lock-free:
+//   join   : rec[v] = (h, p); CAS(head[w], h, v)  -- fails once head[w] == kDead
+//   close  : L = exchange(head[v], kDead)         -- takes the whole list at once
+// which gives the guarantee of the locks: after the close nobody joins S(v),
+// and everybody who joined before it is handed back exactly once.  Lanes of a
+// wavefront run in lock step, so a spinning lock would deadlock there.
+//
+// A vertex that finds no live successor is not closed on the spot: it becomes
+// a "close item".  Vertices may still join it until it is closed; the closer
+// hands them back, so they simply move on to their next successor (the edge
+// was checked once).  Every successor position is passed at most once, so the
+// number of successor checks is the same for every schedule:
+//   sum_dead deg(v) + sum_live (first-live-successor index + 1).
+//
+// Kernels, in stream order:
+//   ac6_init       heads = kDead for out-degree-0 vertices (their lists are
+//                  empty, nothing to hand back), kEmpty otherwise; counters
+//                  and outputs zeroed.
+//   ac6_sweep      DoPost for every vertex, one lane per vertex.  Nothing is
+//                  removed during this kernel, so a live-looking target stays
+//                  live and joining is a plain exchange (no CAS retry storms on
+//                  hub vertices).  Vertices without a live successor are queued
+//                  as close items.
+//   ac6_propagate  persistent workers (the paper's Trim_p) run three kinds of
+//                  items through per-wavefront LDS rings (WaveQueue):
+//                    CLOSE(c)  close both lists of c; the first S_last member
+//                              becomes this lane's next CLOSE, the rest of
+//                              S_last and all of S_more become walk items;
+//                    WLAST(x)  the S_last member after x: CLOSE it, walk on;
+//                    WMORE(x)  resume DoPost of x from the position after its
+//                              old support (edge_index, Section 8), joining
+//                              by CAS, or CLOSE x; walk on to its successor.
+//                  Exits when no item is pending anywhere.
+//   ac6_pack       live bitmap by wavefront ballot, live/dead counts.
+#include "trim_device.h"
+#include "trim_internal.h"
+
+namespace trim {
+
+namespace {
+
+// Table staging: the implicit view reads its degree thresholds from LDS.
+template <class View>
+struct Stage {
+    static constexpr int kWords = 1;
+    __device__ static void apply(View&, uint64_t*) {}
+};
+template <>
+struct Stage<ImplicitView> {
+    static constexpr int kWords = 256;
+    __device__ static void apply(ImplicitView& g, uint64_t* lds) {
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) lds[i] = g.table[i];
+        __syncthreads();
+        g.table = lds;
+    }
+};
+
+template <class View>
+__global__ void ac6_init(View g, int n, int* head, int* ctr, uint64_t* worker_edges, int P,
+                         trim_stats_t* stats) {
+    __shared__ uint64_t lds[Stage<View>::kWords];
+    Stage<View>::apply(g, lds);
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < kCtrInts) ctr[tid] = 0;
+    for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
+    if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
+    if constexpr (View::kPerGraph)
+        for (int gi = tid; gi < g.G; gi += gridDim.x * blockDim.x) g.graph_edges[gi] = 0;
+    for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
+        const int h = (g.end(v) == g.begin(v)) ? kDead : kEmpty;
+        reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
+    }
+}
+
+constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-queue append
+
+template <class View>
+__global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, uint32_t* q,
+                          int* ctr, uint64_t* worker_edges, int P, uint64_t* part) {
+    __shared__ uint64_t lds[Stage<View>::kWords];
+    __shared__ uint32_t cas[kCasBuf];
+    __shared__ int s_chunk, s_ncas, s_base;
+    __shared__ uint64_t red[16];
+    Stage<View>::apply(g, lds);
+    if (threadIdx.x == 0) s_ncas = 0;
+    uint64_t edges = 0;
+    // move the buffered casualties to the shared queue with one reservation
+    auto flush = [&]() {
+        __syncthreads();
+        const int k = s_ncas;
+        if (k > 0) {
+            if (threadIdx.x == 0) {
+                add_dev(ctr + kPending, k);
+                s_base = add_dev(ctr + kQTail, k);
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < k; i += blockDim.x) q[s_base + i] = cas[i];
+            __syncthreads();
+            if (threadIdx.x == 0) s_ncas = 0;
+        }
+        __syncthreads();
+    };
+    for (;;) {
+        // claim the next chunk of vertices (schedule(dynamic, chunk))
+        if (threadIdx.x == 0) s_chunk = add_dev(ctr + kCursor, chunk);
+        __syncthreads();
+        const int cb = s_chunk;
+        __syncthreads();
+        if (cb >= n) break;
+        const int ce = cb + chunk < n ? cb + chunk : n;
+        int hint = 0;
+        if constexpr (View::kPerGraph) hint = g.graph_of(cb);
+        for (int base = cb; base < ce; base += blockDim.x) {
+            if constexpr (View::kPerGraph) hint = g.graph_from(base, hint);
+            const int v = base + threadIdx.x;
+            bool casualty = false;
+            uint64_t mine = 0;
+            int gi = 0;
+            if (v < ce) {
+                const int b = g.begin(v), e = g.end(v);
+                if constexpr (View::kPerGraph) gi = g.graph_from(v, hint);
+                else gi = g.vctx(v);
+                if (b < e) {
+                    int p = b, w = 0;
+                    for (; p < e; ++p) {
+                        w = g.target(v, p, gi);
+                        if (ld_cached(head + 2 * w) != kDead) break;
+                    }
+                    if (p < e) {
+                        const int old = xchg_dev(head + 2 * w + (p + 1 == e), v);
+                        rec[v] = pack_rec(old, p);
+                        mine = (uint64_t)(p - b + 1);
+                    } else {
+                        casualty = true;
+                        mine = (uint64_t)(e - b);
+                    }
+                }
+            }
+            edges += mine;
+            if constexpr (View::kPerGraph) charge_graphs(g.graph_edges, gi, mine, v < ce);
+            const uint64_t mask = ballot(casualty);
+            if (mask) {
+                int wbase = 0;
+                if (lane_id() == 0) wbase = atomicAdd(&s_ncas, popc(mask));
+                wbase = __shfl(wbase, 0);
+                if (casualty) cas[wbase + popc(mask & lanes_below())] = make_item(0, v);
+            }
+            __syncthreads();
+            if (s_ncas > kCasBuf - (int)blockDim.x) flush();
+        }
+    }
+    flush();
+    edges = block_sum(edges, red);
+    if (threadIdx.x == 0) {
+        if (edges) add_dev(worker_edges + (blockIdx.x % P), edges);
+        part[kPartSweep * kPartStride + blockIdx.x] = edges;
+    }
+}
+
+// Resume DoPost of u from cursor position p0.  Returns true if u joined a
+// live successor's list; `edges` receives the positions checked.
+template <class View>
+__device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, uint64_t* rec,
+                                       uint64_t& edges) {
+    const int e = g.end(u);
+    const int ctx = g.vctx(u);
+    int p = p0;
+    for (; p < e; ++p) {
+        const int w = g.target(u, p, ctx);
+        int* slot = head + 2 * w + (p + 1 == e);
+        int h = ld_cached(slot);
+        while (h != kDead) {
+            st_dev(rec + u, pack_rec(h, p));
+            complete_mem();
+            if (cas_dev(slot, h, u)) {
+                edges += (uint64_t)(p - p0 + 1);
+                if constexpr (View::kPerGraph) add_dev(g.graph_edges + ctx, (uint64_t)(p - p0 + 1));
+                return true;
+            }
+        }
+    }
+    edges += (uint64_t)(e - p0);
+    if constexpr (View::kPerGraph)
+        if (e > p0) add_dev(g.graph_edges + ctx, (uint64_t)(e - p0));
+    return false;
+}
+
+enum : uint32_t { kClose = 0, kWalkLast = 1, kWalkMore = 2 };
+constexpr int kHops = 32;   // S_last chain steps one CLOSE item may take in a row
+
+template <class View>
+__global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t* rec, uint32_t* q,
+                                                     int* ctr, uint64_t* worker_edges,
+                                                     uint64_t* part) {
+    __shared__ uint64_t lds[Stage<View>::kWords];
+    __shared__ uint32_t rings[256 / kWave][kLocalQ];
+    __shared__ int ring_tail[256 / kWave];
+    __shared__ uint64_t red[16];
+    Stage<View>::apply(g, lds);
+    WaveQueue wq;
+    const int wv = threadIdx.x / kWave;
+    wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending);
+    uint32_t item = kNone;
+    uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
+    while (wq.acquire(item)) {
+        uint32_t keep = kNone, push_a = kNone;
+        if (item != kNone) {
+            const int x = item_vertex(item);
+            const uint32_t kind = item_kind(item);
+            if (kind == kClose) {
+                // Close x, then follow S_last: its first member has no successor
+                // left, so it is removed at once -- one exchange pair per step.
+                int c = x;
+                for (int hop = 0;; ++hop) {
+                    closes += 1;
+                    const int a = xchg_dev(head + 2 * c, kDead);      // S_more(c)
+                    const int b = xchg_dev(head + 2 * c + 1, kDead);  // S_last(c)
+                    if (a >= 0) wq.push1(make_item(kWalkMore, a));
+                    if (b < 0) break;
+                    visited += 1;
+                    wq.push1(make_item(kWalkLast, b));
+                    if (hop + 1 == kHops) {
+                        keep = make_item(kClose, b);
+                        break;
+                    }
+                    c = b;
+                }
+            } else if (kind == kWalkLast) {
+                // x is dying and never joins a list again, so rec[x] is stable
+                const int y = rec_next(ld_dev(rec + x));
+                if (y >= 0) {
+                    visited += 1;
+                    keep = make_item(kClose, y);
+                    push_a = make_item(kWalkLast, y);
+                }
+            } else {
+                // read x's list link before x re-joins (which rewrites rec[x])
+                const uint64_t r = ld_dev(rec + x);
+                const int nx = rec_next(r);
+                visited += 1;
+                if (nx >= 0) keep = make_item(kWalkMore, nx);
+                if (resume(g, x, rec_cursor(r) + 1, head, rec, edges)) joins += 1;
+                else push_a = make_item(kClose, x);
+            }
+        }
+        item = keep;
+        wq.push(push_a, kNone);
+    }
+    edges = block_sum(edges, red);
+    closes = block_sum(closes, red);
+    joins = block_sum(joins, red);
+    visited = block_sum(visited, red);
+    if (threadIdx.x == 0) {
+        if (edges) add_dev(worker_edges + blockIdx.x, edges);
+        part[kPartCloses * kPartStride + blockIdx.x] = closes;
+        part[kPartJoins * kPartStride + blockIdx.x] = joins;
+        part[kPartVisited * kPartStride + blockIdx.x] = visited;
+    }
+}
+
+struct Ac6Live {
+    const int* head;
+    __device__ __forceinline__ bool operator()(int v) const { return head[2 * v] != kDead; }
+};
+
+// Per-graph bitmaps: word wi of the packed output belongs to graph g with
+// bitmap_base[g] <= wi < bitmap_base[g+1] and covers local vertices
+// 32 * (wi - bitmap_base[g]) .. + 31 (bits past the graph's n are zero).
+__global__ void ac6_pack_batch(const int* head, const int64_t* vbase, const int64_t* bitmap_base,
+                               int G, uint32_t* bitmaps, uint64_t* part) {
+    __shared__ uint64_t red[16];
+    const int64_t total_words = bitmap_base[G];
+    uint64_t live_cnt = 0;
+    for (int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; wi < total_words;
+         wi += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = G - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (bitmap_base[mid] <= wi) lo = mid; else hi = mid - 1;
+        }
+        const int64_t v0 = vbase[lo];
+        const int64_t ng = vbase[lo + 1] - v0;
+        const int64_t l0 = (wi - bitmap_base[lo]) * 32;
+        uint32_t word = 0;
+        for (int j = 0; j < 32; ++j) {
+            const int64_t l = l0 + j;
+            if (l < ng && head[2 * (v0 + l)] != kDead) word |= 1u << j;
+        }
+        bitmaps[wi] = word;
+        live_cnt += (uint64_t)__popc(word);
+    }
+    live_cnt = block_sum(live_cnt, red);
+    if (threadIdx.x == 0) part[kPartLive * kPartStride + blockIdx.x] = live_cnt;
+}
+
+inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
+    long long b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (int)b;
+}
+
+template <class View>
+hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats, const int64_t* vbase = nullptr,
+                   const int64_t* bitmap_base = nullptr, int G = 0) {
+    const int P = lc.workers;
+    const int B = lc.block;
+    int sweep_blocks = 0, pack_blocks = 0;
+    {
+        Timed t(lc, "ac6_init");
+        hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
+                           lc.stream, g, n, w.a, w.ctr, worker_edges, P, stats);
+    }
+    if (n > 0) {
+        const int chunk = ((lc.chunk + B - 1) / B) * B;
+        sweep_blocks = grid_for(n, chunk, lc.cus * 8);
+        {
+            Timed t(lc, "ac6_sweep");
+            hipLaunchKernelGGL(ac6_sweep<View>, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n,
+                               chunk, w.a, w.b, w.q, w.ctr, worker_edges, P, w.part);
+        }
+        {
+            Timed t(lc, "ac6_propagate");
+            hipLaunchKernelGGL(ac6_propagate<View>, dim3(P), dim3(256), 0, lc.stream, g, w.a,
+                               w.b, w.q, w.ctr, worker_edges, w.part);
+        }
+        if (!bitmap_base) {
+            Timed t(lc, "ac6_pack");
+            pack_blocks = grid_for(n, 256, lc.cus * 4);
+            hipLaunchKernelGGL(pack_bitmap<Ac6Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
+                               Ac6Live{w.a}, n, bitmap, w.part);
+        }
+    }
+    if (bitmap_base && n > 0) {
+        Timed t(lc, "ac6_pack_batch");
+        pack_blocks = grid_for(n / 32 + G, 256, lc.cus * 4);
+        hipLaunchKernelGGL(ac6_pack_batch, dim3(pack_blocks), dim3(256), 0, lc.stream, w.a,
+                           vbase, bitmap_base, G, bitmap, w.part);
+    }
+    if (stats) {
+        Timed t(lc, "finalize");
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, sweep_blocks,
+                           n > 0 ? P : 0, pack_blocks, worker_edges, w.part, w.ctr, stats, 0);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t ac6_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats) {
+    ExplicitView v{g.row_off, g.col};
+    return ac6_run(v, g.n, w, lc, bitmap, worker_edges, stats);
+}
+
+hipError_t ac6_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
+                        uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats) {
+    const int n = 1 << g.log2n;
+    ImplicitView v{g.seed, g.zero_thr, g.deg_table, (uint32_t)(n - 1)};
+    return ac6_run(v, n, w, lc, bitmap, worker_edges, stats);
+}
+
+hipError_t ac6_batch(int G, const int64_t* vbase, const int32_t* row_off, const int32_t* col,
+                     int64_t total_n, const int64_t* bitmap_base, const Work& w,
+                     const LaunchCfg& lc, uint32_t* bitmaps, uint64_t* graph_edges,
+                     trim_stats_t* stats) {
+    BatchView v{row_off, col, vbase, graph_edges, G};
+    return ac6_run(v, (int)total_n, w, lc, bitmaps, w.wedges, stats, vbase, bitmap_base, G);
+}
+
+int ac6_max_workers_per_cu(int) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ac6_propagate<ExplicitView>, 256, 0) !=
+        hipSuccess)
+        return 1;
+    int nb2 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, ac6_propagate<ImplicitView>, 256, 0) ==
+            hipSuccess &&
+        nb2 < nb)
+        nb = nb2;
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace trim

@@ -1,0 +1,360 @@
+// trim_api.hip -- the C ABI of libtrim (include/trim.h): contexts, argument
+// checks, working memory and launch sequencing.  All compute is in the kernel
+// files; this layer never touches graph data on the host.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "trim_internal.h"
+
+struct trim_ctx {
+    int device = 0;
+    int cus = 0;
+    size_t cap_n = 0;
+    trim::Work w;
+    int occ6 = 0, occ4 = 0, occ3 = 0;   // resident workgroups per CU
+    // captured launch sequence of trim_batch and the arguments it was made for
+    hipGraphExec_t gexec = nullptr;
+    uint64_t gkey[20] = {};
+    bool timing = false;
+    trim::Timer timer;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(TRIM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+void free_work(trim_ctx* c) {
+    (void)hipFree(c->w.a);
+    (void)hipFree(c->w.b);
+    (void)hipFree(c->w.c);
+    (void)hipFree(c->w.d);
+    (void)hipFree(c->w.q);
+    c->w.q = nullptr;
+    c->w.a = nullptr;
+    c->w.b = nullptr;
+    c->w.c = nullptr;
+    c->w.d = nullptr;
+    c->cap_n = 0;
+}
+
+int ensure(trim_ctx* c, int64_t n) {
+    size_t need = (size_t)(n > 0 ? n : 1);
+    if (need <= c->cap_n) return TRIM_OK;
+    free_work(c);
+    size_t cap = need + need / 8 + 64;
+    if (hipMalloc((void**)&c->w.a, cap * 8) != hipSuccess ||
+        hipMalloc((void**)&c->w.b, cap * 8) != hipSuccess ||
+        hipMalloc((void**)&c->w.c, cap * 4) != hipSuccess ||
+        hipMalloc((void**)&c->w.d, cap * 4) != hipSuccess ||
+        hipMalloc((void**)&c->w.q, cap * 12) != hipSuccess ||
+        // free queue slots hold kNone (all ones); consumers restore it
+        hipMemset(c->w.q, 0xFF, cap * 12) != hipSuccess) {
+        (void)hipGetLastError();
+        free_work(c);
+        return fail(TRIM_E_NOMEM, "cannot allocate working memory for %lld vertices",
+                    (long long)n);
+    }
+    c->cap_n = cap;
+    return TRIM_OK;
+}
+
+int workers_for(trim_ctx* c, int algo, const trim_opts_t* o) {
+    int per_cu = algo == TRIM_AC6 ? c->occ6 : algo == TRIM_AC4 ? c->occ4 : c->occ3;
+    int max_p = per_cu * c->cus;
+    int def = (algo == TRIM_AC3 ? 1 : (per_cu < 2 ? per_cu : 2)) * c->cus;
+    int p = (o && o->workers > 0) ? o->workers : def;
+    if (p > max_p) p = max_p;
+    if (p > trim::kMaxWorkers) p = trim::kMaxWorkers;
+    if (p < 1) p = 1;
+    return p;
+}
+
+int check_opts(const trim_opts_t* o) {
+    if (!o) return TRIM_OK;
+    if (o->block != 0 && (o->block < 64 || o->block > 1024 || o->block % 64 != 0))
+        return fail(TRIM_E_INVAL, "opts.block must be 0 or a multiple of 64 in [64, 1024]");
+    if (o->workers < 0) return fail(TRIM_E_INVAL, "opts.workers must be >= 0");
+    if (o->chunk < 0 || o->chunk > (1 << 24))
+        return fail(TRIM_E_INVAL, "opts.chunk must be in [0, 2^24]");
+    if (o->graph != 0 && o->graph != 1) return fail(TRIM_E_INVAL, "opts.graph must be 0 or 1");
+    return TRIM_OK;
+}
+
+trim::LaunchCfg launch_cfg(trim_ctx* c, int algo, const trim_opts_t* o, void* stream) {
+    trim::LaunchCfg lc;
+    lc.block = (o && o->block) ? o->block : 256;
+    lc.chunk = (o && o->chunk) ? o->chunk : 4096;
+    lc.workers = workers_for(c, algo, o);
+    lc.cus = c->cus;
+    lc.stream = (hipStream_t)stream;
+    if (c->timing) {
+        c->timer.count = 0;
+        lc.timer = &c->timer;
+    }
+    return lc;
+}
+
+__global__ void validate_kernel(const int* row_off, const int* col, int n, long long m,
+                                int* bad) {
+    int errs = 0;
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    if (tid == 0 && (row_off[0] != 0 || (long long)row_off[n] != m)) errs++;
+    for (int v = tid; v < n; v += stride)
+        if (row_off[v] > row_off[v + 1]) errs++;
+    for (long long e = tid; e < m; e += stride) {
+        const int w = col[e];
+        if (w < 0 || w >= n) errs++;
+    }
+    if (errs) atomicAdd(bad, errs);
+}
+
+}  // namespace
+
+namespace trim {
+hipError_t validate_csr(const trim_csr_t& g, const Work& w, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(w.ctr + kBad, 0, sizeof(int), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(validate_kernel, dim3(1024), dim3(256), 0, s, g.row_off, g.col, g.n,
+                       (long long)g.m, w.ctr + kBad);
+    if (g.rrow_off && g.rcol)
+        hipLaunchKernelGGL(validate_kernel, dim3(1024), dim3(256), 0, s, g.rrow_off, g.rcol, g.n,
+                           (long long)g.m, w.ctr + kBad);
+    return hipGetLastError();
+}
+}  // namespace trim
+
+extern "C" {
+
+int trim_version(void) { return TRIM_ABI_VERSION; }
+
+const char* trim_last_error(void) { return g_err.c_str(); }
+
+int trim_ctx_create(trim_ctx** out, int device) {
+    if (!out) return fail(TRIM_E_INVAL, "trim_ctx_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev)
+        return fail(TRIM_E_INVAL, "device %d out of range (%d devices)", device, ndev);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess)
+        return hip_fail(e, "hipGetDeviceProperties");
+    trim_ctx* c = new trim_ctx;
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    c->occ6 = trim::ac6_max_workers_per_cu(256);
+    c->occ4 = trim::ac4_max_workers_per_cu(256);
+    c->occ3 = trim::ac3_max_workers_per_cu(256);
+    if ((e = hipMalloc((void**)&c->w.ctr, trim::kCtrInts * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc((void**)&c->w.wedges, trim::kMaxWorkers * sizeof(uint64_t))) !=
+            hipSuccess ||
+        (e = hipMalloc((void**)&c->w.part,
+                       (size_t)trim::kPartSlots * trim::kPartStride * sizeof(uint64_t))) !=
+            hipSuccess) {
+        (void)hipFree(c->w.ctr);
+        (void)hipFree(c->w.wedges);
+        delete c;
+        return fail(TRIM_E_NOMEM, "cannot allocate control block: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return TRIM_OK;
+}
+
+int trim_ctx_destroy(trim_ctx* c) {
+    if (!c) return TRIM_OK;
+    (void)hipSetDevice(c->device);
+    free_work(c);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (auto& ev : c->timer.ev)
+        if (ev) (void)hipEventDestroy(ev);
+    (void)hipFree(c->w.ctr);
+    (void)hipFree(c->w.wedges);
+    (void)hipFree(c->w.part);
+    delete c;
+    return TRIM_OK;
+}
+
+int trim_num_workers(trim_ctx* c, int algo, const trim_opts_t* o, int32_t* P) {
+    if (!c || !P) return fail(TRIM_E_INVAL, "trim_num_workers: NULL argument");
+    if (algo != TRIM_AC3 && algo != TRIM_AC4 && algo != TRIM_AC6)
+        return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
+    int rc = check_opts(o);
+    if (rc) return rc;
+    *P = workers_for(c, algo, o);
+    return TRIM_OK;
+}
+
+int trim_csr(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
+             uint32_t* live_bitmap, uint64_t* worker_edges, trim_stats_t* stats, void* stream) {
+    if (!c || !g) return fail(TRIM_E_INVAL, "trim_csr: NULL context or graph");
+    if (algo != TRIM_AC3 && algo != TRIM_AC4 && algo != TRIM_AC6)
+        return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
+    if (g->n < 0 || g->n > (1 << 30)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
+    if (g->m < 0 || g->m >= (int64_t)1 << 31)
+        return fail(TRIM_E_INVAL, "m = %lld out of range [0, 2^31)", (long long)g->m);
+    if (!g->row_off) return fail(TRIM_E_INVAL, "row_off is NULL");
+    if (g->m > 0 && !g->col) return fail(TRIM_E_INVAL, "col is NULL");
+    if (g->n > 0 && !live_bitmap) return fail(TRIM_E_INVAL, "live_bitmap is NULL");
+    if (!worker_edges) return fail(TRIM_E_INVAL, "worker_edges is NULL");
+    if (algo == TRIM_AC4 && (!g->rrow_off || (g->m > 0 && !g->rcol)))
+        return fail(TRIM_E_INVAL, "AC-4 needs the transposed graph (rrow_off, rcol)");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((rc = ensure(c, g->n))) return rc;
+    trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
+    if (o && o->validate) {
+        int bad = 0;
+        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate");
+        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
+                                lc.stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate readback");
+        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
+    }
+    switch (algo) {
+        case TRIM_AC6: e = trim::ac6_csr(*g, c->w, lc, live_bitmap, worker_edges, stats); break;
+        case TRIM_AC4: e = trim::ac4_csr(*g, c->w, lc, live_bitmap, worker_edges, stats); break;
+        default: e = trim::ac3_csr(*g, c->w, lc, live_bitmap, worker_edges, stats); break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return TRIM_OK;
+}
+
+int trim_implicit(trim_ctx* c, int algo, const trim_implicit_t* g, const trim_opts_t* o,
+                  uint32_t* live_bitmap, uint64_t* worker_edges, trim_stats_t* stats,
+                  void* stream) {
+    if (!c || !g) return fail(TRIM_E_INVAL, "trim_implicit: NULL context or graph");
+    if (algo == TRIM_AC4)
+        return fail(TRIM_E_UNSUPPORTED,
+                    "AC-4 needs the transposed graph and cannot run on an implicit graph");
+    if (algo != TRIM_AC3 && algo != TRIM_AC6)
+        return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
+    if (g->log2n < 1 || g->log2n > 30)
+        return fail(TRIM_E_INVAL, "log2n = %d out of range [1, 30]", g->log2n);
+    if (!g->deg_table) return fail(TRIM_E_INVAL, "deg_table is NULL");
+    if (!live_bitmap || !worker_edges) return fail(TRIM_E_INVAL, "NULL output");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((rc = ensure(c, (int64_t)1 << g->log2n))) return rc;
+    trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
+    e = algo == TRIM_AC6 ? trim::ac6_implicit(*g, c->w, lc, live_bitmap, worker_edges, stats)
+                         : trim::ac3_implicit(*g, c->w, lc, live_bitmap, worker_edges, stats);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return TRIM_OK;
+}
+
+int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_off,
+               const int32_t* col, int64_t total_n, int64_t total_m, const int64_t* bitmap_base,
+               const trim_opts_t* o, uint32_t* live_bitmaps, uint64_t* graph_edges,
+               trim_stats_t* stats, void* stream) {
+    if (!c) return fail(TRIM_E_INVAL, "trim_batch: NULL context");
+    if (G < 1) return fail(TRIM_E_INVAL, "G = %d must be >= 1", G);
+    if (!vbase || !row_off || !bitmap_base || !live_bitmaps || !graph_edges)
+        return fail(TRIM_E_INVAL, "trim_batch: NULL array");
+    if (total_n < 0 || total_n > (1 << 30) || total_m < 0 || total_m >= (int64_t)1 << 31)
+        return fail(TRIM_E_INVAL, "batch sizes out of range");
+    if (total_m > 0 && !col) return fail(TRIM_E_INVAL, "col is NULL");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((rc = ensure(c, total_n))) return rc;
+    trim::LaunchCfg lc = launch_cfg(c, TRIM_AC6, o, stream);
+    if (o && o->graph) lc.timer = nullptr;   // no event records inside a captured graph
+    if (!(o && o->graph)) {
+        e = trim::ac6_batch(G, vbase, row_off, col, total_n, bitmap_base, c->w, lc, live_bitmaps,
+                            graph_edges, stats);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        return TRIM_OK;
+    }
+    if (!stream) return fail(TRIM_E_INVAL, "opts.graph needs a non-NULL stream");
+    const uint64_t key[20] = {(uint64_t)G, (uint64_t)vbase, (uint64_t)row_off, (uint64_t)col,
+                              (uint64_t)total_n, (uint64_t)total_m, (uint64_t)bitmap_base,
+                              (uint64_t)live_bitmaps, (uint64_t)graph_edges, (uint64_t)stats,
+                              (uint64_t)stream, (uint64_t)lc.block, (uint64_t)lc.chunk,
+                              (uint64_t)lc.workers, (uint64_t)c->w.a, (uint64_t)c->w.b,
+                              (uint64_t)c->w.c, (uint64_t)c->w.ctr, (uint64_t)c->w.wedges, 1};
+    if (!c->gexec || memcmp(key, c->gkey, sizeof key) != 0) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(lc.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = trim::ac6_batch(G, vbase, row_off, col, total_n, bitmap_base, c->w, lc,
+                                        live_bitmaps, graph_edges, stats);
+        e = hipStreamEndCapture(lc.stream, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le, "kernel launch during capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            c->gexec = nullptr;
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        memcpy(c->gkey, key, sizeof key);
+    }
+    if ((e = hipGraphLaunch(c->gexec, lc.stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return TRIM_OK;
+}
+
+int trim_ctx_set_timing(trim_ctx* c, int enable) {
+    if (!c) return fail(TRIM_E_INVAL, "trim_ctx_set_timing: NULL context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (enable && !c->timer.ev[0]) {
+        for (auto& ev : c->timer.ev)
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    c->timing = enable != 0;
+    c->timer.count = 0;
+    return TRIM_OK;
+}
+
+int trim_ctx_kernel_times(trim_ctx* c, int max, const char** names, float* ms) {
+    if (!c || (max > 0 && (!names || !ms)))
+        return fail(TRIM_E_INVAL, "trim_ctx_kernel_times: NULL argument");
+    const int k = c->timer.count < max ? c->timer.count : max;
+    if (c->timer.count > 0) {
+        hipError_t e = hipEventSynchronize(c->timer.ev[2 * c->timer.count - 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    for (int i = 0; i < k; ++i) {
+        names[i] = c->timer.names[i];
+        float t = 0.f;
+        hipError_t e = hipEventElapsedTime(&t, c->timer.ev[2 * i], c->timer.ev[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        ms[i] = t;
+    }
+    return k;
+}
+
+}  // extern "C"

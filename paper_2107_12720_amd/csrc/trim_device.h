@@ -1,0 +1,466 @@
+// trim_device.h -- device-side building blocks shared by the trimming kernels.
+//
+// Memory-ordering protocol (gfx950, 8 XCDs with separate L2 caches).
+// Agent-scope release/acquire orderings compile to whole-L2 write-back and
+// invalidate instructions, far too costly per support registration.  The
+// kernels instead use:
+//  * device-coherent stores and loads (relaxed atomics at agent scope, which
+//    bypass the non-coherent part of the cache hierarchy) for the few words
+//    that one lane publishes to another: the (next, cursor) record of a
+//    registered vertex and queue slots;
+//  * `complete_mem()` -- an s_waitcnt vmcnt(0) with a compiler memory
+//    barrier -- between such a store and the atomic that makes it reachable
+//    (the CAS on a support list head, the queue tail bump), so the store has
+//    been acknowledged at device scope before anyone can find it;
+//  * device-scope atomic RMWs (CAS, exchange, add), which are coherent across
+//    XCDs, for every contended word.
+// Status reads while scanning successors may be stale: a stale read can only
+// show an older, not-yet-removed value, and the CAS that follows fails and
+// reloads.  DEAD is terminal, so it is never seen too early.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "trim_internal.h"
+
+namespace trim {
+
+constexpr int kEmpty = -1;   // support list head: no supporters yet
+constexpr int kDead = -2;    // support list head: vertex removed, list closed
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int ld_cached(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int ld_dev(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned ld_dev(const unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld_dev(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(unsigned* p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int xchg_dev(int* p, int v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// On failure `expected` receives the current value.
+__device__ __forceinline__ bool cas_dev(int* p, int& expected, int desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int add_dev(int* p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned add_dev(unsigned* p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t add_dev(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned max_dev(unsigned* p, unsigned v) {
+    return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every vector memory operation this wave issued has completed.
+__device__ __forceinline__ void complete_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int popc(uint64_t x) { return __popcll(x); }
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned lo = __shfl_xor((unsigned)x, off);
+        unsigned hi = __shfl_xor((unsigned)(x >> 32), off);
+        x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
+// Record written by a vertex when it joins a support list: the previous list
+// head (next supporter) in the low word, its cursor in the high word.
+__device__ __forceinline__ uint64_t pack_rec(int next, int cursor) {
+    return ((uint64_t)(uint32_t)cursor << 32) | (uint32_t)next;
+}
+__device__ __forceinline__ int rec_next(uint64_t r) { return (int)(uint32_t)r; }
+__device__ __forceinline__ int rec_cursor(uint64_t r) { return (int)(uint32_t)(r >> 32); }
+
+// Wave-aggregated append of the lanes with `pred` set: one atomic per wave.
+// Returns the slot of this lane (or -1).  Does not wait for completion.
+__device__ __forceinline__ int wave_append_slot(bool pred, int* tail, int* pending) {
+    uint64_t mask = ballot(pred);
+    if (mask == 0) return -1;
+    int leader = __ffsll((long long)mask) - 1;
+    int cnt = popc(mask);
+    int base = 0;
+    if (lane_id() == leader) {
+        if (pending) add_dev(pending, cnt);
+        base = add_dev(tail, cnt);
+    }
+    base = __shfl(base, leader);
+    return pred ? base + popc(mask & lanes_below()) : -1;
+}
+
+// ------------------------------------------------------------ work queues
+// Items are 32-bit words: a 2-bit kind above a 30-bit vertex id.  kNone marks
+// an empty lane and an empty global queue slot.
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kIdMask = 0x3FFFFFFFu;
+__device__ __forceinline__ uint32_t make_item(uint32_t kind, int v) {
+    return (kind << 30) | (uint32_t)v;
+}
+__device__ __forceinline__ uint32_t item_kind(uint32_t it) { return it >> 30; }
+__device__ __forceinline__ int item_vertex(uint32_t it) { return (int)(it & kIdMask); }
+
+constexpr int kLocalQ = 512;              // LDS ring entries per wavefront
+constexpr int kPollEvery = 64;            // busy iterations between shared-queue polls
+constexpr int kMaxNaps = 16;              // idle back-off cap, in s_sleep(127) naps
+
+// Work distribution of the persistent kernels (the paper's private waiting
+// sets Q_p, Section 5.2 / 6.2).  Each wavefront owns an LDS ring; items go to
+// the shared queue only when the ring is full, and idle wavefronts take from
+// the shared queue.  `pending` counts shared-queue items plus wavefronts that
+// hold private work, so it reaches zero only when no work is left anywhere.
+// Shared-queue slots hold kNone while free: a consumer resets each slot it
+// reads, so the buffer is clean for the next call without a fill pass.
+struct WaveQueue {
+    uint32_t* lq;
+    int* tail_lds;      // ring tail in LDS: lanes may append from divergent code
+    int head;           // wave-uniform ring head (only uniform code moves it)
+    bool holding;       // wave-uniform: counted in *pending
+    uint32_t* q;
+    int* qhead;
+    int* qtail;
+    int* pending;
+    int iter;           // wave-uniform iteration counter
+    int naps;           // wave-uniform idle back-off
+
+    __device__ __forceinline__ void init(uint32_t* ring, int* ring_tail, uint32_t* gq,
+                                         int* ctr_qhead, int* ctr_qtail, int* ctr_pending) {
+        lq = ring;
+        tail_lds = ring_tail;
+        if (lane_id() == 0) *tail_lds = 0;
+        __builtin_amdgcn_wave_barrier();
+        head = 0;
+        holding = false;
+        q = gq;
+        qhead = ctr_qhead;
+        qtail = ctr_qtail;
+        pending = ctr_pending;
+        iter = 0;
+        naps = 1;
+    }
+
+    __device__ __forceinline__ int tail() const {
+        return __hip_atomic_load(tail_lds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+
+    // Idle lanes take items from the LDS ring.
+    __device__ __forceinline__ void refill(uint32_t& item) {
+        const uint64_t idle = ballot(item == kNone);
+        const int avail = tail() - head;
+        if (idle && avail > 0) {
+            const int take = min(popc(idle), avail);
+            const int rank = popc(idle & lanes_below());
+            if (item == kNone && rank < take) item = lq[(head + rank) & (kLocalQ - 1)];
+            head += take;
+        }
+    }
+
+    // Idle lanes take up to one item each from the shared queue.  Returns the
+    // number taken (wave-uniform) and updates *pending.
+    __device__ __forceinline__ int claim(uint32_t& item) {
+        const uint64_t idle = ballot(item == kNone);
+        const int want = popc(idle);
+        int base = 0, got = 0;
+        if (want && lane_id() == 0) {
+            int h = ld_dev(qhead);
+            for (;;) {
+                const int t = ld_dev(qtail);
+                if (h >= t) break;
+                const int k = min(want, t - h);
+                if (cas_dev(qhead, h, h + k)) {
+                    base = h;
+                    got = k;
+                    break;
+                }
+            }
+            if (got) add_dev(pending, (holding ? 0 : 1) - got);
+        }
+        base = __shfl(base, 0);
+        got = __shfl(got, 0);
+        if (got) {
+            holding = true;
+            const int rank = popc(idle & lanes_below());
+            if (item == kNone && rank < got) {
+                // the producer reserved this slot and is writing it
+                const int slot = base + rank;
+                uint32_t x = (uint32_t)ld_dev((const int*)q + slot);
+                while (x == kNone) {
+                    __builtin_amdgcn_s_sleep(1);
+                    x = (uint32_t)ld_dev((const int*)q + slot);
+                }
+                st_dev((int*)q + slot, (int)kNone);
+                item = x;
+            }
+        }
+        return got;
+    }
+
+    // One item from any lane, also from divergent code: into the ring if it
+    // has room, else straight to the shared queue.  The wave must be holding.
+    __device__ __forceinline__ void push1(uint32_t it) {
+        int t = tail();
+        for (;;) {
+            if (t - head >= kLocalQ) {
+                add_dev(pending, 1);
+                complete_mem();
+                const int pos = add_dev(qtail, 1);
+                st_dev((int*)q + pos, (int)it);
+                return;
+            }
+            const int seen = __hip_atomic_compare_exchange_strong(
+                                 tail_lds, &t, t + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WAVEFRONT)
+                                 ? -1
+                                 : t;
+            if (seen < 0) {
+                lq[t & (kLocalQ - 1)] = it;
+                return;
+            }
+        }
+    }
+
+    // Append this lane's a and b (kNone = nothing), from uniform code: to the
+    // ring, or to the shared queue when the ring has no room.
+    __device__ __forceinline__ void push(uint32_t a, uint32_t b) {
+        const uint64_t ma = ballot(a != kNone), mb = ballot(b != kNone);
+        const int ca = popc(ma), total = ca + popc(mb);
+        if (total == 0) return;
+        const int ra = popc(ma & lanes_below());
+        const int rb = ca + popc(mb & lanes_below());
+        const int t = tail();
+        if (total <= kLocalQ - (t - head)) {
+            if (a != kNone) lq[(t + ra) & (kLocalQ - 1)] = a;
+            if (b != kNone) lq[(t + rb) & (kLocalQ - 1)] = b;
+            __builtin_amdgcn_wave_barrier();
+            if (lane_id() == 0) *tail_lds = t + total;
+            __builtin_amdgcn_wave_barrier();
+            return;
+        }
+        int base = 0;
+        if (lane_id() == 0) {
+            add_dev(pending, total);
+            complete_mem();
+            base = add_dev(qtail, total);
+        }
+        base = __shfl(base, 0);
+        if (a != kNone) st_dev((int*)q + base + ra, (int)a);
+        if (b != kNone) st_dev((int*)q + base + rb, (int)b);
+    }
+
+    // Returns false when the whole computation is finished.  Otherwise at
+    // least one lane of the wave holds an item.
+    __device__ __forceinline__ bool acquire(uint32_t& item) {
+        for (;;) {
+            refill(item);
+            const uint64_t busy = ballot(item != kNone);
+            if (busy) {
+                naps = 1;
+                // a busy wave with idle lanes looks at the shared queue now and then
+                if (busy != ~0ull && tail() == head && (++iter & (kPollEvery - 1)) == 0)
+                    claim(item);
+                return true;
+            }
+            if (holding) {
+                if (lane_id() == 0) add_dev(pending, -1);
+                holding = false;
+            }
+            if (claim(item)) return true;
+            if (ld_dev(pending) == 0) return false;
+            for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
+            naps = naps * 2 > kMaxNaps ? kMaxNaps : naps * 2;
+        }
+    }
+};
+
+// Block-wide sum; every thread gets the result.  `scratch` holds >= 16 words.
+__device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* scratch) {
+    x = wave_sum(x);
+    const int w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (lane_id() == 0) scratch[w] = x;
+    __syncthreads();
+    uint64_t s = 0;
+    for (int i = 0; i < nw; ++i) s += scratch[i];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------- outputs and statistics
+// Per-block partial sums live in `part` (kPartStride words per quantity); one
+// finalize block reduces them, so no word is updated by every block.
+
+namespace {   // kernels below get a private copy in every translation unit
+
+// Live bitmap (bit v%32 of word v/32) from a per-vertex predicate, by ballot.
+template <class IsLive>
+__global__ void pack_bitmap(IsLive is_live, int n, uint32_t* bitmap, uint64_t* part) {
+    __shared__ uint64_t red[16];
+    const int nwords = (n + 31) >> 5;
+    const int waves = (gridDim.x * blockDim.x) / kWave;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    uint64_t live_cnt = 0;
+    for (int base = wid * kWave; base < n; base += waves * kWave) {
+        const int v = base + lane_id();
+        const uint64_t b = ballot(v < n && is_live(v));
+        if (lane_id() == 0) {
+            const int w = base >> 5;
+            bitmap[w] = (uint32_t)b;
+            if (w + 1 < nwords) bitmap[w + 1] = (uint32_t)(b >> 32);
+            live_cnt += (uint64_t)popc(b);
+        }
+    }
+    live_cnt = block_sum(live_cnt, red);
+    if (threadIdx.x == 0) part[kPartLive * kPartStride + blockIdx.x] = live_cnt;
+}
+
+__device__ __forceinline__ uint64_t sum_range(const uint64_t* a, int k, uint64_t* red) {
+    uint64_t s = 0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) s += a[i];
+    return block_sum(s, red);
+}
+
+// One block: reduce the partials into *stats.  n_sweep / n_prop = number of
+// sweep / propagation partials (0 when the algorithm has none).
+__global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack,
+                               const uint64_t* worker_edges, const uint64_t* part, const int* ctr,
+                               trim_stats_t* stats, int empty_rounds) {
+    __shared__ uint64_t red[16];
+    const uint64_t edges = sum_range(worker_edges, P, red);
+    const uint64_t live = sum_range(part + kPartLive * kPartStride, n_pack, red);
+    const uint64_t sweep = sum_range(part + kPartSweep * kPartStride, n_sweep, red);
+    const uint64_t closes = sum_range(part + kPartCloses * kPartStride, n_prop, red);
+    const uint64_t joins = sum_range(part + kPartJoins * kPartStride, n_prop, red);
+    const uint64_t visited = sum_range(part + kPartVisited * kPartStride, n_prop, red);
+    if (threadIdx.x == 0) {
+        stats->edges_total = edges;
+        stats->n_live = live;
+        stats->n_dead = (uint64_t)n - live;
+        stats->queued = (uint64_t)ctr[kQTail];
+        stats->edges_sweep = sweep;
+        stats->closes = closes;
+        stats->joins = joins;
+        stats->visited = visited;
+        if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ graph views
+// A view gives, for vertex v: the cursor range [begin(v), end(v)) and the
+// target of cursor position p.  `vctx` carries a per-vertex value the view
+// needs (the graph's vertex base for packed batches).
+struct ExplicitView {
+    static constexpr bool kPerGraph = false;
+    const int* row_off;
+    const int* col;
+    __device__ __forceinline__ int vctx(int) const { return 0; }
+    __device__ __forceinline__ int begin(int v) const { return row_off[v]; }
+    __device__ __forceinline__ int end(int v) const { return row_off[v + 1]; }
+    __device__ __forceinline__ int target(int, int p, int) const { return col[p]; }
+};
+
+// SplitMix64 finalizer (Steele, Lea, Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+constexpr uint64_t kTagZero = 0x5A45524F00000000ull;
+constexpr uint64_t kTagDeg = 0x4445470000000000ull;
+constexpr uint64_t kTagNbr = 0x4E42520000000000ull;
+
+// Hash-generated graph: no stored edges; cursor positions are successor indices.
+struct ImplicitView {
+    static constexpr bool kPerGraph = false;
+    uint64_t seed;
+    uint64_t zero_thr;
+    const uint64_t* table;   // 256 thresholds, normally staged in LDS
+    uint32_t mask;           // n - 1
+    __device__ __forceinline__ int vctx(int) const { return 0; }
+    __device__ __forceinline__ int begin(int) const { return 0; }
+    __device__ __forceinline__ int end(int v) const {
+        uint64_t key = (uint64_t)(uint32_t)v << 8;
+        if (mix64(seed ^ kTagZero ^ key) < zero_thr) return 0;
+        uint64_t u = mix64(seed ^ kTagDeg ^ key);
+        // 1 + #{j < 255 : u >= table[j]}; table is non-decreasing
+        int lo = 0, hi = 255;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (u >= table[mid]) lo = mid + 1; else hi = mid;
+        }
+        return 1 + lo;
+    }
+    __device__ __forceinline__ int target(int v, int p, int) const {
+        uint64_t key = ((uint64_t)(uint32_t)v << 8) | (uint32_t)p;
+        return (int)(mix64(seed ^ kTagNbr ^ key) & mask);
+    }
+};
+
+// Packed batch: graph-local targets shifted by the graph's first vertex.  The
+// per-vertex value is the graph index; traversed edges are charged per graph.
+struct BatchView {
+    static constexpr bool kPerGraph = true;
+    const int* row_off;
+    const int* col;
+    const int64_t* vbase;      // G+1 entries
+    uint64_t* graph_edges;     // G entries
+    int G;
+    __device__ __forceinline__ int graph_of(int v) const {
+        int lo = 0, hi = G - 1;           // largest g with vbase[g] <= v
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (vbase[mid] <= v) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    }
+    // graph of v >= the first vertex of graph `hint`
+    __device__ __forceinline__ int graph_from(int v, int hint) const {
+        while (hint + 1 < G && vbase[hint + 1] <= v) ++hint;
+        return hint;
+    }
+    __device__ __forceinline__ int vctx(int v) const { return graph_of(v); }
+    __device__ __forceinline__ int begin(int v) const { return row_off[v]; }
+    __device__ __forceinline__ int end(int v) const { return row_off[v + 1]; }
+    __device__ __forceinline__ int target(int, int p, int gi) const {
+        return (int)vbase[gi] + col[p];
+    }
+};
+
+// Sum `val` of the lanes with `has` into ge[gi], one atomic per distinct gi.
+__device__ __forceinline__ void charge_graphs(uint64_t* ge, int gi, uint64_t val, bool has) {
+    uint64_t rem = ballot(has && val != 0);
+    while (rem) {
+        const int leader = __ffsll((long long)rem) - 1;
+        const int gl = __shfl(gi, leader);
+        const bool mine = has && val != 0 && gi == gl;
+        const uint64_t mask = ballot(mine);
+        const uint64_t s = wave_sum(mine ? val : 0);
+        if (lane_id() == leader) add_dev(ge + gl, s);
+        rem &= ~mask;
+    }
+}
+
+}  // namespace trim

@@ -1,0 +1,109 @@
+// trim_internal.h -- host-side declarations shared by the kernel files and the
+// C-ABI layer of libtrim.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/trim.h"
+
+namespace trim {
+
+// Counter slots of the per-call control block (int32 unless noted).
+// Hot words sit 128 bytes apart so that they live in different cache lines
+// (and L2 channels): pollers of one do not queue behind atomics on another.
+enum Ctr : int {
+    kQHead = 0,      // next queue slot to hand out
+    kQTail = 32,     // slots reserved by producers
+    kPending = 64,   // queued items + workers holding private work
+    kBad = 96,       // validation failures
+    kBarCount = 128, // grid barrier arrivals
+    kBarGen = 160,   // grid barrier generation
+    kCursor = 192,   // next unclaimed vertex of the chunked sweep
+    kCnt0 = 224,     // AC-3 live-list sizes, rotating over 3 slots
+    kCtrInts = 256
+};
+
+// Working memory of one call, sized for n vertices (owned by trim_ctx).
+struct Work {
+    int* a = nullptr;         // 2n int32: AC-6 list heads / AC-4 counter / AC-3 cursor
+    uint64_t* b = nullptr;    // n uint64: AC-6 (next, cursor) records / AC-3 list
+    int* c = nullptr;         // n int32: queue / AC-3 removal round
+    int* d = nullptr;         // n int32: AC-3 list
+    uint32_t* q = nullptr;    // 3n shared-queue slots, kNone between calls
+    int* ctr = nullptr;       // kCtrInts control words
+    uint64_t* wedges = nullptr;  // per-worker counts when the caller has none (batches)
+    uint64_t* part = nullptr;    // per-block partial sums (kPartSlots x kPartStride)
+};
+constexpr int kMaxWorkers = 16384;
+constexpr int kPartStride = 16384;   // >= workers, sweep blocks and pack blocks
+enum PartSlot : int { kPartCloses = 0, kPartJoins = 1, kPartVisited = 2, kPartSweep = 3,
+                      kPartLive = 4, kPartSlots = 5 };
+
+// Optional per-kernel event timing (trim_ctx_set_timing).
+struct Timer {
+    static constexpr int kMax = 16;
+    hipEvent_t ev[2 * kMax] = {};
+    const char* names[kMax] = {};
+    int count = 0;
+};
+
+struct LaunchCfg;
+// Records events around the kernels launched while it is alive.
+class Timed {
+  public:
+    Timed(const LaunchCfg& lc, const char* name);
+    ~Timed();
+
+  private:
+    Timer* t_;
+    hipStream_t s_;
+    int idx_ = -1;
+};
+
+struct LaunchCfg {
+    int block = 256;          // sweep block size
+    int chunk = 4096;         // vertices per dynamically claimed sweep chunk
+    int workers = 0;          // persistent workgroups
+    int cus = 256;
+    hipStream_t stream = nullptr;
+    Timer* timer = nullptr;   // non-null: record per-kernel events
+};
+
+inline Timed::Timed(const LaunchCfg& lc, const char* name) : t_(lc.timer), s_(lc.stream) {
+    if (t_ && t_->count < Timer::kMax) {
+        idx_ = t_->count++;
+        t_->names[idx_] = name;
+        (void)hipEventRecord(t_->ev[2 * idx_], s_);
+    }
+}
+inline Timed::~Timed() {
+    if (idx_ >= 0) (void)hipEventRecord(t_->ev[2 * idx_ + 1], s_);
+}
+
+// ------------------------------------------------------------------ AC-6
+hipError_t ac6_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats);
+hipError_t ac6_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
+                        uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
+hipError_t ac6_batch(int G, const int64_t* vbase, const int32_t* row_off, const int32_t* col,
+                     int64_t total_n, const int64_t* bitmap_base, const Work& w,
+                     const LaunchCfg& lc, uint32_t* bitmaps, uint64_t* graph_edges,
+                     trim_stats_t* stats);
+int ac6_max_workers_per_cu(int block);
+
+// ------------------------------------------------------------------ AC-4
+hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats);
+int ac4_max_workers_per_cu(int block);
+
+// ------------------------------------------------------------------ AC-3
+hipError_t ac3_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                   uint64_t* worker_edges, trim_stats_t* stats);
+hipError_t ac3_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
+                        uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
+int ac3_max_workers_per_cu(int block);
+
+// ------------------------------------------------------------ validation
+hipError_t validate_csr(const trim_csr_t& g, const Work& w, hipStream_t s);
+
+}  // namespace trim

@@ -1,0 +1,59 @@
+"""The C-ABI library loads and exports every declared symbol; argument errors
+are reported without a GPU (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "trim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(trim_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_calls():
+    import paper_2107_12720_amd as T
+    assert declared_functions() == sorted(T.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2107_12720_amd as T
+    L = T.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert L.trim_version() == 1
+
+
+def test_null_arguments_rejected():
+    import paper_2107_12720_amd as T
+    L = T.lib()
+    assert L.trim_csr(None, 6, None, None, None, None, None, None) == -1
+    assert "NULL" in T.last_error()
+    assert L.trim_ctx_create(None, 0) == -1
+    P = ctypes.c_int32()
+    assert L.trim_num_workers(None, 6, None, ctypes.byref(P)) == -1
+    assert L.trim_batch(None, 1, None, None, None, 0, 0, None, None, None, None, None, None) == -1
+    assert L.trim_ctx_destroy(None) == 0
+
+
+def test_no_gpu_context_fails_cleanly():
+    import torch
+    import paper_2107_12720_amd as T
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = T.lib().trim_ctx_create(ctypes.byref(h), 0)
+    assert rc in (-1, -3) and not h.value
+    with pytest.raises(T.TrimError):
+        T.Context(0)
+
+
+def test_opts_layout_matches_header():
+    import paper_2107_12720_amd as T
+    assert ctypes.sizeof(T.Opts) == 32
+    assert ctypes.sizeof(T.CsrDesc) == 48
+    assert ctypes.sizeof(T.ImplicitDesc) == 32
