@@ -38,16 +38,10 @@
 //                  live and joining is a plain exchange (no CAS retry storms on
 //                  hub vertices).  Vertices without a live successor are queued
 //                  as close items.
-//   ac6_propagate  persistent workers (the paper's Trim_p) run three kinds of
-//                  items through per-wavefront LDS rings (WaveQueue):
-//                    CLOSE(c)  close both lists of c; the first S_last member
-//                              becomes this lane's next CLOSE, the rest of
-//                              S_last and all of S_more become walk items;
-//                    WLAST(x)  the S_last member after x: CLOSE it, walk on;
-//                    WMORE(x)  resume DoPost of x from the position after its
-//                              old support (edge_index, Section 8), joining
-//                              by CAS, or CLOSE x; walk on to its successor.
-//                  Exits when no item is pending anywhere.
+//   ac6_propagate  persistent workers (the paper's Trim_p) run close and walk
+//                  items (see below) through per-wavefront LDS rings
+//                  (WaveQueue); a lane follows an S_last chain for up to
+//                  kHops removals in a row.  Exits when no item is pending.
 //   ac6_pack       live bitmap by wavefront ballot, live/dead counts.
 #include "trim_device.h"
 #include "trim_internal.h"
@@ -202,8 +196,14 @@ __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, 
     return false;
 }
 
-enum : uint32_t { kClose = 0, kWalkLast = 1, kWalkMore = 2 };
-constexpr int kHops = 32;   // S_last chain steps one CLOSE item may take in a row
+// Work items of the propagation:
+//   CLOSE(x)       x found no live successor: close both of its lists;
+//   CLOSE_LAST(x)  the same for a member x of some S_last(p): x is removed with
+//                  p, and x's record links to the next member of S_last(p);
+//   WMORE(x)       x is a member of a closed S_more list: resume its DoPost
+//                  and walk on to the next member.
+enum : uint32_t { kClose = 0, kCloseLast = 1, kWalkMore = 2 };
+constexpr int kHops = 256;   // S_last chain steps one item may take in a row
 
 template <class View>
 __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t* rec, uint32_t* q,
@@ -224,31 +224,42 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
         if (item != kNone) {
             const int x = item_vertex(item);
             const uint32_t kind = item_kind(item);
-            if (kind == kClose) {
-                // Close x, then follow S_last: its first member has no successor
-                // left, so it is removed at once -- one exchange pair per step.
+            if (kind != kWalkMore) {
+                // Close x, then follow S_last: its members have no successor left,
+                // so each is removed at once.  One step = two list-head exchanges
+                // plus, for an S_last member, the load of its list link -- all in
+                // flight together, one round trip.
                 int c = x;
+                bool member = kind == kCloseLast;
                 for (int hop = 0;; ++hop) {
                     closes += 1;
+                    // c is dying and never joins a list again, so rec[c] is stable
+                    const int sib = member ? rec_next(ld_dev(rec + c)) : -1;
                     const int a = xchg_dev(head + 2 * c, kDead);      // S_more(c)
                     const int b = xchg_dev(head + 2 * c + 1, kDead);  // S_last(c)
                     if (a >= 0) wq.push1(make_item(kWalkMore, a));
-                    if (b < 0) break;
-                    visited += 1;
-                    wq.push1(make_item(kWalkLast, b));
-                    if (hop + 1 == kHops) {
-                        keep = make_item(kClose, b);
+                    // depth first: into S_last(c) if it has members, else on to
+                    // the next member of the list c was in
+                    int next;
+                    if (b >= 0) {
+                        visited += 1;
+                        if (sib >= 0) {
+                            visited += 1;
+                            wq.push1(make_item(kCloseLast, sib));
+                        }
+                        next = b;
+                    } else if (sib >= 0) {
+                        visited += 1;
+                        next = sib;
+                    } else {
                         break;
                     }
-                    c = b;
-                }
-            } else if (kind == kWalkLast) {
-                // x is dying and never joins a list again, so rec[x] is stable
-                const int y = rec_next(ld_dev(rec + x));
-                if (y >= 0) {
-                    visited += 1;
-                    keep = make_item(kClose, y);
-                    push_a = make_item(kWalkLast, y);
+                    if (hop + 1 == kHops || wq.fill() > kLocalQ - 64) {
+                        keep = make_item(kCloseLast, next);
+                        break;
+                    }
+                    c = next;
+                    member = true;
                 }
             } else {
                 // read x's list link before x re-joins (which rewrites rec[x])
@@ -262,6 +273,7 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
         }
         item = keep;
         wq.push(push_a, kNone);
+        wq.rebalance();
     }
     edges = block_sum(edges, red);
     closes = block_sum(closes, red);

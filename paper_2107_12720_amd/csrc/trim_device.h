@@ -122,7 +122,8 @@ __device__ __forceinline__ uint32_t make_item(uint32_t kind, int v) {
 __device__ __forceinline__ uint32_t item_kind(uint32_t it) { return it >> 30; }
 __device__ __forceinline__ int item_vertex(uint32_t it) { return (int)(it & kIdMask); }
 
-constexpr int kLocalQ = 512;              // LDS ring entries per wavefront
+constexpr int kLocalQ = 1024;             // LDS ring entries per wavefront
+constexpr int kSpillAbove = kLocalQ / 2;  // ring fill that triggers a bulk hand-off
 constexpr int kPollEvery = 64;            // busy iterations between shared-queue polls
 constexpr int kMaxNaps = 16;              // idle back-off cap, in s_sleep(127) naps
 
@@ -267,6 +268,26 @@ struct WaveQueue {
         base = __shfl(base, 0);
         if (a != kNone) st_dev((int*)q + base + ra, (int)a);
         if (b != kNone) st_dev((int*)q + base + rb, (int)b);
+    }
+
+    __device__ __forceinline__ int fill() const { return tail() - head; }
+
+    // Uniform code: hand the oldest ring items to the shared queue when the
+    // ring is more than half full, one reservation for all of them.
+    __device__ __forceinline__ void rebalance() {
+        const int occ = tail() - head;
+        if (occ <= kSpillAbove) return;
+        const int k = occ - kLocalQ / 8;
+        int base = 0;
+        if (lane_id() == 0) {
+            add_dev(pending, k);
+            complete_mem();
+            base = add_dev(qtail, k);
+        }
+        base = __shfl(base, 0);
+        for (int i = lane_id(); i < k; i += kWave)
+            st_dev((int*)q + base + i, (int)lq[(head + i) & (kLocalQ - 1)]);
+        head += k;
     }
 
     // Returns false when the whole computation is finished.  Otherwise at
