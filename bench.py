@@ -110,6 +110,136 @@ def time_gpu(ctx, fn, steps, warmup):
     return t0.elapsed_time(t1) / steps, ktimes, res
 
 
+def ev_time(fn, reps, warmup, stream):
+    """Median ms of fn() measured with events recorded on `stream`."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    stream.synchronize()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(sorted(times)[len(times) // 2])
+
+
+def bench_batch(ctx, T, gg, oracle, reps):
+    """4,096 core+tail graphs: one autotuned, HIP-graph-captured launch sequence
+    (graphs/s), against the same AC-6 called once per graph and against the
+    disjoint union trimmed as one graph."""
+    import numpy as np
+    import torch
+
+    from paper_2107_12720_amd import autotune
+    log("batch: generating 4096 graphs ...")
+    b = gg.batch(4096, seed=0)
+    bb = b.bitmap_base()
+    G, N, M = b.G, int(b.vbase[-1]), int(b.ebase[-1])
+    vb, ro, col, bbd = (T.to_device(b.vbase), T.to_device(b.row_off), T.to_device(b.col),
+                        T.to_device(bb))
+    lb = torch.empty(int(bb[-1]), dtype=torch.int32, device="cuda")
+    ge = torch.empty(G, dtype=torch.int64, device="cuda")
+    st = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    ctx.set_timing(False)
+
+    def run(opts):
+        return ctx.trim_batch(vb, ro, col, bbd, N, M, live_bitmaps=lb, graph_edges=ge, stats=st,
+                              opts=opts, stream=s)
+    with torch.cuda.stream(s):
+        params, table = autotune.tune(ctx, "batch", N, M, run, workers=(256, 512, 1024),
+                                      reps=3, use_cache=False)
+        log(f"batch: tuned {params}")
+        opts_g = T.make_opts(block=params["block"], chunk=params["chunk"],
+                             workers=params["workers"], graph=True)
+        ms_b = ev_time(lambda: run(opts_g), reps, 2, s)
+        res = run(opts_g)
+        s.synchronize()
+    live, nl, _ = oracle.batch_peel(b)
+    got = res.bitmap_numpy()
+    parity = True
+    for gi in range(G):
+        v0, v1 = int(b.vbase[gi]), int(b.vbase[gi + 1])
+        want = oracle.bitmap(live[v0:v1])
+        if not np.array_equal(got[bb[gi]:bb[gi] + want.shape[0]], want):
+            parity = False
+            break
+    parity = parity and res.stats_dict()["n_live"] == int(nl.sum())
+    # the same AC-6, one call per graph
+    per = []
+    for gi in range(G):
+        v0, v1, e0, e1 = (int(b.vbase[gi]), int(b.vbase[gi + 1]), int(b.ebase[gi]),
+                          int(b.ebase[gi + 1]))
+        per.append((v1 - v0, ro[v0:v1 + 1] - e0, col[e0:e1], lb[int(bb[gi]):int(bb[gi + 1])]))
+    P = ctx.num_workers(T.AC6)
+    we = torch.empty(P, dtype=torch.int64, device="cuda")
+
+    def each():
+        for n_g, r_g, c_g, l_g in per:
+            ctx.trim_csr(T.AC6, n_g, r_g, c_g, live_bitmap=l_g, worker_edges=we, stats=st,
+                         stream=s)
+    with torch.cuda.stream(s):
+        ms_each = ev_time(each, 1, 1, s)
+    # the disjoint union as one graph (global target ids)
+    col_u = T.to_device((b.col.astype(np.int64) + np.repeat(b.vbase[:-1], np.diff(b.ebase)))
+                        .astype(np.int32))
+    lbu = torch.empty((N + 31) // 32, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(s):
+        ms_union = ev_time(lambda: ctx.trim_csr(T.AC6, N, ro, col_u, live_bitmap=lbu,
+                                                worker_edges=we, stats=st, stream=s), reps, 1, s)
+    ctx.set_timing(True)
+    return {"workload": "batch4096_coretail", "graphs": G, "sum_n": N, "sum_m": M,
+            "ms": ms_b, "graphs_per_s": G / (ms_b / 1e3), "edges_per_s": M / (ms_b / 1e3),
+            "parity": bool(parity), "tuned": params,
+            "per_graph_calls": {"ms": ms_each, "graphs_per_s": G / (ms_each / 1e3)},
+            "union_one_graph": {"ms": ms_union, "graphs_per_s": G / (ms_union / 1e3)},
+            "speedup_vs_per_graph_calls": ms_each / ms_b}
+
+
+def bench_implicit(ctx, T, gg, oracle, reps, log2n=28, samples=20000):
+    """AC-6 on the hash-generated graph G = (V, POST) with n = 2^28: successors
+    are generated on the fly.  Checked at full size on sampled vertices: a live
+    vertex has a live successor, a removed one has none."""
+    import numpy as np
+    import torch
+    imp = gg.implicit(log2n=log2n, seed=0)
+    table = T.to_device(imp.table)
+    n = imp.n
+    P = ctx.num_workers(T.AC6)
+    lb = torch.empty((n + 31) // 32, dtype=torch.int32, device="cuda")
+    we = torch.empty(P, dtype=torch.int64, device="cuda")
+    st = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
+    s = torch.cuda.current_stream()
+    ctx.set_timing(False)
+    log(f"implicit: n = 2^{log2n}")
+    ms6 = ev_time(lambda: ctx.trim_implicit(T.AC6, log2n, imp.seed, imp.zero_thr, table,
+                                            live_bitmap=lb, worker_edges=we, stats=st),
+                  reps, 1, s)
+    res = ctx.trim_implicit(T.AC6, log2n, imp.seed, imp.zero_thr, table, live_bitmap=lb,
+                            worker_edges=we, stats=st)
+    torch.cuda.synchronize()
+    stat = res.stats_dict()
+    bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
+    rng = np.random.default_rng(0)
+    ok = True
+    for v in rng.integers(0, n, samples):
+        d = oracle.implicit_deg(imp, int(v))
+        succ_live = any(bits[oracle.implicit_nbr(imp, int(v), i)] for i in range(d))
+        if bool(bits[v]) != succ_live:
+            ok = False
+            break
+    ctx.set_timing(True)
+    m = stat["graph_edges"]
+    return {"workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
+            "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": stat["edges_total"],
+            "n_live": stat["n_live"], "fixpoint_check_on_samples": ok, "samples": samples}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +248,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--no-baselines", action="store_true", help="skip AC-4 / AC-3 / chain runs")
     ap.add_argument("--no-ac3", action="store_true", help="skip the (slow) AC-3 baseline run")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 4,096-graph batch")
+    ap.add_argument("--no-implicit", action="store_true", help="skip the 2^28 implicit graph")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -231,6 +363,13 @@ def main():
                 "rounds": st3["rounds"], "T3J": c.T3J, "parity": ok3,
                 "kernels_ms": {k: float(np.mean(v)) for k, v in kt3.items()}}
             out["baselines"]["ac6_speedup_vs_ac3"] = ms3 / ms
+
+    if not args.no_batch:
+        out["batch"] = bench_batch(ctx, T, gg, oracle, 10)
+        log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s parity={out['batch']['parity']}")
+    if not args.no_implicit:
+        out["implicit"] = bench_implicit(ctx, T, gg, oracle, 3)
+        log(f"implicit: {out['implicit']['edges_per_s']:.3e} edges/s")
 
     if not args.no_cpu:
         # the oracle as it stands, single-threaded, repeated up to ~cpu_seconds

@@ -63,7 +63,7 @@ typedef struct trim_ctx trim_ctx;
 
 /* Explicit graph G = (V, E) in CSR (Section 2.1), plus G^T for AC-4. */
 typedef struct {
-    int32_t n;                /* vertices, 0 <= n <= 2^30 */
+    int32_t n;                /* vertices, 0 <= n <= 2^29 */
     int64_t m;                /* edges, == row_off[n], 0 <= m < 2^31 */
     const int32_t *row_off;   /* (device) n+1 non-decreasing offsets, row_off[0] == 0 */
     const int32_t *col;       /* (device) m targets in [0, n); successor order = array order */
@@ -83,7 +83,7 @@ typedef struct {
  * deg(v) <= 256.
  */
 typedef struct {
-    int32_t log2n;              /* 1 .. 30 */
+    int32_t log2n;              /* 1 .. 29 */
     uint64_t seed;
     uint64_t zero_thr;
     const uint64_t *deg_table;  /* (device) 256 non-decreasing thresholds */
@@ -116,7 +116,8 @@ typedef struct {
                               after the first sweep */
     uint64_t joins;        /* AC-6: support-list joins after the first sweep */
     uint64_t visited;      /* AC-6: support-list members handed back */
-    uint64_t reserved[3];
+    uint64_t graph_edges;  /* AC-6: sum of out-degrees as generated or read (m) */
+    uint64_t reserved[2];
 } trim_stats_t;
 
 /*

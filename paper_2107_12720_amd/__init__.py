@@ -32,7 +32,7 @@ EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destr
            "trim_num_workers", "trim_csr", "trim_implicit", "trim_batch",
            "trim_ctx_set_timing", "trim_ctx_kernel_times")
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
-                "joins", "visited")
+                "joins", "visited", "graph_edges")
 STATS_WORDS = 12
 
 

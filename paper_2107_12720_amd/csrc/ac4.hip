@@ -82,6 +82,7 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
         }
 #pragma unroll
         for (int j = 0; j < kBatch; j += 2) wq.push(out[j], out[j + 1]);
+        wq.rebalance();
     }
     edges = wave_sum(edges);
     if (lane_id() == 0 && edges) add_dev(worker_edges + blockIdx.x, edges);

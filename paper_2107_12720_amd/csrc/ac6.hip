@@ -94,7 +94,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, ui
     __shared__ uint64_t red[16];
     Stage<View>::apply(g, lds);
     if (threadIdx.x == 0) s_ncas = 0;
-    uint64_t edges = 0;
+    uint64_t edges = 0, degsum = 0;
     // move the buffered casualties to the shared queue with one reservation
     auto flush = [&]() {
         __syncthreads();
@@ -129,6 +129,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, ui
             int gi = 0;
             if (v < ce) {
                 const int b = g.begin(v), e = g.end(v);
+                degsum += (uint64_t)(e - b);
                 if constexpr (View::kPerGraph) gi = g.graph_from(v, hint);
                 else gi = g.vctx(v);
                 if (b < e) {
@@ -162,9 +163,11 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, ui
     }
     flush();
     edges = block_sum(edges, red);
+    degsum = block_sum(degsum, red);
     if (threadIdx.x == 0) {
         if (edges) add_dev(worker_edges + (blockIdx.x % P), edges);
         part[kPartSweep * kPartStride + blockIdx.x] = edges;
+        part[kPartDeg * kPartStride + blockIdx.x] = degsum;
     }
 }
 

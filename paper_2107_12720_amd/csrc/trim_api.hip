@@ -62,9 +62,9 @@ int ensure(trim_ctx* c, int64_t n) {
         hipMalloc((void**)&c->w.b, cap * 8) != hipSuccess ||
         hipMalloc((void**)&c->w.c, cap * 4) != hipSuccess ||
         hipMalloc((void**)&c->w.d, cap * 4) != hipSuccess ||
-        hipMalloc((void**)&c->w.q, cap * 12) != hipSuccess ||
+        hipMalloc((void**)&c->w.q, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess ||
         // free queue slots hold kNone (all ones); consumers restore it
-        hipMemset(c->w.q, 0xFF, cap * 12) != hipSuccess) {
+        hipMemset(c->w.q, 0xFF, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess) {
         (void)hipGetLastError();
         free_work(c);
         return fail(TRIM_E_NOMEM, "cannot allocate working memory for %lld vertices",
@@ -208,7 +208,7 @@ int trim_csr(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
     if (!c || !g) return fail(TRIM_E_INVAL, "trim_csr: NULL context or graph");
     if (algo != TRIM_AC3 && algo != TRIM_AC4 && algo != TRIM_AC6)
         return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
-    if (g->n < 0 || g->n > (1 << 30)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
+    if (g->n < 0 || g->n > (1 << 29)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
     if (g->m < 0 || g->m >= (int64_t)1 << 31)
         return fail(TRIM_E_INVAL, "m = %lld out of range [0, 2^31)", (long long)g->m);
     if (!g->row_off) return fail(TRIM_E_INVAL, "row_off is NULL");
@@ -251,8 +251,8 @@ int trim_implicit(trim_ctx* c, int algo, const trim_implicit_t* g, const trim_op
                     "AC-4 needs the transposed graph and cannot run on an implicit graph");
     if (algo != TRIM_AC3 && algo != TRIM_AC6)
         return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
-    if (g->log2n < 1 || g->log2n > 30)
-        return fail(TRIM_E_INVAL, "log2n = %d out of range [1, 30]", g->log2n);
+    if (g->log2n < 1 || g->log2n > 29)
+        return fail(TRIM_E_INVAL, "log2n = %d out of range [1, 29]", g->log2n);
     if (!g->deg_table) return fail(TRIM_E_INVAL, "deg_table is NULL");
     if (!live_bitmap || !worker_edges) return fail(TRIM_E_INVAL, "NULL output");
     int rc = check_opts(o);
@@ -275,7 +275,7 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
     if (G < 1) return fail(TRIM_E_INVAL, "G = %d must be >= 1", G);
     if (!vbase || !row_off || !bitmap_base || !live_bitmaps || !graph_edges)
         return fail(TRIM_E_INVAL, "trim_batch: NULL array");
-    if (total_n < 0 || total_n > (1 << 30) || total_m < 0 || total_m >= (int64_t)1 << 31)
+    if (total_n < 0 || total_n > (1 << 29) || total_m < 0 || total_m >= (int64_t)1 << 31)
         return fail(TRIM_E_INVAL, "batch sizes out of range");
     if (total_m > 0 && !col) return fail(TRIM_E_INVAL, "col is NULL");
     int rc = check_opts(o);

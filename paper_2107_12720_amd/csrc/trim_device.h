@@ -125,15 +125,20 @@ __device__ __forceinline__ int item_vertex(uint32_t it) { return (int)(it & kIdM
 constexpr int kLocalQ = 1024;             // LDS ring entries per wavefront
 constexpr int kSpillAbove = kLocalQ / 2;  // ring fill that triggers a bulk hand-off
 constexpr int kPollEvery = 64;            // busy iterations between shared-queue polls
-constexpr int kMaxNaps = 16;              // idle back-off cap, in s_sleep(127) naps
+constexpr int kMaxNaps = 4;               // idle back-off cap, in s_sleep(127) naps
 
 // Work distribution of the persistent kernels (the paper's private waiting
-// sets Q_p, Section 5.2 / 6.2).  Each wavefront owns an LDS ring; items go to
-// the shared queue only when the ring is full, and idle wavefronts take from
-// the shared queue.  `pending` counts shared-queue items plus wavefronts that
-// hold private work, so it reaches zero only when no work is left anywhere.
-// Shared-queue slots hold kNone while free: a consumer resets each slot it
-// reads, so the buffer is clean for the next call without a fill pass.
+// sets Q_p, Sections 5.2 / 6.2).  Each wavefront owns an LDS ring; items reach
+// the shared queue only when a ring overflows or when some lane elsewhere is
+// waiting for work.  A wavefront with nothing to do takes 64 tickets (one per
+// lane) with a single fetch-add on qhead; ticket t is filled by whoever
+// reserves slot t through qtail, so claims never retry.  `pending` counts
+// shared-queue items plus wavefronts that hold private work: it reaches zero
+// only when no work is left anywhere, and then waiting lanes give up.
+// Free slots hold kNone; a consumer resets the slot it took, so the buffer
+// is clean for the next call without a fill pass.  Outstanding tickets are at
+// most 64 per wavefront, which the queue's slack (kQueueSlots) covers.
+
 struct WaveQueue {
     uint32_t* lq;
     int* tail_lds;      // ring tail in LDS: lanes may append from divergent code
@@ -143,6 +148,7 @@ struct WaveQueue {
     int* qhead;
     int* qtail;
     int* pending;
+    int ticket;         // per lane: shared-queue slot this lane waits on, or -1
     int iter;           // wave-uniform iteration counter
     int naps;           // wave-uniform idle back-off
 
@@ -158,6 +164,7 @@ struct WaveQueue {
         qhead = ctr_qhead;
         qtail = ctr_qtail;
         pending = ctr_pending;
+        ticket = -1;
         iter = 0;
         naps = 1;
     }
@@ -165,6 +172,7 @@ struct WaveQueue {
     __device__ __forceinline__ int tail() const {
         return __hip_atomic_load(tail_lds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
+    __device__ __forceinline__ int fill() const { return tail() - head; }
 
     // Idle lanes take items from the LDS ring.
     __device__ __forceinline__ void refill(uint32_t& item) {
@@ -178,44 +186,43 @@ struct WaveQueue {
         }
     }
 
-    // Idle lanes take up to one item each from the shared queue.  Returns the
-    // number taken (wave-uniform) and updates *pending.
-    __device__ __forceinline__ int claim(uint32_t& item) {
-        const uint64_t idle = ballot(item == kNone);
-        const int want = popc(idle);
-        int base = 0, got = 0;
-        if (want && lane_id() == 0) {
-            int h = ld_dev(qhead);
-            for (;;) {
-                const int t = ld_dev(qtail);
-                if (h >= t) break;
-                const int k = min(want, t - h);
-                if (cas_dev(qhead, h, h + k)) {
-                    base = h;
-                    got = k;
-                    break;
-                }
+    // Idle lanes whose ticket slot has been filled take that item.
+    __device__ __forceinline__ void resolve(uint32_t& item) {
+        bool got = false;
+        if (item == kNone && ticket >= 0) {
+            const uint32_t x = (uint32_t)ld_dev((const int*)q + ticket);
+            if (x != kNone) {
+                st_dev((int*)q + ticket, (int)kNone);
+                item = x;
+                ticket = -1;
+                got = true;
             }
-            if (got) add_dev(pending, (holding ? 0 : 1) - got);
+        }
+        const int r = popc(ballot(got));
+        if (r) {
+            if (lane_id() == 0) add_dev(pending, (holding ? 0 : 1) - r);
+            holding = true;
+        }
+    }
+
+    // Every lane takes a ticket (only when none is outstanding).
+    __device__ __forceinline__ void claim() {
+        int base = 0;
+        if (lane_id() == 0) base = add_dev(qhead, kWave);
+        ticket = __shfl(base, 0) + lane_id();
+    }
+
+    __device__ __forceinline__ void spill_ring(int k) {
+        int base = 0;
+        if (lane_id() == 0) {
+            add_dev(pending, k);
+            complete_mem();
+            base = add_dev(qtail, k);
         }
         base = __shfl(base, 0);
-        got = __shfl(got, 0);
-        if (got) {
-            holding = true;
-            const int rank = popc(idle & lanes_below());
-            if (item == kNone && rank < got) {
-                // the producer reserved this slot and is writing it
-                const int slot = base + rank;
-                uint32_t x = (uint32_t)ld_dev((const int*)q + slot);
-                while (x == kNone) {
-                    __builtin_amdgcn_s_sleep(1);
-                    x = (uint32_t)ld_dev((const int*)q + slot);
-                }
-                st_dev((int*)q + slot, (int)kNone);
-                item = x;
-            }
-        }
-        return got;
+        for (int i = lane_id(); i < k; i += kWave)
+            st_dev((int*)q + base + i, (int)lq[(head + i) & (kLocalQ - 1)]);
+        head += k;
     }
 
     // One item from any lane, also from divergent code: into the ring if it
@@ -230,12 +237,9 @@ struct WaveQueue {
                 st_dev((int*)q + pos, (int)it);
                 return;
             }
-            const int seen = __hip_atomic_compare_exchange_strong(
-                                 tail_lds, &t, t + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WAVEFRONT)
-                                 ? -1
-                                 : t;
-            if (seen < 0) {
+            if (__hip_atomic_compare_exchange_strong(tail_lds, &t, t + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WAVEFRONT)) {
                 lq[t & (kLocalQ - 1)] = it;
                 return;
             }
@@ -270,44 +274,44 @@ struct WaveQueue {
         if (b != kNone) st_dev((int*)q + base + rb, (int)b);
     }
 
-    __device__ __forceinline__ int fill() const { return tail() - head; }
-
-    // Uniform code: hand the oldest ring items to the shared queue when the
-    // ring is more than half full, one reservation for all of them.
+    // Uniform code, now and then: if lanes elsewhere wait for work (tickets
+    // beyond qtail), hand them part of the ring.
     __device__ __forceinline__ void rebalance() {
-        const int occ = tail() - head;
-        if (occ <= kSpillAbove) return;
-        const int k = occ - kLocalQ / 8;
-        int base = 0;
-        if (lane_id() == 0) {
-            add_dev(pending, k);
-            complete_mem();
-            base = add_dev(qtail, k);
-        }
-        base = __shfl(base, 0);
-        for (int i = lane_id(); i < k; i += kWave)
-            st_dev((int*)q + base + i, (int)lq[(head + i) & (kLocalQ - 1)]);
-        head += k;
+        if ((iter & (kPollEvery - 1)) != 0) return;
+        const int occ = fill();
+        if (occ < 2) return;
+        int waiting = 0;
+        if (lane_id() == 0) waiting = ld_dev(qhead) - ld_dev(qtail);
+        waiting = __shfl(waiting, 0);
+        if (waiting > 0) spill_ring(min(occ / 2, waiting));
     }
 
     // Returns false when the whole computation is finished.  Otherwise at
     // least one lane of the wave holds an item.
     __device__ __forceinline__ bool acquire(uint32_t& item) {
         for (;;) {
+            ++iter;
             refill(item);
             const uint64_t busy = ballot(item != kNone);
+            const bool tickets = ballot(ticket >= 0) != 0;
             if (busy) {
                 naps = 1;
-                // a busy wave with idle lanes looks at the shared queue now and then
-                if (busy != ~0ull && tail() == head && (++iter & (kPollEvery - 1)) == 0)
-                    claim(item);
+                if (busy != ~0ull && (iter & 15) == 0) {
+                    if (tickets) resolve(item);
+                    else if (tail() == head && (iter & (kPollEvery - 1)) == 0) claim();
+                }
                 return true;
             }
             if (holding) {
                 if (lane_id() == 0) add_dev(pending, -1);
                 holding = false;
             }
-            if (claim(item)) return true;
+            if (!tickets) claim();
+            resolve(item);
+            if (ballot(item != kNone)) {
+                naps = 1;
+                return true;
+            }
             if (ld_dev(pending) == 0) return false;
             for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
             naps = naps * 2 > kMaxNaps ? kMaxNaps : naps * 2;
@@ -374,6 +378,7 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
     const uint64_t closes = sum_range(part + kPartCloses * kPartStride, n_prop, red);
     const uint64_t joins = sum_range(part + kPartJoins * kPartStride, n_prop, red);
     const uint64_t visited = sum_range(part + kPartVisited * kPartStride, n_prop, red);
+    const uint64_t degsum = sum_range(part + kPartDeg * kPartStride, n_sweep, red);
     if (threadIdx.x == 0) {
         stats->edges_total = edges;
         stats->n_live = live;
@@ -383,6 +388,7 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
         stats->closes = closes;
         stats->joins = joins;
         stats->visited = visited;
+        stats->graph_edges = degsum;
         if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
     }
 }

@@ -35,9 +35,11 @@ struct Work {
     uint64_t* part = nullptr;    // per-block partial sums (kPartSlots x kPartStride)
 };
 constexpr int kMaxWorkers = 16384;
+// shared-queue slack beyond 3n slots: outstanding tickets, 64 per wavefront
+constexpr int kQueueSlots = 64 * 4 * kMaxWorkers;
 constexpr int kPartStride = 16384;   // >= workers, sweep blocks and pack blocks
 enum PartSlot : int { kPartCloses = 0, kPartJoins = 1, kPartVisited = 2, kPartSweep = 3,
-                      kPartLive = 4, kPartSlots = 5 };
+                      kPartLive = 4, kPartDeg = 5, kPartSlots = 6 };
 
 // Optional per-kernel event timing (trim_ctx_set_timing).
 struct Timer {
