@@ -178,6 +178,55 @@ int trim_batch(trim_ctx *ctx, int32_t G, const int64_t *vbase, const int32_t *ro
                const trim_opts_t *opts, uint32_t *live_bitmaps, uint64_t *graph_edges,
                trim_stats_t *stats, void *stream);
 
+/*
+ * Learned successor order (AC-6 checks successors in list order; a live
+ * vertex costs the index of its first live successor + 1 checks, Section 6.1
+ * and the edge_index of Section 8).  A small network scores each edge u -> w
+ * by how likely w is to stay live, and each successor list is reordered by
+ * the score; this changes the traversed edges, never the live set.
+ * Parameters: 1,377 values in this order -- W1[32][8], b1[32], W2[32][32]
+ * (W2[out][in]), b2[32], w3[32], b3 -- as FP32 masters and BF16 copies
+ * (uint16 bit patterns).  All arrays are device memory owned by the caller.
+ */
+#define TRIM_MLP_PARAMS 1377
+
+/* indeg[v] (n entries) and src[e] (m entries: the source of edge e). */
+int trim_mlp_prepare(trim_ctx *ctx, const trim_csr_t *g, int32_t *indeg, int32_t *src,
+                     void *stream);
+
+/*
+ * Gradient of the mean binary cross-entropy "w is live" (labels: live_bitmap,
+ * the trimmed set) over `count` sampled edges; edges with a non-live source
+ * weigh 0.  Edges are edge_ids[0..count) if edge_ids is non-NULL, else hashed
+ * samples of (seed, step).  Accumulates into grad[0..1376] and the loss into
+ * grad[1377] (FP32, 1378 entries).
+ */
+int trim_mlp_grad(trim_ctx *ctx, const trim_csr_t *g, const int32_t *indeg, const int32_t *src,
+                  const uint32_t *live_bitmap, const uint16_t *params_bf16,
+                  const int64_t *edge_ids, int64_t count, uint64_t seed, int32_t step,
+                  float *grad, void *stream);
+
+/* One Adam step (step >= 1) on params; refreshes params_bf16 and clears grad. */
+int trim_mlp_adam(trim_ctx *ctx, float *params, uint16_t *params_bf16, float *adam_m,
+                  float *adam_v, float *grad, float lr, float beta1, float beta2, float eps,
+                  int32_t step, void *stream);
+
+/* scores[e] = logit of edge e (m entries, CSR order). */
+int trim_mlp_score(trim_ctx *ctx, const trim_csr_t *g, const int32_t *indeg, const int32_t *src,
+                   const uint16_t *params_bf16, float *scores, void *stream);
+
+/* Reference orders: kind 0 keys[e] = log1p(outdeg(target)), kind 1 a hash of (seed, e). */
+int trim_edge_keys(trim_ctx *ctx, const trim_csr_t *g, int32_t kind, uint64_t seed, float *keys,
+                   void *stream);
+
+/*
+ * col_out = each successor list reordered by keys, larger first, in 16 equal
+ * levels between lo and hi (clamped), stable within a level.  col_out (m
+ * entries) must not alias g->col; row offsets are unchanged.
+ */
+int trim_order_by_key(trim_ctx *ctx, const trim_csr_t *g, const float *keys, float lo, float hi,
+                      int32_t *col_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

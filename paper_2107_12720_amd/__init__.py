@@ -30,7 +30,9 @@ STATUS = {0: "TRIM_OK", -1: "TRIM_E_INVAL", -2: "TRIM_E_NOMEM", -3: "TRIM_E_HIP"
           -4: "TRIM_E_UNSUPPORTED", -5: "TRIM_E_BADGRAPH", -6: "TRIM_E_STALLED"}
 EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destroy",
            "trim_num_workers", "trim_csr", "trim_implicit", "trim_batch",
-           "trim_ctx_set_timing", "trim_ctx_kernel_times")
+           "trim_ctx_set_timing", "trim_ctx_kernel_times", "trim_mlp_prepare", "trim_mlp_grad",
+           "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key")
+MLP_PARAMS = 1377
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
                 "joins", "visited", "graph_edges")
 STATS_WORDS = 12
@@ -85,8 +87,19 @@ def lib():
         L.trim_ctx_set_timing.argtypes = [vp, ctypes.c_int]
         L.trim_ctx_kernel_times.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p),
                                             ctypes.POINTER(ctypes.c_float)]
+        csr_p = ctypes.POINTER(CsrDesc)
+        f32 = ctypes.c_float
+        L.trim_mlp_prepare.argtypes = [vp, csr_p, vp, vp, vp]
+        L.trim_mlp_grad.argtypes = [vp, csr_p, vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_uint64,
+                                    i32, vp, vp]
+        L.trim_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+        L.trim_mlp_score.argtypes = [vp, csr_p, vp, vp, vp, vp, vp]
+        L.trim_edge_keys.argtypes = [vp, csr_p, i32, ctypes.c_uint64, vp, vp]
+        L.trim_order_by_key.argtypes = [vp, csr_p, vp, f32, f32, vp, vp]
         for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_num_workers", "trim_csr",
-                  "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times"):
+                  "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times",
+                  "trim_mlp_prepare", "trim_mlp_grad", "trim_mlp_adam", "trim_mlp_score",
+                  "trim_edge_keys", "trim_order_by_key"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -246,6 +259,76 @@ class Context:
                                 ctypes.c_void_p(ge.data_ptr()), ctypes.c_void_p(st.data_ptr()),
                                 _stream_handle(stream, self.device)))
         return TrimResult(lb, ge, st)
+
+
+class DeviceGraph:
+    """An explicit CSR graph resident on the GPU (int32 row_off and col)."""
+
+    def __init__(self, n, row_off, col, rrow_off=None, rcol=None):
+        self.n, self.row_off, self.col = int(n), row_off, col
+        self.rrow_off, self.rcol = rrow_off, rcol
+        self.m = int(col.numel()) if col is not None else 0
+
+    def desc(self) -> CsrDesc:
+        import torch
+        return CsrDesc(self.n, self.m, _dev_ptr(self.row_off, torch.int32, "row_off"),
+                       _dev_ptr(self.col, torch.int32, "col") if self.m else None,
+                       _dev_ptr(self.rrow_off, torch.int32, "rrow_off", allow_none=True),
+                       _dev_ptr(self.rcol, torch.int32, "rcol", allow_none=True)
+                       if self.m else None)
+
+    @staticmethod
+    def upload(g, device: int = 0) -> "DeviceGraph":
+        return DeviceGraph(g.n, to_device(g.row_off, device),
+                           to_device(g.col, device) if g.m else None)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _mlp_methods():
+    def mlp_prepare(self, dg: DeviceGraph, indeg, src, stream=None):
+        d = dg.desc()
+        _check(lib().trim_mlp_prepare(self._h, ctypes.byref(d), _ptr(indeg), _ptr(src),
+                                      _stream_handle(stream, self.device)))
+
+    def mlp_grad(self, dg: DeviceGraph, indeg, src, live_bitmap, params_bf16, grad, count,
+                 edge_ids=None, seed=0, step=0, stream=None):
+        d = dg.desc()
+        _check(lib().trim_mlp_grad(self._h, ctypes.byref(d), _ptr(indeg), _ptr(src),
+                                   _ptr(live_bitmap), _ptr(params_bf16), _ptr(edge_ids),
+                                   int(count), int(seed) & (2 ** 64 - 1), int(step), _ptr(grad),
+                                   _stream_handle(stream, self.device)))
+
+    def mlp_adam(self, params, params_bf16, m1, m2, grad, lr, step, beta1=0.9, beta2=0.999,
+                 eps=1e-8, stream=None):
+        _check(lib().trim_mlp_adam(self._h, _ptr(params), _ptr(params_bf16), _ptr(m1), _ptr(m2),
+                                   _ptr(grad), float(lr), float(beta1), float(beta2), float(eps),
+                                   int(step), _stream_handle(stream, self.device)))
+
+    def mlp_score(self, dg: DeviceGraph, indeg, src, params_bf16, scores, stream=None):
+        d = dg.desc()
+        _check(lib().trim_mlp_score(self._h, ctypes.byref(d), _ptr(indeg), _ptr(src),
+                                    _ptr(params_bf16), _ptr(scores),
+                                    _stream_handle(stream, self.device)))
+
+    def edge_keys(self, dg: DeviceGraph, kind, keys, seed=0, stream=None):
+        d = dg.desc()
+        _check(lib().trim_edge_keys(self._h, ctypes.byref(d), int(kind),
+                                    int(seed) & (2 ** 64 - 1), _ptr(keys),
+                                    _stream_handle(stream, self.device)))
+
+    def order_by_key(self, dg: DeviceGraph, keys, lo, hi, col_out, stream=None):
+        d = dg.desc()
+        _check(lib().trim_order_by_key(self._h, ctypes.byref(d), _ptr(keys), float(lo), float(hi),
+                                       _ptr(col_out), _stream_handle(stream, self.device)))
+
+    for f in (mlp_prepare, mlp_grad, mlp_adam, mlp_score, edge_keys, order_by_key):
+        setattr(Context, f.__name__, f)
+
+
+_mlp_methods()
 
 
 def to_device(a: np.ndarray, device: int = 0):

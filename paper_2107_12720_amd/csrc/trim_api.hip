@@ -326,6 +326,87 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
     return TRIM_OK;
 }
 
+namespace {
+int check_graph(trim_ctx* c, const trim_csr_t* g, const char* who) {
+    if (!c || !g) return fail(TRIM_E_INVAL, "%s: NULL context or graph", who);
+    if (g->n < 0 || g->n > (1 << 29)) return fail(TRIM_E_INVAL, "%s: n out of range", who);
+    if (g->m < 0 || g->m >= (int64_t)1 << 31) return fail(TRIM_E_INVAL, "%s: m out of range", who);
+    if (!g->row_off || (g->m > 0 && !g->col)) return fail(TRIM_E_INVAL, "%s: NULL CSR", who);
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return TRIM_OK;
+}
+int launched(hipError_t e) { return e == hipSuccess ? TRIM_OK : hip_fail(e, "kernel launch"); }
+}  // namespace
+
+int trim_mlp_prepare(trim_ctx* c, const trim_csr_t* g, int32_t* indeg, int32_t* src,
+                     void* stream) {
+    int rc = check_graph(c, g, "trim_mlp_prepare");
+    if (rc) return rc;
+    if (!indeg || (g->m > 0 && !src)) return fail(TRIM_E_INVAL, "trim_mlp_prepare: NULL output");
+    return launched(trim::mlp_prepare(g->row_off, g->col, g->n, g->m, indeg, src,
+                                      (hipStream_t)stream));
+}
+
+int trim_mlp_grad(trim_ctx* c, const trim_csr_t* g, const int32_t* indeg, const int32_t* src,
+                  const uint32_t* live_bitmap, const uint16_t* params_bf16,
+                  const int64_t* edge_ids, int64_t count, uint64_t seed, int32_t step,
+                  float* grad, void* stream) {
+    int rc = check_graph(c, g, "trim_mlp_grad");
+    if (rc) return rc;
+    if (!indeg || !src || !live_bitmap || !params_bf16 || !grad)
+        return fail(TRIM_E_INVAL, "trim_mlp_grad: NULL argument");
+    if (count < 1 || g->m < 1) return fail(TRIM_E_INVAL, "trim_mlp_grad: no edges to sample");
+    return launched(trim::mlp_grad_launch(g->row_off, g->col, indeg, src, g->m, live_bitmap,
+                                          (const short*)params_bf16, (const long long*)edge_ids,
+                                          count, seed, step, grad, c->cus, (hipStream_t)stream));
+}
+
+int trim_mlp_adam(trim_ctx* c, float* params, uint16_t* params_bf16, float* adam_m,
+                  float* adam_v, float* grad, float lr, float beta1, float beta2, float eps,
+                  int32_t step, void* stream) {
+    if (!c || !params || !params_bf16 || !adam_m || !adam_v || !grad)
+        return fail(TRIM_E_INVAL, "trim_mlp_adam: NULL argument");
+    if (step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+        !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(TRIM_E_INVAL, "trim_mlp_adam: bad hyper-parameters");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return launched(trim::mlp_adam_launch(params, (short*)params_bf16, adam_m, adam_v, grad, lr,
+                                          beta1, beta2, eps, step, (hipStream_t)stream));
+}
+
+int trim_mlp_score(trim_ctx* c, const trim_csr_t* g, const int32_t* indeg, const int32_t* src,
+                   const uint16_t* params_bf16, float* scores, void* stream) {
+    int rc = check_graph(c, g, "trim_mlp_score");
+    if (rc) return rc;
+    if (!indeg || (g->m > 0 && (!src || !scores)) || !params_bf16)
+        return fail(TRIM_E_INVAL, "trim_mlp_score: NULL argument");
+    return launched(trim::mlp_score_launch(g->row_off, g->col, indeg, src, g->m,
+                                           (const short*)params_bf16, scores, c->cus,
+                                           (hipStream_t)stream));
+}
+
+int trim_edge_keys(trim_ctx* c, const trim_csr_t* g, int32_t kind, uint64_t seed, float* keys,
+                   void* stream) {
+    int rc = check_graph(c, g, "trim_edge_keys");
+    if (rc) return rc;
+    if (kind != 0 && kind != 1) return fail(TRIM_E_INVAL, "trim_edge_keys: kind must be 0 or 1");
+    if (g->m > 0 && !keys) return fail(TRIM_E_INVAL, "trim_edge_keys: NULL keys");
+    return launched(
+        trim::edge_keys_launch(g->row_off, g->col, g->m, kind, seed, keys, (hipStream_t)stream));
+}
+
+int trim_order_by_key(trim_ctx* c, const trim_csr_t* g, const float* keys, float lo, float hi,
+                      int32_t* col_out, void* stream) {
+    int rc = check_graph(c, g, "trim_order_by_key");
+    if (rc) return rc;
+    if (g->m > 0 && (!keys || !col_out)) return fail(TRIM_E_INVAL, "trim_order_by_key: NULL");
+    if (col_out == g->col) return fail(TRIM_E_INVAL, "trim_order_by_key: col_out aliases col");
+    return launched(trim::order_launch(g->row_off, g->col, g->n, keys, lo, hi, col_out, c->cus,
+                                       (hipStream_t)stream));
+}
+
 int trim_ctx_set_timing(trim_ctx* c, int enable) {
     if (!c) return fail(TRIM_E_INVAL, "trim_ctx_set_timing: NULL context");
     hipError_t e = hipSetDevice(c->device);

@@ -105,6 +105,22 @@ hipError_t ac3_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg
                         uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
 int ac3_max_workers_per_cu(int block);
 
+// ------------------------------------------------------------ learned order
+hipError_t mlp_prepare(const int* row_off, const int* col, int n, long long m, int* indeg,
+                       int* src, hipStream_t s);
+hipError_t mlp_grad_launch(const int* row_off, const int* col, const int* indeg, const int* src,
+                           long long m, const uint32_t* live, const short* pbf,
+                           const long long* ids, long long count, uint64_t seed, int step,
+                           float* grad, int cus, hipStream_t s);
+hipError_t mlp_adam_launch(float* p32, short* pbf, float* m1, float* m2, float* grad, float lr,
+                           float beta1, float beta2, float eps, int step, hipStream_t s);
+hipError_t mlp_score_launch(const int* row_off, const int* col, const int* indeg, const int* src,
+                            long long m, const short* pbf, float* score, int cus, hipStream_t s);
+hipError_t edge_keys_launch(const int* row_off, const int* col, long long m, int kind,
+                            uint64_t seed, float* key, hipStream_t s);
+hipError_t order_launch(const int* row_off, const int* col, int n, const float* key, float lo,
+                        float hi, int* col_out, int cus, hipStream_t s);
+
 // ------------------------------------------------------------ validation
 hipError_t validate_csr(const trim_csr_t& g, const Work& w, hipStream_t s);
 

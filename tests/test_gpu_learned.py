@@ -1,0 +1,136 @@
+"""GPU checks of the learned successor order.
+
+* The fused forward/backward kernel against the FP64 CPU reference, which
+  rounds to BF16 where the GPU feeds an MFMA (tolerance 1e-2 relative to the
+  largest gradient of each parameter group; loss to 1e-4).
+* The per-vertex reorder is a stable bucketed sort of each successor list.
+* Training lowers the loss.
+* Any order gives the same live bitmap; the traversed-edge total under the
+  learned order equals the closed form on the reordered graph and is at
+  least the lower bound T6min.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2107_12720_amd as T
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def device_graph(g):
+    import paper_2107_12720_amd as T
+    return T.DeviceGraph.upload(g)
+
+
+def test_gradient_vs_fp64_reference(ctx):
+    import torch
+    import paper_2107_12720_amd as T
+    from paper_2107_12720_amd import learned
+    from oracle import mlp_ref
+    g = gg.rmat(12, 8, seed=4)
+    r = oracle.peel(g)
+    dg = device_graph(g)
+    indeg, src = learned.prepare(ctx, dg)
+    live = T.to_device(oracle.bitmap(r.live).view(np.int32))
+    rng = np.random.default_rng(3)
+    for trial in range(3):
+        p = learned.init_params(seed=trial) * (1.0 + trial)
+        p[256:288] = rng.normal(0, 0.1, 32)      # nonzero biases
+        p[1312:1344] = rng.normal(0, 0.1, 32)
+        pbf_bits = learned.to_bf16_bits(p)
+        pbf = T.to_device(pbf_bits.view(np.int16))
+        ids = rng.integers(0, g.m, 3000).astype(np.int64)
+        grad = torch.zeros(T.MLP_PARAMS + 1, dtype=torch.float32, device="cuda")
+        ctx.mlp_grad(dg, indeg, src, live, pbf, grad, len(ids), edge_ids=T.to_device(ids))
+        torch.cuda.synchronize()
+        gg_ = grad.cpu().numpy().astype(np.float64)
+        X, s_, d_ = mlp_ref.features(g.row_off.astype(np.int64), g.col,
+                                     np.bincount(g.col, minlength=g.n), ids)
+        y = r.live[d_].astype(float)
+        w = r.live[s_].astype(float) / len(ids)
+        # the reference uses the same BF16 weights the GPU reads
+        pw = pbf_bits.astype(np.uint32) << 16
+        loss, ref = mlp_ref.loss_and_grad(pw.view(np.float32).astype(np.float64), X, y, w,
+                                          bf16=True)
+        say(f"  trial {trial}: loss gpu {gg_[-1]:.6f} ref {loss:.6f}")
+        assert abs(gg_[-1] - loss) <= 1e-4 * max(1.0, abs(loss))
+        for k, (o, sh) in mlp_ref.OFF.items():
+            sz = int(np.prod(sh))
+            a, b = gg_[o:o + sz], ref[o:o + sz]
+            err = np.max(np.abs(a - b))
+            assert err <= 1e-2 * np.max(np.abs(b)) + 1e-7, (k, err, np.max(np.abs(b)))
+
+
+def test_order_is_stable_bucketed_permutation(ctx):
+    import torch
+    import paper_2107_12720_amd as T
+    g = gg.rmat(13, 16, seed=9)
+    dg = device_graph(g)
+    keys = torch.empty(g.m, dtype=torch.float32, device="cuda")
+    ctx.edge_keys(dg, 1, keys, seed=5)
+    out = torch.empty_like(dg.col)
+    ctx.order_by_key(dg, keys, 0.0, 1.0, out)
+    torch.cuda.synchronize()
+    k = keys.cpu().numpy()
+    got = out.cpu().numpy()
+    scale = np.float32(16.0)
+    bucket = np.clip(((np.float32(1.0) - k) * scale).astype(np.int32), 0, 15)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_off))
+    order = np.lexsort((np.arange(g.m), bucket, src))     # stable by (src, bucket)
+    assert np.array_equal(got, g.col[order])
+
+
+def test_training_lowers_loss_and_order_keeps_live_set(ctx):
+    import torch
+    import paper_2107_12720_amd as T
+    from paper_2107_12720_amd import learned
+    from gpu_common import upload, run_csr
+    graphs = []
+    for seed in (1, 2):
+        g = gg.rmat(14, 16, seed=seed)
+        dg = device_graph(g)
+        indeg, src = learned.prepare(ctx, dg)
+        res = ctx.trim_csr(6, g.n, dg.row_off, dg.col)    # labels from plain AC-6
+        graphs.append((dg, indeg, src, res.live_bitmap))
+        torch.cuda.synchronize()
+        assert np.array_equal(res.bitmap_numpy()[:(g.n + 31) // 32],
+                              oracle.bitmap(oracle.peel(g).live))
+    tr = learned.Trainer(ctx, seed=0, lr=1e-2)
+    losses = [float(tr.train_step(graphs, 1 << 14, seed=7)) for _ in range(60)]
+    say(f"  loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert np.mean(losses[-10:]) < 0.8 * np.mean(losses[:5])
+    # evaluate on another graph
+    g = gg.rmat(15, 16, seed=3)
+    dg = device_graph(g)
+    indeg, src = learned.prepare(ctx, dg)
+    col_l, _ = learned.learned_order(ctx, dg, indeg, src, tr.pbf)
+    col_h = learned.reference_order(ctx, dg, 0)
+    col_r = learned.reference_order(ctx, dg, 1, seed=11)
+    torch.cuda.synchronize()
+    r = oracle.peel(g)
+    base = oracle.counts(g, r)
+    for name, col in (("learned", col_l), ("heuristic", col_h), ("random", col_r)):
+        go = gg.CSR(g.n, g.row_off, col.cpu().numpy())
+        # same multiset of successors per vertex
+        assert np.array_equal(np.sort(go.col + np.repeat(np.arange(g.n), np.diff(g.row_off)) *
+                                      np.int64(g.n)),
+                              np.sort(g.col + np.repeat(np.arange(g.n), np.diff(g.row_off)) *
+                                      np.int64(g.n)))
+        ro = oracle.peel(go)
+        c = oracle.counts(go, ro)
+        res = ctx.trim_csr(6, g.n, dg.row_off, col)
+        torch.cuda.synchronize()
+        st = res.stats_dict()
+        assert np.array_equal(res.bitmap_numpy()[:(g.n + 31) // 32], oracle.bitmap(r.live))
+        assert st["edges_total"] == c.T6 and c.T6min == base.T6min <= c.T6
+        say(f"  {name}: T6 {c.T6} (plain {base.T6}, min {base.T6min})")

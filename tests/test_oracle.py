@@ -318,3 +318,32 @@ def test_bitmap_layout(orc):
     bm = orc.bitmap(live)
     assert bm.dtype == np.uint32 and bm.shape == (3,)
     assert bm[0] == (1 | (1 << 5) | (1 << 31)) and bm[1] == 1 and bm[2] == (1 << 5)
+
+
+def test_mlp_reference_finite_differences():
+    """The FP64 reference's backward pass against central differences of its
+    own forward pass (no BF16 rounding), on random features and weights."""
+    from oracle import mlp_ref
+    rng = np.random.default_rng(7)
+    p = rng.normal(0, 0.4, mlp_ref.NPARAM)
+    X = rng.normal(0, 1, (24, 8))
+    y = (rng.random(24) < 0.5).astype(float)
+    w = (rng.random(24) < 0.8).astype(float) / 24
+    loss, g = mlp_ref.loss_and_grad(p, X, y, w, bf16=False)
+    eps = 1e-6
+    for i in list(range(0, mlp_ref.NPARAM, 37)) + [255, 287, 1311, 1343, 1375, 1376]:
+        q = p.copy()
+        q[i] += eps
+        lp, _ = mlp_ref.loss_and_grad(q, X, y, w, bf16=False)
+        q[i] -= 2 * eps
+        lm, _ = mlp_ref.loss_and_grad(q, X, y, w, bf16=False)
+        assert abs((lp - lm) / (2 * eps) - g[i]) <= 1e-6 + 1e-5 * abs(g[i]), i
+
+
+def test_mlp_reference_bf16_rounding():
+    from oracle import mlp_ref
+    x = np.array([1.0, 1.00390625, 1.005, 3.14159265, -2.71828, 1e-3, 0.0])
+    r = mlp_ref.bf16_round(x)
+    # BF16 keeps 8 significant bits: 1 + 2^-8 is exactly halfway and rounds to even
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0078125 and r[3] == 3.140625
+    assert r[4] == -2.71875 and r[6] == 0.0
