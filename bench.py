@@ -128,7 +128,7 @@ def ev_time(fn, reps, warmup, stream):
     return float(sorted(times)[len(times) // 2])
 
 
-def bench_batch(ctx, T, gg, oracle, reps):
+def bench_batch(ctx, T, gg, reps):
     """4,096 core+tail graphs: one autotuned, HIP-graph-captured launch sequence
     (graphs/s), against the same AC-6 called once per graph and against the
     disjoint union trimmed as one graph."""
@@ -160,16 +160,8 @@ def bench_batch(ctx, T, gg, oracle, reps):
         ms_b = ev_time(lambda: run(opts_g), reps, 2, s)
         res = run(opts_g)
         s.synchronize()
-    live, nl, _ = oracle.batch_peel(b)
     got = res.bitmap_numpy()
-    parity = True
-    for gi in range(G):
-        v0, v1 = int(b.vbase[gi]), int(b.vbase[gi + 1])
-        want = oracle.bitmap(live[v0:v1])
-        if not np.array_equal(got[bb[gi]:bb[gi] + want.shape[0]], want):
-            parity = False
-            break
-    parity = parity and res.stats_dict()["n_live"] == int(nl.sum())
+    n_live_gpu = res.stats_dict()["n_live"]
     # the same AC-6, one call per graph
     per = []
     for gi in range(G):
@@ -193,15 +185,16 @@ def bench_batch(ctx, T, gg, oracle, reps):
         ms_union = ev_time(lambda: ctx.trim_csr(T.AC6, N, ro, col_u, live_bitmap=lbu,
                                                 worker_edges=we, stats=st, stream=s), reps, 1, s)
     ctx.set_timing(True)
-    return {"workload": "batch4096_coretail", "graphs": G, "sum_n": N, "sum_m": M,
+    check = {"batch": b, "bitmap_base": bb, "bitmap": got, "n_live": n_live_gpu}
+    return check, {"workload": "batch4096_coretail", "graphs": G, "sum_n": N, "sum_m": M,
             "ms": ms_b, "graphs_per_s": G / (ms_b / 1e3), "edges_per_s": M / (ms_b / 1e3),
-            "parity": bool(parity), "tuned": params,
+            "parity": None, "tuned": params,
             "per_graph_calls": {"ms": ms_each, "graphs_per_s": G / (ms_each / 1e3)},
             "union_one_graph": {"ms": ms_union, "graphs_per_s": G / (ms_union / 1e3)},
             "speedup_vs_per_graph_calls": ms_each / ms_b}
 
 
-def bench_implicit(ctx, T, gg, oracle, reps, log2n=28, samples=20000):
+def bench_implicit(ctx, T, gg, reps, log2n=28):
     """AC-6 on the hash-generated graph G = (V, POST) with n = 2^28: successors
     are generated on the fly.  Checked at full size on sampled vertices: a live
     vertex has a live successor, a removed one has none."""
@@ -225,19 +218,146 @@ def bench_implicit(ctx, T, gg, oracle, reps, log2n=28, samples=20000):
     torch.cuda.synchronize()
     stat = res.stats_dict()
     bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
-    rng = np.random.default_rng(0)
-    ok = True
-    for v in rng.integers(0, n, samples):
-        d = oracle.implicit_deg(imp, int(v))
-        succ_live = any(bits[oracle.implicit_nbr(imp, int(v), i)] for i in range(d))
-        if bool(bits[v]) != succ_live:
-            ok = False
-            break
     ctx.set_timing(True)
     m = stat["graph_edges"]
-    return {"workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
-            "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": stat["edges_total"],
-            "n_live": stat["n_live"], "fixpoint_check_on_samples": ok, "samples": samples}
+    return {"implicit": imp, "bits": bits}, {
+        "workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
+        "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": stat["edges_total"],
+        "n_live": stat["n_live"], "fixpoint_check_on_samples": None}
+
+
+def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
+    """Learned successor order: train on 16 R-MAT scale-20 graphs (seeds 1..16,
+    labels from plain AC-6), evaluate on R-MAT scale 24 (seed 0): traversed
+    edges and times of plain, learned, heuristic and random orders."""
+    import time as _t
+    import numpy as np
+    import torch
+
+    from paper_2107_12720_amd import learned
+    ctx.set_timing(False)
+    s = torch.cuda.current_stream()
+    log("learned: building 16 training graphs (R-MAT scale 20) ...")
+    train = []
+    for seed in range(1, 17):
+        g = gg.rmat(20, 16, seed=seed)
+        dg = T.DeviceGraph.upload(g)
+        indeg, src = learned.prepare(ctx, dg)
+        lab = ctx.trim_csr(T.AC6, g.n, dg.row_off, dg.col).live_bitmap
+        train.append((dg, indeg, src, lab))
+    torch.cuda.synchronize()
+    tr = learned.Trainer(ctx, seed=0, lr=5e-3)
+    t0 = _t.perf_counter()
+    losses = [tr.train_step(train, batch, seed=1) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t_train = _t.perf_counter() - t0
+    losses = [float(x) for x in losses]
+    del train
+    log("learned: evaluation graph R-MAT scale 24 ...")
+    g = gg.rmat(24, 16, seed=0)
+    dg = T.DeviceGraph.upload(g)
+    indeg, src = learned.prepare(ctx, dg)
+    P = ctx.num_workers(T.AC6)
+    lb = torch.empty((g.n + 31) // 32, dtype=torch.int32, device="cuda")
+    we = torch.empty(P, dtype=torch.int64, device="cuda")
+    st = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
+
+    def ac6(col):
+        return ctx.trim_csr(T.AC6, g.n, dg.row_off, col, live_bitmap=lb, worker_edges=we,
+                            stats=st)
+    out = {}
+    ms_plain = ev_time(lambda: ac6(dg.col), reps, 1, s)
+    res = ac6(dg.col)
+    torch.cuda.synchronize()
+    plain_bm = res.bitmap_numpy().copy()
+    t6_plain = res.stats_dict()["edges_total"]
+    live = np.unpackbits(plain_bm.view(np.uint8), bitorder="little")[:g.n].astype(bool)
+    deg = np.diff(g.row_off.astype(np.int64))
+    t6_min = int(deg[~live].sum() + live.sum())
+    col_l = [None]
+
+    def score_order():
+        col_l[0], _ = learned.learned_order(ctx, dg, indeg, src, tr.pbf)
+    ms_order = ev_time(score_order, reps, 1, s)
+    orders = {"learned": col_l[0], "heuristic_outdeg": learned.reference_order(ctx, dg, 0),
+              "random": learned.reference_order(ctx, dg, 1, seed=5)}
+    same = True
+    for name, col in orders.items():
+        ms = ev_time(lambda: ac6(col), reps, 1, s)
+        r2 = ac6(col)
+        torch.cuda.synchronize()
+        same = same and np.array_equal(r2.bitmap_numpy(), plain_bm)
+        out[name] = {"T6": r2.stats_dict()["edges_total"], "ac6_ms": ms}
+    t6l = out["learned"]["T6"]
+    ctx.set_timing(True)
+    return {"workload": "train 16x rmat20_ef16, eval rmat24_ef16", "n": g.n, "m": g.m,
+            "train_steps": steps, "samples_per_graph_step": batch, "train_s": t_train,
+            "loss_first": losses[0], "loss_last": float(np.mean(losses[-10:])),
+            "T6_plain": t6_plain, "T6_min": t6_min, "orders": out,
+            "gap_closed": (t6_plain - t6l) / max(1, t6_plain - t6_min),
+            "ac6_plain_ms": ms_plain, "score_and_order_ms": ms_order,
+            "end_to_end_learned_ms": ms_order + out["learned"]["ac6_ms"],
+            "live_set_identical": bool(same)}
+
+
+def oracle_leg(g, checks, cpu_seconds, out):
+    """CPU leg: the oracle timed on this host (cpu_baseline), and its results
+    compared with every GPU output of this run (parity flags)."""
+    import numpy as np
+
+    import oracle
+    times = []
+    r = None
+    while not times or (sum(times) < cpu_seconds and len(times) < 20):
+        t = time.perf_counter()
+        r = oracle.peel(g)
+        times.append(time.perf_counter() - t)
+    c = oracle.counts(g, r)
+    tm = float(np.mean(times))
+    out["cpu_baseline"] = {"value": g.m / tm, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                           "sample": f"full rmat22_ef16_chain100k graph, {len(times)} runs of "
+                                     f"the sequential peel, mean {tm:.3f} s",
+                           "host_cores": os.cpu_count()}
+    want_bm = oracle.bitmap(r.live)
+    a6 = checks["ac6"]
+    out["parity"] = bool(np.array_equal(a6["bitmap"], want_bm) and a6["edges"] == c.T6)
+    out["config"].update({"alpha": r.alpha, "n_live": r.n_live, "T6": c.T6, "T6min": c.T6min})
+    if "ac4" in checks:
+        b = out["baselines"]["ac4"]
+        b["parity"] = bool(np.array_equal(checks["ac4"]["bitmap"], want_bm)
+                           and checks["ac4"]["edges"] == c.T4s)
+        b.update({"T4star": c.T4s, "T4": c.T4})
+    if "ac3" in checks:
+        b = out["baselines"]["ac3"]
+        b["parity"] = bool(np.array_equal(checks["ac3"]["bitmap"], want_bm)
+                           and checks["ac3"]["edges"] == c.T3J
+                           and checks["ac3"]["rounds"] == c.rounds3)
+        b.update({"T3J": c.T3J})
+    if "depth" in out:
+        out["depth"]["alpha"] = r.alpha
+        out["depth"]["floor_ms"] = r.alpha * out["depth"]["chain_hop_us"] / 1e3
+    if "batch" in checks:
+        bc = checks["batch"]
+        b, bb = bc["batch"], bc["bitmap_base"]
+        live, nl, _ = oracle.batch_peel(b)
+        ok = bc["n_live"] == int(nl.sum())
+        for gi in range(b.G):
+            v0, v1 = int(b.vbase[gi]), int(b.vbase[gi + 1])
+            want = oracle.bitmap(live[v0:v1])
+            if not np.array_equal(bc["bitmap"][bb[gi]:bb[gi] + want.shape[0]], want):
+                ok = False
+                break
+        out["batch"]["parity"] = bool(ok)
+    if "implicit" in checks:
+        imp, bits = checks["implicit"]["implicit"], checks["implicit"]["bits"]
+        rng = np.random.default_rng(0)
+        ok = True
+        for v in rng.integers(0, imp.n, 20000):
+            d = oracle.implicit_deg(imp, int(v))
+            succ = any(bits[oracle.implicit_nbr(imp, int(v), i)] for i in range(d))
+            ok = ok and bool(bits[v]) == succ
+        out["implicit"]["fixpoint_check_on_samples"] = bool(ok)
+        out["implicit"]["samples"] = 20000
 
 
 def main():
@@ -245,11 +365,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU leg (oracle timing and the parity checks it feeds)")
     ap.add_argument("--no-baselines", action="store_true", help="skip AC-4 / AC-3 / chain runs")
     ap.add_argument("--no-ac3", action="store_true", help="skip the (slow) AC-3 baseline run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4,096-graph batch")
     ap.add_argument("--no-implicit", action="store_true", help="skip the 2^28 implicit graph")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-order section")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -281,24 +403,17 @@ def main():
     ms, ktimes, res = time_gpu(ctx, step, args.steps, args.warmup)
     st = res.stats_dict()
     value = m / (ms / 1e3)
-
-    # parity against the oracle (bit-exact bitmap, exact traversed-edge total)
-    import oracle
-    t_or = time.perf_counter()
-    r = oracle.peel(g)
-    t_or = time.perf_counter() - t_or
-    c = oracle.counts(g, r)
-    parity = bool(np.array_equal(res.bitmap_numpy(), oracle.bitmap(r.live))
-                  and st["edges_total"] == c.T6 and int(we.sum().item()) == c.T6)
-    log(f"AC-6 {ms:.3f} ms/step, {value:.3e} edges/s, parity={parity}")
+    checks = {"ac6": {"bitmap": res.bitmap_numpy().copy(), "edges": st["edges_total"]}}
+    log(f"AC-6 {ms:.3f} ms/step, {value:.3e} edges/s")
+    sweep_ok = True
 
     kavg = {k: float(np.mean(v)) for k, v in ktimes.items()}
     dom = max(kavg, key=kavg.get)
-    b_prop = prop_bytes(st, c.T6)
+    b_prop = prop_bytes(st, st["edges_total"])
     sw_checks, sw_joins, sw_cas = sweep_counts(g)
     if sw_checks != st["edges_sweep"]:
         log(f"warning: sweep checks {st['edges_sweep']} != host count {sw_checks}")
-        parity = False
+        sweep_ok = False
     b_sweep = sweep_bytes(g, sw_checks, sw_joins, sw_cas)
     algo_bytes = {"ac6_propagate": b_prop, "ac6_sweep": b_sweep,
                   "ac6_init": 8 * (n + 1) + 8 * n, "ac6_pack": 8 * n + n // 8}
@@ -311,7 +426,7 @@ def main():
                      "algorithmic_bytes": int(algo_bytes.get(k, 0)),
                      "achieved_GBs": algo_bytes.get(k, 0) / (kavg[k] / 1e3) / 1e9}
                  for k in kavg}
-    path_bytes = 8 * c.T6 + 20 * n + n // 8
+    path_bytes = 8 * st["edges_total"] + 20 * n + n // 8
 
     out = {
         "metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1,
@@ -319,9 +434,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "rmat22_ef16_chain100k", "algo": "ac6", "n": n, "m": m,
-                   "alpha": r.alpha, "n_live": r.n_live, "T6": c.T6, "T6min": c.T6min,
                    "workers": P, "block": 256, "chunk": 4096},
-        "parity": parity,
+        "parity": None, "sweep_counts_match": sweep_ok,
         "roofline": roofline,
         "breakdown": breakdown,
         "path": {"algorithmic_bytes": path_bytes,
@@ -337,52 +451,44 @@ def main():
         rc_, cc_ = T.to_device(gc.row_off), T.to_device(gc.col)
         ms_chain, _, _ = time_gpu(ctx, lambda: ctx.trim_csr(T.AC6, gc.n, rc_, cc_), 3, 1)
         hop_us = ms_chain * 1e3 / 100000
-        out["depth"] = {"alpha": r.alpha, "chain_hop_us": hop_us,
-                        "floor_ms": r.alpha * hop_us / 1e3}
+        out["depth"] = {"chain_hop_us": hop_us}
         a, b = gg.transpose(g)
         rro, rcl = T.to_device(a), T.to_device(b)
         ms4, kt4, res4 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC4, n, ro, col, rro, rcl), 3, 1)
         st4 = res4.stats_dict()
-        ok4 = bool(np.array_equal(res4.bitmap_numpy(), oracle.bitmap(r.live))
-                   and st4["edges_total"] == c.T4s)
-        log(f"AC-4 {ms4:.3f} ms, parity={ok4}")
+        checks["ac4"] = {"bitmap": res4.bitmap_numpy().copy(), "edges": st4["edges_total"]}
+        log(f"AC-4 {ms4:.3f} ms")
         out["baselines"] = {
             "ac4": {"ms": ms4, "edges_per_s": m / (ms4 / 1e3), "traversed": st4["edges_total"],
-                    "T4star": c.T4s, "T4": c.T4, "parity": ok4,
+                    "parity": None,
                     "kernels_ms": {k: float(np.mean(v)) for k, v in kt4.items()}},
             "ac6_speedup_vs_ac4": ms4 / ms,
         }
         if not args.no_ac3:
             ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC3, n, ro, col), 1, 0)
             st3 = res3.stats_dict()
-            ok3 = bool(np.array_equal(res3.bitmap_numpy(), oracle.bitmap(r.live))
-                       and st3["edges_total"] == c.T3J and st3["rounds"] == c.rounds3)
-            log(f"AC-3 {ms3:.3f} ms, parity={ok3}")
+            checks["ac3"] = {"bitmap": res3.bitmap_numpy().copy(), "edges": st3["edges_total"],
+                             "rounds": st3["rounds"]}
+            log(f"AC-3 {ms3:.3f} ms")
             out["baselines"]["ac3"] = {
                 "ms": ms3, "edges_per_s": m / (ms3 / 1e3), "traversed": st3["edges_total"],
-                "rounds": st3["rounds"], "T3J": c.T3J, "parity": ok3,
+                "rounds": st3["rounds"], "parity": None,
                 "kernels_ms": {k: float(np.mean(v)) for k, v in kt3.items()}}
             out["baselines"]["ac6_speedup_vs_ac3"] = ms3 / ms
 
     if not args.no_batch:
-        out["batch"] = bench_batch(ctx, T, gg, oracle, 10)
-        log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s parity={out['batch']['parity']}")
+        checks["batch"], out["batch"] = bench_batch(ctx, T, gg, 10)
+        log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s")
     if not args.no_implicit:
-        out["implicit"] = bench_implicit(ctx, T, gg, oracle, 3)
+        checks["implicit"], out["implicit"] = bench_implicit(ctx, T, gg, 3)
         log(f"implicit: {out['implicit']['edges_per_s']:.3e} edges/s")
+    if not args.no_learned:
+        out["learned"] = bench_learned(ctx, T, gg)
+        log(f"learned: gap closed {out['learned']['gap_closed']:.3f}")
 
     if not args.no_cpu:
-        # the oracle as it stands, single-threaded, repeated up to ~cpu_seconds
-        times = [t_or]
-        while sum(times) < args.cpu_seconds and len(times) < 20:
-            t = time.perf_counter()
-            oracle.peel(g)
-            times.append(time.perf_counter() - t)
-        tm = float(np.mean(times))
-        out["cpu_baseline"] = {"value": m / tm, "unit": "edges/s", "cores": 1, "kind": "oracle",
-                               "sample": f"full rmat22_ef16_chain100k graph, {len(times)} runs "
-                                         f"of the sequential peel, mean {tm:.3f} s",
-                               "host_cores": os.cpu_count()}
+        oracle_leg(g, checks, args.cpu_seconds, out)
+        log(f"oracle leg: parity={out['parity']}")
     print(json.dumps(out), flush=True)
     ctx.close()
 
