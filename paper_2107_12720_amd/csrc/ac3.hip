@@ -19,6 +19,7 @@
 #include <climits>
 
 #include "trim_device.h"
+#include "trim_stats.h"
 #include "trim_internal.h"
 
 namespace trim {

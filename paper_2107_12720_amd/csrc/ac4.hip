@@ -13,6 +13,7 @@
 // a lane walks the predecessors of its removed vertex eight at a time, with
 // the eight decrements in flight together), ac4_pack (bitmap from cnt > 0).
 #include "trim_device.h"
+#include "trim_stats.h"
 #include "trim_internal.h"
 
 namespace trim {

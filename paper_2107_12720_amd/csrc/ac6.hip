@@ -44,6 +44,7 @@
 //                  kHops removals in a row.  Exits when no item is pending.
 //   ac6_pack       live bitmap by wavefront ballot, live/dead counts.
 #include "trim_device.h"
+#include "trim_stats.h"
 #include "trim_internal.h"
 
 namespace trim {
@@ -75,8 +76,6 @@ __global__ void ac6_init(View g, int n, int* head, int* ctr, uint64_t* worker_ed
     if (tid < kCtrInts) ctr[tid] = 0;
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
-    if constexpr (View::kPerGraph)
-        for (int gi = tid; gi < g.G; gi += gridDim.x * blockDim.x) g.graph_edges[gi] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
         const int h = (g.end(v) == g.begin(v)) ? kDead : kEmpty;
         reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
@@ -119,10 +118,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, ui
         __syncthreads();
         if (cb >= n) break;
         const int ce = cb + chunk < n ? cb + chunk : n;
-        int hint = 0;
-        if constexpr (View::kPerGraph) hint = g.graph_of(cb);
         for (int base = cb; base < ce; base += blockDim.x) {
-            if constexpr (View::kPerGraph) hint = g.graph_from(base, hint);
             const int v = base + threadIdx.x;
             bool casualty = false;
             uint64_t mine = 0;
@@ -130,9 +126,8 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, ui
             if (v < ce) {
                 const int b = g.begin(v), e = g.end(v);
                 degsum += (uint64_t)(e - b);
-                if constexpr (View::kPerGraph) gi = g.graph_from(v, hint);
-                else gi = g.vctx(v);
                 if (b < e) {
+                    gi = g.vctx(v);
                     int p = b, w = 0;
                     for (; p < e; ++p) {
                         w = g.target(v, p, gi);
@@ -149,7 +144,6 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, ui
                 }
             }
             edges += mine;
-            if constexpr (View::kPerGraph) charge_graphs(g.graph_edges, gi, mine, v < ce);
             const uint64_t mask = ballot(casualty);
             if (mask) {
                 int wbase = 0;
@@ -188,14 +182,11 @@ __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, 
             complete_mem();
             if (cas_dev(slot, h, u)) {
                 edges += (uint64_t)(p - p0 + 1);
-                if constexpr (View::kPerGraph) add_dev(g.graph_edges + ctx, (uint64_t)(p - p0 + 1));
                 return true;
             }
         }
     }
     edges += (uint64_t)(e - p0);
-    if constexpr (View::kPerGraph)
-        if (e > p0) add_dev(g.graph_edges + ctx, (uint64_t)(e - p0));
     return false;
 }
 
@@ -325,6 +316,35 @@ __global__ void ac6_pack_batch(const int* head, const int64_t* vbase, const int6
     if (threadIdx.x == 0) part[kPartLive * kPartStride + blockIdx.x] = live_cnt;
 }
 
+// base[v] = first vertex of v's graph (one block per graph).
+__global__ void batch_bases(const int64_t* vbase, int G, int* base) {
+    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        const int v0 = (int)vbase[gi], v1 = (int)vbase[gi + 1];
+        for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) base[v] = v0;
+    }
+}
+
+// Traversed edges of each graph, read off the final state: a removed vertex
+// checked all its successors, a live one every position up to its support
+// (its cursor).  AC-6's total does not depend on the schedule, so this equals
+// the number of checks the run made.
+__global__ void batch_graph_edges(const int* head, const uint64_t* rec, const int* row_off,
+                                  const int64_t* vbase, int G, uint64_t* graph_edges) {
+    __shared__ uint64_t red[16];
+    for (int gi = blockIdx.x; gi < G; gi += gridDim.x) {
+        const int v0 = (int)vbase[gi], v1 = (int)vbase[gi + 1];
+        uint64_t s = 0;
+        for (int v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+            const int b = row_off[v], e = row_off[v + 1];
+            if (head[2 * v] == kDead) s += (uint64_t)(e - b);
+            else s += (uint64_t)(rec_cursor(rec[v]) - b + 1);
+        }
+        s = block_sum(s, red);
+        if (threadIdx.x == 0) graph_edges[gi] = s;
+        __syncthreads();
+    }
+}
+
 inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
     long long b = (n + block - 1) / block;
     if (b < 1) b = 1;
@@ -397,8 +417,18 @@ hipError_t ac6_batch(int G, const int64_t* vbase, const int32_t* row_off, const 
                      int64_t total_n, const int64_t* bitmap_base, const Work& w,
                      const LaunchCfg& lc, uint32_t* bitmaps, uint64_t* graph_edges,
                      trim_stats_t* stats) {
-    BatchView v{row_off, col, vbase, graph_edges, G};
-    return ac6_run(v, (int)total_n, w, lc, bitmaps, w.wedges, stats, vbase, bitmap_base, G);
+    const int gb = G < 16384 ? G : 16384;
+    {
+        Timed t(lc, "batch_bases");
+        hipLaunchKernelGGL(batch_bases, dim3(gb), dim3(256), 0, lc.stream, vbase, G, w.d);
+    }
+    BatchView v{row_off, col, w.d};
+    hipError_t e = ac6_run(v, (int)total_n, w, lc, bitmaps, w.wedges, stats, vbase, bitmap_base, G);
+    if (e != hipSuccess) return e;
+    Timed t(lc, "batch_graph_edges");
+    hipLaunchKernelGGL(batch_graph_edges, dim3(gb), dim3(256), 0, lc.stream, w.a, w.b, row_off,
+                       vbase, G, graph_edges);
+    return hipGetLastError();
 }
 
 int ac6_max_workers_per_cu(int) {

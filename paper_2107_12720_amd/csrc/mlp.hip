@@ -306,84 +306,6 @@ __global__ __launch_bounds__(256) void mlp_score(Graph g, const short* p, float*
     }
 }
 
-// src[e] = u for every edge e of u.
-__global__ void edge_sources(const int* row_off, int n, int* src) {
-    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        for (int e = row_off[v]; e < row_off[v + 1]; ++e) src[e] = v;
-}
-
-__global__ void in_degrees(const int* col, long long m, int* indeg) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < m;
-         e += (long long)gridDim.x * blockDim.x)
-        atomicAdd(indeg + col[e], 1);
-}
-
-__global__ void zero_ints(int* a, long long k) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < k;
-         i += (long long)gridDim.x * blockDim.x)
-        a[i] = 0;
-}
-
-// Keys for the reference orders: 0 = outdeg(w) (larger first), 1 = a hash of
-// (seed, e) (a random order).
-__global__ void edge_keys(const int* row_off, const int* col, long long m, int kind, uint64_t seed,
-                          float* key) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < m;
-         e += (long long)gridDim.x * blockDim.x) {
-        if (kind == 0) {
-            const int w = col[e];
-            key[e] = log1pf((float)(row_off[w + 1] - row_off[w]));
-        } else {
-            key[e] = (float)(mix64(seed ^ (uint64_t)e) >> 40) * (1.f / 16777216.f);
-        }
-    }
-}
-
-constexpr int kBuckets = 16;
-
-// Reorder every adjacency list by key, larger first, in kBuckets levels
-// between lo and hi; stable within a level (a counting sort per vertex).  One
-// wavefront per vertex.
-__global__ void order_by_key(const int* row_off, const int* col, int n, const float* key, float lo,
-                             float hi, int* col_out) {
-    const int waves = (gridDim.x * blockDim.x) / kWave;
-    const float scale = hi > lo ? (float)kBuckets / (hi - lo) : 0.f;
-    for (int v = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; v < n; v += waves) {
-        const int b = row_off[v], e = row_off[v + 1];
-        if (e - b <= 1) {
-            if (e - b == 1 && lane_id() == 0) col_out[b] = col[b];
-            continue;
-        }
-        int cnt[kBuckets];
-        for (int k = 0; k < kBuckets; ++k) cnt[k] = 0;
-        auto bucket_of = [&](int p) {
-            int k = (int)((hi - key[p]) * scale);
-            return k < 0 ? 0 : (k >= kBuckets ? kBuckets - 1 : k);
-        };
-        for (int base = b; base < e; base += kWave) {
-            const int p = base + lane_id();
-            const int k = p < e ? bucket_of(p) : -1;
-            for (int q = 0; q < kBuckets; ++q) cnt[q] += popc(ballot(k == q));
-        }
-        int off[kBuckets];
-        int run = b;
-        for (int q = 0; q < kBuckets; ++q) {
-            off[q] = run;
-            run += cnt[q];
-        }
-        for (int base = b; base < e; base += kWave) {
-            const int p = base + lane_id();
-            const int k = p < e ? bucket_of(p) : -1;
-            const int c = p < e ? col[p] : 0;
-            for (int q = 0; q < kBuckets; ++q) {
-                const uint64_t mk = ballot(k == q);
-                if (k == q) col_out[off[q] + popc(mk & lanes_below())] = c;
-                off[q] += popc(mk);
-            }
-        }
-    }
-}
-
 inline int grid_for(long long n, int block, int max_blocks) {
     long long b = (n + block - 1) / block;
     if (b < 1) b = 1;
@@ -392,19 +314,6 @@ inline int grid_for(long long n, int block, int max_blocks) {
 }
 
 }  // namespace
-
-hipError_t mlp_prepare(const int* row_off, const int* col, int n, long long m, int* indeg,
-                       int* src, hipStream_t s) {
-    hipLaunchKernelGGL(zero_ints, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, indeg,
-                       (long long)n);
-    if (m > 0) {
-        hipLaunchKernelGGL(in_degrees, dim3(grid_for(m, 256, 16384)), dim3(256), 0, s, col, m,
-                           indeg);
-        hipLaunchKernelGGL(edge_sources, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, row_off,
-                           n, src);
-    }
-    return hipGetLastError();
-}
 
 hipError_t mlp_grad_launch(const int* row_off, const int* col, const int* indeg, const int* src,
                            long long m, const uint32_t* live, const short* pbf,
@@ -432,22 +341,6 @@ hipError_t mlp_score_launch(const int* row_off, const int* col, const int* indeg
     if (m > 0)
         hipLaunchKernelGGL(mlp_score, dim3(grid_for((m + 31) / 32, 4, cus * 16)), dim3(256), 0, s,
                            g, pbf, score);
-    return hipGetLastError();
-}
-
-hipError_t edge_keys_launch(const int* row_off, const int* col, long long m, int kind,
-                            uint64_t seed, float* key, hipStream_t s) {
-    if (m > 0)
-        hipLaunchKernelGGL(edge_keys, dim3(grid_for(m, 256, 16384)), dim3(256), 0, s, row_off,
-                           col, m, kind, seed, key);
-    return hipGetLastError();
-}
-
-hipError_t order_launch(const int* row_off, const int* col, int n, const float* key, float lo,
-                        float hi, int* col_out, int cus, hipStream_t s) {
-    if (n > 0)
-        hipLaunchKernelGGL(order_by_key, dim3(grid_for(n, 4, cus * 16)), dim3(256), 0, s, row_off,
-                           col, n, key, lo, hi, col_out);
     return hipGetLastError();
 }
 

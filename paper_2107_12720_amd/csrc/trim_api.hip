@@ -16,9 +16,15 @@ struct trim_ctx {
     int occ6 = 0, occ4 = 0, occ3 = 0;   // resident workgroups per CU
     // captured launch sequence of trim_batch and the arguments it was made for
     hipGraphExec_t gexec = nullptr;
-    uint64_t gkey[20] = {};
+    uint64_t gkey[23] = {};
     bool timing = false;
     trim::Timer timer;
+    // tile tables of the preprocessing and reordering kernels
+    int* tiles = nullptr;
+    long long cap_tiles = 0;
+    // per-XCD in-degree copies of trim_mlp_prepare
+    int* copies = nullptr;
+    long long cap_copies = 0;
 };
 
 namespace {
@@ -71,6 +77,22 @@ int ensure(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n = cap;
+    return TRIM_OK;
+}
+
+int ensure_tiles(trim_ctx* c, long long m) {
+    const long long need = trim::tile_scratch_ints(m > 0 ? m : 1);
+    if (need <= c->cap_tiles) return TRIM_OK;
+    (void)hipFree(c->tiles);
+    c->tiles = nullptr;
+    c->cap_tiles = 0;
+    const long long cap = need + need / 8 + 64;
+    if (hipMalloc((void**)&c->tiles, (size_t)cap * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        c->tiles = nullptr;
+        return fail(TRIM_E_NOMEM, "cannot allocate tile tables for %lld edges", m);
+    }
+    c->cap_tiles = cap;
     return TRIM_OK;
 }
 
@@ -189,6 +211,8 @@ int trim_ctx_destroy(trim_ctx* c) {
     (void)hipFree(c->w.ctr);
     (void)hipFree(c->w.wedges);
     (void)hipFree(c->w.part);
+    (void)hipFree(c->tiles);
+    (void)hipFree(c->copies);
     delete c;
     return TRIM_OK;
 }
@@ -292,12 +316,13 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
         return TRIM_OK;
     }
     if (!stream) return fail(TRIM_E_INVAL, "opts.graph needs a non-NULL stream");
-    const uint64_t key[20] = {(uint64_t)G, (uint64_t)vbase, (uint64_t)row_off, (uint64_t)col,
+    const uint64_t key[23] = {(uint64_t)G, (uint64_t)vbase, (uint64_t)row_off, (uint64_t)col,
                               (uint64_t)total_n, (uint64_t)total_m, (uint64_t)bitmap_base,
                               (uint64_t)live_bitmaps, (uint64_t)graph_edges, (uint64_t)stats,
                               (uint64_t)stream, (uint64_t)lc.block, (uint64_t)lc.chunk,
                               (uint64_t)lc.workers, (uint64_t)c->w.a, (uint64_t)c->w.b,
-                              (uint64_t)c->w.c, (uint64_t)c->w.ctr, (uint64_t)c->w.wedges, 1};
+                              (uint64_t)c->w.c, (uint64_t)c->w.d, (uint64_t)c->w.q,
+                              (uint64_t)c->w.part, (uint64_t)c->w.ctr, (uint64_t)c->w.wedges, 1};
     if (!c->gexec || memcmp(key, c->gkey, sizeof key) != 0) {
         if (c->gexec) {
             (void)hipGraphExecDestroy(c->gexec);
@@ -344,8 +369,26 @@ int trim_mlp_prepare(trim_ctx* c, const trim_csr_t* g, int32_t* indeg, int32_t* 
     int rc = check_graph(c, g, "trim_mlp_prepare");
     if (rc) return rc;
     if (!indeg || (g->m > 0 && !src)) return fail(TRIM_E_INVAL, "trim_mlp_prepare: NULL output");
-    return launched(trim::mlp_prepare(g->row_off, g->col, g->n, g->m, indeg, src,
-                                      (hipStream_t)stream));
+    if ((rc = ensure_tiles(c, g->m))) return rc;
+    int* copies = nullptr;
+    if (g->n <= trim::kXcdCopiesMaxN) {
+        const long long need = (long long)trim::kXcdCopies * (g->n > 0 ? g->n : 1);
+        if (need > c->cap_copies) {
+            (void)hipFree(c->copies);
+            c->copies = nullptr;
+            c->cap_copies = 0;
+            if (hipMalloc((void**)&c->copies, (size_t)need * 4) != hipSuccess) {
+                (void)hipGetLastError();
+                c->copies = nullptr;
+                return fail(TRIM_E_NOMEM, "cannot allocate in-degree copies for %d vertices",
+                            g->n);
+            }
+            c->cap_copies = need;
+        }
+        copies = c->copies;
+    }
+    return launched(trim::mlp_prepare(g->row_off, g->col, g->n, g->m, indeg, src, c->tiles,
+                                      copies, (hipStream_t)stream));
 }
 
 int trim_mlp_grad(trim_ctx* c, const trim_csr_t* g, const int32_t* indeg, const int32_t* src,
@@ -403,8 +446,10 @@ int trim_order_by_key(trim_ctx* c, const trim_csr_t* g, const float* keys, float
     if (rc) return rc;
     if (g->m > 0 && (!keys || !col_out)) return fail(TRIM_E_INVAL, "trim_order_by_key: NULL");
     if (col_out == g->col) return fail(TRIM_E_INVAL, "trim_order_by_key: col_out aliases col");
-    return launched(trim::order_launch(g->row_off, g->col, g->n, keys, lo, hi, col_out, c->cus,
-                                       (hipStream_t)stream));
+    if ((rc = ensure_tiles(c, g->m))) return rc;
+    const long long T = (g->m + trim::kTileE - 1) / trim::kTileE;
+    return launched(trim::order_launch(g->row_off, g->col, g->n, g->m, keys, lo, hi, col_out,
+                                       c->tiles, c->tiles + 3 * T, (hipStream_t)stream));
 }
 
 int trim_ctx_set_timing(trim_ctx* c, int enable) {

@@ -332,75 +332,11 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* scratch) {
     return s;
 }
 
-// ---------------------------------------------------- outputs and statistics
-// Per-block partial sums live in `part` (kPartStride words per quantity); one
-// finalize block reduces them, so no word is updated by every block.
-
-namespace {   // kernels below get a private copy in every translation unit
-
-// Live bitmap (bit v%32 of word v/32) from a per-vertex predicate, by ballot.
-template <class IsLive>
-__global__ void pack_bitmap(IsLive is_live, int n, uint32_t* bitmap, uint64_t* part) {
-    __shared__ uint64_t red[16];
-    const int nwords = (n + 31) >> 5;
-    const int waves = (gridDim.x * blockDim.x) / kWave;
-    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    uint64_t live_cnt = 0;
-    for (int base = wid * kWave; base < n; base += waves * kWave) {
-        const int v = base + lane_id();
-        const uint64_t b = ballot(v < n && is_live(v));
-        if (lane_id() == 0) {
-            const int w = base >> 5;
-            bitmap[w] = (uint32_t)b;
-            if (w + 1 < nwords) bitmap[w + 1] = (uint32_t)(b >> 32);
-            live_cnt += (uint64_t)popc(b);
-        }
-    }
-    live_cnt = block_sum(live_cnt, red);
-    if (threadIdx.x == 0) part[kPartLive * kPartStride + blockIdx.x] = live_cnt;
-}
-
-__device__ __forceinline__ uint64_t sum_range(const uint64_t* a, int k, uint64_t* red) {
-    uint64_t s = 0;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) s += a[i];
-    return block_sum(s, red);
-}
-
-// One block: reduce the partials into *stats.  n_sweep / n_prop = number of
-// sweep / propagation partials (0 when the algorithm has none).
-__global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack,
-                               const uint64_t* worker_edges, const uint64_t* part, const int* ctr,
-                               trim_stats_t* stats, int empty_rounds) {
-    __shared__ uint64_t red[16];
-    const uint64_t edges = sum_range(worker_edges, P, red);
-    const uint64_t live = sum_range(part + kPartLive * kPartStride, n_pack, red);
-    const uint64_t sweep = sum_range(part + kPartSweep * kPartStride, n_sweep, red);
-    const uint64_t closes = sum_range(part + kPartCloses * kPartStride, n_prop, red);
-    const uint64_t joins = sum_range(part + kPartJoins * kPartStride, n_prop, red);
-    const uint64_t visited = sum_range(part + kPartVisited * kPartStride, n_prop, red);
-    const uint64_t degsum = sum_range(part + kPartDeg * kPartStride, n_sweep, red);
-    if (threadIdx.x == 0) {
-        stats->edges_total = edges;
-        stats->n_live = live;
-        stats->n_dead = (uint64_t)n - live;
-        stats->queued = (uint64_t)ctr[kQTail];
-        stats->edges_sweep = sweep;
-        stats->closes = closes;
-        stats->joins = joins;
-        stats->visited = visited;
-        stats->graph_edges = degsum;
-        if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
-    }
-}
-
-}  // namespace
-
 // ------------------------------------------------------------ graph views
 // A view gives, for vertex v: the cursor range [begin(v), end(v)) and the
 // target of cursor position p.  `vctx` carries a per-vertex value the view
-// needs (the graph's vertex base for packed batches).
+// needs (the first vertex of v's graph for packed batches).
 struct ExplicitView {
-    static constexpr bool kPerGraph = false;
     const int* row_off;
     const int* col;
     __device__ __forceinline__ int vctx(int) const { return 0; }
@@ -421,7 +357,6 @@ constexpr uint64_t kTagNbr = 0x4E42520000000000ull;
 
 // Hash-generated graph: no stored edges; cursor positions are successor indices.
 struct ImplicitView {
-    static constexpr bool kPerGraph = false;
     uint64_t seed;
     uint64_t zero_thr;
     const uint64_t* table;   // 256 thresholds, normally staged in LDS
@@ -446,48 +381,16 @@ struct ImplicitView {
     }
 };
 
-// Packed batch: graph-local targets shifted by the graph's first vertex.  The
-// per-vertex value is the graph index; traversed edges are charged per graph.
+// Packed batch: graph-local targets shifted by the first vertex of the
+// source's graph, held per vertex in `base` (filled once per call).
 struct BatchView {
-    static constexpr bool kPerGraph = true;
     const int* row_off;
     const int* col;
-    const int64_t* vbase;      // G+1 entries
-    uint64_t* graph_edges;     // G entries
-    int G;
-    __device__ __forceinline__ int graph_of(int v) const {
-        int lo = 0, hi = G - 1;           // largest g with vbase[g] <= v
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (vbase[mid] <= v) lo = mid; else hi = mid - 1;
-        }
-        return lo;
-    }
-    // graph of v >= the first vertex of graph `hint`
-    __device__ __forceinline__ int graph_from(int v, int hint) const {
-        while (hint + 1 < G && vbase[hint + 1] <= v) ++hint;
-        return hint;
-    }
-    __device__ __forceinline__ int vctx(int v) const { return graph_of(v); }
+    const int* base;
+    __device__ __forceinline__ int vctx(int v) const { return base[v]; }
     __device__ __forceinline__ int begin(int v) const { return row_off[v]; }
     __device__ __forceinline__ int end(int v) const { return row_off[v + 1]; }
-    __device__ __forceinline__ int target(int, int p, int gi) const {
-        return (int)vbase[gi] + col[p];
-    }
+    __device__ __forceinline__ int target(int, int p, int b) const { return b + col[p]; }
 };
-
-// Sum `val` of the lanes with `has` into ge[gi], one atomic per distinct gi.
-__device__ __forceinline__ void charge_graphs(uint64_t* ge, int gi, uint64_t val, bool has) {
-    uint64_t rem = ballot(has && val != 0);
-    while (rem) {
-        const int leader = __ffsll((long long)rem) - 1;
-        const int gl = __shfl(gi, leader);
-        const bool mine = has && val != 0 && gi == gl;
-        const uint64_t mask = ballot(mine);
-        const uint64_t s = wave_sum(mine ? val : 0);
-        if (lane_id() == leader) add_dev(ge + gl, s);
-        rem &= ~mask;
-    }
-}
 
 }  // namespace trim

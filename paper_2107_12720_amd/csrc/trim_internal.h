@@ -106,8 +106,19 @@ hipError_t ac3_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg
 int ac3_max_workers_per_cu(int block);
 
 // ------------------------------------------------------------ learned order
+// Edge-parallel tiles of the preprocessing and reordering kernels: the
+// scratch they need is tile_scratch_ints(m) ints.
+constexpr int kTileE = 4096;
+inline long long tile_scratch_ints(long long m) {
+    const long long T = (m + kTileE - 1) / kTileE;
+    const long long B = (T + 1 + 63) / 64;   // chunks of 64 scan rows
+    return 3 * T + (T + 1) * 16 + B * 16;
+}
+// Per-XCD in-degree copies (kXcdCopies * n ints) are used up to this n.
+constexpr int kXcdCopies = 8;
+constexpr int kXcdCopiesMaxN = 1 << 26;
 hipError_t mlp_prepare(const int* row_off, const int* col, int n, long long m, int* indeg,
-                       int* src, hipStream_t s);
+                       int* src, int* tinfo, int* copies, hipStream_t s);
 hipError_t mlp_grad_launch(const int* row_off, const int* col, const int* indeg, const int* src,
                            long long m, const uint32_t* live, const short* pbf,
                            const long long* ids, long long count, uint64_t seed, int step,
@@ -118,8 +129,9 @@ hipError_t mlp_score_launch(const int* row_off, const int* col, const int* indeg
                             long long m, const short* pbf, float* score, int cus, hipStream_t s);
 hipError_t edge_keys_launch(const int* row_off, const int* col, long long m, int kind,
                             uint64_t seed, float* key, hipStream_t s);
-hipError_t order_launch(const int* row_off, const int* col, int n, const float* key, float lo,
-                        float hi, int* col_out, int cus, hipStream_t s);
+hipError_t order_launch(const int* row_off, const int* col, int n, long long m, const float* key,
+                        float lo, float hi, int* col_out, int* tinfo, int* tcnt,
+                        hipStream_t s);
 
 // ------------------------------------------------------------ validation
 hipError_t validate_csr(const trim_csr_t& g, const Work& w, hipStream_t s);

@@ -71,15 +71,43 @@ def test_gradient_vs_fp64_reference(ctx):
             assert err <= 1e-2 * np.max(np.abs(b)) + 1e-7, (k, err, np.max(np.abs(b)))
 
 
-def test_order_is_stable_bucketed_permutation(ctx):
+def hub_graph():
+    """Random graph plus lists longer than one wavefront's share (2,048
+    entries): a hub of 50,000 successors, one of exactly 2,049, one of 2,048,
+    and a vertex with no successors between them."""
+    rng = np.random.default_rng(7)
+    n = 60000
+    s0, d0 = rng.integers(0, n, 200000), rng.integers(0, n, 200000)
+    keep = ~np.isin(s0, (3, 10, 11, 12))
+    src, dst = [s0[keep]], [d0[keep]]
+    for v, d in ((3, 50000), (10, 2049), (12, 2048)):
+        src.append(np.full(d, v))
+        dst.append(rng.integers(0, n, d))
+    return gg.from_edges(n, np.concatenate(src), np.concatenate(dst))
+
+
+def exact_tiles_graph():
+    """m = 3 x 4,096 exactly, the last vertex's list of 5,000 entries ending
+    at m, and vertices 0..99 without successors."""
+    rng = np.random.default_rng(8)
+    n = 1000
+    s = np.concatenate([rng.integers(100, n - 1, 3 * 4096 - 5000), np.full(5000, n - 1)])
+    return gg.from_edges(n, s, rng.integers(0, n, s.shape[0]))
+
+
+@pytest.mark.parametrize("which", ["rmat13", "hubs", "exact_tiles"])
+def test_order_is_stable_bucketed_permutation(ctx, which):
     import torch
-    import paper_2107_12720_amd as T
-    g = gg.rmat(13, 16, seed=9)
+    from paper_2107_12720_amd import learned
+    g = {"rmat13": lambda: gg.rmat(13, 16, seed=9), "hubs": hub_graph,
+         "exact_tiles": exact_tiles_graph}[which]()
+    say(f"  {which}: n={g.n} m={g.m} max deg={int(np.diff(g.row_off).max())}")
     dg = device_graph(g)
     keys = torch.empty(g.m, dtype=torch.float32, device="cuda")
     ctx.edge_keys(dg, 1, keys, seed=5)
     out = torch.empty_like(dg.col)
     ctx.order_by_key(dg, keys, 0.0, 1.0, out)
+    indeg, src_d = learned.prepare(ctx, dg)
     torch.cuda.synchronize()
     k = keys.cpu().numpy()
     got = out.cpu().numpy()
@@ -88,6 +116,8 @@ def test_order_is_stable_bucketed_permutation(ctx):
     src = np.repeat(np.arange(g.n), np.diff(g.row_off))
     order = np.lexsort((np.arange(g.m), bucket, src))     # stable by (src, bucket)
     assert np.array_equal(got, g.col[order])
+    assert np.array_equal(src_d.cpu().numpy()[:g.m], src)
+    assert np.array_equal(indeg.cpu().numpy()[:g.n], np.bincount(g.col, minlength=g.n))
 
 
 def test_training_lowers_loss_and_order_keeps_live_set(ctx):
