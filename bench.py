@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edges/s + graphs/s: batched/learned-order AC-6 vs plain AC-6, bit-exact live set"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("ac6.hip", "ac4.hip", "ac3.hip", "trim_device.h", "trim_api.hip")
+KERNEL_SOURCES = ("ac6.hip", "ac4.hip", "ac3.hip", "trim_device.h", "trim_stats.h",
+                  "trim_internal.h", "trim_api.hip")
 
 
 def log(*a):
@@ -226,6 +227,44 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
         "n_live": stat["n_live"], "fixpoint_check_on_samples": None}
 
 
+def bench_explicit26(ctx, T, gg, reps):
+    """AC-6 on the explicit R-MAT scale-26 graph (edge factor 16, about 1.07e9
+    edges, no planted chain): time per trim, kernel breakdown and each kernel's
+    algorithmic bytes.  Full oracle parity at this size is a GPU test; here the
+    fixpoint property is checked on sampled vertices in the CPU leg."""
+    import numpy as np
+    import torch
+    log("explicit: generating R-MAT scale 26 ...")
+    g = gg.config2_explicit()
+    n, m = g.n, g.m
+    ro, col = T.to_device(g.row_off), T.to_device(g.col)
+    P = ctx.num_workers(T.AC6)
+    lb = torch.empty((n + 31) // 32, dtype=torch.int32, device="cuda")
+    we = torch.empty(P, dtype=torch.int64, device="cuda")
+    st_t = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
+    ms, ktimes, res = time_gpu(ctx, lambda: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=lb,
+                                                         worker_edges=we, stats=st_t), reps, 1)
+    st = res.stats_dict()
+    kavg = {k: float(np.mean(v)) for k, v in ktimes.items()}
+    sweep_joins = st["visited"] - st["joins"] + st["n_live"]
+    algo = {"ac6_sweep": 4 * (n + 1) + 8 * st["edges_sweep"] + 16 * sweep_joins,
+            "ac6_propagate": prop_bytes(st, st["edges_total"]),
+            "ac6_init": 8 * (n + 1) + 8 * n, "ac6_pack": 8 * n + n // 8}
+    kern = {k: {"avg_ms": kavg[k], "algorithmic_bytes": int(algo.get(k, 0)),
+                "achieved_GBs": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9,
+                "frac": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9 / HBM_PEAK_GBS} for k in kavg}
+    dom = max(kavg, key=kavg.get)
+    bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
+    path_bytes = 8 * st["edges_total"] + 20 * n + n // 8
+    out = {"workload": "rmat26_ef16", "n": n, "m": m, "ms": ms, "edges_per_s": m / (ms / 1e3),
+           "T6": st["edges_total"], "n_live": st["n_live"], "kernels": kern, "dominant": dom,
+           "path": {"algorithmic_bytes": path_bytes, "GBs": path_bytes / (ms / 1e3) / 1e9,
+                    "frac": path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+           "fixpoint_check_on_samples": None, "parity": "full oracle parity: GPU test"}
+    del ro, col
+    return {"graph": g, "bits": bits}, out
+
+
 def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
     """Learned successor order: train on 16 R-MAT scale-20 graphs (seeds 1..16,
     labels from plain AC-6), evaluate on R-MAT scale 24 (seed 0): traversed
@@ -348,6 +387,15 @@ def oracle_leg(g, checks, cpu_seconds, out):
                 ok = False
                 break
         out["batch"]["parity"] = bool(ok)
+    if "explicit26" in checks:
+        g26, bits = checks["explicit26"]["graph"], checks["explicit26"]["bits"]
+        rng = np.random.default_rng(0)
+        ok = True
+        for v in rng.integers(0, g26.n, 20000):
+            succ = g26.col[g26.row_off[v]:g26.row_off[v + 1]]
+            ok = ok and bool(bits[v]) == bool(bits[succ].any())
+        out["explicit26"]["fixpoint_check_on_samples"] = bool(ok)
+        out["explicit26"]["samples"] = 20000
     if "implicit" in checks:
         imp, bits = checks["implicit"]["implicit"], checks["implicit"]["bits"]
         rng = np.random.default_rng(0)
@@ -371,8 +419,13 @@ def main():
     ap.add_argument("--no-ac3", action="store_true", help="skip the (slow) AC-3 baseline run")
     ap.add_argument("--no-batch", action="store_true", help="skip the 4,096-graph batch")
     ap.add_argument("--no-implicit", action="store_true", help="skip the 2^28 implicit graph")
+    ap.add_argument("--no-explicit26", action="store_true",
+                    help="skip the explicit R-MAT scale-26 graph")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-order section")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (the known-size "
+                         "kernel that scales the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs "
@@ -381,6 +434,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}), flush=True)
+        return
 
     import graphgen as gg
     import paper_2107_12720_amd as T
@@ -479,6 +542,9 @@ def main():
     if not args.no_batch:
         checks["batch"], out["batch"] = bench_batch(ctx, T, gg, 10)
         log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s")
+    if not args.no_explicit26:
+        checks["explicit26"], out["explicit26"] = bench_explicit26(ctx, T, gg, 3)
+        log(f"explicit26: {out['explicit26']['edges_per_s']:.3e} edges/s")
     if not args.no_implicit:
         checks["implicit"], out["implicit"] = bench_implicit(ctx, T, gg, 3)
         log(f"implicit: {out['implicit']['edges_per_s']:.3e} edges/s")
