@@ -220,39 +220,36 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
             const uint32_t kind = item_kind(item);
             if (kind != kWalkMore) {
                 // Close x, then follow S_last: its members have no successor left,
-                // so each is removed at once.  One step = two list-head exchanges
-                // plus, for an S_last member, the load of its list link -- all in
-                // flight together, one round trip.
-                int c = x;
+                // so each is removed at once.  One step = one exchange of both
+                // list heads plus, for an S_last member, the load of its list
+                // link -- both in flight together, one round trip.
+                // The next step's memory operations are issued before this
+                // step's pushes, so the LDS queue work overlaps the round trip.
                 bool member = kind == kCloseLast;
+                uint64_t rr = member ? ld_dev(rec + x) : 0;
+                int2 ab = xchg2_dev(head + 2 * x, kDead, kDead);   // S_more(x), S_last(x)
+                int fill = 0;   // ring fill read after the previous step's pushes
                 for (int hop = 0;; ++hop) {
                     closes += 1;
-                    // c is dying and never joins a list again, so rec[c] is stable
-                    const int sib = member ? rec_next(ld_dev(rec + c)) : -1;
-                    const int a = xchg_dev(head + 2 * c, kDead);      // S_more(c)
-                    const int b = xchg_dev(head + 2 * c + 1, kDead);  // S_last(c)
-                    if (a >= 0) wq.push1(make_item(kWalkMore, a));
+                    // a dying vertex never joins a list again, so its record is stable
+                    const int sib = member ? rec_next(rr) : -1;
+                    const int a = ab.x, b = ab.y;
                     // depth first: into S_last(c) if it has members, else on to
                     // the next member of the list c was in
-                    int next;
-                    if (b >= 0) {
-                        visited += 1;
-                        if (sib >= 0) {
-                            visited += 1;
-                            wq.push1(make_item(kCloseLast, sib));
-                        }
-                        next = b;
-                    } else if (sib >= 0) {
-                        visited += 1;
-                        next = sib;
-                    } else {
+                    const int next = b >= 0 ? b : sib;
+                    visited += (b >= 0) + (sib >= 0);
+                    const bool go = next >= 0 && hop + 1 < kHops && fill <= kLocalQ - 256;
+                    if (go) {
+                        rr = ld_dev(rec + next);
+                        ab = xchg2_dev(head + 2 * next, kDead, kDead);
+                    }
+                    if (a >= 0) wq.push1(make_item(kWalkMore, a));
+                    if (b >= 0 && sib >= 0) wq.push1(make_item(kCloseLast, sib));
+                    fill = wq.fill();
+                    if (!go) {
+                        if (next >= 0) keep = make_item(kCloseLast, next);
                         break;
                     }
-                    if (hop + 1 == kHops || wq.fill() > kLocalQ - 64) {
-                        keep = make_item(kCloseLast, next);
-                        break;
-                    }
-                    c = next;
                     member = true;
                 }
             } else {

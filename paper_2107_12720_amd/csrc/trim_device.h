@@ -54,6 +54,14 @@ __device__ __forceinline__ int xchg_dev(int* p, int v) {
     return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // On failure `expected` receives the current value.
+// Exchange of an aligned pair of ints as one 8-byte atomic; returns the old
+// pair (x = p[0], y = p[1]).
+__device__ __forceinline__ int2 xchg2_dev(int* p, int v0, int v1) {
+    const uint64_t v = ((uint64_t)(uint32_t)v1 << 32) | (uint32_t)v0;
+    const uint64_t old = __hip_atomic_exchange(reinterpret_cast<uint64_t*>(p), v,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int2((int)(uint32_t)old, (int)(uint32_t)(old >> 32));
+}
 __device__ __forceinline__ bool cas_dev(int* p, int& expected, int desired) {
     return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -336,13 +344,16 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* scratch) {
 // A view gives, for vertex v: the cursor range [begin(v), end(v)) and the
 // target of cursor position p.  `vctx` carries a per-vertex value the view
 // needs (the first vertex of v's graph for packed batches).
+// The CSR arrays are read with non-temporal loads: they are streamed once by
+// the first sweep, and caching them would evict the list heads and records
+// that the propagation keeps revisiting.
 struct ExplicitView {
     const int* row_off;
     const int* col;
     __device__ __forceinline__ int vctx(int) const { return 0; }
-    __device__ __forceinline__ int begin(int v) const { return row_off[v]; }
-    __device__ __forceinline__ int end(int v) const { return row_off[v + 1]; }
-    __device__ __forceinline__ int target(int, int p, int) const { return col[p]; }
+    __device__ __forceinline__ int begin(int v) const { return __builtin_nontemporal_load(row_off + v); }
+    __device__ __forceinline__ int end(int v) const { return __builtin_nontemporal_load(row_off + v + 1); }
+    __device__ __forceinline__ int target(int, int p, int) const { return __builtin_nontemporal_load(col + p); }
 };
 
 // SplitMix64 finalizer (Steele, Lea, Flood, OOPSLA 2014).
