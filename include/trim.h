@@ -117,7 +117,11 @@ typedef struct {
     uint64_t joins;        /* AC-6: support-list joins after the first sweep */
     uint64_t visited;      /* AC-6: support-list members handed back */
     uint64_t graph_edges;  /* AC-6: sum of out-degrees as generated or read (m) */
-    uint64_t reserved[2];
+    uint64_t q_highwater;  /* AC-6/AC-4: largest number of items any wavefront's private
+                              LDS queue held (the analogue of the bound on |Q_p| in
+                              Section 9.2; capped by the 1,024-entry ring, beyond which
+                              items go to the shared queue) */
+    uint64_t reserved;
 } trim_stats_t;
 
 /*

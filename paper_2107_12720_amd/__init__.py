@@ -34,7 +34,7 @@ EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destr
            "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key")
 MLP_PARAMS = 1377
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
-                "joins", "visited", "graph_edges")
+                "joins", "visited", "graph_edges", "q_highwater")
 STATS_WORDS = 12
 
 

@@ -165,7 +165,7 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     // an empty graph still runs the repeat-until loop once
     if (stats)
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
-                           pack_blocks, worker_edges, w.part, w.ctr, stats, 1);
+                           pack_blocks, 0, worker_edges, w.part, w.ctr, stats, 1);
     return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@
 // Kernels: ac4_init (counters), ac4_seed (out-degree-0 vertices queued),
 // ac4_propagate (persistent workers on per-wavefront LDS rings, WaveQueue;
 // a lane walks the predecessors of its removed vertex eight at a time, with
-// the eight decrements in flight together), ac4_pack (bitmap from cnt > 0).
+// the eight decrements in flight together, and then goes on with one of the
+// vertices it removed itself, depth first), ac4_pack (bitmap from cnt > 0).
 #include "trim_device.h"
 #include "trim_stats.h"
 #include "trim_internal.h"
@@ -42,7 +43,7 @@ constexpr int kBatch = 8;
 
 __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const int* rcol,
                                                      int* cnt, uint32_t* q, int* ctr,
-                                                     uint64_t* worker_edges) {
+                                                     uint64_t* worker_edges, uint64_t* part) {
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
     WaveQueue wq;
@@ -79,6 +80,14 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
             if (k >= e) {
                 item = kNone;
                 started = false;
+                // depth first: go on with one vertex this lane has just
+                // removed instead of handing it to the queue
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j)
+                    if (item == kNone && out[j] != kNone) {
+                        item = out[j];
+                        out[j] = kNone;
+                    }
             }
         }
 #pragma unroll
@@ -87,6 +96,9 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
     }
     edges = wave_sum(edges);
     if (lane_id() == 0 && edges) add_dev(worker_edges + blockIdx.x, edges);
+    __shared__ int red[16];
+    const int qhw = block_max(wq.hw, red);
+    if (threadIdx.x == 0) part[kPartQhw * kPartStride + blockIdx.x] = (uint64_t)qhw;
 }
 
 struct Ac4Live {
@@ -121,7 +133,7 @@ hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
         {
             Timed t(lc, "ac4_propagate");
             hipLaunchKernelGGL(ac4_propagate, dim3(P), dim3(256), 0, lc.stream, g.rrow_off,
-                               g.rcol, w.a, w.q, w.ctr, worker_edges);
+                               g.rcol, w.a, w.q, w.ctr, worker_edges, w.part);
         }
         Timed t(lc, "ac4_pack");
         pack_blocks = grid_for(n, 256, lc.cus * 4);
@@ -130,7 +142,7 @@ hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
     }
     if (stats)
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
-                           pack_blocks, worker_edges, w.part, w.ctr, stats, 0);
+                           pack_blocks, n > 0 ? P : 0, worker_edges, w.part, w.ctr, stats, 0);
     return hipGetLastError();
 }
 

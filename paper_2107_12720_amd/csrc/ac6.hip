@@ -270,11 +270,13 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
     closes = block_sum(closes, red);
     joins = block_sum(joins, red);
     visited = block_sum(visited, red);
+    const int qhw = block_max(wq.hw, reinterpret_cast<int*>(red));
     if (threadIdx.x == 0) {
         if (edges) add_dev(worker_edges + blockIdx.x, edges);
         part[kPartCloses * kPartStride + blockIdx.x] = closes;
         part[kPartJoins * kPartStride + blockIdx.x] = joins;
         part[kPartVisited * kPartStride + blockIdx.x] = visited;
+        part[kPartQhw * kPartStride + blockIdx.x] = (uint64_t)qhw;
     }
 }
 
@@ -390,7 +392,8 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     if (stats) {
         Timed t(lc, "finalize");
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, sweep_blocks,
-                           n > 0 ? P : 0, pack_blocks, worker_edges, w.part, w.ctr, stats, 0);
+                           n > 0 ? P : 0, pack_blocks, n > 0 ? P : 0, worker_edges, w.part,
+                           w.ctr, stats, 0);
     }
     return hipGetLastError();
 }

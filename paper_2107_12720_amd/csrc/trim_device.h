@@ -159,6 +159,7 @@ struct WaveQueue {
     int ticket;         // per lane: shared-queue slot this lane waits on, or -1
     int iter;           // wave-uniform iteration counter
     int naps;           // wave-uniform idle back-off
+    int hw;             // per lane: largest ring fill this lane has seen after a push
 
     __device__ __forceinline__ void init(uint32_t* ring, int* ring_tail, uint32_t* gq,
                                          int* ctr_qhead, int* ctr_qtail, int* ctr_pending) {
@@ -175,6 +176,7 @@ struct WaveQueue {
         ticket = -1;
         iter = 0;
         naps = 1;
+        hw = 0;
     }
 
     __device__ __forceinline__ int tail() const {
@@ -249,6 +251,7 @@ struct WaveQueue {
                                                      __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_WAVEFRONT)) {
                 lq[t & (kLocalQ - 1)] = it;
+                hw = max(hw, t + 1 - head);
                 return;
             }
         }
@@ -269,6 +272,7 @@ struct WaveQueue {
             __builtin_amdgcn_wave_barrier();
             if (lane_id() == 0) *tail_lds = t + total;
             __builtin_amdgcn_wave_barrier();
+            hw = max(hw, t + total - head);
             return;
         }
         int base = 0;
@@ -326,6 +330,19 @@ struct WaveQueue {
         }
     }
 };
+
+// Block-wide maximum of a non-negative value; every thread gets the result.
+__device__ __forceinline__ int block_max(int x, int* scratch) {
+    for (int off = kWave / 2; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off));
+    const int w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+    __syncthreads();
+    if (lane_id() == 0) scratch[w] = x;
+    __syncthreads();
+    int m = 0;
+    for (int i = 0; i < nw; ++i) m = max(m, scratch[i]);
+    __syncthreads();
+    return m;
+}
 
 // Block-wide sum; every thread gets the result.  `scratch` holds >= 16 words.
 __device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* scratch) {

@@ -39,7 +39,7 @@ constexpr int kMaxWorkers = 16384;
 constexpr int kQueueSlots = 64 * 4 * kMaxWorkers;
 constexpr int kPartStride = 16384;   // >= workers, sweep blocks and pack blocks
 enum PartSlot : int { kPartCloses = 0, kPartJoins = 1, kPartVisited = 2, kPartSweep = 3,
-                      kPartLive = 4, kPartDeg = 5, kPartSlots = 6 };
+                      kPartLive = 4, kPartDeg = 5, kPartQhw = 6, kPartSlots = 7 };
 
 // Optional per-kernel event timing (trim_ctx_set_timing).
 struct Timer {

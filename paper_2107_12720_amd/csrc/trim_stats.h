@@ -39,12 +39,20 @@ __device__ __forceinline__ uint64_t sum_range(const uint64_t* a, int k, uint64_t
     return block_sum(s, red);
 }
 
+__device__ __forceinline__ uint64_t max_range(const uint64_t* a, int k, uint64_t* red) {
+    int m = 0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) m = max(m, (int)a[i]);
+    return (uint64_t)block_max(m, reinterpret_cast<int*>(red));
+}
+
 // One block: reduce the partials into *stats.  n_sweep / n_prop = number of
-// sweep / propagation partials (0 when the algorithm has none).
-__global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack,
+// sweep / propagation partials (0 when the algorithm has none); n_qhw =
+// number of ring high-water partials.
+__global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack, int n_qhw,
                                const uint64_t* worker_edges, const uint64_t* part, const int* ctr,
                                trim_stats_t* stats, int empty_rounds) {
     __shared__ uint64_t red[16];
+    const uint64_t qhw = max_range(part + kPartQhw * kPartStride, n_qhw, red);
     const uint64_t edges = sum_range(worker_edges, P, red);
     const uint64_t live = sum_range(part + kPartLive * kPartStride, n_pack, red);
     const uint64_t sweep = sum_range(part + kPartSweep * kPartStride, n_sweep, red);
@@ -62,6 +70,7 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
         stats->joins = joins;
         stats->visited = visited;
         stats->graph_edges = degsum;
+        stats->q_highwater = qhw;
         if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
     }
 }

@@ -73,6 +73,10 @@ def check_all(ctx, g, algos=(6, 4, 3), opts=None, name=""):
         assert st["n_live"] == r.n_live and st["n_dead"] == g.n - r.n_live, st
         if a == 3:
             assert st["rounds"] == r.alpha + 1, st
+            assert st["q_highwater"] == 0, st
+        else:
+            # private LDS queues never hold more than their 1,024 entries
+            assert 0 <= st["q_highwater"] <= 1024, st
         if a == 6:
             checks, joins, _ = sweep_counts(g)
             deg0 = int((np.diff(g.row_off) == 0).sum())
