@@ -10,9 +10,10 @@
 //
 // Kernels: ac4_init (counters), ac4_seed (out-degree-0 vertices queued),
 // ac4_propagate (persistent workers on per-wavefront LDS rings, WaveQueue;
-// a lane walks the predecessors of its removed vertex eight at a time, with
-// the eight decrements in flight together, and then goes on with one of the
-// vertices it removed itself, depth first), ac4_pack (bitmap from cnt > 0).
+// a lane walks a short predecessor list of its removed vertex eight at a
+// time, with the eight decrements in flight together, and then goes on with
+// one of the vertices it removed itself, depth first; long lists are walked
+// by the whole wavefront), ac4_pack (bitmap from cnt > 0).
 #include "trim_device.h"
 #include "trim_stats.h"
 #include "trim_internal.h"
@@ -40,6 +41,7 @@ __global__ void ac4_seed(const int* cnt, int n, uint32_t* q, int* ctr) {
 }
 
 constexpr int kBatch = 8;
+constexpr int kCoop = 16;   // predecessor lists longer than this are walked by the wavefront
 
 __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const int* rcol,
                                                      int* cnt, uint32_t* q, int* ctr,
@@ -57,14 +59,45 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
         uint32_t out[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) out[j] = kNone;
-        if (item != kNone) {
-            if (!started) {
-                const int w = item_vertex(item);
-                k = rrow_off[w];
-                e = rrow_off[w + 1];
-                started = true;
-                edges += (uint64_t)(e - k);
+        if (item != kNone && !started) {
+            const int w = item_vertex(item);
+            k = rrow_off[w];
+            e = rrow_off[w + 1];
+            started = true;
+            edges += (uint64_t)(e - k);
+        }
+        // Long predecessor lists: the whole wavefront walks them, one list at
+        // a time, 64 x kBatch decrements in flight per round.
+        for (uint64_t big = ballot(item != kNone && e - k > kCoop); big; big &= big - 1) {
+            const int owner = __ffsll((unsigned long long)big) - 1;
+            const int kb = __shfl(k, owner), eb = __shfl(e, owner);
+            for (int base = kb; base < eb; base += kWave * kBatch) {
+                int u[kBatch], old[kBatch];
+                uint32_t o[kBatch];
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    const int p = base + j * kWave + lane_id();
+                    if (p < eb) u[j] = rcol[p];
+                }
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    const int p = base + j * kWave + lane_id();
+                    if (p < eb) old[j] = add_dev(cnt + u[j], -1);
+                }
+#pragma unroll
+                for (int j = 0; j < kBatch; ++j) {
+                    const int p = base + j * kWave + lane_id();
+                    o[j] = (p < eb && old[j] == 1) ? make_item(0, u[j]) : kNone;
+                }
+#pragma unroll
+                for (int j = 0; j < kBatch; j += 2) wq.push(o[j], o[j + 1]);
             }
+            if (lane_id() == owner) {
+                item = kNone;
+                started = false;
+            }
+        }
+        if (item != kNone) {
             const int nb = min(kBatch, e - k);
             int u[kBatch], old[kBatch];
 #pragma unroll
