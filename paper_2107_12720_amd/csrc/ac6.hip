@@ -67,9 +67,14 @@ struct Stage<ImplicitView> {
     }
 };
 
+// Also writes sinks[]: bit v set iff v has no successor.  During the first
+// sweep these are the only removed vertices, so the sweep tests this small,
+// cache-resident bitmap instead of a list head in HBM.  Each wavefront covers
+// 64 consecutive ids (blockDim and the grid stride are multiples of 64); the
+// last wavefront may write one word past ceil(n/32), which the buffer has.
 template <class View>
-__global__ void ac6_init(View g, int n, int* head, int* ctr, uint64_t* worker_edges, int P,
-                         trim_stats_t* stats) {
+__global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, int* ctr,
+                         uint64_t* worker_edges, int P, trim_stats_t* stats) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     Stage<View>::apply(g, lds);
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -77,16 +82,23 @@ __global__ void ac6_init(View g, int n, int* head, int* ctr, uint64_t* worker_ed
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
-        const int h = (g.end(v) == g.begin(v)) ? kDead : kEmpty;
+        const bool sink = g.end(v) == g.begin(v);
+        const int h = sink ? kDead : kEmpty;
         reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
+        const uint64_t m = ballot(sink);
+        if (lane_id() == 0) {
+            sinks[v >> 5] = (uint32_t)m;
+            sinks[(v >> 5) + 1] = (uint32_t)(m >> 32);
+        }
     }
 }
 
 constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-queue append
 
 template <class View>
-__global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, uint32_t* q,
-                          int* ctr, uint64_t* worker_edges, int P, uint64_t* part) {
+__global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* sinks,
+                          uint64_t* rec, uint32_t* q, int* ctr, uint64_t* worker_edges, int P,
+                          uint64_t* part) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t cas[kCasBuf];
     __shared__ int s_chunk, s_ncas, s_base;
@@ -131,7 +143,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, uint64_t* rec, ui
                     int p = b, w = 0;
                     for (; p < e; ++p) {
                         w = g.target(v, p, gi);
-                        if (ld_cached(head + 2 * w) != kDead) break;
+                        if (!((sinks[w >> 5] >> (w & 31)) & 1u)) break;
                     }
                     if (p < e) {
                         const int old = xchg_dev(head + 2 * w + (p + 1 == e), v);
@@ -361,7 +373,8 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     {
         Timed t(lc, "ac6_init");
         hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           lc.stream, g, n, w.a, w.ctr, worker_edges, P, stats);
+                           lc.stream, g, n, w.a, reinterpret_cast<uint32_t*>(w.c), w.ctr,
+                           worker_edges, P, stats);
     }
     if (n > 0) {
         const int chunk = ((lc.chunk + B - 1) / B) * B;
@@ -369,7 +382,8 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         {
             Timed t(lc, "ac6_sweep");
             hipLaunchKernelGGL(ac6_sweep<View>, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n,
-                               chunk, w.a, w.b, w.q, w.ctr, worker_edges, P, w.part);
+                               chunk, w.a, reinterpret_cast<const uint32_t*>(w.c), w.b, w.q,
+                               w.ctr, worker_edges, P, w.part);
         }
         {
             Timed t(lc, "ac6_propagate");
