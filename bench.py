@@ -208,23 +208,20 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
     lb = torch.empty((n + 31) // 32, dtype=torch.int32, device="cuda")
     we = torch.empty(P, dtype=torch.int64, device="cuda")
     st = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
-    s = torch.cuda.current_stream()
-    ctx.set_timing(False)
     log(f"implicit: n = 2^{log2n}")
-    ms6 = ev_time(lambda: ctx.trim_implicit(T.AC6, log2n, imp.seed, imp.zero_thr, table,
-                                            live_bitmap=lb, worker_edges=we, stats=st),
-                  reps, 1, s)
-    res = ctx.trim_implicit(T.AC6, log2n, imp.seed, imp.zero_thr, table, live_bitmap=lb,
-                            worker_edges=we, stats=st)
+    ms6, ktimes, res = time_gpu(ctx, lambda: ctx.trim_implicit(
+        T.AC6, log2n, imp.seed, imp.zero_thr, table, live_bitmap=lb, worker_edges=we,
+        stats=st), reps, 1)
     torch.cuda.synchronize()
     stat = res.stats_dict()
     bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
-    ctx.set_timing(True)
     m = stat["graph_edges"]
     return {"implicit": imp, "bits": bits}, {
         "workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
         "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": stat["edges_total"],
-        "n_live": stat["n_live"], "fixpoint_check_on_samples": None}
+        "n_live": stat["n_live"],
+        "kernels_ms": {k: float(np.mean(v)) for k, v in ktimes.items()},
+        "fixpoint_check_on_samples": None}
 
 
 def bench_explicit26(ctx, T, gg, reps):

@@ -64,6 +64,16 @@ def features(row_off, col, indeg, edges) -> np.ndarray:
     return X.astype(np.float64), src, dst
 
 
+def logits(params, X, bf16=True):
+    """Network output (logit) for feature rows X, with the same BF16 rounding
+    points as loss_and_grad."""
+    r = bf16_round if bf16 else (lambda a: np.asarray(a, np.float64))
+    P = unpack(r(params) if bf16 else params)
+    h1 = r(np.maximum(r(X) @ P["W1"].T + P["b1"], 0.0))
+    h2 = np.maximum(h1 @ P["W2"].T + P["b2"], 0.0)
+    return h2 @ P["w3"] + P["b3"][0]
+
+
 def loss_and_grad(params, X, y, w, bf16=True):
     """(loss, grad[1377]) of sum_e w_e * BCE(s_e, y_e) for feature rows X."""
     r = bf16_round if bf16 else (lambda a: np.asarray(a, np.float64))

@@ -2,7 +2,8 @@
 
 Host-side orchestration only: every computation (features, forward,
 backward, Adam, scoring, reordering) runs in the HIP kernels of libtrim
-(mlp.hip); this module allocates device buffers and loops over steps.
+(mlp.hip, order.hip); this module allocates device buffers and loops over
+steps.
 
 Labels are the live sets of the training graphs, produced by plain AC-6 on
 the GPU (the same greatest fixed point the CPU oracle computes; the tests
@@ -79,9 +80,8 @@ def learned_order(ctx, dg, indeg, src, pbf):
     scores = torch.empty(max(dg.m, 1), dtype=torch.float32, device="cuda")
     ctx.mlp_score(dg, indeg, src, pbf, scores)
     # probability of staying live, 16 equal levels over [0, 1]
-    prob = torch.sigmoid(scores)
     col_out = torch.empty_like(dg.col)
-    ctx.order_by_key(dg, prob, 0.0, 1.0, col_out)
+    ctx.order_by_key(dg, scores, 0.0, 1.0, col_out)
     return col_out, scores
 
 

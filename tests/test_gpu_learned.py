@@ -71,6 +71,32 @@ def test_gradient_vs_fp64_reference(ctx):
             assert err <= 1e-2 * np.max(np.abs(b)) + 1e-7, (k, err, np.max(np.abs(b)))
 
 
+def test_scores_vs_fp64_reference(ctx):
+    """Every edge's probability from the scoring kernel against the FP64
+    forward pass on the same BF16 weights."""
+    import torch
+    import paper_2107_12720_amd as T
+    from paper_2107_12720_amd import learned
+    from oracle import mlp_ref
+    g = gg.rmat(11, 8, seed=6)
+    dg = device_graph(g)
+    indeg, src = learned.prepare(ctx, dg)
+    p = learned.init_params(seed=4) * 2.0
+    p[256:288] = np.random.default_rng(1).normal(0, 0.1, 32)
+    bits = learned.to_bf16_bits(p)
+    scores = torch.empty(g.m, dtype=torch.float32, device="cuda")
+    ctx.mlp_score(dg, indeg, src, T.to_device(bits.view(np.int16)), scores)
+    torch.cuda.synchronize()
+    X, _, _ = mlp_ref.features(g.row_off.astype(np.int64), g.col,
+                               np.bincount(g.col, minlength=g.n), np.arange(g.m))
+    pw = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    want = 1.0 / (1.0 + np.exp(-mlp_ref.logits(pw, X)))
+    got = scores.cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(got - want))
+    say(f"  scores: m={g.m} max |p_gpu - p_ref| = {err:.2e}")
+    assert err <= 2e-3
+
+
 def hub_graph():
     """Random graph plus lists longer than one wavefront's share (2,048
     entries): a hub of 50,000 successors, one of exactly 2,049, one of 2,048,

@@ -347,3 +347,25 @@ def test_mlp_reference_bf16_rounding():
     # BF16 keeps 8 significant bits: 1 + 2^-8 is exactly halfway and rounds to even
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0078125 and r[3] == 3.140625
     assert r[4] == -2.71875 and r[6] == 0.0
+
+
+def test_mlp_logits_hand_computed():
+    """A network with one path 8 -> 1 -> 1 -> 1 computes 6 relu(x0) - 1 by
+    hand: W1[0][0] = 1, W2[0][0] = 2, w3[0] = 3, b3 = -1, all else 0."""
+    from oracle import mlp_ref
+    p = np.zeros(mlp_ref.NPARAM)
+    p[0] = 1.0            # W1[0][0]
+    p[288] = 2.0          # W2[0][0]
+    p[1344] = 3.0         # w3[0]
+    p[1376] = -1.0        # b3
+    X = np.zeros((3, 8))
+    X[:, 0] = [0.5, -1.0, 2.0]
+    X[:, 3] = [9.0, 9.0, 9.0]     # other inputs have zero weight
+    np.testing.assert_allclose(mlp_ref.logits(p, X, bf16=False), [2.0, -1.0, 11.0])
+    # the loss of loss_and_grad is the BCE of these logits
+    y = np.array([1.0, 0.0, 1.0])
+    w = np.ones(3)
+    s = np.array([2.0, -1.0, 11.0])
+    want = np.sum(np.log1p(np.exp(-s)) * y + np.log1p(np.exp(s)) * (1 - y))
+    loss, _ = mlp_ref.loss_and_grad(p, X, y, w, bf16=False)
+    assert abs(loss - want) < 1e-12
