@@ -237,14 +237,16 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
                 // link -- both in flight together, one round trip.
                 // The next step's memory operations are issued before this
                 // step's pushes, so the LDS queue work overlaps the round trip.
+                // Only the link half of a record is loaded: a 32-bit load, so no
+                // register of an in-flight load is reused by the pushes below.
                 bool member = kind == kCloseLast;
-                uint64_t rr = member ? ld_dev(rec + x) : 0;
+                int link = member ? ld_dev(rec_link(rec, x)) : -1;
                 int2 ab = xchg2_dev(head + 2 * x, kDead, kDead);   // S_more(x), S_last(x)
                 int fill = 0;   // ring fill read after the previous step's pushes
                 for (int hop = 0;; ++hop) {
                     closes += 1;
                     // a dying vertex never joins a list again, so its record is stable
-                    const int sib = member ? rec_next(rr) : -1;
+                    const int sib = member ? link : -1;
                     const int a = ab.x, b = ab.y;
                     // depth first: into S_last(c) if it has members, else on to
                     // the next member of the list c was in
@@ -252,7 +254,7 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
                     visited += (b >= 0) + (sib >= 0);
                     const bool go = next >= 0 && hop + 1 < kHops && fill <= kLocalQ - 256;
                     if (go) {
-                        rr = ld_dev(rec + next);
+                        link = ld_dev(rec_link(rec, next));
                         ab = xchg2_dev(head + 2 * next, kDead, kDead);
                     }
                     if (a >= 0) wq.push1(make_item(kWalkMore, a));

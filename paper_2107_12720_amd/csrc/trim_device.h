@@ -102,6 +102,10 @@ __device__ __forceinline__ uint64_t pack_rec(int next, int cursor) {
 }
 __device__ __forceinline__ int rec_next(uint64_t r) { return (int)(uint32_t)r; }
 __device__ __forceinline__ int rec_cursor(uint64_t r) { return (int)(uint32_t)(r >> 32); }
+// The link half of rec[v] (the low word on this little-endian target).
+__device__ __forceinline__ const int* rec_link(const uint64_t* rec, int v) {
+    return reinterpret_cast<const int*>(rec + v);
+}
 
 // Wave-aggregated append of the lanes with `pred` set: one atomic per wave.
 // Returns the slot of this lane (or -1).  Does not wait for completion.
