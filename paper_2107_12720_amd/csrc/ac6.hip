@@ -31,13 +31,13 @@
 //
 // Kernels, in stream order:
 //   ac6_init       heads = kDead for out-degree-0 vertices (their lists are
-//                  empty, nothing to hand back), kEmpty otherwise; counters
-//                  and outputs zeroed.
-//   ac6_sweep      DoPost for every vertex, one lane per vertex.  Nothing is
-//                  removed during this kernel, so a live-looking target stays
-//                  live and joining is a plain exchange (no CAS retry storms on
-//                  hub vertices).  Vertices without a live successor are queued
-//                  as close items.
+//                  empty, nothing to hand back), kEmpty otherwise; the sinks
+//                  bitmap; counters and outputs zeroed.
+//   ac6_sweep      DoPost for every vertex, one lane per vertex.  Only sinks
+//                  are removed while this kernel runs, so a target is live iff
+//                  its sinks bit is clear, and joining is a plain exchange (no
+//                  CAS retry storms on hub vertices).  Vertices without a live
+//                  successor are queued as close items.
 //   ac6_propagate  persistent workers (the paper's Trim_p) run close and walk
 //                  items (see below) through per-wavefront LDS rings
 //                  (WaveQueue); a lane follows an S_last chain for up to
