@@ -290,9 +290,15 @@ struct WaveQueue {
         if (b != kNone) st_dev((int*)q + base + rb, (int)b);
     }
 
-    // Uniform code, now and then: if lanes elsewhere wait for work (tickets
-    // beyond qtail), hand them part of the ring.
+    // Uniform code.  A ring close to full hands its oldest items above
+    // kSpillAbove to the shared queue in one reservation (so single pushes
+    // rarely take the slow path).  Now and then: if lanes elsewhere wait for
+    // work (tickets beyond qtail), hand them part of the ring.
     __device__ __forceinline__ void rebalance() {
+        if (fill() > kLocalQ - 256) {
+            spill_ring(fill() - kSpillAbove);
+            return;
+        }
         if ((iter & (kPollEvery - 1)) != 0) return;
         const int occ = fill();
         if (occ < 2) return;
