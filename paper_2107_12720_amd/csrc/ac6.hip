@@ -182,19 +182,31 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
 template <class View>
 __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, uint64_t* rec,
                                        uint64_t& edges) {
+    // kScan successors at a time: their targets, then their list heads, each
+    // group of loads in flight together, then the joins in list order.
+    constexpr int kScan = 4;
     const int e = g.end(u);
     const int ctx = g.vctx(u);
-    int p = p0;
-    for (; p < e; ++p) {
-        const int w = g.target(u, p, ctx);
-        int* slot = head + 2 * w + (p + 1 == e);
-        int h = ld_cached(slot);
-        while (h != kDead) {
-            st_dev(rec + u, pack_rec(h, p));
-            complete_mem();
-            if (cas_dev(slot, h, u)) {
-                edges += (uint64_t)(p - p0 + 1);
-                return true;
+    for (int p = p0; p < e; p += kScan) {
+        int w[kScan], h[kScan];
+#pragma unroll
+        for (int j = 0; j < kScan; ++j)
+            if (p + j < e) w[j] = g.target(u, p + j, ctx);
+#pragma unroll
+        for (int j = 0; j < kScan; ++j)
+            if (p + j < e) h[j] = ld_cached(head + 2 * w[j] + (p + j + 1 == e));
+#pragma unroll
+        for (int j = 0; j < kScan; ++j) {
+            if (p + j >= e) break;
+            int* slot = head + 2 * w[j] + (p + j + 1 == e);
+            int hj = h[j];
+            while (hj != kDead) {
+                st_dev(rec + u, pack_rec(hj, p + j));
+                complete_mem();
+                if (cas_dev(slot, hj, u)) {
+                    edges += (uint64_t)(p + j - p0 + 1);
+                    return true;
+                }
             }
         }
     }
