@@ -86,11 +86,12 @@ def sweep_counts(g):
     return int(checks), int(has.sum()), int(((deg > 0) & ~has).sum())
 
 
-def sweep_bytes(g, checks, joins, casualties):
-    """Algorithmic bytes of one ac6_sweep launch: 4 B of offsets per vertex, 8 B
-    per successor check (target id + target status), 16 B per join (head
-    exchange + record store), 4 B per queued casualty."""
-    return 4 * (g.n + 1) + 8 * checks + 16 * joins + 4 * casualties
+def sweep_bytes(n, checks, joins, casualties):
+    """Algorithmic bytes of one ac6_sweep launch: 4 B of offsets per vertex, 4 B
+    per successor check (its target id; the target's status is a bit of the
+    n/8-byte sinks bitmap, read once), 16 B per join (head exchange + record
+    store), 4 B per queued casualty."""
+    return 4 * (n + 1) + n // 8 + 4 * checks + 16 * joins + 4 * casualties
 
 
 def time_gpu(ctx, fn, steps, warmup):
@@ -244,9 +245,9 @@ def bench_explicit26(ctx, T, gg, reps):
     st = res.stats_dict()
     kavg = {k: float(np.mean(v)) for k, v in ktimes.items()}
     sweep_joins = st["visited"] - st["joins"] + st["n_live"]
-    algo = {"ac6_sweep": 4 * (n + 1) + 8 * st["edges_sweep"] + 16 * sweep_joins,
+    algo = {"ac6_sweep": sweep_bytes(n, st["edges_sweep"], sweep_joins, 0),
             "ac6_propagate": prop_bytes(st, st["edges_total"]),
-            "ac6_init": 8 * (n + 1) + 8 * n, "ac6_pack": 8 * n + n // 8}
+            "ac6_init": 4 * (n + 1) + 8 * n + n // 8, "ac6_pack": 8 * n + n // 8}
     kern = {k: {"avg_ms": kavg[k], "algorithmic_bytes": int(algo.get(k, 0)),
                 "achieved_GBs": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9,
                 "frac": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9 / HBM_PEAK_GBS} for k in kavg}
@@ -474,9 +475,9 @@ def main():
     if sw_checks != st["edges_sweep"]:
         log(f"warning: sweep checks {st['edges_sweep']} != host count {sw_checks}")
         sweep_ok = False
-    b_sweep = sweep_bytes(g, sw_checks, sw_joins, sw_cas)
+    b_sweep = sweep_bytes(n, sw_checks, sw_joins, sw_cas)
     algo_bytes = {"ac6_propagate": b_prop, "ac6_sweep": b_sweep,
-                  "ac6_init": 8 * (n + 1) + 8 * n, "ac6_pack": 8 * n + n // 8}
+                  "ac6_init": 4 * (n + 1) + 8 * n + n // 8, "ac6_pack": 8 * n + n // 8}
     ach = algo_bytes[dom] / (kavg[dom] / 1e3) / 1e9
     traffic = measured_traffic(dom, "rmat22_chain")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
