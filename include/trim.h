@@ -100,8 +100,16 @@ typedef struct {
     int32_t graph;      /* trim_batch only: 1 = capture the launch sequence into a HIP
                            graph on the first call and replay it while every argument
                            is unchanged (needs a non-NULL stream) */
-    int32_t reserved[3];
+    int32_t schedule;   /* schedule perturbation for race testing, bit flags:
+                           TRIM_SCHED_REVERSE = the first sweep claims its chunks from
+                           the last vertex down; TRIM_SCHED_JITTER = short
+                           pseudo-random pauses inside the race windows (join versus
+                           close, AC-4 decrements).  Results never depend on them. */
+    int32_t reserved[2];
 } trim_opts_t;
+
+#define TRIM_SCHED_REVERSE 1
+#define TRIM_SCHED_JITTER 2
 
 /* Per-call statistics, written to device memory. */
 typedef struct {

@@ -47,7 +47,8 @@ class TrimError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("graph", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class CsrDesc(ctypes.Structure):
@@ -114,8 +115,13 @@ def _check(code: int):
         raise TrimError(code, last_error())
 
 
-def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False) -> Opts:
-    return Opts(block, workers, chunk, int(bool(validate)), int(bool(graph)), (0, 0, 0))
+SCHED_REVERSE = 1
+SCHED_JITTER = 2
+
+
+def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False, schedule=0) -> Opts:
+    return Opts(block, workers, chunk, int(bool(validate)), int(bool(graph)), int(schedule),
+                (0, 0))
 
 
 def _dev_ptr(t, dtype, name, allow_none=False):

@@ -45,7 +45,8 @@ constexpr int kCoop = 16;   // predecessor lists longer than this are walked by 
 
 __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const int* rcol,
                                                      int* cnt, uint32_t* q, int* ctr,
-                                                     uint64_t* worker_edges, uint64_t* part) {
+                                                     uint64_t* worker_edges, uint64_t* part,
+                                                     int sched) {
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
     WaveQueue wq;
@@ -79,6 +80,7 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
                     const int p = base + j * kWave + lane_id();
                     if (p < eb) u[j] = rcol[p];
                 }
+                if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)kb << 20) ^ base);
 #pragma unroll
                 for (int j = 0; j < kBatch; ++j) {
                     const int p = base + j * kWave + lane_id();
@@ -103,6 +105,7 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
 #pragma unroll
             for (int j = 0; j < kBatch; ++j)
                 if (j < nb) u[j] = rcol[k + j];
+            if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)k << 16) ^ item);
 #pragma unroll
             for (int j = 0; j < kBatch; ++j)
                 if (j < nb) old[j] = add_dev(cnt + u[j], -1);
@@ -166,7 +169,7 @@ hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
         {
             Timed t(lc, "ac4_propagate");
             hipLaunchKernelGGL(ac4_propagate, dim3(P), dim3(256), 0, lc.stream, g.rrow_off,
-                               g.rcol, w.a, w.q, w.ctr, worker_edges, w.part);
+                               g.rcol, w.a, w.q, w.ctr, worker_edges, w.part, lc.schedule);
         }
         Timed t(lc, "ac4_pack");
         pack_blocks = grid_for(n, 256, lc.cus * 4);

@@ -98,7 +98,7 @@ constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-
 template <class View>
 __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* sinks,
                           uint64_t* rec, uint32_t* q, int* ctr, uint64_t* worker_edges, int P,
-                          uint64_t* part) {
+                          uint64_t* part, int sched) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t cas[kCasBuf];
     __shared__ int s_chunk, s_ncas, s_base;
@@ -126,9 +126,11 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
         // claim the next chunk of vertices (schedule(dynamic, chunk))
         if (threadIdx.x == 0) s_chunk = add_dev(ctr + kCursor, chunk);
         __syncthreads();
-        const int cb = s_chunk;
+        const int claim = s_chunk;
         __syncthreads();
-        if (cb >= n) break;
+        if (claim >= n) break;
+        int cb = claim;
+        if (sched & TRIM_SCHED_REVERSE) cb = ((n + chunk - 1) / chunk - 1 - claim / chunk) * chunk;
         const int ce = cb + chunk < n ? cb + chunk : n;
         for (int base = cb; base < ce; base += blockDim.x) {
             const int v = base + threadIdx.x;
@@ -146,6 +148,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
                         if (!((sinks[w >> 5] >> (w & 31)) & 1u)) break;
                     }
                     if (p < e) {
+                        if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)blockIdx.x << 32) ^ v);
                         const int old = xchg_dev(head + 2 * w + (p + 1 == e), v);
                         rec[v] = pack_rec(old, p);
                         mine = (uint64_t)(p - b + 1);
@@ -181,7 +184,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
 // live successor's list; `edges` receives the positions checked.
 template <class View>
 __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, uint64_t* rec,
-                                       uint64_t& edges) {
+                                       uint64_t& edges, int sched) {
     // kScan successors at a time: their targets, then their list heads, each
     // group of loads in flight together, then the joins in list order.
     constexpr int kScan = 4;
@@ -203,6 +206,7 @@ __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, 
             while (hj != kDead) {
                 st_dev(rec + u, pack_rec(hj, p + j));
                 complete_mem();
+                if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)u << 24) ^ (p + j));
                 if (cas_dev(slot, hj, u)) {
                     edges += (uint64_t)(p + j - p0 + 1);
                     return true;
@@ -226,7 +230,7 @@ constexpr int kHops = 256;   // S_last chain steps one item may take in a row
 template <class View>
 __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t* rec, uint32_t* q,
                                                      int* ctr, uint64_t* worker_edges,
-                                                     uint64_t* part) {
+                                                     uint64_t* part, int sched) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
@@ -266,6 +270,7 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
                     visited += (b >= 0) + (sib >= 0);
                     const bool go = next >= 0 && hop + 1 < kHops && fill <= kLocalQ - 256;
                     if (go) {
+                        if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)next << 8) ^ hop);
                         link = ld_dev(rec_link(rec, next));
                         ab = xchg2_dev(head + 2 * next, kDead, kDead);
                     }
@@ -284,7 +289,8 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
                 const int nx = rec_next(r);
                 visited += 1;
                 if (nx >= 0) keep = make_item(kWalkMore, nx);
-                if (resume(g, x, rec_cursor(r) + 1, head, rec, edges)) joins += 1;
+                if (sched & TRIM_SCHED_JITTER) jitter_nap(x);
+                if (resume(g, x, rec_cursor(r) + 1, head, rec, edges, sched)) joins += 1;
                 else push_a = make_item(kClose, x);
             }
         }
@@ -397,12 +403,12 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
             Timed t(lc, "ac6_sweep");
             hipLaunchKernelGGL(ac6_sweep<View>, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n,
                                chunk, w.a, reinterpret_cast<const uint32_t*>(w.c), w.b, w.q,
-                               w.ctr, worker_edges, P, w.part);
+                               w.ctr, worker_edges, P, w.part, lc.schedule);
         }
         {
             Timed t(lc, "ac6_propagate");
             hipLaunchKernelGGL(ac6_propagate<View>, dim3(P), dim3(256), 0, lc.stream, g, w.a,
-                               w.b, w.q, w.ctr, worker_edges, w.part);
+                               w.b, w.q, w.ctr, worker_edges, w.part, lc.schedule);
         }
         if (!bitmap_base) {
             Timed t(lc, "ac6_pack");

@@ -115,6 +115,8 @@ int check_opts(const trim_opts_t* o) {
     if (o->chunk < 0 || o->chunk > (1 << 24))
         return fail(TRIM_E_INVAL, "opts.chunk must be in [0, 2^24]");
     if (o->graph != 0 && o->graph != 1) return fail(TRIM_E_INVAL, "opts.graph must be 0 or 1");
+    if (o->schedule & ~(TRIM_SCHED_REVERSE | TRIM_SCHED_JITTER))
+        return fail(TRIM_E_INVAL, "opts.schedule has unknown bits");
     return TRIM_OK;
 }
 
@@ -122,6 +124,7 @@ trim::LaunchCfg launch_cfg(trim_ctx* c, int algo, const trim_opts_t* o, void* st
     trim::LaunchCfg lc;
     lc.block = (o && o->block) ? o->block : 256;
     lc.chunk = (o && o->chunk) ? o->chunk : 4096;
+    lc.schedule = o ? o->schedule : 0;
     lc.workers = workers_for(c, algo, o);
     lc.cus = c->cus;
     lc.stream = (hipStream_t)stream;
@@ -319,7 +322,8 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
     const uint64_t key[23] = {(uint64_t)G, (uint64_t)vbase, (uint64_t)row_off, (uint64_t)col,
                               (uint64_t)total_n, (uint64_t)total_m, (uint64_t)bitmap_base,
                               (uint64_t)live_bitmaps, (uint64_t)graph_edges, (uint64_t)stats,
-                              (uint64_t)stream, (uint64_t)lc.block, (uint64_t)lc.chunk,
+                              (uint64_t)stream, (uint64_t)lc.block,
+                              (uint64_t)lc.chunk | ((uint64_t)lc.schedule << 32),
                               (uint64_t)lc.workers, (uint64_t)c->w.a, (uint64_t)c->w.b,
                               (uint64_t)c->w.c, (uint64_t)c->w.d, (uint64_t)c->w.q,
                               (uint64_t)c->w.part, (uint64_t)c->w.ctr, (uint64_t)c->w.wedges, 1};

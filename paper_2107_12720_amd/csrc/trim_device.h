@@ -102,6 +102,15 @@ __device__ __forceinline__ uint64_t pack_rec(int next, int cursor) {
 }
 __device__ __forceinline__ int rec_next(uint64_t r) { return (int)(uint32_t)r; }
 __device__ __forceinline__ int rec_cursor(uint64_t r) { return (int)(uint32_t)(r >> 32); }
+// Schedule perturbation (TRIM_SCHED_JITTER): a wavefront pauses for 0..7
+// short naps, chosen by a hash of `salt`, inside a race window.
+__device__ __forceinline__ void jitter_nap(uint64_t salt) {
+    uint64_t z = salt * 0x9E3779B97F4A7C15ull;
+    z ^= z >> 29;
+    const int naps = (int)((z * 0xBF58476D1CE4E5B9ull) >> 61);
+    for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(2);
+}
+
 // The link half of rec[v] (the low word on this little-endian target).
 __device__ __forceinline__ const int* rec_link(const uint64_t* rec, int v) {
     return reinterpret_cast<const int*>(rec + v);

@@ -65,6 +65,7 @@ class Timed {
 struct LaunchCfg {
     int block = 256;          // sweep block size
     int chunk = 4096;         // vertices per dynamically claimed sweep chunk
+    int schedule = 0;         // TRIM_SCHED_* perturbation flags (tests)
     int workers = 0;          // persistent workgroups
     int cus = 256;
     hipStream_t stream = nullptr;

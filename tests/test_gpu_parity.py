@@ -57,10 +57,10 @@ def test_config0(ctx):
 
 
 def test_star_contention(ctx):
-    """One hub with 200k supporters that dies (its only successor is a sink),
+    """One hub with 10^6 supporters that dies (its only successor is a sink),
     so every supporter is handed back at once; and the same hub kept alive by
-    a self-loop, so 200k vertices register on one list."""
-    N = 200000
+    a self-loop, so 10^6 vertices register on one list."""
+    N = 1000000
     src = np.arange(1, N + 1, dtype=np.int32)
     dst = np.zeros(N, np.int32)
     g = gg.from_edges(N + 2, np.r_[src, 0], np.r_[dst, N + 1])
@@ -116,6 +116,44 @@ def test_schedule_invariance(ctx):
             assert np.array_equal(got, bm) and edges == want
 
 
+def reverse_star(n):
+    """The hub points at n vertices that are all sinks but one, and that one
+    points back: the hub and its live successor survive, the hub's cursor has
+    to pass n - 1 dead targets."""
+    src = np.zeros(n, np.int32)
+    dst = np.arange(1, n + 1, dtype=np.int32)
+    return gg.from_edges(n + 1, np.r_[src, n], np.r_[dst, 0])
+
+
+def test_reverse_star(ctx):
+    check_all(ctx, reverse_star(300000), name="reverse star")
+
+
+@pytest.mark.parametrize("schedule", [1, 2, 3])
+def test_schedule_perturbation(ctx, schedule):
+    """Reversed sweep chunks (1), pauses inside the race windows (2), and both:
+    fifty repeats each on a dying hub with duplicate edges, a reverse star and
+    R-MAT with a chain; output never changes."""
+    import paper_2107_12720_amd as T
+    N = 20000
+    src2 = np.repeat(np.arange(1, N + 1, dtype=np.int32), 3)
+    dst2 = np.stack([np.zeros(N, np.int32), np.zeros(N, np.int32),
+                     np.arange(1, N + 1, dtype=np.int32)], 1).ravel()
+    graphs = [("hub duplicates", gg.from_edges(N + 2, np.r_[src2, 0], np.r_[dst2, N + 1])),
+              ("reverse star", reverse_star(20000)),
+              ("rmat14+chain", gg.rmat(14, 16, seed=9, chain=800))]
+    for name, g in graphs:
+        r, c, bm = expected(g)
+        dev6 = upload(g)
+        dev4 = upload(g, with_reverse=True)
+        say(f"  schedule={schedule} {name}: 50 repeats of AC-6 and AC-4")
+        for k in range(50):
+            opts = T.make_opts(schedule=schedule, chunk=(64, 4096)[k % 2], workers=(0, 37)[k % 2])
+            for a, want, dev in ((6, c.T6, dev6), (4, c.T4s, dev4)):
+                got, edges, st = run_csr(ctx, g, a, opts=opts, dev=dev)
+                assert np.array_equal(got, bm) and edges == want, (name, a, k)
+
+
 def test_repeat_stability(ctx):
     """Fifty repeats (Section 9.5 repeats every run 50 times): identical output."""
     g = gg.rmat(16, 16, seed=5, chain=500)
@@ -154,6 +192,9 @@ def test_errors(ctx):
     assert e.value.code == -5
     with pytest.raises(T.TrimError) as e:
         ctx.trim_csr(6, g.n, ro, col, opts=T.make_opts(block=100))
+    assert e.value.code == -1
+    with pytest.raises(T.TrimError) as e:
+        ctx.trim_csr(6, g.n, ro, col, opts=T.make_opts(schedule=4))   # unknown flag
     assert e.value.code == -1
     table = torch.zeros(256, dtype=torch.int64, device="cuda")
     with pytest.raises(T.TrimError) as e:
