@@ -58,24 +58,29 @@ __global__ void ac3_init(View g, int n, int* ptr, int* dround, int* list1, int* 
 }
 
 // Sense-free grid barrier: arrivals counted in *count, the last arrival resets
-// it and bumps *gen.  Agent-scope fences make every block's writes of the
-// round visible to every other block (and XCD) after the barrier.
+// it and bumps *gen.  Everything a round shares with later rounds (lists,
+// cursors, removal rounds) is written and read with device-coherent accesses,
+// so arriving after one's own stores have completed (s_waitcnt) is enough; no
+// agent-scope fence (a whole-L2 write-back and invalidate on gfx950) runs.
 __device__ __forceinline__ void grid_barrier(int* count, int* gen) {
+    complete_mem();
     __syncthreads();
     if (threadIdx.x == 0) {
         const int g0 = ld_dev(gen);
-        __threadfence();
         if (add_dev(count, 1) == (int)gridDim.x - 1) {
             st_dev(count, 0);
-            __threadfence();
+            complete_mem();
             add_dev(gen, 1);
         } else {
             while (ld_dev(gen) == g0) __builtin_amdgcn_s_sleep(2);
         }
-        __threadfence();
     }
     __syncthreads();
 }
+
+// kUnroll list entries per lane per step, their loads in flight together, and
+// one output reservation per wavefront per step.
+constexpr int kUnroll = 4;
 
 template <class View>
 __global__ __launch_bounds__(256) void ac3_rounds(View g, int* ptr, int* dround, int* list0,
@@ -85,35 +90,61 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int* ptr, int* dround,
     Stage3<View>::apply(g, lds);
     uint64_t edges = 0;
     int r = 1;
+    const int stride = gridDim.x * blockDim.x;
     for (;; ++r) {
         const int* in = (r & 1) ? list1 : list0;
         int* out = (r & 1) ? list0 : list1;
         const int cnt_in = ld_dev(ctr + kCnt0 + r % 3);
         int* cnt_out = ctr + kCnt0 + (r + 1) % 3;
         if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
-        for (int base = blockIdx.x * blockDim.x; base < cnt_in; base += gridDim.x * blockDim.x) {
-            const int i = base + threadIdx.x;
-            bool keep = false;
-            int v = 0;
-            if (i < cnt_in) {
-                v = in[i];
-                const int p0 = ptr[v];
-                const int e = g.end(v);
-                const int ctx = g.vctx(v);
-                int p = p0;
-                for (; p < e; ++p)
-                    if (dround[g.target(v, p, ctx)] >= r) break;
-                if (p < e) {
-                    edges += (uint64_t)(p - p0 + 1);
-                    if (p != p0) ptr[v] = p;
-                    keep = true;
+        for (int base = blockIdx.x * blockDim.x; base < cnt_in; base += stride * kUnroll) {
+            int v[kUnroll], p0[kUnroll], e[kUnroll];
+            bool keep[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                const int i = base + k * stride + threadIdx.x;
+                v[k] = i < cnt_in ? ld_dev(in + i) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k)
+                if (v[k] >= 0) {
+                    p0[k] = ld_dev(ptr + v[k]);
+                    e[k] = g.end(v[k]);
+                }
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                keep[k] = false;
+                if (v[k] < 0) continue;
+                const int ctx = g.vctx(v[k]);
+                int p = p0[k];
+                for (; p < e[k]; ++p)
+                    if (ld_dev(dround + g.target(v[k], p, ctx)) >= r) break;
+                if (p < e[k]) {
+                    edges += (uint64_t)(p - p0[k] + 1);
+                    if (p != p0[k]) st_dev(ptr + v[k], p);
+                    keep[k] = true;
                 } else {
-                    edges += (uint64_t)(e - p0);
-                    dround[v] = r;
+                    edges += (uint64_t)(e[k] - p0[k]);
+                    st_dev(dround + v[k], r);
                 }
             }
-            const int slot = wave_append_slot(keep, cnt_out, nullptr);
-            if (keep) out[slot] = v;
+            uint64_t masks[kUnroll];
+            int total = 0;
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                masks[k] = ballot(keep[k]);
+                total += popc(masks[k]);
+            }
+            if (total) {
+                int at = 0;
+                if (lane_id() == 0) at = add_dev(cnt_out, total);
+                at = __shfl(at, 0);
+#pragma unroll
+                for (int k = 0; k < kUnroll; ++k) {
+                    if (keep[k]) st_dev(out + at + popc(masks[k] & lanes_below()), v[k]);
+                    at += popc(masks[k]);
+                }
+            }
         }
         grid_barrier(ctr + kBarCount, ctr + kBarGen);
         if (ld_dev(cnt_out) == cnt_in) break;   // no removal in round r
