@@ -41,6 +41,10 @@ struct Stage3<ImplicitView> {
     }
 };
 
+// A list of live vertices holds, per entry, the vertex and the target of its
+// cursor (kNoTarget without successors), as two arrays of `n` ints.
+constexpr int kNoTarget = -1;
+
 template <class View>
 __global__ void ac3_init(View g, int n, int* ptr, int* dround, int* list1, int* ctr,
                          uint64_t* worker_edges, int P, trim_stats_t* stats) {
@@ -51,9 +55,11 @@ __global__ void ac3_init(View g, int n, int* ptr, int* dround, int* list1, int* 
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
-        ptr[v] = g.begin(v);
+        const int b = g.begin(v), e = g.end(v);
+        ptr[v] = b;
         dround[v] = INT_MAX;
         list1[v] = v;
+        list1[n + v] = b < e ? g.target(v, b, g.vctx(v)) : kNoTarget;
     }
 }
 
@@ -79,13 +85,15 @@ __device__ __forceinline__ void grid_barrier(int* count, int* gen) {
 }
 
 // kUnroll list entries per lane per step, their loads in flight together, and
-// one output reservation per wavefront per step.
+// one output reservation per wavefront per step.  An entry whose cursor target
+// is still live costs one random access (the target's removal round); only
+// when it has died are the cursor, the offsets and further successors read.
 constexpr int kUnroll = 4;
 
 template <class View>
-__global__ __launch_bounds__(256) void ac3_rounds(View g, int* ptr, int* dround, int* list0,
-                                                  int* list1, int* ctr, uint64_t* worker_edges,
-                                                  trim_stats_t* stats) {
+__global__ __launch_bounds__(256) void ac3_rounds(View g, int n, int* ptr, int* dround,
+                                                  int* list0, int* list1, int* ctr,
+                                                  uint64_t* worker_edges, trim_stats_t* stats) {
     __shared__ uint64_t lds[Stage3<View>::kWords];
     Stage3<View>::apply(g, lds);
     uint64_t edges = 0;
@@ -98,33 +106,45 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int* ptr, int* dround,
         int* cnt_out = ctr + kCnt0 + (r + 1) % 3;
         if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
         for (int base = blockIdx.x * blockDim.x; base < cnt_in; base += stride * kUnroll) {
-            int v[kUnroll], p0[kUnroll], e[kUnroll];
+            int v[kUnroll], w[kUnroll], d[kUnroll];
             bool keep[kUnroll];
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
                 const int i = base + k * stride + threadIdx.x;
-                v[k] = i < cnt_in ? ld_dev(in + i) : -1;
+                v[k] = -1;
+                if (i < cnt_in) {
+                    v[k] = ld_dev(in + i);
+                    w[k] = ld_dev(in + n + i);
+                }
             }
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k)
-                if (v[k] >= 0) {
-                    p0[k] = ld_dev(ptr + v[k]);
-                    e[k] = g.end(v[k]);
-                }
+                d[k] = (v[k] >= 0 && w[k] != kNoTarget) ? ld_dev(dround + w[k]) : 0;
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
                 keep[k] = false;
                 if (v[k] < 0) continue;
+                if (w[k] != kNoTarget && d[k] >= r) {   // the cursor edge, checked again
+                    edges += 1;
+                    keep[k] = true;
+                    continue;
+                }
+                // the cursor target is removed (or there is none): scan on
+                const int p0 = ld_dev(ptr + v[k]);
+                const int e = g.end(v[k]);
                 const int ctx = g.vctx(v[k]);
-                int p = p0[k];
-                for (; p < e[k]; ++p)
-                    if (ld_dev(dround + g.target(v[k], p, ctx)) >= r) break;
-                if (p < e[k]) {
-                    edges += (uint64_t)(p - p0[k] + 1);
-                    if (p != p0[k]) st_dev(ptr + v[k], p);
+                int p = p0 + 1, t = kNoTarget;
+                for (; p < e; ++p) {
+                    t = g.target(v[k], p, ctx);
+                    if (ld_dev(dround + t) >= r) break;
+                }
+                if (p < e) {
+                    edges += (uint64_t)(p - p0 + 1);
+                    st_dev(ptr + v[k], p);
+                    w[k] = t;
                     keep[k] = true;
                 } else {
-                    edges += (uint64_t)(e[k] - p0[k]);
+                    edges += (uint64_t)(e - p0);
                     st_dev(dround + v[k], r);
                 }
             }
@@ -141,7 +161,11 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int* ptr, int* dround,
                 at = __shfl(at, 0);
 #pragma unroll
                 for (int k = 0; k < kUnroll; ++k) {
-                    if (keep[k]) st_dev(out + at + popc(masks[k] & lanes_below()), v[k]);
+                    if (keep[k]) {
+                        const int slot = at + popc(masks[k] & lanes_below());
+                        st_dev(out + slot, v[k]);
+                        st_dev(out + n + slot, w[k]);
+                    }
                     at += popc(masks[k]);
                 }
             }
@@ -171,9 +195,10 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
                    uint64_t* worker_edges, trim_stats_t* stats) {
     const int P = lc.workers;
     int pack_blocks = 0;
-    int* ptr = w.a;
+    // lists: 2n ints each (vertices, cursor targets) in the two 8n-byte arrays
+    int* ptr = w.d;
     int* dround = w.c;
-    int* list1 = w.d;
+    int* list1 = reinterpret_cast<int*>(w.a);
     int* list0 = reinterpret_cast<int*>(w.b);
     {
         Timed t(lc, "ac3_init");
@@ -181,7 +206,9 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
                            lc.stream, g, n, ptr, dround, list1, w.ctr, worker_edges, P, stats);
     }
     if (n > 0) {
-        void* args[] = {&g, &ptr, &dround, &list0, &list1, (void*)&w.ctr, &worker_edges, &stats};
+        int nn = n;
+        void* args[] = {&g,     &nn,          &ptr,          &dround, &list0,
+                        &list1, (void*)&w.ctr, &worker_edges, &stats};
         {
             Timed t(lc, "ac3_rounds");
             hipError_t e = hipLaunchCooperativeKernel((const void*)ac3_rounds<View>, dim3(P),

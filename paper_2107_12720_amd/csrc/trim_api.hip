@@ -96,8 +96,15 @@ int ensure_tiles(trim_ctx* c, long long m) {
     return TRIM_OK;
 }
 
+// AC-3's single cooperative launch is limited to two workgroups per CU: a run
+// with eight per CU (the occupancy maximum) stopped making progress once, and
+// more workgroups only lengthen its grid barrier (one round costs more, not
+// less, beyond one per CU).
+constexpr int kAc3MaxPerCu = 2;
+
 int workers_for(trim_ctx* c, int algo, const trim_opts_t* o) {
     int per_cu = algo == TRIM_AC6 ? c->occ6 : algo == TRIM_AC4 ? c->occ4 : c->occ3;
+    if (algo == TRIM_AC3 && per_cu > kAc3MaxPerCu) per_cu = kAc3MaxPerCu;
     int max_p = per_cu * c->cus;
     int def = (algo == TRIM_AC3 ? 1 : (per_cu < 2 ? per_cu : 2)) * c->cus;
     int p = (o && o->workers > 0) ? o->workers : def;
