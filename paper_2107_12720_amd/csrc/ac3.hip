@@ -68,11 +68,16 @@ __global__ void ac3_init(View g, int n, int* ptr, int* dround, int* list1, int* 
 // cursors, removal rounds) is written and read with device-coherent accesses,
 // so arriving after one's own stores have completed (s_waitcnt) is enough; no
 // agent-scope fence (a whole-L2 write-back and invalidate on gfx950) runs.
+// The generation must be read before arriving: the two accesses go to
+// different addresses, and without the wait in between the read can be
+// performed after the last arrival has already bumped *gen; the block would
+// then wait for a release that never comes.
 __device__ __forceinline__ void grid_barrier(int* count, int* gen) {
     complete_mem();
     __syncthreads();
     if (threadIdx.x == 0) {
         const int g0 = ld_dev(gen);
+        complete_mem();   // g0 is read before this block can complete the barrier
         if (add_dev(count, 1) == (int)gridDim.x - 1) {
             st_dev(count, 0);
             complete_mem();

@@ -96,10 +96,12 @@ int ensure_tiles(trim_ctx* c, long long m) {
     return TRIM_OK;
 }
 
-// AC-3's single cooperative launch is limited to two workgroups per CU: a run
-// with eight per CU (the occupancy maximum) stopped making progress once, and
-// more workgroups only lengthen its grid barrier (one round costs more, not
-// less, beyond one per CU).
+// AC-3's single cooperative launch is limited to two workgroups per CU.  With
+// eight per CU (the occupancy maximum, 2,048 workgroups) the rounds kernel
+// stopped making progress, also after the barrier's generation read was
+// ordered before the arrival; the cause is not known, so that configuration
+// stays off.  More workgroups only lengthen the barrier anyway: a round costs
+// least at one per CU, the default.
 constexpr int kAc3MaxPerCu = 2;
 
 int workers_for(trim_ctx* c, int algo, const trim_opts_t* o) {
