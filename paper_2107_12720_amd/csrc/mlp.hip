@@ -58,21 +58,41 @@ struct Graph {
     const int* indeg;
     const int* src;
     long long m;
+    // per-vertex (log1p(outdeg), log1p(indeg)) when precomputed, else NULL
+    const float2* vf;
 };
+
+// (log1p(outdeg v), log1p(indeg v)) in FP32, the same expressions the edge
+// features use.
+__global__ void vertex_features(const int* row_off, const int* indeg, int n, float2* vf) {
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
+        vf[v] = make_float2(log1pf((float)(row_off[v + 1] - row_off[v])),
+                            log1pf((float)indeg[v]));
+}
 
 // This lane's four features (half 0: features 0-3, half 1: 4-7) of edge e.
 __device__ __forceinline__ void features(const Graph& g, long long e, int half, float f[4],
                                          int& u, int& w) {
     u = g.src[e];
     w = g.col[e];
-    const int du = g.row_off[u + 1] - g.row_off[u];
-    const int dw = g.row_off[w + 1] - g.row_off[w];
-    const float lu = log1pf((float)du), lw = log1pf((float)dw);
+    float lu, lw, iu, iw;
+    if (g.vf) {   // one 8-byte gather per endpoint
+        const float2 a = g.vf[u], b = g.vf[w];
+        lu = a.x;
+        iu = a.y;
+        lw = b.x;
+        iw = b.y;
+    } else {
+        lu = log1pf((float)(g.row_off[u + 1] - g.row_off[u]));
+        lw = log1pf((float)(g.row_off[w + 1] - g.row_off[w]));
+        iu = log1pf((float)g.indeg[u]);
+        iw = log1pf((float)g.indeg[w]);
+    }
     if (half == 0) {
         f[0] = lu;
-        f[1] = log1pf((float)g.indeg[u]);
+        f[1] = iu;
         f[2] = lw;
-        f[3] = log1pf((float)g.indeg[w]);
+        f[3] = iw;
     } else {
         const uint64_t h = mix64((uint64_t)(e - g.row_off[u]));
         f[0] = lu - lw;
@@ -320,7 +340,7 @@ hipError_t mlp_grad_launch(const int* row_off, const int* col, const int* indeg,
                            long long m, const uint32_t* live, const short* pbf,
                            const long long* ids, long long count, uint64_t seed, int step,
                            float* grad, int cus, hipStream_t s) {
-    Graph g{row_off, col, indeg, src, m};
+    Graph g{row_off, col, indeg, src, m, nullptr};
     const int blocks = grid_for((count + 31) / 32, 4, cus * 8);
     hipLaunchKernelGGL(mlp_grad, dim3(blocks), dim3(256), 0, s, g, live, pbf, ids, count, seed,
                        step, grad);
@@ -337,11 +357,15 @@ hipError_t mlp_adam_launch(float* p32, short* pbf, float* m1, float* m2, float* 
 }
 
 hipError_t mlp_score_launch(const int* row_off, const int* col, const int* indeg, const int* src,
-                            long long m, const short* pbf, float* score, int cus, hipStream_t s) {
-    Graph g{row_off, col, indeg, src, m};
-    if (m > 0)
+                            int n, long long m, const short* pbf, float* score, float2* vf,
+                            int cus, hipStream_t s) {
+    Graph g{row_off, col, indeg, src, m, vf};
+    if (m > 0) {
+        hipLaunchKernelGGL(vertex_features, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s,
+                           row_off, indeg, n, vf);
         hipLaunchKernelGGL(mlp_score, dim3(grid_for((m + 31) / 32, 4, cus * 16)), dim3(256), 0, s,
                            g, pbf, score);
+    }
     return hipGetLastError();
 }
 

@@ -25,6 +25,9 @@ struct trim_ctx {
     // per-XCD in-degree copies of trim_mlp_prepare
     int* copies = nullptr;
     long long cap_copies = 0;
+    // per-vertex features of trim_mlp_score (float2 per vertex)
+    float* vf = nullptr;
+    long long cap_vf = 0;
 };
 
 namespace {
@@ -225,6 +228,7 @@ int trim_ctx_destroy(trim_ctx* c) {
     (void)hipFree(c->w.part);
     (void)hipFree(c->tiles);
     (void)hipFree(c->copies);
+    (void)hipFree(c->vf);
     delete c;
     return TRIM_OK;
 }
@@ -438,8 +442,21 @@ int trim_mlp_score(trim_ctx* c, const trim_csr_t* g, const int32_t* indeg, const
     if (rc) return rc;
     if (!indeg || (g->m > 0 && (!src || !scores)) || !params_bf16)
         return fail(TRIM_E_INVAL, "trim_mlp_score: NULL argument");
-    return launched(trim::mlp_score_launch(g->row_off, g->col, indeg, src, g->m,
-                                           (const short*)params_bf16, scores, c->cus,
+    const long long need = 2LL * (g->n > 0 ? g->n : 1);   // float2 per vertex
+    if (need > c->cap_vf) {
+        (void)hipFree(c->vf);
+        c->vf = nullptr;
+        c->cap_vf = 0;
+        if (hipMalloc((void**)&c->vf, (size_t)need * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            c->vf = nullptr;
+            return fail(TRIM_E_NOMEM, "cannot allocate vertex features for %d vertices", g->n);
+        }
+        c->cap_vf = need;
+    }
+    return launched(trim::mlp_score_launch(g->row_off, g->col, indeg, src, g->n, g->m,
+                                           (const short*)params_bf16, scores,
+                                           reinterpret_cast<float2*>(c->vf), c->cus,
                                            (hipStream_t)stream));
 }
 

@@ -127,7 +127,8 @@ hipError_t mlp_grad_launch(const int* row_off, const int* col, const int* indeg,
 hipError_t mlp_adam_launch(float* p32, short* pbf, float* m1, float* m2, float* grad, float lr,
                            float beta1, float beta2, float eps, int step, hipStream_t s);
 hipError_t mlp_score_launch(const int* row_off, const int* col, const int* indeg, const int* src,
-                            long long m, const short* pbf, float* score, int cus, hipStream_t s);
+                            int n, long long m, const short* pbf, float* score, float2* vf,
+                            int cus, hipStream_t s);
 hipError_t edge_keys_launch(const int* row_off, const int* col, long long m, int kind,
                             uint64_t seed, float* key, hipStream_t s);
 hipError_t order_launch(const int* row_off, const int* col, int n, long long m, const float* key,
