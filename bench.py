@@ -252,6 +252,11 @@ def bench_explicit26(ctx, T, gg, reps):
                 "achieved_GBs": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9,
                 "frac": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9 / HBM_PEAK_GBS} for k in kavg}
     dom = max(kavg, key=kavg.get)
+    traffic = measured_traffic(dom, "rmat26")
+    if traffic is not None:
+        kern[dom]["traffic"] = traffic
+        kern[dom]["traffic_GBs"] = traffic / (kavg[dom] / 1e3) / 1e9
+        kern[dom]["traffic_frac"] = kern[dom]["traffic_GBs"] / HBM_PEAK_GBS
     bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
     path_bytes = 8 * st["edges_total"] + 20 * n + n // 8
     out = {"workload": "rmat26_ef16", "n": n, "m": m, "ms": ms, "edges_per_s": m / (ms / 1e3),
