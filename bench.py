@@ -40,10 +40,15 @@ def log(*a):
 
 
 def source_hash():
+    """Hash of the kernel sources with comments and blank space removed, so a
+    comment-only edit keeps a committed counter summary valid."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2107_12720_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2107_12720_amd", "csrc", f)) as fh:
+            code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

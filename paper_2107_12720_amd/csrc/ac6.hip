@@ -17,7 +17,8 @@
 //
 // The paper's Lock(w)/recheck/add and Lock(v)/DEAD/Unlock become lock-free:
 //   join   : rec[v] = (h, p); CAS(head[w], h, v)  -- fails once head[w] == kDead
-//   close  : L = exchange(head[v], kDead)         -- takes the whole list at once
+//   close  : one 8-byte exchange of both heads of v with kDead -- takes both
+//            lists whole at once
 // which gives the guarantee of the locks: after the close nobody joins S(v),
 // and everybody who joined before it is handed back exactly once.  Lanes of a
 // wavefront run in lock step, so a spinning lock would deadlock there.

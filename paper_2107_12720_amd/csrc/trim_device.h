@@ -75,9 +75,6 @@ __device__ __forceinline__ unsigned add_dev(unsigned* p, unsigned v) {
 __device__ __forceinline__ uint64_t add_dev(uint64_t* p, uint64_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ unsigned max_dev(unsigned* p, unsigned v) {
-    return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 // Wait until every vector memory operation this wave issued has completed.
 __device__ __forceinline__ void complete_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
