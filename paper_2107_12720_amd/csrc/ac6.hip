@@ -243,60 +243,74 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
     uint32_t item = kNone;
     uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
     while (wq.acquire(item)) {
-        uint32_t keep = kNone, push_a = kNone;
+        uint32_t keep = kNone;
+        // A walk member that finds no live successor is closed in the same
+        // iteration (its next member goes to the ring instead), so a peeling
+        // step through a supporter list costs one queue round, not two.
+        bool close_now = false;
+        int cx = 0;
+        bool member = false;
         if (item != kNone) {
             const int x = item_vertex(item);
             const uint32_t kind = item_kind(item);
-            if (kind != kWalkMore) {
-                // Close x, then follow S_last: its members have no successor left,
-                // so each is removed at once.  One step = one exchange of both
-                // list heads plus, for an S_last member, the load of its list
-                // link -- both in flight together, one round trip.
-                // The next step's memory operations are issued before this
-                // step's pushes, so the LDS queue work overlaps the round trip.
-                // Only the link half of a record is loaded: a 32-bit load, so no
-                // register of an in-flight load is reused by the pushes below.
-                bool member = kind == kCloseLast;
-                int link = member ? ld_dev(rec_link(rec, x)) : -1;
-                int2 ab = xchg2_dev(head + 2 * x, kDead, kDead);   // S_more(x), S_last(x)
-                int fill = 0;   // ring fill read after the previous step's pushes
-                for (int hop = 0;; ++hop) {
-                    closes += 1;
-                    // a dying vertex never joins a list again, so its record is stable
-                    const int sib = member ? link : -1;
-                    const int a = ab.x, b = ab.y;
-                    // depth first: into S_last(c) if it has members, else on to
-                    // the next member of the list c was in
-                    const int next = b >= 0 ? b : sib;
-                    visited += (b >= 0) + (sib >= 0);
-                    const bool go = next >= 0 && hop + 1 < kHops && fill <= kLocalQ - 256;
-                    if (go) {
-                        if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)next << 8) ^ hop);
-                        link = ld_dev(rec_link(rec, next));
-                        ab = xchg2_dev(head + 2 * next, kDead, kDead);
-                    }
-                    if (a >= 0) wq.push1(make_item(kWalkMore, a));
-                    if (b >= 0 && sib >= 0) wq.push1(make_item(kCloseLast, sib));
-                    fill = wq.fill();
-                    if (!go) {
-                        if (next >= 0) keep = make_item(kCloseLast, next);
-                        break;
-                    }
-                    member = true;
-                }
-            } else {
+            if (kind == kWalkMore) {
                 // read x's list link before x re-joins (which rewrites rec[x])
                 const uint64_t r = ld_dev(rec + x);
                 const int nx = rec_next(r);
                 visited += 1;
-                if (nx >= 0) keep = make_item(kWalkMore, nx);
                 if (sched & TRIM_SCHED_JITTER) jitter_nap(x);
-                if (resume(g, x, rec_cursor(r) + 1, head, rec, edges, sched)) joins += 1;
-                else push_a = make_item(kClose, x);
+                if (resume(g, x, rec_cursor(r) + 1, head, rec, edges, sched)) {
+                    joins += 1;
+                    if (nx >= 0) keep = make_item(kWalkMore, nx);
+                } else {
+                    if (nx >= 0) wq.push1(make_item(kWalkMore, nx));
+                    close_now = true;
+                    cx = x;
+                }
+            } else {
+                close_now = true;
+                cx = x;
+                member = kind == kCloseLast;
+            }
+        }
+        if (close_now) {
+            // Close cx, then follow S_last: its members have no successor left,
+            // so each is removed at once.  One step = one exchange of both list
+            // heads plus, for an S_last member, the load of its list link --
+            // both in flight together, one round trip.  The next step's memory
+            // operations are issued before this step's pushes, so the LDS queue
+            // work overlaps the round trip.  Only the link half of a record is
+            // loaded: a 32-bit load, so no register of an in-flight load is
+            // reused by the pushes below.
+            int link = member ? ld_dev(rec_link(rec, cx)) : -1;
+            int2 ab = xchg2_dev(head + 2 * cx, kDead, kDead);   // S_more(cx), S_last(cx)
+            int fill = 0;   // ring fill read after the previous step's pushes
+            for (int hop = 0;; ++hop) {
+                closes += 1;
+                // a dying vertex never joins a list again, so its record is stable
+                const int sib = member ? link : -1;
+                const int a = ab.x, b = ab.y;
+                // depth first: into S_last(c) if it has members, else on to the
+                // next member of the list c was in
+                const int next = b >= 0 ? b : sib;
+                visited += (b >= 0) + (sib >= 0);
+                const bool go = next >= 0 && hop + 1 < kHops && fill <= kLocalQ - 256;
+                if (go) {
+                    if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)next << 8) ^ hop);
+                    link = ld_dev(rec_link(rec, next));
+                    ab = xchg2_dev(head + 2 * next, kDead, kDead);
+                }
+                if (a >= 0) wq.push1(make_item(kWalkMore, a));
+                if (b >= 0 && sib >= 0) wq.push1(make_item(kCloseLast, sib));
+                fill = wq.fill();
+                if (!go) {
+                    if (next >= 0) keep = make_item(kCloseLast, next);
+                    break;
+                }
+                member = true;
             }
         }
         item = keep;
-        wq.push(push_a, kNone);
         wq.rebalance();
     }
     edges = block_sum(edges, red);
