@@ -20,6 +20,10 @@ Paper: "Efficient Parallel Graph Trimming by Arc-Consistency" (arXiv
 * :func:`counts` -- closed forms of the traversed-edge totals.
 * :func:`implicit_csr` -- materialises the hash-generated graph with the
   oracle's own SplitMix64 implementation.
+* :func:`peel2` -- two-sided trimming, the first improvement listed in
+  Section 4.1: a vertex must also keep a live predecessor (checked over G^T);
+  two counters per vertex, removed vertices processed in peeling-step order.
+* :func:`counts2` -- totals of the two-sided algorithms for a final live set.
 """
 from __future__ import annotations
 
@@ -73,6 +77,10 @@ def lib():
                                       ctypes.c_void_p]
         L.or_batch_peel.restype = ctypes.c_int64
         L.or_batch_peel.argtypes = [ctypes.c_int64, i64p, i32p, i32p, u8p, i64p, ctypes.c_int]
+        L.or_peel2.restype = ctypes.c_int64
+        L.or_peel2.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, i32p, i64p]
+        L.or_counts2.restype = ctypes.c_int64
+        L.or_counts2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i64p]
         L.or_num_threads.restype = ctypes.c_int
         L.or_fin64.restype = ctypes.c_uint64
         L.or_fin64.argtypes = [ctypes.c_uint64]
@@ -127,6 +135,43 @@ def peel(g) -> PeelResult:
     if nd < 0:
         raise MemoryError("oracle peel: allocation failed")
     return PeelResult(live, level, order[:nd].copy(), int(st[0]), int(st[1]), int(st[2]))
+
+
+@dataclass
+class Counts2:
+    T6live: int     # two-sided AC-6 checks made by the vertices that stay live
+    dead_lo: int    # least checks the removed vertices can make
+    dead_hi: int    # most checks the removed vertices can make
+    T4two: int      # two-sided AC-4: edges walked, both directions
+    n_live: int
+
+
+def peel2(g) -> PeelResult:
+    """Greatest vertex set in which every vertex keeps a live successor and a
+    live predecessor, plus the peeling step of every other vertex.
+    ``rev_edges`` counts the edges walked in both directions."""
+    ro, col = _csr(g)
+    live = np.empty(g.n, np.uint8)
+    level = np.empty(g.n, np.int32)
+    order = np.empty(max(g.n, 1), np.int32)
+    st = np.zeros(3, np.int64)
+    nd = lib().or_peel2(g.n, ro, col, live, level, order, st)
+    if nd < 0:
+        raise MemoryError("oracle peel2: allocation failed")
+    return PeelResult(live, level, order[:nd].copy(), int(st[0]), int(st[1]), int(st[2]))
+
+
+def counts2(g, rrow_off, rcol, live) -> Counts2:
+    """Totals of the two-sided algorithms for the live set ``live``, with G^T
+    given as (rrow_off, rcol) in the order the in-side scans use."""
+    ro, col = _csr(g)
+    rro = np.ascontiguousarray(rrow_off, dtype=np.int32)
+    rc = np.ascontiguousarray(rcol, dtype=np.int32)
+    out = np.zeros(5, np.int64)
+    r = lib().or_counts2(g.n, ro, col, rro, rc, np.ascontiguousarray(live, np.uint8), out)
+    if r != 0:
+        raise ValueError(f"oracle counts2: live vertex {-r - 1} lacks a live neighbour")
+    return Counts2(*[int(x) for x in out])
 
 
 def counts(g, res: PeelResult) -> Counts:

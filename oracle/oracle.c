@@ -30,6 +30,11 @@
  *                  implicit graphs) with this file's own SplitMix64.
  *   or_batch_peel  or_peel on every graph of a packed batch, one graph per
  *                  thread.
+ *   or_peel2       two-sided trimming: the improvement of Section 4.1 that
+ *                  also requires at least one live predecessor (the in-degree
+ *                  check over G^T), by two counters per vertex.
+ *   or_counts2     traversed-edge totals of the two-sided AC-4 algorithm and
+ *                  the schedule-independent part of the two-sided AC-6 one.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -378,4 +383,132 @@ int or_num_threads(void) {
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------- two-sided */
+/*
+ * Two-sided trimming (Section 4.1, first improvement: with G^T in memory a
+ * vertex must also keep an incoming edge from a live vertex).  Removes, one
+ * peeling step after the other, every vertex whose live out-degree or live
+ * in-degree is zero.  cout[v] starts at |v.post|, cin[v] at |v.pre| (both
+ * counted from offsets; duplicates and self-loops included).  A removed w
+ * decrements cout[u] once per edge u->w and cin[x] once per edge w->x.
+ *
+ * Outputs as for or_peel; stats[0] = number of peeling steps, stats[1] =
+ * n_live, stats[2] = edges walked during propagation (both directions).
+ */
+int64_t or_peel2(int32_t n, const int32_t *row_off, const int32_t *col, uint8_t *live,
+                 int32_t *level, int32_t *order, int64_t *stats) {
+    int64_t m = row_off[n];
+    int64_t *pre_off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *pre = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int64_t *fill = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *cout = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *cin = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!pre_off || !pre || !fill || !cout || !cin) {
+        free(pre_off); free(pre); free(fill); free(cout); free(cin);
+        return -1;
+    }
+    for (int64_t e = 0; e < m; ++e) pre_off[col[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) pre_off[v + 1] += pre_off[v];
+    memcpy(fill, pre_off, ((size_t)n + 1) * sizeof(int64_t));
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_off[u]; e < row_off[u + 1]; ++e) pre[fill[col[e]]++] = u;
+
+    int64_t qh = 0, qt = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        cout[v] = row_off[v + 1] - row_off[v];
+        cin[v] = pre_off[v + 1] - pre_off[v];
+        live[v] = 1;
+        level[v] = 0;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (cout[v] == 0 || cin[v] == 0) {
+            live[v] = 0;
+            level[v] = 1;
+            order[qt++] = v;
+        }
+    }
+    int64_t walked = 0;
+    int32_t steps = qt > 0 ? 1 : 0;
+    while (qh < qt) {
+        int32_t w = order[qh++];
+        /* w no longer supports its predecessors ... */
+        for (int64_t k = pre_off[w]; k < pre_off[w + 1]; ++k) {
+            int32_t u = pre[k];
+            ++walked;
+            cout[u] -= 1;
+            if (cout[u] == 0 && live[u]) {
+                live[u] = 0;
+                level[u] = level[w] + 1;
+                if (level[u] > steps) steps = level[u];
+                order[qt++] = u;
+            }
+        }
+        /* ... nor its successors */
+        for (int64_t k = row_off[w]; k < row_off[w + 1]; ++k) {
+            int32_t x = col[k];
+            ++walked;
+            cin[x] -= 1;
+            if (cin[x] == 0 && live[x]) {
+                live[x] = 0;
+                level[x] = level[w] + 1;
+                if (level[x] > steps) steps = level[x];
+                order[qt++] = x;
+            }
+        }
+    }
+    stats[0] = steps;
+    stats[1] = n - qt;
+    stats[2] = walked;
+    free(pre_off); free(pre); free(fill); free(cout); free(cin);
+    return qt;
+}
+
+/*
+ * Totals of the two-sided algorithms for a given final live set, with G^T as
+ * (rrow_off, rcol) in the order the in-side scans use.  fl_out(v) / fl_in(v)
+ * = index of the first LIVE successor / predecessor of a live v.
+ *   out[0] live part of two-sided AC-6 = sum_live (fl_out + 1 + fl_in + 1):
+ *          a live vertex's final supports are its first finally-live
+ *          neighbours on each side, whatever the schedule
+ *   out[1] least checks of the removed vertices = sum over removed vertices
+ *          with both degrees positive of min(deg, indeg): such a vertex dies
+ *          only after one side's scan has passed its whole list
+ *   out[2] most checks of the removed vertices = the same sum of deg + indeg
+ *   out[3] two-sided AC-4 = sum_dead (deg + indeg): every removed vertex
+ *          walks both of its lists once
+ *   out[4] n_live
+ * Returns 0, or -(v+1) for a live vertex without a live neighbour on a side.
+ */
+int64_t or_counts2(int32_t n, const int32_t *row_off, const int32_t *col,
+                   const int32_t *rrow_off, const int32_t *rcol, const uint8_t *live,
+                   int64_t *out) {
+    int64_t t_live = 0, lo = 0, hi = 0, t4 = 0, n_live = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t b = row_off[v], e = row_off[v + 1], rb = rrow_off[v], re = rrow_off[v + 1];
+        int64_t deg = e - b, indeg = re - rb;
+        if (live[v]) {
+            int64_t fo = -1, fi = -1;
+            for (int64_t k = b; k < e; ++k)
+                if (live[col[k]]) { fo = k - b; break; }
+            for (int64_t k = rb; k < re; ++k)
+                if (live[rcol[k]]) { fi = k - rb; break; }
+            if (fo < 0 || fi < 0) return -((int64_t)v + 1);
+            t_live += fo + 1 + fi + 1;
+            n_live += 1;
+        } else {
+            t4 += deg + indeg;
+            if (deg > 0 && indeg > 0) {
+                lo += deg < indeg ? deg : indeg;
+                hi += deg + indeg;
+            }
+        }
+    }
+    out[0] = t_live;
+    out[1] = lo;
+    out[2] = hi;
+    out[3] = t4;
+    out[4] = n_live;
+    return 0;
 }

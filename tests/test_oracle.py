@@ -369,3 +369,130 @@ def test_mlp_logits_hand_computed():
     want = np.sum(np.log1p(np.exp(-s)) * y + np.log1p(np.exp(s)) * (1 - y))
     loss, _ = mlp_ref.loss_and_grad(p, X, y, w, bf16=False)
     assert abs(loss - want) < 1e-12
+
+
+# --------------------------------------------------------- two-sided trimming
+def greatest_two_sided_by_subsets(n, adj_masks):
+    """Union of every subset S in which each vertex has a successor and a
+    predecessor in S (the in-degree improvement of Section 4.1); such sets are
+    closed under union, so this is the greatest one."""
+    pred = [0] * n
+    for u in range(n):
+        for v in range(n):
+            if (adj_masks[u] >> v) & 1:
+                pred[v] |= 1 << u
+    best = 0
+    for S in range(1 << n):
+        if all(not (S >> v) & 1 or ((adj_masks[v] & S) and (pred[v] & S)) for v in range(n)):
+            best |= S
+    return best
+
+
+def stepwise_peel2(adj):
+    """Peeling by whole steps: each step removes, all at once, every remaining
+    vertex without a remaining successor or without a remaining predecessor."""
+    n = len(adj)
+    pred = [[] for _ in range(n)]
+    for u in range(n):
+        for w in adj[u]:
+            pred[w].append(u)
+    alive = [True] * n
+    level = [0] * n
+    step = 0
+    while True:
+        step += 1
+        rm = [v for v in range(n) if alive[v] and
+              (not any(alive[w] for w in adj[v]) or not any(alive[u] for u in pred[v]))]
+        if not rm:
+            break
+        for v in rm:
+            alive[v] = False
+            level[v] = step
+    return alive, level
+
+
+def test_two_sided_hand_examples(orc, gen):
+    # 0 -> 1 <-> 2 -> 3: 0 has no predecessor, 3 no successor; the 2-cycle stays
+    g = gen.from_adjacency([[1], [2], [1, 3], []])
+    r = orc.peel2(g)
+    assert list(r.live) == [0, 1, 1, 0] and list(r.level) == [1, 0, 0, 1] and r.alpha == 1
+    rro, rcol = gen.transpose(g)
+    assert list(rcol[rro[1]:rro[2]]) == [0, 2]
+    c = orc.counts2(g, rro, rcol, r.live)
+    # live 1: successor 2 first (1 check); predecessors 0 (dead), 2 (2 checks)
+    # live 2: successor 1 first, predecessor 1 first: 2 checks
+    assert (c.T6live, c.dead_lo, c.dead_hi, c.T4two, c.n_live) == (5, 0, 0, 2, 2)
+    assert r.rev_edges == 2
+    # one-sided trimming keeps vertex 0 (it reaches the cycle)
+    assert list(orc.peel(g).live) == [1, 1, 1, 0]
+    # 0 -> 1 -> 2 with a self-loop on 2: removal runs forward along the path
+    g = gen.from_adjacency([[1], [2], [2]])
+    r = orc.peel2(g)
+    assert list(r.live) == [0, 0, 1] and list(r.level) == [1, 2, 0] and r.alpha == 2
+    rro, rcol = gen.transpose(g)
+    c = orc.counts2(g, rro, rcol, r.live)
+    # live 2: own self-loop found first as successor; predecessors 1 (dead), 2
+    assert (c.T6live, c.dead_lo, c.dead_hi, c.T4two) == (3, 1, 2, 3)
+    assert r.rev_edges == 3
+    # a directed cycle keeps everything, a path loses everything
+    assert orc.peel2(gen.from_adjacency([[1], [2], [0]])).n_live == 3
+    r = orc.peel2(gen.from_adjacency([[1], [2], [3], []]))
+    assert r.n_live == 0 and list(r.level) == [1, 2, 2, 1] and r.alpha == 2
+    # empty graph
+    r = orc.peel2(gen.from_adjacency([]))
+    assert r.n_live == 0 and r.alpha == 0
+
+
+def test_two_sided_exhaustive_three_and_four(orc, gen):
+    for n in (3, 4):
+        full = (1 << n) - 1
+        for code in range(1 << (n * n)):
+            masks = [(code >> (n * v)) & full for v in range(n)]
+            adj = [[w for w in range(n) if (masks[v] >> w) & 1] for v in range(n)]
+            g = gen.from_adjacency(adj)
+            r = orc.peel2(g)
+            got = sum(1 << v for v in range(n) if r.live[v])
+            assert got == greatest_two_sided_by_subsets(n, masks), (code, adj)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_two_sided_levels_by_whole_steps(orc, gen, seed):
+    rng = np.random.default_rng(seed)
+    for n, m in ((12, 14), (40, 50), (200, 260)):
+        src = rng.integers(0, n, m)
+        dst = rng.integers(0, n, m)
+        adj = [[] for _ in range(n)]
+        for s, d in zip(src, dst):
+            adj[int(s)].append(int(d))
+        g = gen.from_adjacency(adj)
+        r = orc.peel2(g)
+        alive, level = stepwise_peel2(adj)
+        assert list(r.live.astype(bool)) == alive
+        assert list(r.level) == level
+        assert r.alpha == max(level + [0])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_two_sided_reach_and_reached_from_cycle(orc, gen, seed):
+    """v survives two-sided trimming iff it reaches a cycle and a cycle reaches
+    it: the path from one cycle through v to the other, with both cycles, is a
+    set in which every vertex has both neighbours; conversely, following
+    predecessors (successors) inside a finite such set must close a cycle."""
+    for n, m in ((1000, 1100), (5000, 6500), (20000, 26000)):
+        g = gen.uniform(n, m, seed=seed * 5 + 3, drop_self=bool(seed % 2))
+        rro, rcol = gen.transpose(g)
+        gt = gen.CSR(g.n, rro, rcol)
+        r = orc.peel2(g)
+        fwd = reaches_cycle(g)
+        bwd = reaches_cycle(gt)
+        assert (r.live.astype(bool) == (fwd & bwd)).all()
+        # and equals one-sided trimming of G intersected with that of G^T
+        assert (r.live == (orc.peel(g).live & orc.peel(gt).live)).all()
+        c = orc.counts2(g, rro, rcol, r.live)
+        deg = np.diff(g.row_off)
+        indeg = np.diff(rro)
+        dead = r.live == 0
+        assert c.T4two == r.rev_edges == int((deg + indeg)[dead].sum())
+        both = dead & (deg > 0) & (indeg > 0)
+        assert c.dead_lo == int(np.minimum(deg, indeg)[both].sum())
+        assert c.n_live == r.n_live
