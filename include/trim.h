@@ -67,8 +67,8 @@ typedef struct {
     int64_t m;                /* edges, == row_off[n], 0 <= m < 2^31 */
     const int32_t *row_off;   /* (device) n+1 non-decreasing offsets, row_off[0] == 0 */
     const int32_t *col;       /* (device) m targets in [0, n); successor order = array order */
-    const int32_t *rrow_off;  /* (device) G^T offsets, n+1; AC-4 only, else NULL */
-    const int32_t *rcol;      /* (device) G^T sources, m; AC-4 only, else NULL */
+    const int32_t *rrow_off;  /* (device) G^T offsets, n+1; AC-4 and two-sided only */
+    const int32_t *rcol;      /* (device) G^T sources, m; AC-4 and two-sided only */
 } trim_csr_t;
 
 /*
@@ -164,6 +164,38 @@ int trim_num_workers(trim_ctx *ctx, int algo, const trim_opts_t *opts, int32_t *
  */
 int trim_csr(trim_ctx *ctx, int algo, const trim_csr_t *g, const trim_opts_t *opts,
              uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats, void *stream);
+
+/*
+ * Two-sided trimming of an explicit graph: the first improvement of Section
+ * 4.1 for implementations that hold G^T, where a vertex must also keep a
+ * live predecessor (its in-degree is checked too).  The result is the
+ * greatest vertex set in which every vertex has a successor and a predecessor
+ * inside the set, i.e. the vertices that reach a cycle and are reached from
+ * one (a self-loop counts as a cycle).
+ *   TRIM_AC6  every vertex keeps one support per side (a live successor and
+ *             a live predecessor), each found by the AC-6 support search
+ *             over its list in G or in G^T; a removed vertex hands back the
+ *             vertices it supported on either side.  worker_edges count
+ *             neighbour checks on both sides; their sum depends on the
+ *             schedule for removed vertices only.
+ *   TRIM_AC4  two counters per vertex (live successors, live predecessors),
+ *             both from offsets; every removed vertex walks its predecessor
+ *             and successor lists once, so the sum of worker_edges is
+ *             sum over removed v of (out-degree + in-degree).
+ *   TRIM_AC3  TRIM_E_UNSUPPORTED.
+ * g->rrow_off and g->rcol are required (TRIM_E_INVAL without them) and must
+ * hold the transpose of (row_off, col); the in-side scans follow rcol's order.
+ * opts.validate checks ranges and offsets of both, not that they are
+ * transposes of each other.  Outputs as for trim_csr, with worker_edges
+ * sized by trim_num_workers for the same algo.  Stats: closes (AC-6) counts
+ * the vertices removed after the start, i.e. those that had a successor and
+ * a predecessor; n_dead all removed vertices.  AC-6 uses 48 bytes per vertex
+ * of context memory beyond trim_csr (in-side lists and records, a larger
+ * queue), allocated on the first call.
+ */
+int trim_csr_two_sided(trim_ctx *ctx, int algo, const trim_csr_t *g, const trim_opts_t *opts,
+                       uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats,
+                       void *stream);
 
 /*
  * Trim an implicit graph (AC-6 or AC-3 only; AC-4 needs G^T and returns

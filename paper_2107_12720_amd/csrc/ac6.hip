@@ -47,6 +47,7 @@
 #include "trim_device.h"
 #include "trim_stats.h"
 #include "trim_internal.h"
+#include "ac6_support.h"
 
 namespace trim {
 
@@ -179,44 +180,6 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
         part[kPartSweep * kPartStride + blockIdx.x] = edges;
         part[kPartDeg * kPartStride + blockIdx.x] = degsum;
     }
-}
-
-// Resume DoPost of u from cursor position p0.  Returns true if u joined a
-// live successor's list; `edges` receives the positions checked.
-template <class View>
-__device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, uint64_t* rec,
-                                       uint64_t& edges, int sched) {
-    // kScan successors at a time: their targets, then their list heads, each
-    // group of loads in flight together, then the joins in list order.
-    constexpr int kScan = 4;
-    const int e = g.end(u);
-    const int ctx = g.vctx(u);
-    for (int p = p0; p < e; p += kScan) {
-        int w[kScan], h[kScan];
-#pragma unroll
-        for (int j = 0; j < kScan; ++j)
-            if (p + j < e) w[j] = g.target(u, p + j, ctx);
-#pragma unroll
-        for (int j = 0; j < kScan; ++j)
-            if (p + j < e) h[j] = ld_cached(head + 2 * w[j] + (p + j + 1 == e));
-#pragma unroll
-        for (int j = 0; j < kScan; ++j) {
-            if (p + j >= e) break;
-            int* slot = head + 2 * w[j] + (p + j + 1 == e);
-            int hj = h[j];
-            while (hj != kDead) {
-                st_dev(rec + u, pack_rec(hj, p + j));
-                complete_mem();
-                if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)u << 24) ^ (p + j));
-                if (cas_dev(slot, hj, u)) {
-                    edges += (uint64_t)(p + j - p0 + 1);
-                    return true;
-                }
-            }
-        }
-    }
-    edges += (uint64_t)(e - p0);
-    return false;
 }
 
 // Work items of the propagation:

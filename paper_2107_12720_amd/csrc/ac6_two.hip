@@ -1,0 +1,351 @@
+// ac6_two.hip -- two-sided AC-6 trimming on gfx950: the in-degree check of
+// Section 4.1 (with G^T in memory, a vertex must also keep a live
+// predecessor) applied to the AC-6-based algorithm (Section 6.2).
+//
+// A vertex stays only while it has a live successor and a live predecessor.
+// It keeps one support per side, each found by the AC-6 support search over
+// its own list: successors in G for the out-side, predecessors in G^T for the
+// in-side.  Each side has the list pair and records of the one-sided kernels
+// (ac6.hip):
+//   hout[2w], hout[2w+1]  S_more / S_last of the vertices whose out-support is w
+//   hin[2w],  hin[2w+1]   the same for the vertices whose in-support is w
+//   rec_out[v], rec_in[v] (next, cursor) of v in the list of its support
+// Removing x exchanges both pairs of x with kDead (one 8-byte exchange each).
+// That hands back the predecessors x supported (they resume their out-scans)
+// and the successors x supported (in-scans); members of an S_last list lose
+// their last neighbour on that side and are removed at once.  Each pair is a
+// lock of its own, as in the one-sided algorithm: its first exchange takes the
+// lists, a later one (a vertex removed from both sides at once) gets kDead.
+//
+// A vertex removed through one side may still be a member of a list on the
+// other side.  When that list is handed back the member is skipped (no scan)
+// and the walk goes on to the next member.  A member that dies during its own
+// scan may still join a list; it is skipped when that list is handed back.
+//
+// Checks per vertex: a live vertex ends with each support at its first
+// finally-live neighbour, so its checks do not depend on the schedule; a
+// removed one checks at most its two lists once, and at least the whole list
+// of the side that removed it.
+//
+// Kernels, in stream order: ac6t_init (list heads, the bitmap of vertices
+// without successors or predecessors, counters), ac6t_sweep (both support
+// searches per vertex; only that bitmap's vertices are removed while it runs,
+// so joining is a plain exchange), ac6t_propagate (persistent workers on
+// per-wavefront LDS rings), pack.
+#include "trim_device.h"
+#include "trim_stats.h"
+#include "trim_internal.h"
+#include "ac6_support.h"
+
+namespace trim {
+
+namespace {
+
+struct TwoGraph {
+    const int* row_off;
+    const int* col;
+    const int* rrow_off;
+    const int* rcol;
+    int* hout;
+    int* hin;
+    uint64_t* rec_out;
+    uint64_t* rec_in;
+};
+
+// Sets dead0 bit v iff v has no successor or no predecessor; each wavefront
+// covers 64 consecutive ids (the last may write one word past ceil(n/32),
+// which the buffer has).
+__global__ void ac6t_init(TwoGraph g, int n, uint32_t* dead0, int* ctr, uint64_t* worker_edges,
+                          int P, trim_stats_t* stats) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < kCtrInts) ctr[tid] = 0;
+    for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
+    if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
+    for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
+        const bool d = g.row_off[v + 1] == g.row_off[v] || g.rrow_off[v + 1] == g.rrow_off[v];
+        const int h = d ? kDead : kEmpty;
+        reinterpret_cast<int2*>(g.hout)[v] = make_int2(h, h);
+        reinterpret_cast<int2*>(g.hin)[v] = make_int2(h, h);
+        const uint64_t m = ballot(d);
+        if (lane_id() == 0) {
+            dead0[v >> 5] = (uint32_t)m;
+            dead0[(v >> 5) + 1] = (uint32_t)(m >> 32);
+        }
+    }
+}
+
+__device__ __forceinline__ bool bit(const uint32_t* bm, int v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+
+// First scan of one side of v over [b, e): the first neighbour outside dead0,
+// joined by exchange.  Returns false if there is none; `checks` receives the
+// positions checked.
+__device__ __forceinline__ bool first_join(const int* adj, int b, int e, const uint32_t* dead0,
+                                           int* head, uint64_t* rec, int v, uint64_t& checks,
+                                           int sched, uint64_t salt) {
+    int p = b, w = 0;
+    for (; p < e; ++p) {
+        w = __builtin_nontemporal_load(adj + p);
+        if (!bit(dead0, w)) break;
+    }
+    if (p == e) {
+        checks += (uint64_t)(e - b);
+        return false;
+    }
+    if (sched & TRIM_SCHED_JITTER) jitter_nap(salt);
+    const int old = xchg_dev(head + 2 * w + (p + 1 == e), v);
+    rec[v] = pack_rec(old, p);
+    checks += (uint64_t)(p - b + 1);
+    return true;
+}
+
+constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-queue append
+
+__global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, uint32_t* q,
+                           int* ctr, uint64_t* worker_edges, int P, uint64_t* part, int sched) {
+    __shared__ uint32_t cas[kCasBuf];
+    __shared__ int s_chunk, s_ncas, s_base;
+    __shared__ uint64_t red[16];
+    if (threadIdx.x == 0) s_ncas = 0;
+    uint64_t edges = 0, degsum = 0;
+    auto flush = [&]() {
+        __syncthreads();
+        const int k = s_ncas;
+        if (k > 0) {
+            if (threadIdx.x == 0) {
+                add_dev(ctr + kPending, k);
+                s_base = add_dev(ctr + kQTail, k);
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < k; i += blockDim.x) q[s_base + i] = cas[i];
+            __syncthreads();
+            if (threadIdx.x == 0) s_ncas = 0;
+        }
+        __syncthreads();
+    };
+    for (;;) {
+        if (threadIdx.x == 0) s_chunk = add_dev(ctr + kCursor, chunk);
+        __syncthreads();
+        const int claim = s_chunk;
+        __syncthreads();
+        if (claim >= n) break;
+        int cb = claim;
+        if (sched & TRIM_SCHED_REVERSE) cb = ((n + chunk - 1) / chunk - 1 - claim / chunk) * chunk;
+        const int ce = cb + chunk < n ? cb + chunk : n;
+        for (int base = cb; base < ce; base += blockDim.x) {
+            const int v = base + threadIdx.x;
+            bool casualty = false;
+            uint64_t mine = 0;
+            if (v < ce) {
+                const int b = g.row_off[v], e = g.row_off[v + 1];
+                const int rb = g.rrow_off[v], re = g.rrow_off[v + 1];
+                degsum += (uint64_t)(e - b);
+                if (b < e && rb < re) {
+                    const uint64_t salt = ((uint64_t)blockIdx.x << 32) ^ v;
+                    casualty = !first_join(g.col, b, e, dead0, g.hout, g.rec_out, v, mine, sched,
+                                           salt) ||
+                               !first_join(g.rcol, rb, re, dead0, g.hin, g.rec_in, v, mine, sched,
+                                           salt ^ 1);
+                }
+            }
+            edges += mine;
+            const uint64_t mask = ballot(casualty);
+            if (mask) {
+                int wbase = 0;
+                if (lane_id() == 0) wbase = atomicAdd(&s_ncas, popc(mask));
+                wbase = __shfl(wbase, 0);
+                if (casualty) cas[wbase + popc(mask & lanes_below())] = (uint32_t)v;
+            }
+            __syncthreads();
+            if (s_ncas > kCasBuf - (int)blockDim.x) flush();
+        }
+    }
+    flush();
+    edges = block_sum(edges, red);
+    degsum = block_sum(degsum, red);
+    if (threadIdx.x == 0) {
+        if (edges) add_dev(worker_edges + (blockIdx.x % P), edges);
+        part[kPartSweep * kPartStride + blockIdx.x] = edges;
+        part[kPartDeg * kPartStride + blockIdx.x] = degsum;
+    }
+}
+
+// Work items: a 3-bit kind above a 29-bit vertex id (n <= 2^29).
+//   CLOSE(x)        x lost every neighbour on one side: close both pairs of x;
+//   LAST_OUT(x)     x is a member of a closed S_last list on the out-side (its
+//                   last successor died): remove it; rec_out[x] links to the
+//                   next member;  LAST_IN(x) the same on the in-side;
+//   MORE_OUT(x)     x is a member of a closed S_more list on the out-side:
+//                   resume its out-scan (unless it is already removed), then
+//                   walk on to the next member;  MORE_IN(x) likewise.
+enum : uint32_t { kTClose = 0, kTLastOut = 1, kTLastIn = 2, kTMoreOut = 3, kTMoreIn = 4 };
+constexpr uint32_t kTIdMask = 0x1FFFFFFFu;
+__device__ __forceinline__ uint32_t titem(uint32_t kind, int v) { return (kind << 29) | (uint32_t)v; }
+__device__ __forceinline__ uint32_t last_kind(int side) { return side ? kTLastIn : kTLastOut; }
+constexpr int kTHops = 256;   // removals one item may chain in a row
+
+__global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, int* ctr,
+                                                      uint64_t* worker_edges, uint64_t* part,
+                                                      int sched) {
+    __shared__ uint32_t rings[256 / kWave][kLocalQ];
+    __shared__ int ring_tail[256 / kWave];
+    __shared__ uint64_t red[16];
+    WaveQueue wq;
+    const int wv = threadIdx.x / kWave;
+    wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending);
+    const ExplicitView out_view{g.row_off, g.col}, in_view{g.rrow_off, g.rcol};
+    uint32_t item = kNone;
+    uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
+    while (wq.acquire(item)) {
+        uint32_t keep = kNone;
+        bool close_now = false;
+        int cx = 0;
+        int side = -1;   // list of cx's S_last membership: 0 out, 1 in, -1 none
+        if (item != kNone) {
+            const int x = (int)(item & kTIdMask);
+            const uint32_t kind = item >> 29;
+            if (kind >= kTMoreOut) {
+                const bool in = kind == kTMoreIn;
+                // read x's link before x can re-join (which rewrites its record)
+                const uint64_t r = ld_dev((in ? g.rec_in : g.rec_out) + x);
+                const int nx = rec_next(r);
+                visited += 1;
+                bool stays = true;   // a removed member is skipped
+                if (ld_dev(g.hout + 2 * x) != kDead) {
+                    if (sched & TRIM_SCHED_JITTER) jitter_nap(x);
+                    stays = in ? resume(in_view, x, rec_cursor(r) + 1, g.hin, g.rec_in, edges, sched)
+                               : resume(out_view, x, rec_cursor(r) + 1, g.hout, g.rec_out, edges,
+                                        sched);
+                    joins += stays;
+                }
+                if (stays) {
+                    if (nx >= 0) keep = titem(kind, nx);
+                } else {
+                    if (nx >= 0) wq.push1(titem(kind, nx));
+                    close_now = true;
+                    cx = x;
+                }
+            } else {
+                close_now = true;
+                cx = x;
+                side = kind == kTLastOut ? 0 : kind == kTLastIn ? 1 : -1;
+            }
+        }
+        if (close_now) {
+            // Close cx and go on depth first: into S_last on the out-side, else
+            // on the in-side, else to the next member of cx's own S_last list.
+            // One step = the two pair exchanges plus, for a list member, the
+            // load of its link, all in flight together; the next step's memory
+            // operations are issued before this step's pushes.
+            int link = side >= 0 ? ld_dev(rec_link(side ? g.rec_in : g.rec_out, cx)) : -1;
+            int2 o = xchg2_dev(g.hout + 2 * cx, kDead, kDead);
+            int2 i = xchg2_dev(g.hin + 2 * cx, kDead, kDead);
+            int fill = 0;
+            for (int hop = 0;; ++hop) {
+                closes += (o.x != kDead);   // the out-pair's exchange counts the removal
+                const int ao = o.x, bo = o.y, ai = i.x, bi = i.y;
+                const int sib = side >= 0 ? link : -1;
+                int next = sib, nside = side;
+                if (bo >= 0) {
+                    next = bo;
+                    nside = 0;
+                } else if (bi >= 0) {
+                    next = bi;
+                    nside = 1;
+                }
+                visited += (bo >= 0) + (bi >= 0) + (sib >= 0);
+                const bool go = next >= 0 && hop + 1 < kTHops && fill <= kLocalQ - 256;
+                if (go) {
+                    if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)next << 8) ^ hop);
+                    link = ld_dev(rec_link(nside ? g.rec_in : g.rec_out, next));
+                    o = xchg2_dev(g.hout + 2 * next, kDead, kDead);
+                    i = xchg2_dev(g.hin + 2 * next, kDead, kDead);
+                }
+                if (ao >= 0) wq.push1(titem(kTMoreOut, ao));
+                if (ai >= 0) wq.push1(titem(kTMoreIn, ai));
+                if (bo >= 0 && bi >= 0) wq.push1(titem(kTLastIn, bi));
+                if ((bo >= 0 || bi >= 0) && sib >= 0) wq.push1(titem(last_kind(side), sib));
+                fill = wq.fill();
+                if (!go) {
+                    if (next >= 0) keep = titem(last_kind(nside), next);
+                    break;
+                }
+                side = nside;
+            }
+        }
+        item = keep;
+        wq.rebalance();
+    }
+    edges = block_sum(edges, red);
+    closes = block_sum(closes, red);
+    joins = block_sum(joins, red);
+    visited = block_sum(visited, red);
+    const int qhw = block_max(wq.hw, reinterpret_cast<int*>(red));
+    if (threadIdx.x == 0) {
+        if (edges) add_dev(worker_edges + blockIdx.x, edges);
+        part[kPartCloses * kPartStride + blockIdx.x] = closes;
+        part[kPartJoins * kPartStride + blockIdx.x] = joins;
+        part[kPartVisited * kPartStride + blockIdx.x] = visited;
+        part[kPartQhw * kPartStride + blockIdx.x] = (uint64_t)qhw;
+    }
+}
+
+struct TwoLive {
+    const int* hout;
+    __device__ __forceinline__ bool operator()(int v) const { return hout[2 * v] != kDead; }
+};
+
+inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
+    long long b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    if (b > max_blocks) b = max_blocks;
+    return (int)b;
+}
+
+}  // namespace
+
+hipError_t ac6_two_csr(const trim_csr_t& gc, const Work& w, const Work2& x, const LaunchCfg& lc,
+                       uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats) {
+    const int n = gc.n, P = lc.workers, B = lc.block;
+    TwoGraph g{gc.row_off, gc.col, gc.rrow_off, gc.rcol, w.a, x.hin, w.b, x.rec_in};
+    uint32_t* dead0 = reinterpret_cast<uint32_t*>(w.c);
+    int sweep_blocks = 0, pack_blocks = 0;
+    {
+        Timed t(lc, "ac6t_init");
+        hipLaunchKernelGGL(ac6t_init, dim3(grid_for(n, 256, 16384)), dim3(256), 0, lc.stream, g,
+                           n, dead0, w.ctr, worker_edges, P, stats);
+    }
+    if (n > 0) {
+        const int chunk = ((lc.chunk + B - 1) / B) * B;
+        sweep_blocks = grid_for(n, chunk, lc.cus * 8);
+        {
+            Timed t(lc, "ac6t_sweep");
+            hipLaunchKernelGGL(ac6t_sweep, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n, chunk,
+                               dead0, x.q, w.ctr, worker_edges, P, w.part, lc.schedule);
+        }
+        {
+            Timed t(lc, "ac6t_propagate");
+            hipLaunchKernelGGL(ac6t_propagate, dim3(P), dim3(256), 0, lc.stream, g, x.q, w.ctr,
+                               worker_edges, w.part, lc.schedule);
+        }
+        Timed t(lc, "ac6t_pack");
+        pack_blocks = grid_for(n, 256, lc.cus * 4);
+        hipLaunchKernelGGL(pack_bitmap<TwoLive>, dim3(pack_blocks), dim3(256), 0, lc.stream,
+                           TwoLive{w.a}, n, bitmap, w.part);
+    }
+    if (stats) {
+        Timed t(lc, "finalize");
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, sweep_blocks,
+                           n > 0 ? P : 0, pack_blocks, n > 0 ? P : 0, worker_edges, w.part,
+                           w.ctr, stats, 0);
+    }
+    return hipGetLastError();
+}
+
+int ac6_two_max_workers_per_cu(int) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ac6t_propagate, 256, 0) != hipSuccess)
+        return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+}  // namespace trim

@@ -13,7 +13,10 @@ struct trim_ctx {
     int cus = 0;
     size_t cap_n = 0;
     trim::Work w;
-    int occ6 = 0, occ4 = 0, occ3 = 0;   // resident workgroups per CU
+    // two-sided AC-6 extras, sized for cap_n2 vertices
+    size_t cap_n2 = 0;
+    trim::Work2 w2;
+    int occ6 = 0, occ4 = 0, occ3 = 0;   // resident workgroups per CU (occ6: both AC-6 forms)
     // captured launch sequence of trim_batch and the arguments it was made for
     hipGraphExec_t gexec = nullptr;
     uint64_t gkey[23] = {};
@@ -80,6 +83,36 @@ int ensure(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n = cap;
+    return TRIM_OK;
+}
+
+void free_work2(trim_ctx* c) {
+    (void)hipFree(c->w2.hin);
+    (void)hipFree(c->w2.rec_in);
+    (void)hipFree(c->w2.q);
+    c->w2 = trim::Work2{};
+    c->cap_n2 = 0;
+}
+
+// Two-sided AC-6 queues at most 7 items per vertex: one close, one S_last
+// member per side, one S_more list head per side and one failed scan per
+// side.  8n slots cover that.
+int ensure2(trim_ctx* c, int64_t n) {
+    size_t need = (size_t)(n > 0 ? n : 1);
+    if (need <= c->cap_n2) return TRIM_OK;
+    free_work2(c);
+    size_t cap = need + need / 8 + 64;
+    const size_t qbytes = cap * 32 + (size_t)trim::kQueueSlots * 4;
+    if (hipMalloc((void**)&c->w2.hin, cap * 8) != hipSuccess ||
+        hipMalloc((void**)&c->w2.rec_in, cap * 8) != hipSuccess ||
+        hipMalloc((void**)&c->w2.q, qbytes) != hipSuccess ||
+        hipMemset(c->w2.q, 0xFF, qbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        free_work2(c);
+        return fail(TRIM_E_NOMEM, "cannot allocate two-sided working memory for %lld vertices",
+                    (long long)n);
+    }
+    c->cap_n2 = cap;
     return TRIM_OK;
 }
 
@@ -199,6 +232,10 @@ int trim_ctx_create(trim_ctx** out, int device) {
     c->device = device;
     c->cus = prop.multiProcessorCount;
     c->occ6 = trim::ac6_max_workers_per_cu(256);
+    {
+        const int occ6t = trim::ac6_two_max_workers_per_cu(256);
+        if (occ6t < c->occ6) c->occ6 = occ6t;
+    }
     c->occ4 = trim::ac4_max_workers_per_cu(256);
     c->occ3 = trim::ac3_max_workers_per_cu(256);
     if ((e = hipMalloc((void**)&c->w.ctr, trim::kCtrInts * sizeof(int))) != hipSuccess ||
@@ -220,6 +257,7 @@ int trim_ctx_destroy(trim_ctx* c) {
     if (!c) return TRIM_OK;
     (void)hipSetDevice(c->device);
     free_work(c);
+    free_work2(c);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& ev : c->timer.ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -278,6 +316,45 @@ int trim_csr(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
         case TRIM_AC4: e = trim::ac4_csr(*g, c->w, lc, live_bitmap, worker_edges, stats); break;
         default: e = trim::ac3_csr(*g, c->w, lc, live_bitmap, worker_edges, stats); break;
     }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return TRIM_OK;
+}
+
+int trim_csr_two_sided(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
+                       uint32_t* live_bitmap, uint64_t* worker_edges, trim_stats_t* stats,
+                       void* stream) {
+    if (!c || !g) return fail(TRIM_E_INVAL, "trim_csr_two_sided: NULL context or graph");
+    if (algo == TRIM_AC3)
+        return fail(TRIM_E_UNSUPPORTED, "two-sided trimming is built for AC-6 and AC-4");
+    if (algo != TRIM_AC4 && algo != TRIM_AC6)
+        return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
+    if (g->n < 0 || g->n > (1 << 29)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
+    if (g->m < 0 || g->m >= (int64_t)1 << 31)
+        return fail(TRIM_E_INVAL, "m = %lld out of range [0, 2^31)", (long long)g->m);
+    if (!g->row_off || !g->rrow_off) return fail(TRIM_E_INVAL, "row_off or rrow_off is NULL");
+    if (g->m > 0 && (!g->col || !g->rcol)) return fail(TRIM_E_INVAL, "col or rcol is NULL");
+    if (g->n > 0 && !live_bitmap) return fail(TRIM_E_INVAL, "live_bitmap is NULL");
+    if (!worker_edges) return fail(TRIM_E_INVAL, "worker_edges is NULL");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((rc = ensure(c, g->n))) return rc;
+    if (algo == TRIM_AC6 && (rc = ensure2(c, g->n))) return rc;
+    trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
+    if (o && o->validate) {
+        int bad = 0;
+        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate");
+        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
+                                lc.stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate readback");
+        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
+    }
+    e = algo == TRIM_AC6
+            ? trim::ac6_two_csr(*g, c->w, c->w2, lc, live_bitmap, worker_edges, stats)
+            : trim::ac4_two_csr(*g, c->w, lc, live_bitmap, worker_edges, stats);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return TRIM_OK;
 }

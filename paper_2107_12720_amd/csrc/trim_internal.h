@@ -25,14 +25,22 @@ enum Ctr : int {
 
 // Working memory of one call, sized for n vertices (owned by trim_ctx).
 struct Work {
-    int* a = nullptr;         // 2n int32: AC-6 list heads / AC-4 counter / AC-3 cursor
-    uint64_t* b = nullptr;    // n uint64: AC-6 (next, cursor) records / AC-3 list
-    int* c = nullptr;         // n int32: queue / AC-3 removal round
-    int* d = nullptr;         // n int32: AC-3 list
+    int* a = nullptr;         // 2n int32: AC-6 (out-side) list heads / AC-4 counters /
+                              //   AC-3 list
+    uint64_t* b = nullptr;    // n uint64: AC-6 (out-side) records / AC-3 list
+    int* c = nullptr;         // n int32: AC-6 bitmap of vertices removed at the start /
+                              //   AC-3 removal round
+    int* d = nullptr;         // n int32: AC-3 cursor / two-sided AC-4 removal flags
     uint32_t* q = nullptr;    // 3n shared-queue slots, kNone between calls
     int* ctr = nullptr;       // kCtrInts control words
     uint64_t* wedges = nullptr;  // per-worker counts when the caller has none (batches)
     uint64_t* part = nullptr;    // per-block partial sums (kPartSlots x kPartStride)
+};
+// Extra working memory of two-sided AC-6 (allocated on its first use).
+struct Work2 {
+    int* hin = nullptr;         // 2n int32: in-side list heads
+    uint64_t* rec_in = nullptr; // n uint64: in-side (next, cursor) records
+    uint32_t* q = nullptr;      // 8n shared-queue slots (+ kQueueSlots), kNone between calls
 };
 constexpr int kMaxWorkers = 16384;
 // shared-queue slack beyond 3n slots: outstanding tickets, 64 per wavefront
@@ -93,10 +101,15 @@ hipError_t ac6_batch(int G, const int64_t* vbase, const int32_t* row_off, const 
                      const LaunchCfg& lc, uint32_t* bitmaps, uint64_t* graph_edges,
                      trim_stats_t* stats);
 int ac6_max_workers_per_cu(int block);
+hipError_t ac6_two_csr(const trim_csr_t& g, const Work& w, const Work2& x, const LaunchCfg& lc,
+                       uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
+int ac6_two_max_workers_per_cu(int block);
 
 // ------------------------------------------------------------------ AC-4
 hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
                    uint64_t* worker_edges, trim_stats_t* stats);
+hipError_t ac4_two_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
+                       uint64_t* worker_edges, trim_stats_t* stats);
 int ac4_max_workers_per_cu(int block);
 
 // ------------------------------------------------------------------ AC-3
