@@ -15,7 +15,9 @@ Also reported on the same JSON line:
   cpu_baseline  the oracle (sequential peel) timed on this host on the same graph;
   breakdown     every kernel's average duration;
   baselines     AC-4 and AC-3 on the same graph (one or a few runs each);
-  depth         alpha times the measured per-step latency of a bare chain.
+  depth         alpha times the measured per-step latency of a bare chain;
+  two_sided     two-sided trimming (live successor and live predecessor) of the
+                same graph with AC-6 and AC-4, kernel bytes and the oracle's time.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-baselines]
 """
@@ -31,8 +33,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edges/s + graphs/s: batched/learned-order AC-6 vs plain AC-6, bit-exact live set"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("ac6.hip", "ac4.hip", "ac3.hip", "trim_device.h", "trim_stats.h",
-                  "trim_internal.h", "trim_api.hip")
+KERNEL_SOURCES = ("ac6.hip", "ac6_support.h", "ac6_two.hip", "ac4.hip", "ac3.hip",
+                  "trim_device.h", "trim_stats.h", "trim_internal.h", "trim_api.hip")
 
 
 def log(*a):
@@ -97,6 +99,100 @@ def sweep_bytes(n, checks, joins, casualties):
     n/8-byte sinks bitmap, read once), 16 B per join (head exchange + record
     store), 4 B per queued casualty."""
     return 4 * (n + 1) + n // 8 + 4 * checks + 16 * joins + 4 * casualties
+
+
+def first_ok(row_off, col, ok):
+    """Per vertex: index in its list of the first neighbour with ok[] set, or -1."""
+    import numpy as np
+    start = row_off[:-1].astype(np.int64)
+    end = row_off[1:].astype(np.int64)
+    good = np.flatnonzero(ok[col]) if col.size else np.zeros(0, np.int64)
+    j = np.searchsorted(good, start)
+    first = np.where(j < good.size, good[np.minimum(j, max(good.size - 1, 0))], -1) \
+        if good.size else np.full(start.shape, -1)
+    has = (first >= start) & (first < end)
+    return np.where(has, first - start, -1)
+
+
+def two_sided_sweep_counts(g, rro, rcol):
+    """(checks, joins, casualties) of the two-sided first sweep.  Vertices
+    without a successor or a predecessor are the only ones removed while it
+    runs; every other vertex scans its successors for the first one not
+    removed, and only if it finds one, its predecessors likewise."""
+    import numpy as np
+    deg = np.diff(g.row_off.astype(np.int64))
+    indeg = np.diff(rro.astype(np.int64))
+    alive0 = (deg > 0) & (indeg > 0)
+    fo = first_ok(g.row_off, g.col, alive0)
+    fi = first_ok(rro, rcol, alive0)
+    out_ok = alive0 & (fo >= 0)
+    in_ok = out_ok & (fi >= 0)
+    checks = np.where(out_ok, fo + 1, deg)[alive0].sum() + np.where(fi >= 0, fi + 1, indeg)[out_ok].sum()
+    joins = int(out_ok.sum() + in_ok.sum())
+    return int(checks), joins, int((alive0 & ~in_ok).sum())
+
+
+def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps):
+    """Two-sided trimming (a live successor and a live predecessor, Section 4.1)
+    of the same graph: AC-6 and AC-4, with the kernels' algorithmic bytes."""
+    import numpy as np
+    n, m = g.n, g.m
+    rro, rcl = T.to_device(rro_h), T.to_device(rcol_h)
+    ms6, kt6, res6 = time_gpu(ctx, lambda: ctx.trim_csr_two_sided(T.AC6, n, ro, col, rro, rcl),
+                              reps, 1)
+    st6 = res6.stats_dict()
+    ms4, kt4, res4 = time_gpu(ctx, lambda: ctx.trim_csr_two_sided(T.AC4, n, ro, col, rro, rcl),
+                              reps, 1)
+    st4 = res4.stats_dict()
+    # depth: a bare 100,000-vertex path whose first vertex has a self-loop
+    # peels from its sink end only, one removal per step, like the planted chain
+    L = 100000
+    s_ = np.r_[np.arange(L - 1, dtype=np.int32), np.int32(0)]
+    d_ = np.r_[np.arange(1, L, dtype=np.int32), np.int32(0)]
+    import graphgen as gg
+    gc = gg.from_edges(L, s_, d_)
+    rc_t = gg.transpose(gc)
+    dc = [T.to_device(x) for x in (gc.row_off, gc.col, rc_t[0], rc_t[1])]
+    ms_chain, _, res_c = time_gpu(ctx, lambda: ctx.trim_csr_two_sided(T.AC6, L, *dc), 3, 1)
+    chain_ok = res_c.stats_dict()["n_live"] == 1
+    sc, sj, scas = two_sided_sweep_counts(g, rro_h, rcol_h)
+    # bytes per unit: 4 B per read or write, 8 B per 4-byte atomic, 16 B per
+    # 8-byte exchange (the paper's per-edge and per-vertex terms, both sides)
+    algo = {
+        "ac6t_init": 8 * (n + 1) + 16 * n + n // 8,
+        "ac6t_sweep": 8 * (n + 1) + n // 8 + 4 * sc + 16 * sj + 4 * scas,
+        "ac6t_propagate": (8 * (st6["edges_total"] - st6["edges_sweep"]) + 32 * st6["closes"]
+                           + 16 * st6["joins"] + 8 * st6["visited"]),
+        "ac6t_pack": 8 * n + n // 8,
+    }
+    k6 = {k: float(np.mean(v)) for k, v in kt6.items()}
+    kernels = {k: {"avg_ms": v, "algorithmic_bytes": int(algo.get(k, 0)),
+                   "achieved_GBs": algo.get(k, 0) / (v / 1e3) / 1e9,
+                   "frac": algo.get(k, 0) / (v / 1e3) / 1e9 / HBM_PEAK_GBS} for k, v in k6.items()}
+    dom = max(k6, key=k6.get)
+    # AC-4: per removed vertex its two offsets pairs and queue slot (16 B), per
+    # walked edge the neighbour id and the counter fetch-add (12 B)
+    b4 = 12 * st4["edges_total"] + 8 * n + 16 * st4["n_dead"] + n // 8
+    out = {"workload": "rmat22_ef16_chain100k", "n": n, "m": m,
+           "ac6": {"ms": ms6, "edges_per_s": m / (ms6 / 1e3), "traversed": st6["edges_total"],
+                   "n_live": st6["n_live"], "closes": st6["closes"], "joins": st6["joins"],
+                   "sweep_checks_match": sc == st6["edges_sweep"],
+                   "kernels": kernels, "dominant": dom,
+                   "roofline": {"bound": "hbm", "kernel": dom,
+                                "achieved": kernels[dom]["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": kernels[dom]["frac"]},
+                   "parity": None},
+           "ac4": {"ms": ms4, "edges_per_s": m / (ms4 / 1e3), "traversed": st4["edges_total"],
+                   "n_live": st4["n_live"],
+                   "kernels_ms": {k: float(np.mean(v)) for k, v in kt4.items()},
+                   "algorithmic_bytes": b4, "path_GBs": b4 / (ms4 / 1e3) / 1e9,
+                   "parity": None},
+           "ac6_speedup_vs_ac4": ms4 / ms6,
+           "depth": {"chain_hop_us": ms_chain * 1e3 / (L - 1), "chain_live_ok": chain_ok}}
+    checks = {"rro": rro_h, "rcol": rcol_h,
+              "ac6": {"bitmap": res6.bitmap_numpy().copy(), "edges": st6["edges_total"]},
+              "ac4": {"bitmap": res4.bitmap_numpy().copy(), "edges": st4["edges_total"]}}
+    return checks, out
 
 
 def time_gpu(ctx, fn, steps, warmup):
@@ -380,6 +476,24 @@ def oracle_leg(g, checks, cpu_seconds, out):
                            and checks["ac3"]["edges"] == c.T3J
                            and checks["ac3"]["rounds"] == c.rounds3)
         b.update({"T3J": c.T3J})
+    if "two_sided" in checks:
+        tc, to = checks["two_sided"], out["two_sided"]
+        t = time.perf_counter()
+        r2 = oracle.peel2(g)
+        t2 = time.perf_counter() - t
+        c2 = oracle.counts2(g, tc["rro"], tc["rcol"], r2.live)
+        bm2 = oracle.bitmap(r2.live)
+        to["oracle"] = {"s": t2, "edges_per_s": g.m / t2, "cores": 1,
+                        "sample": "one run of the two-sided sequential peel on the same graph"}
+        to["alpha"] = r2.alpha
+        to["depth"]["floor_ms"] = r2.alpha * to["depth"]["chain_hop_us"] / 1e3
+        to["ac6"]["parity"] = bool(np.array_equal(tc["ac6"]["bitmap"], bm2)
+                                   and c2.T6live + c2.dead_lo <= tc["ac6"]["edges"]
+                                   <= c2.T6live + c2.dead_hi)
+        to["ac6"]["T6live"] = c2.T6live
+        to["ac4"]["parity"] = bool(np.array_equal(tc["ac4"]["bitmap"], bm2)
+                                   and tc["ac4"]["edges"] == c2.T4two)
+        to["ac4"]["T4two"] = c2.T4two
     if "depth" in out:
         out["depth"]["alpha"] = r.alpha
         out["depth"]["floor_ms"] = r.alpha * out["depth"]["chain_hop_us"] / 1e3
@@ -430,6 +544,8 @@ def main():
     ap.add_argument("--no-explicit26", action="store_true",
                     help="skip the explicit R-MAT scale-26 graph")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-order section")
+    ap.add_argument("--no-two-sided", action="store_true",
+                    help="skip two-sided trimming (AC-6 and AC-4) of the same graph")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size "
@@ -523,7 +639,7 @@ def main():
         ms_chain, _, _ = time_gpu(ctx, lambda: ctx.trim_csr(T.AC6, gc.n, rc_, cc_), 3, 1)
         hop_us = ms_chain * 1e3 / 100000
         out["depth"] = {"chain_hop_us": hop_us}
-        a, b = gg.transpose(g)
+        a, b = gt = gg.transpose(g)
         rro, rcl = T.to_device(a), T.to_device(b)
         ms4, kt4, res4 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC4, n, ro, col, rro, rcl), 3, 1)
         st4 = res4.stats_dict()
@@ -547,6 +663,12 @@ def main():
                 "kernels_ms": {k: float(np.mean(v)) for k, v in kt3.items()}}
             out["baselines"]["ac6_speedup_vs_ac3"] = ms3 / ms
 
+    if not args.no_two_sided:
+        if args.no_baselines:
+            gt = gg.transpose(g)
+        checks["two_sided"], out["two_sided"] = bench_two_sided(ctx, T, g, ro, col, gt[0], gt[1], 5)
+        log(f"two-sided: AC-6 {out['two_sided']['ac6']['ms']:.3f} ms, "
+            f"AC-4 {out['two_sided']['ac4']['ms']:.3f} ms")
     if not args.no_batch:
         checks["batch"], out["batch"] = bench_batch(ctx, T, gg, 10)
         log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s")
