@@ -20,6 +20,9 @@ Paper: "Efficient Parallel Graph Trimming by Arc-Consistency" (arXiv
 * :func:`counts` -- closed forms of the traversed-edge totals.
 * :func:`implicit_csr` -- materialises the hash-generated graph with the
   oracle's own SplitMix64 implementation.
+* :func:`peel` and :func:`counts` with ``preset`` -- some vertices set to DEAD
+  before trimming starts (the vertex sampling of the scalability experiments,
+  Section 9).
 * :func:`peel2` -- two-sided trimming, the first improvement listed in
   Section 4.1: a vertex must also keep a live predecessor (checked over G^T);
   two counters per vertex, removed vertices processed in peeling-step order.
@@ -77,6 +80,11 @@ def lib():
                                       ctypes.c_void_p]
         L.or_batch_peel.restype = ctypes.c_int64
         L.or_batch_peel.argtypes = [ctypes.c_int64, i64p, i32p, i32p, u8p, i64p, ctypes.c_int]
+        L.or_peel_preset.restype = ctypes.c_int64
+        L.or_peel_preset.argtypes = [ctypes.c_int32, i32p, i32p, u8p, u8p, i32p, i32p, i64p]
+        L.or_counts_preset.restype = ctypes.c_int64
+        L.or_counts_preset.argtypes = [ctypes.c_int32, i32p, i32p, u8p, u8p, i32p,
+                                       ctypes.c_int32, i64p]
         L.or_peel2.restype = ctypes.c_int64
         L.or_peel2.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, i32p, i64p]
         L.or_counts2.restype = ctypes.c_int64
@@ -123,15 +131,26 @@ def _csr(g):
             np.ascontiguousarray(g.col, dtype=np.int32))
 
 
-def peel(g) -> PeelResult:
+def _preset(g, preset):
+    p = np.ascontiguousarray(preset, dtype=np.uint8)
+    if p.shape != (g.n,):
+        raise ValueError("preset must hold one flag per vertex")
+    return p
+
+
+def peel(g, preset=None) -> PeelResult:
     """Greatest vertex set in which every vertex keeps a live successor, plus the
-    peeling step of every other vertex."""
+    peeling step of every other vertex.  With ``preset`` (one flag per vertex),
+    the flagged vertices are DEAD from the start (level 0, not in ``order``)."""
     ro, col = _csr(g)
     live = np.empty(g.n, np.uint8)
     level = np.empty(g.n, np.int32)
     order = np.empty(max(g.n, 1), np.int32)
     st = np.zeros(3, np.int64)
-    nd = lib().or_peel(g.n, ro, col, live, level, order, st)
+    if preset is not None:
+        nd = lib().or_peel_preset(g.n, ro, col, _preset(g, preset), live, level, order, st)
+    else:
+        nd = lib().or_peel(g.n, ro, col, live, level, order, st)
     if nd < 0:
         raise MemoryError("oracle peel: allocation failed")
     return PeelResult(live, level, order[:nd].copy(), int(st[0]), int(st[1]), int(st[2]))
@@ -174,11 +193,16 @@ def counts2(g, rrow_off, rcol, live) -> Counts2:
     return Counts2(*[int(x) for x in out])
 
 
-def counts(g, res: PeelResult) -> Counts:
-    """Closed-form traversed-edge totals for the given (oracle) result."""
+def counts(g, res: PeelResult, preset=None) -> Counts:
+    """Closed-form traversed-edge totals for the given (oracle) result; pass the
+    same ``preset`` as to :func:`peel`."""
     ro, col = _csr(g)
     out = np.zeros(8, np.int64)
-    rc = lib().or_counts(g.n, ro, col, res.live, res.level, res.alpha, out)
+    if preset is not None:
+        rc = lib().or_counts_preset(g.n, ro, col, _preset(g, preset), res.live, res.level,
+                                    res.alpha, out)
+    else:
+        rc = lib().or_counts(g.n, ro, col, res.live, res.level, res.alpha, out)
     if rc != 0:
         raise ValueError(f"oracle counts: live vertex {-rc - 1} has no live successor")
     return Counts(*[int(x) for x in out])

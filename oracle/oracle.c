@@ -30,6 +30,9 @@
  *                  implicit graphs) with this file's own SplitMix64.
  *   or_batch_peel  or_peel on every graph of a packed batch, one graph per
  *                  thread.
+ *   or_peel_preset / or_counts_preset  or_peel and or_counts with some
+ *                  vertices set to DEAD before trimming starts (the vertex
+ *                  sampling of the scalability experiments, Section 9).
  *   or_peel2       two-sided trimming: the improvement of Section 4.1 that
  *                  also requires at least one live predecessor (the in-degree
  *                  check over G^T), by two counters per vertex.
@@ -510,5 +513,129 @@ int64_t or_counts2(int32_t n, const int32_t *row_off, const int32_t *col,
     out[2] = hi;
     out[3] = t4;
     out[4] = n_live;
+    return 0;
+}
+
+/* ------------------------------------------------------ preset removals */
+/*
+ * or_peel with the vertices marked in preset[] (1 = DEAD from the start)
+ * removed before the first step: they get level 0, are propagated first
+ * (their predecessors lose them as successors), and are not in order[].
+ * Every other vertex follows or_peel: a vertex left without a live successor
+ * is removed at 1 + the largest level among its successors.
+ * stats[0] = alpha (max level of the vertices removed by trimming), stats[1]
+ * = n_live, stats[2] = reverse edges traversed (preset vertices included).
+ * Returns the number of vertices removed by trimming (not counting preset).
+ */
+int64_t or_peel_preset(int32_t n, const int32_t *row_off, const int32_t *col,
+                       const uint8_t *preset, uint8_t *live, int32_t *level, int32_t *order,
+                       int64_t *stats) {
+    int64_t m = row_off[n];
+    int64_t *pre_off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int32_t *pre = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int64_t *fill = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *cnt = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int32_t *q = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    if (!pre_off || !pre || !fill || !cnt || !q) {
+        free(pre_off); free(pre); free(fill); free(cnt); free(q);
+        return -1;
+    }
+    for (int64_t e = 0; e < m; ++e) pre_off[col[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) pre_off[v + 1] += pre_off[v];
+    memcpy(fill, pre_off, ((size_t)n + 1) * sizeof(int64_t));
+    for (int32_t u = 0; u < n; ++u)
+        for (int64_t e = row_off[u]; e < row_off[u + 1]; ++e) pre[fill[col[e]]++] = u;
+
+    int64_t qh = 0, qt = 0, nd = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        cnt[v] = row_off[v + 1] - row_off[v];
+        live[v] = 1;
+        level[v] = 0;
+    }
+    /* the preset removals first (level 0), then the out-degree-0 vertices */
+    for (int32_t v = 0; v < n; ++v)
+        if (preset[v]) {
+            live[v] = 0;
+            q[qt++] = v;
+        }
+    for (int32_t v = 0; v < n; ++v)
+        if (!preset[v] && cnt[v] == 0) {
+            live[v] = 0;
+            level[v] = 1;
+            q[qt++] = v;
+            order[nd++] = v;
+        }
+    int64_t rev = 0;
+    int32_t alpha = nd > 0 ? 1 : 0;
+    while (qh < qt) {
+        int32_t w = q[qh++];
+        for (int64_t k = pre_off[w]; k < pre_off[w + 1]; ++k) {
+            int32_t u = pre[k];
+            ++rev;
+            cnt[u] -= 1;
+            if (cnt[u] == 0 && live[u]) {
+                live[u] = 0;
+                level[u] = level[w] + 1;
+                if (level[u] > alpha) alpha = level[u];
+                q[qt++] = u;
+                order[nd++] = u;
+            }
+        }
+    }
+    stats[0] = alpha;
+    stats[1] = n - qt;
+    stats[2] = rev;
+    free(pre_off); free(pre); free(fill); free(cnt); free(q);
+    return nd;
+}
+
+/*
+ * or_counts for a run with preset removals: preset vertices make no checks
+ * of their own (they never run DoPost or a sweep), and a successor that is
+ * preset counts as removed from the start.
+ *   out[0] T6  = sum_{removed by trimming} deg + sum_live (fl + 1)
+ *   out[1] T4* = sum_{all removed, preset included} indeg
+ *   out[2] T4  = m + T4*
+ *   out[3] T3J = sum_{removed by trimming} (deg + level - 1)
+ *                + sum_live (fl + alpha + 1)
+ *   out[4] rounds = alpha + 1, out[5] T6min, out[6] m, out[7] n_live
+ */
+int64_t or_counts_preset(int32_t n, const int32_t *row_off, const int32_t *col,
+                         const uint8_t *preset, const uint8_t *live, const int32_t *level,
+                         int32_t alpha, int64_t *out) {
+    int64_t m = row_off[n];
+    int64_t *indeg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!indeg) return -1;
+    for (int64_t e = 0; e < m; ++e) indeg[col[e]]++;
+    int64_t t6 = 0, t4s = 0, t3 = 0, t6min = 0, n_live = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t b = row_off[v], e = row_off[v + 1], deg = e - b;
+        if (live[v]) {
+            int64_t fl = -1;
+            for (int64_t k = b; k < e; ++k)
+                if (live[col[k]]) { fl = k - b; break; }
+            if (fl < 0) { free(indeg); return -((int64_t)v + 1); }
+            t6 += fl + 1;
+            t3 += fl + (int64_t)alpha + 1;
+            t6min += 1;
+            n_live += 1;
+        } else {
+            t4s += indeg[v];
+            if (!preset[v]) {
+                t6 += deg;
+                t3 += deg + (int64_t)level[v] - 1;
+                t6min += deg;
+            }
+        }
+    }
+    out[0] = t6;
+    out[1] = t4s;
+    out[2] = m + t4s;
+    out[3] = t3;
+    out[4] = (int64_t)alpha + 1;
+    out[5] = t6min;
+    out[6] = m;
+    out[7] = n_live;
+    free(indeg);
     return 0;
 }

@@ -496,3 +496,143 @@ def test_two_sided_reach_and_reached_from_cycle(orc, gen, seed):
         both = dead & (deg > 0) & (indeg > 0)
         assert c.dead_lo == int(np.minimum(deg, indeg)[both].sum())
         assert c.n_live == r.n_live
+
+
+# ------------------------------------------------- vertices removed up front
+def literal_runs_with_preset(adj, preset):
+    """The three algorithms run step by step with the preset vertices DEAD from
+    the start (vertex sampling, Section 9), counting every check:
+    sequential AC-6 (Section 6.1: DoPost from a cursor, supporters handed back
+    when their support dies), Jacobi AC-3 with cursor (Section 4.1 and the
+    edge_index of Section 8), and AC-4 with counters from offsets (Section 5.1,
+    AC4Trim* of Section 9.3; every removed vertex, preset ones included, walks
+    its predecessors).  Returns (live, t6, t3, rounds, t4)."""
+    n = len(adj)
+    pred = [[] for _ in range(n)]
+    for u in range(n):
+        for w in adj[u]:
+            pred[w].append(u)
+    # AC-6
+    live = [not preset[v] for v in range(n)]
+    cur = [0] * n
+    S = [[] for _ in range(n)]
+    t6 = 0
+
+    def dopost(v, Q):
+        nonlocal t6
+        while cur[v] < len(adj[v]):
+            w = adj[v][cur[v]]
+            cur[v] += 1
+            t6 += 1
+            if live[w]:
+                S[w].append(v)
+                return
+        live[v] = False
+        Q.append(v)
+
+    for v in range(n):
+        if not live[v]:
+            continue
+        Q = []
+        dopost(v, Q)
+        while Q:
+            w = Q.pop()
+            members, S[w] = S[w], []
+            for u in members:
+                dopost(u, Q)
+    live6 = live
+    # Jacobi AC-3
+    INF = 1 << 60
+    dround = [0 if preset[v] else INF for v in range(n)]
+    cur = [0] * n
+    t3 = rounds = 0
+    while True:
+        rounds += 1
+        changed = False
+        for v in range(n):
+            if dround[v] != INF:
+                continue
+            while cur[v] < len(adj[v]):
+                t3 += 1
+                if dround[adj[v][cur[v]]] >= rounds:
+                    break
+                cur[v] += 1
+            else:
+                dround[v] = rounds
+                changed = True
+        if not changed:
+            break
+    # AC-4*
+    cnt = [len(adj[v]) for v in range(n)]
+    dead = [bool(preset[v]) for v in range(n)]
+    Q = [v for v in range(n) if preset[v]] + [v for v in range(n) if not preset[v] and cnt[v] == 0]
+    for v in Q:
+        dead[v] = True
+    t4 = 0
+    while Q:
+        w = Q.pop()
+        for u in pred[w]:
+            t4 += 1
+            cnt[u] -= 1
+            if cnt[u] == 0 and not dead[u]:
+                dead[u] = True
+                Q.append(u)
+    assert [dround[v] == INF for v in range(n)] == live6 == [not d for d in dead]
+    return live6, t6, t3, rounds, t4
+
+
+def test_preset_exhaustive_three_vertices(orc, gen):
+    n = 3
+    for code in range(1 << (n * n)):
+        masks = [(code >> (n * v)) & 0x7 for v in range(n)]
+        adj = [[w for w in range(n) if (masks[v] >> w) & 1] for v in range(n)]
+        g = gen.from_adjacency(adj)
+        for pm in range(1 << n):
+            preset = np.array([(pm >> v) & 1 for v in range(n)], np.uint8)
+            keep = [m & ~pm for m in masks]
+            want = greatest_by_subsets(n, [keep[v] if not (pm >> v) & 1 else 0
+                                           for v in range(n)]) & ~pm
+            r = orc.peel(g, preset=preset)
+            assert sum(1 << v for v in range(n) if r.live[v]) == want, (code, pm)
+            c = orc.counts(g, r, preset=preset)
+            live, t6, t3, rounds, t4 = literal_runs_with_preset(adj, preset)
+            assert list(r.live.astype(bool)) == live
+            assert (c.T6, c.T3J, c.rounds3, c.T4s) == (t6, t3, rounds, t4), (code, pm)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_preset_equals_induced_subgraph(orc, gen, seed):
+    """Removing the preset vertices first is trimming the subgraph they leave:
+    same live set, same peeling steps."""
+    rng = np.random.default_rng(seed)
+    for n, m, ratio in ((500, 700, 0.3), (4000, 5200, 0.5), (20000, 30000, 0.9)):
+        g = gen.uniform(n, m, seed=seed * 11 + n)
+        preset = (rng.random(n) >= ratio).astype(np.uint8)
+        keep = np.flatnonzero(preset == 0)
+        new_id = np.full(n, -1, np.int64)
+        new_id[keep] = np.arange(keep.size)
+        adj = []
+        for v in keep:
+            succ = g.col[g.row_off[v]:g.row_off[v + 1]]
+            adj.append([int(new_id[w]) for w in succ if new_id[w] >= 0])
+        sub = orc.peel(gen.from_adjacency(adj))
+        r = orc.peel(g, preset=preset)
+        assert (r.live[keep] == sub.live).all() and not r.live[preset == 1].any()
+        assert (r.level[keep] == sub.level).all() and (r.level[preset == 1] == 0).all()
+        assert r.alpha == sub.alpha and r.n_dead == sub.n_dead
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_preset_totals_by_literal_runs(orc, gen, seed):
+    rng = np.random.default_rng(100 + seed)
+    for n, m in ((60, 80), (300, 420), (2000, 2600)):
+        g = gen.uniform(n, m, seed=seed * 13 + n)
+        adj = [list(g.col[g.row_off[v]:g.row_off[v + 1]]) for v in range(n)]
+        for ratio in (0.1, 0.5, 1.0):
+            preset = (rng.random(n) >= ratio).astype(np.uint8)
+            r = orc.peel(g, preset=preset)
+            c = orc.counts(g, r, preset=preset)
+            live, t6, t3, rounds, t4 = literal_runs_with_preset(adj, preset)
+            assert list(r.live.astype(bool)) == live
+            assert (c.T6, c.T3J, c.rounds3, c.T4s) == (t6, t3, rounds, t4), (n, ratio)
+            assert r.rev_edges == c.T4s
