@@ -196,6 +196,33 @@ def rmat(scale: int, edge_factor: int = 16, seed: int = 0, chain: int = 0,
     return g
 
 
+def sample_vertices(n: int, ratio: float, seed: int = 0):
+    """Vertex sampling of the scalability experiments: each vertex is kept with
+    probability `ratio`; the others are to be removed before trimming.
+    Returns (preset uint8[n], 1 = not sampled; the same flags as a uint32
+    bitmap of ceil(n/32) words, bit v % 32 of word v // 32)."""
+    rng = np.random.default_rng([seed & MASK64, 0x5653414D])   # stream tag "VSAM"
+    preset = (rng.random(n) >= ratio).astype(np.uint8)
+    words = (n + 31) // 32
+    bits = np.zeros(max(words, 1) * 32, np.uint8)
+    bits[:n] = preset
+    bm = np.packbits(bits, bitorder="little").view(np.uint32)[:max(words, 1)].copy()
+    return preset, bm
+
+
+def sample_edges(g: CSR, ratio: float, seed: int = 0) -> CSR:
+    """Edge sampling of the scalability experiments: each edge is kept with
+    probability `ratio`, in its list order; the others are dropped."""
+    rng = np.random.default_rng([seed & MASK64, 0x4553414D])   # stream tag "ESAM"
+    keep = rng.random(g.m) < ratio
+    src = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_off.astype(np.int64)))
+    cnt = np.bincount(src[keep], minlength=g.n)
+    row_off = np.zeros(g.n + 1, np.int32)
+    np.cumsum(cnt, out=row_off[1:])
+    return CSR(g.n, row_off, g.col[keep].astype(np.int32),
+               dict(g.meta, edge_sample=ratio, edge_sample_seed=seed))
+
+
 def transpose(g: CSR):
     """(rrow_off, rcol): the transposed graph G^T in CSR form."""
     rrow_off = np.zeros(g.n + 1, np.int32)

@@ -166,6 +166,25 @@ int trim_csr(trim_ctx *ctx, int algo, const trim_csr_t *g, const trim_opts_t *op
              uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats, void *stream);
 
 /*
+ * Trimming with some vertices removed before it starts: the vertex sampling
+ * of the scalability experiments (Section 9), where unsampled vertices are set
+ * to DEAD.  As trim_csr, plus preset_dead (device, ceil(n/32) words, the
+ * live_bitmap layout; bits at positions >= n are ignored): a set bit removes
+ * that vertex from the start.  The live set is the trimmed graph of the
+ * subgraph the other vertices induce.  Preset vertices make no checks of
+ * their own; a preset successor is passed like any removed one.  Totals:
+ * AC-6 sum over vertices removed by trimming of deg + sum over live v of
+ * (fl(v) + 1); AC-4 sum over every removed vertex, preset ones included, of
+ * its in-degree (their removal is propagated); AC-3 as for trim_csr over the
+ * vertices removed by trimming, alpha counting their peeling steps only.
+ * stats.n_dead includes the preset vertices.  preset_dead may be NULL only
+ * when n == 0 (TRIM_E_INVAL otherwise).
+ */
+int trim_csr_preset(trim_ctx *ctx, int algo, const trim_csr_t *g, const uint32_t *preset_dead,
+                    const trim_opts_t *opts, uint32_t *live_bitmap, uint64_t *worker_edges,
+                    trim_stats_t *stats, void *stream);
+
+/*
  * Two-sided trimming of an explicit graph: the first improvement of Section
  * 4.1 for implementations that hold G^T, where a vertex must also keep a
  * live predecessor (its in-degree is checked too).  The result is the

@@ -29,7 +29,8 @@ ALGOS = {"ac3": AC3, "ac4": AC4, "ac6": AC6}
 STATUS = {0: "TRIM_OK", -1: "TRIM_E_INVAL", -2: "TRIM_E_NOMEM", -3: "TRIM_E_HIP",
           -4: "TRIM_E_UNSUPPORTED", -5: "TRIM_E_BADGRAPH", -6: "TRIM_E_STALLED"}
 EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destroy",
-           "trim_num_workers", "trim_csr", "trim_csr_two_sided", "trim_implicit", "trim_batch",
+           "trim_num_workers", "trim_csr", "trim_csr_preset", "trim_csr_two_sided",
+           "trim_implicit", "trim_batch",
            "trim_ctx_set_timing", "trim_ctx_kernel_times", "trim_mlp_prepare", "trim_mlp_grad",
            "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key")
 MLP_PARAMS = 1377
@@ -81,6 +82,8 @@ def lib():
                                        ctypes.POINTER(i32)]
         L.trim_csr.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(Opts),
                                vp, vp, vp, vp]
+        L.trim_csr_preset.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc), vp,
+                                      ctypes.POINTER(Opts), vp, vp, vp, vp]
         L.trim_csr_two_sided.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc),
                                          ctypes.POINTER(Opts), vp, vp, vp, vp]
         L.trim_implicit.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ImplicitDesc),
@@ -100,7 +103,7 @@ def lib():
         L.trim_edge_keys.argtypes = [vp, csr_p, i32, ctypes.c_uint64, vp, vp]
         L.trim_order_by_key.argtypes = [vp, csr_p, vp, f32, f32, vp, vp]
         for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_num_workers", "trim_csr",
-                  "trim_csr_two_sided",
+                  "trim_csr_preset", "trim_csr_two_sided",
                   "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times",
                   "trim_mlp_prepare", "trim_mlp_grad", "trim_mlp_adam", "trim_mlp_score",
                   "trim_edge_keys", "trim_order_by_key"):
@@ -229,6 +232,29 @@ class Context:
         _check(lib().trim_csr(self._h, int(algo), ctypes.byref(d), ctypes.byref(opts),
                               ctypes.c_void_p(lb.data_ptr()), ctypes.c_void_p(we.data_ptr()),
                               ctypes.c_void_p(st.data_ptr()), _stream_handle(stream, self.device)))
+        return TrimResult(lb, we, st)
+
+    def trim_csr_preset(self, algo, n, row_off, col, preset_dead, rrow_off=None, rcol=None, *,
+                        live_bitmap=None, worker_edges=None, stats=None,
+                        opts: Opts | None = None, stream=None) -> TrimResult:
+        """Trim with the vertices set in ``preset_dead`` (int32 device bitmap of
+        ceil(n/32) words) removed from the start; algo 3/4/6."""
+        import torch
+        algo = ALGOS.get(algo, algo)
+        opts = opts or Opts()
+        m = int(col.numel()) if col is not None else 0
+        d = CsrDesc(int(n), m, _dev_ptr(row_off, torch.int32, "row_off"),
+                    _dev_ptr(col, torch.int32, "col") if m else None,
+                    _dev_ptr(rrow_off, torch.int32, "rrow_off", allow_none=True),
+                    _dev_ptr(rcol, torch.int32, "rcol", allow_none=True) if m else None)
+        pd = _dev_ptr(preset_dead, torch.int32, "preset_dead", allow_none=int(n) == 0)
+        P = self.num_workers(algo, opts)
+        lb, we, st = self._outputs((int(n) + 31) // 32, P, live_bitmap, worker_edges, stats)
+        _check(lib().trim_csr_preset(self._h, int(algo), ctypes.byref(d), pd, ctypes.byref(opts),
+                                     ctypes.c_void_p(lb.data_ptr()),
+                                     ctypes.c_void_p(we.data_ptr()),
+                                     ctypes.c_void_p(st.data_ptr()),
+                                     _stream_handle(stream, self.device)))
         return TrimResult(lb, we, st)
 
     def trim_csr_two_sided(self, algo, n, row_off, col, rrow_off, rcol, *, live_bitmap=None,

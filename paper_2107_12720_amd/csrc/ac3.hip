@@ -45,21 +45,47 @@ struct Stage3<ImplicitView> {
 // cursor (kNoTarget without successors), as two arrays of `n` ints.
 constexpr int kNoTarget = -1;
 
+// With a preset bitmap (vertices removed before trimming, the vertex sampling
+// of Section 9) those vertices get removal round 0, so every round reads them
+// as DEAD, and the first list is built by ac3_list_preset without them.
 template <class View>
-__global__ void ac3_init(View g, int n, int* ptr, int* dround, int* list1, int* ctr,
-                         uint64_t* worker_edges, int P, trim_stats_t* stats) {
+__global__ void ac3_init(View g, int n, const uint32_t* preset, int* ptr, int* dround,
+                         int* list1, int* ctr, uint64_t* worker_edges, int P,
+                         trim_stats_t* stats) {
     __shared__ uint64_t lds[Stage3<View>::kWords];
     Stage3<View>::apply(g, lds);
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid < kCtrInts) ctr[tid] = (tid == kCnt0 + 1) ? n : 0;
+    if (tid < kCtrInts) ctr[tid] = (tid == kCnt0 + 1 && !preset) ? n : 0;
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
         const int b = g.begin(v), e = g.end(v);
         ptr[v] = b;
-        dround[v] = INT_MAX;
-        list1[v] = v;
-        list1[n + v] = b < e ? g.target(v, b, g.vctx(v)) : kNoTarget;
+        if (preset) {
+            dround[v] = ((preset[v >> 5] >> (v & 31)) & 1u) ? 0 : INT_MAX;
+        } else {
+            dround[v] = INT_MAX;
+            list1[v] = v;
+            list1[n + v] = b < e ? g.target(v, b, g.vctx(v)) : kNoTarget;
+        }
+    }
+}
+
+// The first list without the preset vertices (wavefront-aggregated appends;
+// the order of the list does not matter to the rounds).
+template <class View>
+__global__ void ac3_list_preset(View g, int n, const uint32_t* preset, int* list1, int* ctr) {
+    __shared__ uint64_t lds[Stage3<View>::kWords];
+    Stage3<View>::apply(g, lds);
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int v = base + threadIdx.x;
+        const bool keep = v < n && !((preset[v >> 5] >> (v & 31)) & 1u);
+        const int slot = wave_append_slot(keep, ctr + kCnt0 + 1, nullptr);
+        if (keep) {
+            const int b = g.begin(v), e = g.end(v);
+            list1[slot] = v;
+            list1[n + slot] = b < e ? g.target(v, b, g.vctx(v)) : kNoTarget;
+        }
     }
 }
 
@@ -197,7 +223,7 @@ inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
 
 template <class View>
 hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats) {
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset = nullptr) {
     const int P = lc.workers;
     int pack_blocks = 0;
     // lists: 2n ints each (vertices, cursor targets) in the two 8n-byte arrays
@@ -208,7 +234,13 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     {
         Timed t(lc, "ac3_init");
         hipLaunchKernelGGL(ac3_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           lc.stream, g, n, ptr, dround, list1, w.ctr, worker_edges, P, stats);
+                           lc.stream, g, n, preset, ptr, dround, list1, w.ctr, worker_edges, P,
+                           stats);
+    }
+    if (preset && n > 0) {
+        Timed t(lc, "ac3_list_preset");
+        hipLaunchKernelGGL(ac3_list_preset<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
+                           lc.stream, g, n, preset, list1, w.ctr);
     }
     if (n > 0) {
         int nn = n;
@@ -235,9 +267,9 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
 }  // namespace
 
 hipError_t ac3_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats) {
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset) {
     ExplicitView v{g.row_off, g.col};
-    return ac3_run(v, g.n, w, lc, bitmap, worker_edges, stats);
+    return ac3_run(v, g.n, w, lc, bitmap, worker_edges, stats, preset);
 }
 
 hipError_t ac3_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,

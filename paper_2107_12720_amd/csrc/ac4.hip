@@ -29,16 +29,20 @@ namespace trim {
 
 namespace {
 
+// A preset vertex (removed before trimming) starts at cnt = 0: it is queued
+// like an out-degree-0 vertex, and its counter only goes negative after that,
+// so no decrement ever returns 1 for it.
 template <bool kTwo>
-__global__ void ac4_init(const int* row_off, const int* rrow_off, int n, int* cnt, int* dead,
-                         int* ctr, uint64_t* worker_edges, int P, trim_stats_t* stats) {
+__global__ void ac4_init(const int* row_off, const int* rrow_off, const uint32_t* preset, int n,
+                         int* cnt, int* dead, int* ctr, uint64_t* worker_edges, int P,
+                         trim_stats_t* stats) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < kCtrInts) ctr[tid] = 0;
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
         const int d = row_off[v + 1] - row_off[v];
-        cnt[v] = d;
+        cnt[v] = (preset && ((preset[v >> 5] >> (v & 31)) & 1u)) ? 0 : d;
         if (kTwo) {
             const int di = rrow_off[v + 1] - rrow_off[v];
             cnt[n + v] = di;
@@ -204,14 +208,14 @@ inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
 
 template <bool kTwo>
 hipError_t ac4_run(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats) {
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset) {
     const int n = g.n, P = lc.workers, B = lc.block;
     int pack_blocks = 0;
     {
         Timed t(lc, kTwo ? "ac4t_init" : "ac4_init");
         hipLaunchKernelGGL(ac4_init<kTwo>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           lc.stream, g.row_off, g.rrow_off, n, w.a, w.d, w.ctr, worker_edges, P,
-                           stats);
+                           lc.stream, g.row_off, g.rrow_off, preset, n, w.a, w.d, w.ctr,
+                           worker_edges, P, stats);
     }
     if (n > 0) {
         {
@@ -243,13 +247,13 @@ hipError_t ac4_run(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
 }  // namespace
 
 hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats) {
-    return ac4_run<false>(g, w, lc, bitmap, worker_edges, stats);
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset) {
+    return ac4_run<false>(g, w, lc, bitmap, worker_edges, stats, preset);
 }
 
 hipError_t ac4_two_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
                        uint64_t* worker_edges, trim_stats_t* stats) {
-    return ac4_run<true>(g, w, lc, bitmap, worker_edges, stats);
+    return ac4_run<true>(g, w, lc, bitmap, worker_edges, stats, nullptr);
 }
 
 int ac4_max_workers_per_cu(int) {

@@ -32,8 +32,10 @@
 //
 // Kernels, in stream order:
 //   ac6_init       heads = kDead for out-degree-0 vertices (their lists are
-//                  empty, nothing to hand back), kEmpty otherwise; the sinks
-//                  bitmap; counters and outputs zeroed.
+//                  empty, nothing to hand back) and for vertices removed
+//                  before trimming (the optional preset bitmap: the vertex
+//                  sampling of Section 9), kEmpty otherwise; the sinks bitmap
+//                  marks both; counters and outputs zeroed.
 //   ac6_sweep      DoPost for every vertex, one lane per vertex.  Only sinks
 //                  are removed while this kernel runs, so a target is live iff
 //                  its sinks bit is clear, and joining is a plain exchange (no
@@ -69,14 +71,15 @@ struct Stage<ImplicitView> {
     }
 };
 
-// Also writes sinks[]: bit v set iff v has no successor.  During the first
-// sweep these are the only removed vertices, so the sweep tests this small,
-// cache-resident bitmap instead of a list head in HBM.  Each wavefront covers
-// 64 consecutive ids (blockDim and the grid stride are multiples of 64); the
-// last wavefront may write one word past ceil(n/32), which the buffer has.
+// Also writes sinks[]: bit v set iff v has no successor or is preset.  During
+// the first sweep these are the only removed vertices, so the sweep tests this
+// small, cache-resident bitmap instead of a list head in HBM.  Each wavefront
+// covers 64 consecutive ids (blockDim and the grid stride are multiples of
+// 64); the last wavefront may write one word past ceil(n/32), which the
+// buffer has.
 template <class View>
-__global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, int* ctr,
-                         uint64_t* worker_edges, int P, trim_stats_t* stats) {
+__global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, const uint32_t* preset,
+                         int* ctr, uint64_t* worker_edges, int P, trim_stats_t* stats) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     Stage<View>::apply(g, lds);
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,7 +87,8 @@ __global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, int* ctr,
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
-        const bool sink = g.end(v) == g.begin(v);
+        const bool sink =
+            g.end(v) == g.begin(v) || (preset && ((preset[v >> 5] >> (v & 31)) & 1u));
         const int h = sink ? kDead : kEmpty;
         reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
         const uint64_t m = ballot(sink);
@@ -99,8 +103,8 @@ constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-
 
 template <class View>
 __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* sinks,
-                          uint64_t* rec, uint32_t* q, int* ctr, uint64_t* worker_edges, int P,
-                          uint64_t* part, int sched) {
+                          const uint32_t* preset, uint64_t* rec, uint32_t* q, int* ctr,
+                          uint64_t* worker_edges, int P, uint64_t* part, int sched) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t cas[kCasBuf];
     __shared__ int s_chunk, s_ncas, s_base;
@@ -142,7 +146,8 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
             if (v < ce) {
                 const int b = g.begin(v), e = g.end(v);
                 degsum += (uint64_t)(e - b);
-                if (b < e) {
+                // a preset vertex is removed already: no DoPost
+                if (b < e && !(preset && ((preset[v >> 5] >> (v & 31)) & 1u))) {
                     gi = g.vctx(v);
                     int p = b, w = 0;
                     for (; p < e; ++p) {
@@ -364,15 +369,16 @@ inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
 template <class View>
 hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
                    uint64_t* worker_edges, trim_stats_t* stats, const int64_t* vbase = nullptr,
-                   const int64_t* bitmap_base = nullptr, int G = 0) {
+                   const int64_t* bitmap_base = nullptr, int G = 0,
+                   const uint32_t* preset = nullptr) {
     const int P = lc.workers;
     const int B = lc.block;
     int sweep_blocks = 0, pack_blocks = 0;
     {
         Timed t(lc, "ac6_init");
         hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           lc.stream, g, n, w.a, reinterpret_cast<uint32_t*>(w.c), w.ctr,
-                           worker_edges, P, stats);
+                           lc.stream, g, n, w.a, reinterpret_cast<uint32_t*>(w.c), preset,
+                           w.ctr, worker_edges, P, stats);
     }
     if (n > 0) {
         const int chunk = ((lc.chunk + B - 1) / B) * B;
@@ -380,8 +386,8 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         {
             Timed t(lc, "ac6_sweep");
             hipLaunchKernelGGL(ac6_sweep<View>, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n,
-                               chunk, w.a, reinterpret_cast<const uint32_t*>(w.c), w.b, w.q,
-                               w.ctr, worker_edges, P, w.part, lc.schedule);
+                               chunk, w.a, reinterpret_cast<const uint32_t*>(w.c), preset, w.b,
+                               w.q, w.ctr, worker_edges, P, w.part, lc.schedule);
         }
         {
             Timed t(lc, "ac6_propagate");
@@ -413,9 +419,9 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
 }  // namespace
 
 hipError_t ac6_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats) {
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset) {
     ExplicitView v{g.row_off, g.col};
-    return ac6_run(v, g.n, w, lc, bitmap, worker_edges, stats);
+    return ac6_run(v, g.n, w, lc, bitmap, worker_edges, stats, nullptr, nullptr, 0, preset);
 }
 
 hipError_t ac6_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,

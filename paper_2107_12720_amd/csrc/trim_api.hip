@@ -320,6 +320,54 @@ int trim_csr(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
     return TRIM_OK;
 }
 
+int trim_csr_preset(trim_ctx* c, int algo, const trim_csr_t* g, const uint32_t* preset_dead,
+                    const trim_opts_t* o, uint32_t* live_bitmap, uint64_t* worker_edges,
+                    trim_stats_t* stats, void* stream) {
+    if (!c || !g) return fail(TRIM_E_INVAL, "trim_csr_preset: NULL context or graph");
+    if (g && g->n > 0 && !preset_dead) return fail(TRIM_E_INVAL, "preset_dead is NULL");
+    if (g->n == 0) preset_dead = nullptr;
+    if (algo != TRIM_AC3 && algo != TRIM_AC4 && algo != TRIM_AC6)
+        return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
+    if (g->n < 0 || g->n > (1 << 29)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
+    if (g->m < 0 || g->m >= (int64_t)1 << 31)
+        return fail(TRIM_E_INVAL, "m = %lld out of range [0, 2^31)", (long long)g->m);
+    if (!g->row_off) return fail(TRIM_E_INVAL, "row_off is NULL");
+    if (g->m > 0 && !g->col) return fail(TRIM_E_INVAL, "col is NULL");
+    if (g->n > 0 && !live_bitmap) return fail(TRIM_E_INVAL, "live_bitmap is NULL");
+    if (!worker_edges) return fail(TRIM_E_INVAL, "worker_edges is NULL");
+    if (algo == TRIM_AC4 && (!g->rrow_off || (g->m > 0 && !g->rcol)))
+        return fail(TRIM_E_INVAL, "AC-4 needs the transposed graph (rrow_off, rcol)");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((rc = ensure(c, g->n))) return rc;
+    trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
+    if (o && o->validate) {
+        int bad = 0;
+        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate");
+        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
+                                lc.stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate readback");
+        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
+    }
+    switch (algo) {
+        case TRIM_AC6:
+            e = trim::ac6_csr(*g, c->w, lc, live_bitmap, worker_edges, stats, preset_dead);
+            break;
+        case TRIM_AC4:
+            e = trim::ac4_csr(*g, c->w, lc, live_bitmap, worker_edges, stats, preset_dead);
+            break;
+        default:
+            e = trim::ac3_csr(*g, c->w, lc, live_bitmap, worker_edges, stats, preset_dead);
+            break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return TRIM_OK;
+}
+
 int trim_csr_two_sided(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
                        uint32_t* live_bitmap, uint64_t* worker_edges, trim_stats_t* stats,
                        void* stream) {

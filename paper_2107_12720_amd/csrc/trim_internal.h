@@ -92,8 +92,9 @@ inline Timed::~Timed() {
 }
 
 // ------------------------------------------------------------------ AC-6
+// preset: optional device bitmap of vertices removed before trimming (NULL = none)
 hipError_t ac6_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats);
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset = nullptr);
 hipError_t ac6_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
                         uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
 hipError_t ac6_batch(int G, const int64_t* vbase, const int32_t* row_off, const int32_t* col,
@@ -107,14 +108,14 @@ int ac6_two_max_workers_per_cu(int block);
 
 // ------------------------------------------------------------------ AC-4
 hipError_t ac4_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats);
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset = nullptr);
 hipError_t ac4_two_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
                        uint64_t* worker_edges, trim_stats_t* stats);
 int ac4_max_workers_per_cu(int block);
 
 // ------------------------------------------------------------------ AC-3
 hipError_t ac3_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
-                   uint64_t* worker_edges, trim_stats_t* stats);
+                   uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset = nullptr);
 hipError_t ac3_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
                         uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
 int ac3_max_workers_per_cu(int block);
