@@ -17,7 +17,9 @@ Also reported on the same JSON line:
   baselines     AC-4 and AC-3 on the same graph (one or a few runs each);
   depth         alpha times the measured per-step latency of a bare chain;
   two_sided     two-sided trimming (live successor and live predecessor) of the
-                same graph with AC-6 and AC-4, kernel bytes and the oracle's time.
+                same graph with AC-6 and AC-4, kernel bytes and the oracle's time;
+  sampling      edges or vertices sampled at 10 % .. 100 % (R-MAT scale 22), the
+                scalability experiment of Section 9, all three algorithms.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-baselines]
 """
@@ -192,6 +194,63 @@ def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps):
     checks = {"rro": rro_h, "rcol": rcol_h,
               "ac6": {"bitmap": res6.bitmap_numpy().copy(), "edges": st6["edges_total"]},
               "ac4": {"bitmap": res4.bitmap_numpy().copy(), "edges": st4["edges_total"]}}
+    return checks, out
+
+
+def bench_sampling(ctx, T, gg, ratios=tuple(k / 10 for k in range(1, 11))):
+    """The scalability experiment of Section 9 on R-MAT scale 22, edge factor
+    16 (the stand-in for the paper's largest graphs): edges or vertices are
+    sampled at 10 % .. 100 %; unsampled edges are dropped, unsampled vertices
+    are set to DEAD before trimming (trim_csr_preset).  Per ratio and
+    algorithm: time, traversed edges, the largest per-worker count, and the
+    share of vertices removed."""
+    import numpy as np
+    g = gg.rmat(22, 16, seed=0)
+    n = g.n
+    ro, col = T.to_device(g.row_off), T.to_device(g.col)
+    rro_h, rcol_h = gg.transpose(g)
+    rro, rcl = T.to_device(rro_h), T.to_device(rcol_h)
+    names = {6: "ac6", 4: "ac4", 3: "ac3"}
+
+    def measure(fn):
+        ms, _, res = time_gpu(ctx, fn, 1, 1)
+        st = res.stats_dict()
+        return {"ms": ms, "traversed": st["edges_total"],
+                "max_worker": int(res.worker_edges.max().item()), "n_live": st["n_live"]}, res
+
+    out = {"workload": "rmat22_ef16", "n": n, "m": g.m, "edge": [], "vertex": []}
+    checks = {}
+    for ratio in ratios:
+        preset, bm = gg.sample_vertices(n, ratio, seed=1)
+        pd = T.to_device(bm.view(np.int32))
+        row = {"ratio": ratio, "preset": int(preset.sum())}
+        for a in (6, 4, 3):
+            row[names[a]], res = measure(
+                lambda: ctx.trim_csr_preset(a, n, ro, col, pd, rro, rcl))
+            if ratio == 0.5:
+                checks.setdefault("vertex", {"preset": preset})[a] = {
+                    "bitmap": res.bitmap_numpy().copy(), "edges": row[names[a]]["traversed"]}
+        row["removed_by_trimming_pct"] = 100.0 * (n - row["ac6"]["n_live"] - row["preset"]) / n
+        row["dead_pct"] = 100.0 * (n - row["ac6"]["n_live"]) / n
+        out["vertex"].append(row)
+
+        h = g if ratio >= 1.0 else gg.sample_edges(g, ratio, seed=1)
+        hro, hcol = T.to_device(h.row_off), T.to_device(h.col)
+        a_h, b_h = (rro_h, rcol_h) if h is g else gg.transpose(h)
+        hrro, hrcl = T.to_device(a_h), T.to_device(b_h)
+        row = {"ratio": ratio, "m": h.m}
+        for a in (6, 4, 3):
+            row[names[a]], res = measure(
+                lambda: ctx.trim_csr(a, n, hro, hcol, hrro if a == 4 else None,
+                                     hrcl if a == 4 else None))
+            if ratio == 0.5:
+                checks.setdefault("edge", {"graph": h})[a] = {
+                    "bitmap": res.bitmap_numpy().copy(), "edges": row[names[a]]["traversed"]}
+        row["dead_pct"] = 100.0 * (n - row["ac6"]["n_live"]) / n
+        out["edge"].append(row)
+        log(f"sampling {ratio:.1f}: vertex AC-6 {out['vertex'][-1]['ac6']['ms']:.3f} ms, "
+            f"edge AC-6 {row['ac6']['ms']:.3f} ms")
+    checks["graph"] = g
     return checks, out
 
 
@@ -494,6 +553,26 @@ def oracle_leg(g, checks, cpu_seconds, out):
         to["ac4"]["parity"] = bool(np.array_equal(tc["ac4"]["bitmap"], bm2)
                                    and tc["ac4"]["edges"] == c2.T4two)
         to["ac4"]["T4two"] = c2.T4two
+    if "sampling" in checks:
+        sc = checks["sampling"]
+        ok = True
+        if "vertex" in sc:
+            pre = sc["vertex"]["preset"]
+            rv = oracle.peel(sc["graph"], preset=pre)
+            cv = oracle.counts(sc["graph"], rv, preset=pre)
+            bmv = oracle.bitmap(rv.live)
+            for a, want in ((6, cv.T6), (4, cv.T4s), (3, cv.T3J)):
+                ok = ok and np.array_equal(sc["vertex"][a]["bitmap"], bmv) \
+                    and sc["vertex"][a]["edges"] == want
+        if "edge" in sc:
+            h = sc["edge"]["graph"]
+            re_ = oracle.peel(h)
+            ce = oracle.counts(h, re_)
+            bme = oracle.bitmap(re_.live)
+            for a, want in ((6, ce.T6), (4, ce.T4s), (3, ce.T3J)):
+                ok = ok and np.array_equal(sc["edge"][a]["bitmap"], bme) \
+                    and sc["edge"][a]["edges"] == want
+        out["sampling"]["parity_at_50pct"] = bool(ok)
     if "depth" in out:
         out["depth"]["alpha"] = r.alpha
         out["depth"]["floor_ms"] = r.alpha * out["depth"]["chain_hop_us"] / 1e3
@@ -546,6 +625,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-order section")
     ap.add_argument("--no-two-sided", action="store_true",
                     help="skip two-sided trimming (AC-6 and AC-4) of the same graph")
+    ap.add_argument("--no-sampling", action="store_true",
+                    help="skip the edge / vertex sampling sweep (R-MAT scale 22)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size "
@@ -669,6 +750,8 @@ def main():
         checks["two_sided"], out["two_sided"] = bench_two_sided(ctx, T, g, ro, col, gt[0], gt[1], 5)
         log(f"two-sided: AC-6 {out['two_sided']['ac6']['ms']:.3f} ms, "
             f"AC-4 {out['two_sided']['ac4']['ms']:.3f} ms")
+    if not args.no_sampling:
+        checks["sampling"], out["sampling"] = bench_sampling(ctx, T, gg)
     if not args.no_batch:
         checks["batch"], out["batch"] = bench_batch(ctx, T, gg, 10)
         log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s")
