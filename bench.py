@@ -35,8 +35,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edges/s + graphs/s: batched/learned-order AC-6 vs plain AC-6, bit-exact live set"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("ac6.hip", "ac6_support.h", "ac6_two.hip", "ac4.hip", "ac3.hip",
-                  "trim_device.h", "trim_stats.h", "trim_internal.h", "trim_api.hip")
+# What the one-sided AC-6 kernels compile from: a committed counter summary of
+# one of them stays valid while these are unchanged (other kernel files are
+# separate translation units and cannot change them).
+KERNEL_SOURCES = ("paper_2107_12720_amd/csrc/ac6.hip", "paper_2107_12720_amd/csrc/ac6_support.h",
+                  "paper_2107_12720_amd/csrc/trim_device.h",
+                  "paper_2107_12720_amd/csrc/trim_stats.h",
+                  "paper_2107_12720_amd/csrc/trim_internal.h", "include/trim.h")
 
 
 def log(*a):
@@ -49,16 +54,16 @@ def source_hash():
     import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2107_12720_amd", "csrc", f)) as fh:
+        with open(os.path.join(ROOT, f)) as fh:
             code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
         code = re.sub(r"//[^\n]*", " ", code)
         h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, workers=None):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
+    taken on the current kernel source and launch size; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm.json")
     if not os.path.exists(path):
         return None
@@ -67,6 +72,8 @@ def measured_traffic(kernel, workload):
     except (OSError, ValueError):
         return None
     if d.get("source_hash") != source_hash():
+        return None
+    if workers is not None and d.get("workers") not in (None, workers):
         return None
     return d.get("bytes_per_launch")
 
@@ -686,7 +693,7 @@ def main():
     algo_bytes = {"ac6_propagate": b_prop, "ac6_sweep": b_sweep,
                   "ac6_init": 4 * (n + 1) + 8 * n + n // 8, "ac6_pack": 8 * n + n // 8}
     ach = algo_bytes[dom] / (kavg[dom] / 1e3) / 1e9
-    traffic = measured_traffic(dom, "rmat22_chain")
+    traffic = measured_traffic(dom, "rmat22_chain", P)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                 "algorithmic_bytes": int(algo_bytes[dom]), "avg_ms": kavg[dom]}
