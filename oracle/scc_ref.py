@@ -1,0 +1,48 @@
+"""Strongly connected components -- TEST INFRASTRUCTURE ONLY.
+
+The partition of V into strongly connected components, which FW-BW SCC
+decomposition (Section 1.1, the application of graph trimming) computes:
+u and v are in one component iff each reaches the other.  The partition is
+unique, so it is the plain definition that any decomposition must match.
+It is computed with scipy's strong-component routine (a library primitive)
+and given as canonical labels: every vertex is labelled with the smallest
+vertex id of its component.  Shares no code with the GPU path.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def canonical(labels) -> np.ndarray:
+    """Relabel a partition so that every vertex carries the smallest vertex id
+    of its class (labels are arbitrary ints; equal ints = one class)."""
+    labels = np.asarray(labels, dtype=np.int64)
+    n = labels.shape[0]
+    if n == 0:
+        return np.zeros(0, np.int64)
+    uniq, inv = np.unique(labels, return_inverse=True)
+    first = np.full(uniq.shape[0], n, np.int64)
+    np.minimum.at(first, inv, np.arange(n, dtype=np.int64))
+    return first[inv]
+
+
+def scc_labels(g) -> np.ndarray:
+    """Canonical SCC labels of the CSR graph g (int64[n])."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+    n = g.n
+    if n == 0:
+        return np.zeros(0, np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.row_off.astype(np.int64)))
+    A = sp.csr_matrix((np.ones(g.m, np.int8), (src, g.col.astype(np.int64))), shape=(n, n))
+    _, lab = connected_components(A, directed=True, connection="strong")
+    return canonical(lab)
+
+
+def summary(labels) -> dict:
+    """Number of components, of size-1 components, and the largest size."""
+    labels = np.asarray(labels)
+    if labels.size == 0:
+        return {"n_scc": 0, "n_single": 0, "largest": 0}
+    _, cnt = np.unique(labels, return_counts=True)
+    return {"n_scc": int(cnt.size), "n_single": int((cnt == 1).sum()), "largest": int(cnt.max())}

@@ -636,3 +636,65 @@ def test_preset_totals_by_literal_runs(orc, gen, seed):
             assert list(r.live.astype(bool)) == live
             assert (c.T6, c.T3J, c.rounds3, c.T4s) == (t6, t3, rounds, t4), (n, ratio)
             assert r.rev_edges == c.T4s
+
+
+# ------------------------------------------------- strongly connected components
+def closure_scc(adj):
+    """SCC labels by brute force: reachability by repeated squaring of the
+    boolean adjacency (Warshall), then u ~ v iff each reaches the other;
+    label = smallest id of the class."""
+    n = len(adj)
+    R = np.eye(n, dtype=bool)
+    for u in range(n):
+        for w in adj[u]:
+            R[u, w] = True
+    for k in range(n):
+        R = R | (R[:, k:k + 1] & R[k:k + 1, :])
+    both = R & R.T
+    return np.array([int(np.flatnonzero(both[v])[0]) for v in range(n)], np.int64)
+
+
+def test_scc_reference_against_closure(gen):
+    from oracle.scc_ref import scc_labels
+    rng = np.random.default_rng(7)
+    for trial in range(300):
+        n = int(rng.integers(1, 12))
+        m = int(rng.integers(0, 3 * n))
+        adj = [[] for _ in range(n)]
+        for _ in range(m):
+            adj[int(rng.integers(n))].append(int(rng.integers(n)))
+        g = gen.from_adjacency(adj)
+        assert (scc_labels(g) == closure_scc(adj)).all(), adj
+
+
+def test_scc_reference_closed_forms(gen):
+    from oracle.scc_ref import scc_labels, summary, canonical
+    # a directed cycle is one component; a path is n singletons
+    n = 1000
+    g = gen.from_edges(n, np.arange(n, dtype=np.int32), (np.arange(n, dtype=np.int32) + 1) % n)
+    assert (scc_labels(g) == 0).all()
+    g = gen.from_edges(n, np.arange(n - 1, dtype=np.int32), np.arange(1, n, dtype=np.int32))
+    assert (scc_labels(g) == np.arange(n)).all()
+    # two 3-cycles joined by one edge stay two components
+    g = gen.from_adjacency([[1], [2], [0, 3], [4], [5], [3]])
+    assert list(scc_labels(g)) == [0, 0, 0, 3, 3, 3]
+    assert summary(scc_labels(g)) == {"n_scc": 2, "n_single": 0, "largest": 3}
+    assert list(canonical([7, 3, 7, 3, 9])) == [0, 1, 0, 1, 4]
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_scc_reference_versus_trimming(orc, gen, seed):
+    """Vertices that two-sided trimming removes lie on no cycle, so each is a
+    component of its own; a vertex with a self-loop or in a component of two
+    or more vertices survives it."""
+    from oracle.scc_ref import scc_labels
+    g = gen.uniform(20000, 26000, seed=seed + 40)
+    lab = scc_labels(g)
+    size = np.bincount(lab, minlength=g.n)[lab]
+    loop = np.zeros(g.n, bool)
+    src = np.repeat(np.arange(g.n), np.diff(g.row_off))
+    loop[src[src == g.col]] = True
+    r2 = orc.peel2(g)
+    on_cycle = (size > 1) | loop
+    assert not (r2.live.astype(bool) == 0)[on_cycle].any()
+    assert (lab[r2.live == 0] == np.flatnonzero(r2.live == 0)).all()
