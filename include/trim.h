@@ -216,6 +216,39 @@ int trim_csr_two_sided(trim_ctx *ctx, int algo, const trim_csr_t *g, const trim_
                        uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats,
                        void *stream);
 
+/* Counts of one SCC decomposition (host memory). */
+typedef struct {
+    int64_t n_scc;         /* strongly connected components */
+    int64_t trimmed;       /* vertices found as size-1 components by trimming */
+    int64_t giant;         /* size of the pivot's component (forward-backward search) */
+    int32_t trims;         /* two-sided trimming passes */
+    int32_t color_rounds;  /* colouring rounds after the forward-backward search */
+    int32_t color_sweeps;  /* max-label sweeps over all colouring rounds */
+    int32_t reserved;
+} trim_scc_stats_t;
+
+/*
+ * Strongly connected components by forward-backward search with trimming,
+ * the application of graph trimming in Section 1.1: two-sided trimming (as
+ * trim_csr_two_sided with AC-6) takes out the size-1 components, a forward
+ * and backward search from one pivot (the vertex with the largest
+ * (outdeg+1)(indeg+1)) takes out its component, trimming runs again, and
+ * colouring rounds (each unassigned vertex takes the largest id that reaches
+ * it; a vertex keeping its own id is a root whose component is the vertices
+ * of its colour that reach it) take out the rest, with trimming after each
+ * round.  g->rrow_off and g->rcol are required and must hold the transpose.
+ * Output: label (device, n int32): label[v] is the id of one vertex of v's
+ * component, so u and v share a component iff label[u] == label[v], and
+ * label[label[v]] == label[v].  stats (host, may be NULL) receives the
+ * counts.  The rounds are driven from the host: the call synchronises
+ * `stream` several times and returns when the labels are final.  Uses
+ * 72 bytes per vertex of context memory (the two-sided trimming arrays plus
+ * 8 bytes of SCC marks and colours).  TRIM_E_STALLED if a round made no
+ * progress (a guard; the method always progresses).
+ */
+int trim_scc(trim_ctx *ctx, const trim_csr_t *g, const trim_opts_t *opts, int32_t *label,
+             trim_scc_stats_t *stats, void *stream);
+
 /*
  * Trim an implicit graph (AC-6 or AC-3 only; AC-4 needs G^T and returns
  * TRIM_E_UNSUPPORTED, Table trim: AC-4 lacks the on-the-fly property).

@@ -30,7 +30,7 @@ STATUS = {0: "TRIM_OK", -1: "TRIM_E_INVAL", -2: "TRIM_E_NOMEM", -3: "TRIM_E_HIP"
           -4: "TRIM_E_UNSUPPORTED", -5: "TRIM_E_BADGRAPH", -6: "TRIM_E_STALLED"}
 EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destroy",
            "trim_num_workers", "trim_csr", "trim_csr_preset", "trim_csr_two_sided",
-           "trim_implicit", "trim_batch",
+           "trim_scc", "trim_implicit", "trim_batch",
            "trim_ctx_set_timing", "trim_ctx_kernel_times", "trim_mlp_prepare", "trim_mlp_grad",
            "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key")
 MLP_PARAMS = 1377
@@ -58,6 +58,12 @@ class CsrDesc(ctypes.Structure):
                 ("rrow_off", ctypes.c_void_p), ("rcol", ctypes.c_void_p)]
 
 
+class SccStats(ctypes.Structure):
+    _fields_ = [("n_scc", ctypes.c_int64), ("trimmed", ctypes.c_int64), ("giant", ctypes.c_int64),
+                ("trims", ctypes.c_int32), ("color_rounds", ctypes.c_int32),
+                ("color_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class ImplicitDesc(ctypes.Structure):
     _fields_ = [("log2n", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("zero_thr", ctypes.c_uint64), ("deg_table", ctypes.c_void_p)]
@@ -82,6 +88,8 @@ def lib():
                                        ctypes.POINTER(i32)]
         L.trim_csr.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(Opts),
                                vp, vp, vp, vp]
+        L.trim_scc.argtypes = [vp, ctypes.POINTER(CsrDesc), ctypes.POINTER(Opts), vp,
+                               ctypes.POINTER(SccStats), vp]
         L.trim_csr_preset.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc), vp,
                                       ctypes.POINTER(Opts), vp, vp, vp, vp]
         L.trim_csr_two_sided.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc),
@@ -103,7 +111,7 @@ def lib():
         L.trim_edge_keys.argtypes = [vp, csr_p, i32, ctypes.c_uint64, vp, vp]
         L.trim_order_by_key.argtypes = [vp, csr_p, vp, f32, f32, vp, vp]
         for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_num_workers", "trim_csr",
-                  "trim_csr_preset", "trim_csr_two_sided",
+                  "trim_csr_preset", "trim_csr_two_sided", "trim_scc",
                   "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times",
                   "trim_mlp_prepare", "trim_mlp_grad", "trim_mlp_adam", "trim_mlp_score",
                   "trim_edge_keys", "trim_order_by_key"):
@@ -233,6 +241,27 @@ class Context:
                               ctypes.c_void_p(lb.data_ptr()), ctypes.c_void_p(we.data_ptr()),
                               ctypes.c_void_p(st.data_ptr()), _stream_handle(stream, self.device)))
         return TrimResult(lb, we, st)
+
+    def trim_scc(self, n, row_off, col, rrow_off, rcol, *, label=None,
+                 opts: Opts | None = None, stream=None):
+        """Strongly connected components by forward-backward search with
+        trimming.  Returns (label int32 device tensor, stats dict); label[v] is
+        the id of one vertex of v's component.  Synchronises the stream."""
+        import torch
+        opts = opts or Opts()
+        m = int(col.numel()) if col is not None else 0
+        d = CsrDesc(int(n), m, _dev_ptr(row_off, torch.int32, "row_off"),
+                    _dev_ptr(col, torch.int32, "col") if m else None,
+                    _dev_ptr(rrow_off, torch.int32, "rrow_off"),
+                    _dev_ptr(rcol, torch.int32, "rcol") if m else None)
+        if label is None:
+            label = torch.empty(max(int(n), 1), dtype=torch.int32,
+                                device=torch.device("cuda", self.device))
+        st = SccStats()
+        _check(lib().trim_scc(self._h, ctypes.byref(d), ctypes.byref(opts),
+                              ctypes.c_void_p(label.data_ptr()), ctypes.byref(st),
+                              _stream_handle(stream, self.device)))
+        return label, {k: int(getattr(st, k)) for k, _ in SccStats._fields_ if k != "reserved"}
 
     def trim_csr_preset(self, algo, n, row_off, col, preset_dead, rrow_off=None, rcol=None, *,
                         live_bitmap=None, worker_edges=None, stats=None,

@@ -36,6 +36,7 @@
 #include "trim_stats.h"
 #include "trim_internal.h"
 #include "ac6_support.h"
+#include "scc_internal.h"
 
 namespace trim {
 
@@ -52,17 +53,18 @@ struct TwoGraph {
     uint64_t* rec_in;
 };
 
-// Sets dead0 bit v iff v has no successor or no predecessor; each wavefront
-// covers 64 consecutive ids (the last may write one word past ceil(n/32),
-// which the buffer has).
-__global__ void ac6t_init(TwoGraph g, int n, uint32_t* dead0, int* ctr, uint64_t* worker_edges,
-                          int P, trim_stats_t* stats) {
+// Sets dead0 bit v iff v has no successor, no predecessor, or is preset
+// (removed before trimming); each wavefront covers 64 consecutive ids (the
+// last may write one word past ceil(n/32), which the buffer has).
+__global__ void ac6t_init(TwoGraph g, int n, uint32_t* dead0, const uint32_t* preset, int* ctr,
+                          uint64_t* worker_edges, int P, trim_stats_t* stats) {
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < kCtrInts) ctr[tid] = 0;
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
-        const bool d = g.row_off[v + 1] == g.row_off[v] || g.rrow_off[v + 1] == g.rrow_off[v];
+        const bool d = g.row_off[v + 1] == g.row_off[v] || g.rrow_off[v + 1] == g.rrow_off[v] ||
+                       (preset && ((preset[v >> 5] >> (v & 31)) & 1u));
         const int h = d ? kDead : kEmpty;
         reinterpret_cast<int2*>(g.hout)[v] = make_int2(h, h);
         reinterpret_cast<int2*>(g.hin)[v] = make_int2(h, h);
@@ -139,7 +141,7 @@ __global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, 
                 const int b = g.row_off[v], e = g.row_off[v + 1];
                 const int rb = g.rrow_off[v], re = g.rrow_off[v + 1];
                 degsum += (uint64_t)(e - b);
-                if (b < e && rb < re) {
+                if (!bit(dead0, v)) {   // has both lists and is not preset
                     const uint64_t salt = ((uint64_t)blockIdx.x << 32) ^ v;
                     casualty = !first_join(g.col, b, e, dead0, g.hout, g.rec_out, v, mine, sched,
                                            salt) ||
@@ -305,6 +307,12 @@ inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
 
 hipError_t ac6_two_csr(const trim_csr_t& gc, const Work& w, const Work2& x, const LaunchCfg& lc,
                        uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats) {
+    return ac6_two_csr_preset(gc, w, x, lc, bitmap, worker_edges, stats, nullptr);
+}
+
+hipError_t ac6_two_csr_preset(const trim_csr_t& gc, const Work& w, const Work2& x,
+                              const LaunchCfg& lc, uint32_t* bitmap, uint64_t* worker_edges,
+                              trim_stats_t* stats, const uint32_t* preset) {
     const int n = gc.n, P = lc.workers, B = lc.block;
     TwoGraph g{gc.row_off, gc.col, gc.rrow_off, gc.rcol, w.a, x.hin, w.b, x.rec_in};
     uint32_t* dead0 = reinterpret_cast<uint32_t*>(w.c);
@@ -312,7 +320,7 @@ hipError_t ac6_two_csr(const trim_csr_t& gc, const Work& w, const Work2& x, cons
     {
         Timed t(lc, "ac6t_init");
         hipLaunchKernelGGL(ac6t_init, dim3(grid_for(n, 256, 16384)), dim3(256), 0, lc.stream, g,
-                           n, dead0, w.ctr, worker_edges, P, stats);
+                           n, dead0, preset, w.ctr, worker_edges, P, stats);
     }
     if (n > 0) {
         const int chunk = ((lc.chunk + B - 1) / B) * B;

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "trim_internal.h"
+#include "scc_internal.h"
 
 struct trim_ctx {
     int device = 0;
@@ -16,6 +17,9 @@ struct trim_ctx {
     // two-sided AC-6 extras, sized for cap_n2 vertices
     size_t cap_n2 = 0;
     trim::Work2 w2;
+    // SCC decomposition arrays, sized for cap_scc vertices
+    size_t cap_scc = 0;
+    trim::SccWork sw;
     int occ6 = 0, occ4 = 0, occ3 = 0;   // resident workgroups per CU (occ6: both AC-6 forms)
     // captured launch sequence of trim_batch and the arguments it was made for
     hipGraphExec_t gexec = nullptr;
@@ -113,6 +117,36 @@ int ensure2(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n2 = cap;
+    return TRIM_OK;
+}
+
+void free_scc(trim_ctx* c) {
+    (void)hipFree(c->sw.assigned);
+    (void)hipFree(c->sw.live);
+    (void)hipFree(c->sw.flags);
+    (void)hipFree(c->sw.color);
+    (void)hipFree(c->sw.misc);
+    c->sw = trim::SccWork{};
+    c->cap_scc = 0;
+}
+
+int ensure_scc(trim_ctx* c, int64_t n) {
+    size_t need = (size_t)(n > 0 ? n : 1);
+    if (need <= c->cap_scc) return TRIM_OK;
+    free_scc(c);
+    size_t cap = need + need / 8 + 64;
+    const size_t words = cap / 32 + 64;
+    if (hipMalloc((void**)&c->sw.assigned, words * 4) != hipSuccess ||
+        hipMalloc((void**)&c->sw.live, words * 4) != hipSuccess ||
+        hipMalloc((void**)&c->sw.flags, cap * 4) != hipSuccess ||
+        hipMalloc((void**)&c->sw.color, cap * 4) != hipSuccess ||
+        hipMalloc((void**)&c->sw.misc, trim::kSccMisc * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        free_scc(c);
+        return fail(TRIM_E_NOMEM, "cannot allocate SCC working memory for %lld vertices",
+                    (long long)n);
+    }
+    c->cap_scc = cap;
     return TRIM_OK;
 }
 
@@ -258,6 +292,7 @@ int trim_ctx_destroy(trim_ctx* c) {
     (void)hipSetDevice(c->device);
     free_work(c);
     free_work2(c);
+    free_scc(c);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& ev : c->timer.ev)
         if (ev) (void)hipEventDestroy(ev);
@@ -365,6 +400,48 @@ int trim_csr_preset(trim_ctx* c, int algo, const trim_csr_t* g, const uint32_t* 
             break;
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return TRIM_OK;
+}
+
+int trim_scc(trim_ctx* c, const trim_csr_t* g, const trim_opts_t* o, int32_t* label,
+             trim_scc_stats_t* stats, void* stream) {
+    if (!c || !g) return fail(TRIM_E_INVAL, "trim_scc: NULL context or graph");
+    if (g->n < 0 || g->n > (1 << 29)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
+    if (g->m < 0 || g->m >= (int64_t)1 << 31)
+        return fail(TRIM_E_INVAL, "m = %lld out of range [0, 2^31)", (long long)g->m);
+    if (!g->row_off || !g->rrow_off) return fail(TRIM_E_INVAL, "row_off or rrow_off is NULL");
+    if (g->m > 0 && (!g->col || !g->rcol)) return fail(TRIM_E_INVAL, "col or rcol is NULL");
+    if (g->n > 0 && !label) return fail(TRIM_E_INVAL, "label is NULL");
+    int rc = check_opts(o);
+    if (rc) return rc;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((rc = ensure(c, g->n)) || (rc = ensure2(c, g->n)) || (rc = ensure_scc(c, g->n))) return rc;
+    trim::LaunchCfg lc = launch_cfg(c, TRIM_AC6, o, stream);
+    lc.timer = nullptr;   // many launches; timed as a whole by the caller
+    if (o && o->validate) {
+        int bad = 0;
+        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate");
+        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
+                                lc.stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
+            return hip_fail(e, "validate readback");
+        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
+    }
+    trim::SccCounts k;
+    e = trim::scc_run(*g, c->w, c->w2, c->sw, lc, label, &k);
+    if (e != hipSuccess) return hip_fail(e, "SCC decomposition");
+    if (k.stalled) return fail(TRIM_E_STALLED, "SCC decomposition made no progress");
+    if (stats) {
+        stats->n_scc = k.n_scc;
+        stats->trimmed = k.trimmed;
+        stats->giant = k.giant;
+        stats->trims = k.trims;
+        stats->color_rounds = k.color_rounds;
+        stats->color_sweeps = k.color_sweeps;
+        stats->reserved = 0;
+    }
     return TRIM_OK;
 }
 

@@ -40,6 +40,7 @@ def test_null_arguments_rejected():
     assert L.trim_csr_two_sided(None, 6, None, None, None, None, None, None) == -1
     assert "NULL" in T.last_error()
     assert L.trim_csr_preset(None, 6, None, None, None, None, None, None, None) == -1
+    assert L.trim_scc(None, None, None, None, None, None) == -1
     assert "NULL" in T.last_error()
     assert L.trim_ctx_destroy(None) == 0
 
