@@ -19,7 +19,9 @@ Also reported on the same JSON line:
   two_sided     two-sided trimming (live successor and live predecessor) of the
                 same graph with AC-6 and AC-4, kernel bytes and the oracle's time;
   sampling      edges or vertices sampled at 10 % .. 100 % (R-MAT scale 22), the
-                scalability experiment of Section 9, all three algorithms.
+                scalability experiment of Section 9, all three algorithms;
+  scc           strongly connected components by forward-backward search with
+                two-sided trimming (Section 1.1), against scipy's in the CPU leg.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-baselines]
 """
@@ -258,6 +260,43 @@ def bench_sampling(ctx, T, gg, ratios=tuple(k / 10 for k in range(1, 11))):
         log(f"sampling {ratio:.1f}: vertex AC-6 {out['vertex'][-1]['ac6']['ms']:.3f} ms, "
             f"edge AC-6 {row['ac6']['ms']:.3f} ms")
     checks["graph"] = g
+    return checks, out
+
+
+def bench_scc(ctx, T, graphs, reps):
+    """SCC decomposition (forward-backward search with two-sided trimming,
+    Section 1.1) of each (name, graph, G^T on the host) in `graphs`."""
+    import numpy as np
+    import torch
+    out, checks = {}, {}
+    for name, g, (rro_h, rcol_h) in graphs:
+        ro, col = T.to_device(g.row_off), T.to_device(g.col)
+        rro, rcl = T.to_device(rro_h), T.to_device(rcol_h)
+        label = torch.empty(g.n, dtype=torch.int32, device="cuda")
+        ctx.trim_scc(g.n, ro, col, rro, rcl, label=label)   # warm-up
+        times, st = [], None
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            _, st = ctx.trim_scc(g.n, ro, col, rro, rcl, label=label)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        # search bytes: per examined list entry its neighbour id and the
+        # neighbour's mark word (8 B); the live bits are a cache-resident bitmap
+        sb = 8 * st["search_edges"]
+        out[name] = {"n": g.n, "m": g.m, "ms": ms, "edges_per_s": g.m / (ms / 1e3), "stats": st,
+                     "search_roofline": {"bound": "hbm", "algorithmic_bytes": sb,
+                                         "achieved": sb / (st["search_ms"] / 1e3) / 1e9
+                                         if st["search_ms"] > 0 else None,
+                                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                         "note": "search_ms is host-timed and includes the "
+                                                 "pivot choice and a synchronisation"},
+                     "parity": None}
+        checks[name] = {"graph": g, "label": label.cpu().numpy()[: g.n].copy()}
+        log(f"scc {name}: {ms:.3f} ms, {st['n_scc']} components, giant {st['giant']}")
     return checks, out
 
 
@@ -580,6 +619,14 @@ def oracle_leg(g, checks, cpu_seconds, out):
                 ok = ok and np.array_equal(sc["edge"][a]["bitmap"], bme) \
                     and sc["edge"][a]["edges"] == want
         out["sampling"]["parity_at_50pct"] = bool(ok)
+    if "scc" in checks:
+        from oracle.scc_ref import canonical, scc_labels
+        for name, sc in checks["scc"].items():
+            t = time.perf_counter()
+            want = scc_labels(sc["graph"])
+            ts = time.perf_counter() - t
+            out["scc"][name]["oracle"] = {"s": ts, "cores": 1, "kind": "scipy strong components"}
+            out["scc"][name]["parity"] = bool(np.array_equal(canonical(sc["label"]), want))
     if "depth" in out:
         out["depth"]["alpha"] = r.alpha
         out["depth"]["floor_ms"] = r.alpha * out["depth"]["chain_hop_us"] / 1e3
@@ -634,6 +681,8 @@ def main():
                     help="skip two-sided trimming (AC-6 and AC-4) of the same graph")
     ap.add_argument("--no-sampling", action="store_true",
                     help="skip the edge / vertex sampling sweep (R-MAT scale 22)")
+    ap.add_argument("--no-scc", action="store_true",
+                    help="skip the SCC decomposition (R-MAT scale 22 with and without chain)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size "
@@ -719,6 +768,7 @@ def main():
         "stats": st,
     }
 
+    gt = None   # G^T on the host, built once when a section needs it
     if not args.no_baselines:
         # depth floor: a bare 100,000-vertex chain costs alpha dependent steps
         s = np.arange(99999, dtype=np.int32)
@@ -752,11 +802,18 @@ def main():
             out["baselines"]["ac6_speedup_vs_ac3"] = ms3 / ms
 
     if not args.no_two_sided:
-        if args.no_baselines:
+        if gt is None:
             gt = gg.transpose(g)
         checks["two_sided"], out["two_sided"] = bench_two_sided(ctx, T, g, ro, col, gt[0], gt[1], 5)
         log(f"two-sided: AC-6 {out['two_sided']['ac6']['ms']:.3f} ms, "
             f"AC-4 {out['two_sided']['ac4']['ms']:.3f} ms")
+    if not args.no_scc:
+        if gt is None:
+            gt = gg.transpose(g)
+        g22 = gg.rmat(22, 16, seed=0)
+        checks["scc"], out["scc"] = bench_scc(
+            ctx, T, [("rmat22_ef16_chain100k", g, gt), ("rmat22_ef16", g22, gg.transpose(g22))], 3)
+        del g22
     if not args.no_sampling:
         checks["sampling"], out["sampling"] = bench_sampling(ctx, T, gg)
     if not args.no_batch:

@@ -225,6 +225,10 @@ typedef struct {
     int32_t color_rounds;  /* colouring rounds after the forward-backward search */
     int32_t color_sweeps;  /* max-label sweeps over all colouring rounds */
     int32_t reserved;
+    int64_t search_edges;  /* list entries examined by the forward and backward searches */
+    double trim_ms;        /* host-timed phases: trimming passes, */
+    double search_ms;      /* the pivot's forward-backward search, */
+    double color_ms;       /* colouring rounds (without their trimming) */
 } trim_scc_stats_t;
 
 /*

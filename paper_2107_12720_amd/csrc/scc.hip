@@ -27,6 +27,8 @@
 // a vertex to expand forward (successors) or backward (predecessors); a
 // neighbour is taken once per direction, by the lane whose fetch-or sets its
 // mark first.
+#include <chrono>
+
 #include "trim_device.h"
 #include "trim_internal.h"
 #include "scc_internal.h"
@@ -200,7 +202,8 @@ __device__ __forceinline__ bool take(int w, int bit, int c, const uint32_t* live
 __global__ __launch_bounds__(256) void scc_reach(const int* row_off, const int* col,
                                                  const int* rrow_off, const int* rcol,
                                                  const uint32_t* live, const int* color,
-                                                 int* flags, uint32_t* q, int* ctr) {
+                                                 int* flags, uint32_t* q, int* ctr,
+                                                 unsigned long long* misc) {
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
     WaveQueue wq;
@@ -209,6 +212,7 @@ __global__ __launch_bounds__(256) void scc_reach(const int* row_off, const int* 
     uint32_t item = kNone;
     int k = 0, e = 0, dir = 0, cv = 0;
     bool started = false;
+    uint64_t examined = 0;
     while (wq.acquire(item)) {
         uint32_t out[kRBatch];
 #pragma unroll
@@ -221,6 +225,7 @@ __global__ __launch_bounds__(256) void scc_reach(const int* row_off, const int* 
             e = off[v + 1];
             cv = color ? color[v] : 0;
             started = true;
+            examined += (uint64_t)(e - k);
         }
         for (uint64_t big = ballot(item != kNone && e - k > kRCoop); big; big &= big - 1) {
             const int owner = __ffsll((unsigned long long)big) - 1;
@@ -278,6 +283,8 @@ __global__ __launch_bounds__(256) void scc_reach(const int* row_off, const int* 
         for (int j = 0; j < kRBatch; j += 2) wq.push(out[j], out[j + 1]);
         wq.rebalance();
     }
+    examined = wave_sum(examined);
+    if (lane_id() == 0 && examined) add_misc(misc + kSccEdges, examined);
 }
 
 // Unassigned vertices with the wanted marks join a component: mode 0 (both
@@ -345,9 +352,14 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
     auto reset = [&](int mask) {
         hipLaunchKernelGGL(scc_reset, dim3(1), dim3(256), 0, st, s.misc, mask, w.ctr);
     };
+    using clock = std::chrono::steady_clock;
+    auto ms_since = [](clock::time_point t0) {
+        return std::chrono::duration<double, std::milli>(clock::now() - t0).count();
+    };
     // two-sided trim of the unassigned vertices; returns how many remain
     long long active = 0;
     auto trim_round = [&]() -> hipError_t {
+        const auto t0 = clock::now();
         hipError_t r = ac6_two_csr_preset(g, w, x, lc, s.live, w.wedges, nullptr, s.assigned);
         if (r != hipSuccess) return r;
         reset((1 << kSccActive) | (1 << kSccTaken));
@@ -357,6 +369,7 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
         active = (long long)host[kSccActive];
         counts->trimmed += (long long)host[kSccTaken];
         counts->trims += 1;
+        counts->trim_ms += ms_since(t0);
         return hipSuccess;
     };
 
@@ -366,20 +379,24 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
     if ((e = trim_round()) != hipSuccess) return e;
     if (active > 0) {
         // the pivot's component by forward-backward search
+        const auto t0 = clock::now();
         reset((1 << kSccPivot) | (1 << kSccTaken));
         hipLaunchKernelGGL(scc_pivot, dim3(gv), dim3(256), 0, st, n, g.row_off, g.rrow_off, s.live,
                            s.misc);
         hipLaunchKernelGGL(scc_seed_pivot, dim3(1), dim3(64), 0, st, s.misc, s.flags, w.q, w.ctr);
         hipLaunchKernelGGL(scc_reach, dim3(lc.workers), dim3(256), 0, st, g.row_off, g.col,
-                           g.rrow_off, g.rcol, s.live, (const int*)nullptr, s.flags, w.q, w.ctr);
+                           g.rrow_off, g.rcol, s.live, (const int*)nullptr, s.flags, w.q, w.ctr,
+                           s.misc);
         hipLaunchKernelGGL(scc_take_marked, dim3(gv), dim3(256), 0, st, n, 0, s.live, s.flags,
                            (const int*)nullptr, label, s.assigned, s.misc);
         if ((e = hipGetLastError()) != hipSuccess || (e = read_misc()) != hipSuccess) return e;
         counts->giant = (long long)host[kSccTaken];
+        counts->search_ms += ms_since(t0);
         if ((e = trim_round()) != hipSuccess) return e;
     }
     while (active > 0) {
         // colouring round
+        const auto t0 = clock::now();
         hipLaunchKernelGGL(scc_color_init, dim3(gv), dim3(256), 0, st, n, s.live, s.color, s.flags);
         for (long long sweep = 0;; ++sweep) {
             if (sweep > (long long)n + 1) {   // a colour travels at most n - 1 edges
@@ -397,7 +414,8 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
         hipLaunchKernelGGL(scc_seed_roots, dim3(gv), dim3(256), 0, st, n, s.live, s.color, s.flags,
                            w.q, w.ctr);
         hipLaunchKernelGGL(scc_reach, dim3(lc.workers), dim3(256), 0, st, g.row_off, g.col,
-                           g.rrow_off, g.rcol, s.live, (const int*)s.color, s.flags, w.q, w.ctr);
+                           g.rrow_off, g.rcol, s.live, (const int*)s.color, s.flags, w.q, w.ctr,
+                           s.misc);
         hipLaunchKernelGGL(scc_take_marked, dim3(gv), dim3(256), 0, st, n, 1, s.live, s.flags,
                            (const int*)s.color, label, s.assigned, s.misc);
         if ((e = hipGetLastError()) != hipSuccess || (e = read_misc()) != hipSuccess) return e;
@@ -406,12 +424,14 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
             return hipSuccess;
         }
         counts->color_rounds += 1;
+        counts->color_ms += ms_since(t0);
         if ((e = trim_round()) != hipSuccess) return e;
     }
     reset(1 << kSccCount);
     hipLaunchKernelGGL(scc_count_reps, dim3(gv), dim3(256), 0, st, n, label, s.misc);
     if ((e = hipGetLastError()) != hipSuccess || (e = read_misc()) != hipSuccess) return e;
     counts->n_scc = (long long)host[kSccCount];
+    counts->search_edges = (long long)host[kSccEdges];
     return hipSuccess;
 }
 

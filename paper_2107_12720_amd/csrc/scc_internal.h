@@ -20,12 +20,14 @@ struct SccWork {
     unsigned long long* misc = nullptr;  // kSccMisc words: pivot key, counters
 };
 enum SccMisc : int { kSccPivot = 0, kSccActive = 1, kSccChanged = 2, kSccTaken = 3,
-                     kSccCount = 4, kSccMisc = 16 };
+                     kSccCount = 4, kSccEdges = 5, kSccMisc = 16 };
 
 // Counts of one decomposition (host side).
 struct SccCounts {
     long long n_scc = 0, trimmed = 0, giant = 0;
     int trims = 0, color_rounds = 0, color_sweeps = 0;
+    long long search_edges = 0;   // list entries the searches examined
+    double trim_ms = 0, search_ms = 0, color_ms = 0;   // host-timed phases
     bool stalled = false;   // a round made no progress (cannot happen; guarded)
 };
 

@@ -441,6 +441,10 @@ int trim_scc(trim_ctx* c, const trim_csr_t* g, const trim_opts_t* o, int32_t* la
         stats->color_rounds = k.color_rounds;
         stats->color_sweeps = k.color_sweeps;
         stats->reserved = 0;
+        stats->search_edges = k.search_edges;
+        stats->trim_ms = k.trim_ms;
+        stats->search_ms = k.search_ms;
+        stats->color_ms = k.color_ms;
     }
     return TRIM_OK;
 }
