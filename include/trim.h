@@ -224,8 +224,10 @@ typedef struct {
     int32_t trims;         /* two-sided trimming passes */
     int32_t color_rounds;  /* colouring rounds after the forward-backward search */
     int32_t color_sweeps;  /* max-label sweeps over all colouring rounds */
-    int32_t reserved;
+    int32_t search_levels; /* frontier levels of all searches */
     int64_t search_edges;  /* list entries examined by the forward and backward searches */
+    int64_t search_ors;    /* mark fetch-ors the searches issued (a measure of contention:
+                              at most 2 per vertex win) */
     double trim_ms;        /* host-timed phases: trimming passes, */
     double search_ms;      /* the pivot's forward-backward search, */
     double color_ms;       /* colouring rounds (without their trimming) */
@@ -244,10 +246,10 @@ typedef struct {
  * Output: label (device, n int32): label[v] is the id of one vertex of v's
  * component, so u and v share a component iff label[u] == label[v], and
  * label[label[v]] == label[v].  stats (host, may be NULL) receives the
- * counts.  The rounds are driven from the host: the call synchronises
- * `stream` several times and returns when the labels are final.  Uses
- * 72 bytes per vertex of context memory (the two-sided trimming arrays plus
- * 8 bytes of SCC marks and colours).  TRIM_E_STALLED if a round made no
+ * counts.  The rounds and search levels are driven from the host: the call
+ * synchronises `stream` once per level and returns when the labels are final.
+ * Uses 96 bytes per vertex of context memory (the two-sided trimming arrays,
+ * SCC marks and colours, two search frontiers and their prefix sums).  TRIM_E_STALLED if a round made no
  * progress (a guard; the method always progresses).
  */
 int trim_scc(trim_ctx *ctx, const trim_csr_t *g, const trim_opts_t *opts, int32_t *label,

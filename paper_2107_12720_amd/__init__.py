@@ -61,8 +61,9 @@ class CsrDesc(ctypes.Structure):
 class SccStats(ctypes.Structure):
     _fields_ = [("n_scc", ctypes.c_int64), ("trimmed", ctypes.c_int64), ("giant", ctypes.c_int64),
                 ("trims", ctypes.c_int32), ("color_rounds", ctypes.c_int32),
-                ("color_sweeps", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("search_edges", ctypes.c_int64), ("trim_ms", ctypes.c_double),
+                ("color_sweeps", ctypes.c_int32), ("search_levels", ctypes.c_int32),
+                ("search_edges", ctypes.c_int64), ("search_ors", ctypes.c_int64),
+                ("trim_ms", ctypes.c_double),
                 ("search_ms", ctypes.c_double), ("color_ms", ctypes.c_double)]
 
 
@@ -264,7 +265,7 @@ class Context:
                               ctypes.c_void_p(label.data_ptr()), ctypes.byref(st),
                               _stream_handle(stream, self.device)))
         return label, {k: (float if t is ctypes.c_double else int)(getattr(st, k))
-                       for k, t in SccStats._fields_ if k != "reserved"}
+                       for k, t in SccStats._fields_}
 
     def trim_csr_preset(self, algo, n, row_off, col, preset_dead, rrow_off=None, rcol=None, *,
                         live_bitmap=None, worker_edges=None, stats=None,

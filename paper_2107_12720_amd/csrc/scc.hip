@@ -22,11 +22,14 @@
 // label[v] is the id of one vertex of v's component (v itself, the pivot or
 // the root); equal labels mean one component.
 //
-// The searches run in one persistent launch each, on the same per-wavefront
-// LDS rings and shared queue as the trimming kernels (WaveQueue): an item is
-// a vertex to expand forward (successors) or backward (predecessors); a
-// neighbour is taken once per direction, by the lane whose fetch-or sets its
-// mark first.
+// The searches go level by level over a frontier of items (a vertex and a
+// direction: forward follows successors, backward predecessors).  A level
+// scans the frontier's list lengths, then deals their entries out evenly: each
+// block takes a contiguous range of kLBS entries, stages the frontier items
+// that own them in LDS and finds each entry's owner by binary search, so a hub
+// and a thousand short lists cost the same per entry.  A neighbour is taken
+// once per direction, by the lane whose fetch-or sets its mark first, and
+// appended to the next frontier.
 #include <chrono>
 
 #include "trim_device.h"
@@ -130,16 +133,15 @@ __global__ void scc_pivot(int n, const int* row_off, const int* rrow_off, const 
 // Search items: bit 30 = backward, low 30 bits = vertex.
 __device__ __forceinline__ uint32_t ritem(int dir, int v) { return ((uint32_t)dir << 30) | (uint32_t)v; }
 
-// The pivot, marked and queued in both directions (one block, counters zeroed
-// by scc_reset before).
-__global__ void scc_seed_pivot(const unsigned long long* misc, int* flags, uint32_t* q, int* ctr) {
+// The pivot, marked and placed in the frontier in both directions (one
+// thread; misc[kSccFront] = 2).
+__global__ void scc_seed_pivot(unsigned long long* misc, int* flags, uint32_t* front) {
     if (threadIdx.x == 0) {
         const int v = (int)(misc[kSccPivot] & 0xFFFFFFFFull);
         flags[v] = 3;
-        q[0] = ritem(0, v);
-        q[1] = ritem(1, v);
-        ctr[kQTail] = 2;
-        ctr[kPending] = 2;
+        front[0] = ritem(0, v);
+        front[1] = ritem(1, v);
+        misc[kSccFront] = 2;
     }
 }
 
@@ -171,120 +173,233 @@ __global__ void scc_color_sweep(int n, const int* row_off, const int* col, const
     if (ballot(changed) && lane_id() == 0) add_misc(misc + kSccChanged, 1);
 }
 
-// Roots (unassigned v with colour v): marked backward and queued backward
-// (counters zeroed by scc_reset before).
+// Appends this lane's item (if any) to `out` with one counter update per
+// wavefront.
+__device__ __forceinline__ void append_item(bool has, uint32_t it, uint32_t* out,
+                                            unsigned long long* count) {
+    const uint64_t m = ballot(has);
+    if (!m) return;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader)
+        base = __hip_atomic_fetch_add(count, (unsigned long long)popc(m), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    base = ((unsigned long long)__shfl((unsigned)(base >> 32), leader) << 32) |
+           __shfl((unsigned)base, leader);
+    if (has) out[base + popc(m & lanes_below())] = it;
+}
+
+// Roots (unassigned v with colour v): marked backward, placed in the frontier
+// backward (misc[kSccFront] zeroed before).
 __global__ void scc_seed_roots(int n, const uint32_t* live, const int* color, int* flags,
-                               uint32_t* q, int* ctr) {
+                               uint32_t* front, unsigned long long* misc) {
     for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         const int v = base + threadIdx.x;
         const bool root = v < n && has_bit(live, v) && color[v] == v;
         if (root) flags[v] = 2;
-        const int slot = wave_append_slot(root, ctr + kQTail, ctr + kPending);
-        if (root) q[slot] = ritem(1, v);
+        append_item(root, ritem(1, v), front, misc + kSccFront);
     }
 }
-
-constexpr int kRBatch = 8;
-constexpr int kRCoop = 32;   // lists longer than this are expanded by the whole wavefront
 
 // Takes w for direction bit `bit` if it is unassigned, in colour c (when
 // colours are used) and not yet marked: the fetch-or that sets the mark wins.
 __device__ __forceinline__ bool take(int w, int bit, int c, const uint32_t* live, const int* color,
-                                     int* flags) {
+                                     int* flags, bool& tried) {
+    tried = false;
     if (!has_bit(live, w)) return false;
     if (color && color[w] != c) return false;
     if (ld_cached(flags + w) & bit) return false;
+    tried = true;
     return (or_dev(flags + w, bit) & bit) == 0;
 }
 
-// Forward / backward search from the queued items, inside the unassigned
-// vertices (and inside one colour when `color` is given).
-__global__ __launch_bounds__(256) void scc_reach(const int* row_off, const int* col,
-                                                 const int* rrow_off, const int* rcol,
-                                                 const uint32_t* live, const int* color,
-                                                 int* flags, uint32_t* q, int* ctr,
-                                                 unsigned long long* misc) {
-    __shared__ uint32_t rings[256 / kWave][kLocalQ];
-    __shared__ int ring_tail[256 / kWave];
-    WaveQueue wq;
-    const int wv = threadIdx.x / kWave;
-    wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending);
-    uint32_t item = kNone;
-    int k = 0, e = 0, dir = 0, cv = 0;
-    bool started = false;
-    uint64_t examined = 0;
-    while (wq.acquire(item)) {
-        uint32_t out[kRBatch];
+__device__ __forceinline__ uint32_t item_len(uint32_t it, const int* row_off, const int* rrow_off) {
+    const int v = (int)(it & kIdMask);
+    const int* off = (it >> 30) ? rrow_off : row_off;
+    return (uint32_t)(off[v + 1] - off[v]);
+}
+
+// Prefix scan of the frontier's list lengths, step 1: an exclusive scan inside
+// each chunk of kScanChunk items (one block of 256 threads, 4 items each);
+// the chunk's total goes to bsum.
+__global__ __launch_bounds__(256) void scc_scan_chunks(const uint32_t* front, const int* row_off,
+                                                       const int* rrow_off, uint32_t* pre,
+                                                       uint32_t* bsum,
+                                                       const unsigned long long* misc) {
+    __shared__ uint32_t s_w[256 / kWave];
+    const long long F = (long long)misc[kSccFront];
+    const long long chunks = (F + kScanChunk - 1) / kScanChunk;
+    for (long long c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const long long i0 = c * kScanChunk + threadIdx.x * 4;
+        uint32_t len[4], sum = 0;
 #pragma unroll
-        for (int j = 0; j < kRBatch; ++j) out[j] = kNone;
-        if (item != kNone && !started) {
-            const int v = (int)(item & kIdMask);
-            dir = (int)(item >> 30);
-            const int* off = dir ? rrow_off : row_off;
-            k = off[v];
-            e = off[v + 1];
-            cv = color ? color[v] : 0;
-            started = true;
-            examined += (uint64_t)(e - k);
+        for (int j = 0; j < 4; ++j) {
+            len[j] = i0 + j < F ? item_len(front[i0 + j], row_off, rrow_off) : 0;
+            sum += len[j];
         }
-        for (uint64_t big = ballot(item != kNone && e - k > kRCoop); big; big &= big - 1) {
-            const int owner = __ffsll((unsigned long long)big) - 1;
-            const int kb = __shfl(k, owner), eb = __shfl(e, owner);
-            const int db = __shfl(dir, owner), cb = __shfl(cv, owner);
-            const int* adj = db ? rcol : col;
-            const int bit = db ? 2 : 1;
-            for (int base = kb; base < eb; base += kWave * kRBatch) {
-                int u[kRBatch];
-                uint32_t o[kRBatch];
-#pragma unroll
-                for (int j = 0; j < kRBatch; ++j) {
-                    const int p = base + j * kWave + lane_id();
-                    if (p < eb) u[j] = adj[p];
-                }
-#pragma unroll
-                for (int j = 0; j < kRBatch; ++j) {
-                    const int p = base + j * kWave + lane_id();
-                    o[j] = (p < eb && take(u[j], bit, cb, live, color, flags)) ? ritem(db, u[j])
-                                                                              : kNone;
-                }
-#pragma unroll
-                for (int j = 0; j < kRBatch; j += 2) wq.push(o[j], o[j + 1]);
-            }
-            if (lane_id() == owner) {
-                item = kNone;
-                started = false;
-            }
+        // exclusive scan of the per-thread sums over the block
+        uint32_t inc = sum;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d);
+            if (lane_id() >= d) inc += t;
         }
-        if (item != kNone) {
-            const int nb = min(kRBatch, e - k);
-            const int* adj = dir ? rcol : col;
-            const int bit = dir ? 2 : 1;
-            int u[kRBatch];
+        if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = inc;
+        __syncthreads();
+        uint32_t wbase = 0;
+        for (int w = 0; w < threadIdx.x / kWave; ++w) wbase += s_w[w];
+        uint32_t run = wbase + inc - sum;
 #pragma unroll
-            for (int j = 0; j < kRBatch; ++j)
-                if (j < nb) u[j] = adj[k + j];
-#pragma unroll
-            for (int j = 0; j < kRBatch; ++j)
-                if (j < nb && take(u[j], bit, cv, live, color, flags)) out[j] = ritem(dir, u[j]);
-            k += nb;
-            if (k >= e) {
-                item = kNone;
-                started = false;
-                // depth first: go on with a vertex this lane has just taken
-#pragma unroll
-                for (int j = 0; j < kRBatch; ++j)
-                    if (item == kNone && out[j] != kNone) {
-                        item = out[j];
-                        out[j] = kNone;
-                    }
-            }
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < F) pre[i0 + j] = run;
+            run += len[j];
         }
-#pragma unroll
-        for (int j = 0; j < kRBatch; j += 2) wq.push(out[j], out[j + 1]);
-        wq.rebalance();
+        if (threadIdx.x == blockDim.x - 1) bsum[c] = wbase + inc;
+        __syncthreads();
     }
-    examined = wave_sum(examined);
-    if (lane_id() == 0 && examined) add_misc(misc + kSccEdges, examined);
+}
+
+// Step 2 (one block): exclusive scan of the chunk sums, and the frontier's
+// total entries into misc[kSccTotal].
+__global__ void scc_scan_sums(uint32_t* bsum, unsigned long long* misc) {
+    __shared__ uint32_t s_w[16];
+    __shared__ uint32_t s_carry;
+    const long long F = (long long)misc[kSccFront];
+    const long long chunks = (F + kScanChunk - 1) / kScanChunk;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (long long c0 = 0; c0 < chunks; c0 += blockDim.x) {
+        const long long c = c0 + threadIdx.x;
+        const uint32_t x = c < chunks ? bsum[c] : 0;
+        uint32_t inc = x;
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d);
+            if (lane_id() >= d) inc += t;
+        }
+        if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = inc;
+        __syncthreads();
+        uint32_t wbase = s_carry;
+        for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) wbase += s_w[w];
+        if (c < chunks) bsum[c] = wbase + inc - x;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) s_carry = wbase + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        misc[kSccTotal] = s_carry;
+        misc[kSccEdges] += s_carry;
+        misc[kSccNext] = 0;
+    }
+}
+
+// Step 3: add the chunk offsets.
+__global__ void scc_scan_add(uint32_t* pre, const uint32_t* bsum, const unsigned long long* misc) {
+    const long long F = (long long)misc[kSccFront];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < F;
+         i += (long long)gridDim.x * blockDim.x)
+        pre[i] += bsum[i / kScanChunk];
+}
+
+constexpr int kLBS = 2048;   // entries per block range of one level (256 threads x 8)
+
+// The last index i in [0, F) with pre[i] <= key, found by the whole block: a
+// 256-way search, one parallel probe round per step (three steps cover 2^24
+// items) instead of a chain of dependent loads.
+__device__ long long owner_search(const uint32_t* pre, long long F, unsigned long long key) {
+    long long lo = 0, hi = F - 1;
+    while (lo < hi) {   // block-uniform
+        // step 1 probes every index of the range, so the loop ends exactly
+        const long long step = (hi - lo + 1 + blockDim.x - 1) / blockDim.x;
+        const long long i = lo + (long long)threadIdx.x * step;
+        const bool ok = i <= hi && (unsigned long long)pre[i] <= key;
+        // the probes are in order and pre[lo] <= key, so the true ones form a prefix
+        const long long t = __syncthreads_count(ok);
+        const long long nlo = lo + (t - 1) * step;
+        const long long nhi = min(hi, lo + t * step - 1);
+        lo = nlo;
+        hi = step == 1 ? nlo : nhi;
+    }
+    return lo;
+}
+
+// One level: every entry of the frontier's lists, dealt out in block ranges of
+// kLBS consecutive entries; the taken neighbours form the next frontier (one
+// reservation per block range, so the counter is not a hot spot).
+__global__ __launch_bounds__(256) void scc_expand(const uint32_t* front, const uint32_t* pre,
+                                                  const int* row_off, const int* col,
+                                                  const int* rrow_off, const int* rcol,
+                                                  const uint32_t* live, const int* color,
+                                                  int* flags, uint32_t* next,
+                                                  unsigned long long* misc) {
+    __shared__ uint32_t s_pre[kLBS + 1];
+    __shared__ int s_start[kLBS + 1];
+    __shared__ uint32_t s_item[kLBS + 1];
+    __shared__ int s_cv[kLBS + 1];
+    __shared__ uint32_t s_out[kLBS];
+    __shared__ int s_nout;
+    __shared__ unsigned long long s_base;
+    const long long F = (long long)misc[kSccFront];
+    const unsigned long long E = misc[kSccTotal];
+    unsigned long long ors = 0;
+    for (unsigned long long e0 = (unsigned long long)blockIdx.x * kLBS; e0 < E;
+         e0 += (unsigned long long)gridDim.x * kLBS) {
+        const unsigned long long e1 = e0 + kLBS < E ? e0 + kLBS : E;
+        // the frontier items that own the range's first and last entries
+        const long long o0 = owner_search(pre, F, e0);
+        const long long o1 = owner_search(pre, F, e1 - 1);
+        // Every frontier vertex is unassigned, so both of its lists are
+        // non-empty: the owners of kLBS consecutive entries are at most kLBS.
+        const int cnt = (int)min(o1 - o0 + 1, (long long)kLBS);
+        if (threadIdx.x == 0) s_nout = 0;
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const uint32_t it = front[o0 + t];
+            const int v = (int)(it & kIdMask);
+            s_pre[t] = pre[o0 + t];
+            s_item[t] = it;
+            s_start[t] = ((it >> 30) ? rrow_off : row_off)[v];
+            s_cv[t] = color ? color[v] : 0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int j = 0; j < kLBS / 256; ++j) {
+            const unsigned long long e = e0 + (unsigned long long)j * 256 + threadIdx.x;
+            if (e < e1) {
+                int lo = 0, hi = cnt - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((unsigned long long)s_pre[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint32_t it = s_item[lo];
+                const int dir = (int)(it >> 30);
+                const int w = (dir ? rcol : col)[s_start[lo] + (int)(e - s_pre[lo])];
+                bool tried;
+                if (take(w, dir ? 2 : 1, s_cv[lo], live, color, flags, tried))
+                    s_out[atomicAdd(&s_nout, 1)] = ritem(dir, w);
+                ors += tried;
+            }
+        }
+        __syncthreads();
+        const int nout = s_nout;
+        if (nout > 0) {
+            if (threadIdx.x == 0)
+                s_base = __hip_atomic_fetch_add(misc + kSccNext, (unsigned long long)nout,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+            const unsigned long long base = s_base;
+            for (int t = threadIdx.x; t < nout; t += blockDim.x) next[base + t] = s_out[t];
+        }
+        __syncthreads();
+    }
+    ors = wave_sum(ors);
+    if (lane_id() == 0 && ors) add_misc(misc + kSccOrs, ors);
+}
+
+// After a level: the next frontier becomes the current one.
+__global__ void scc_level_done(unsigned long long* misc) {
+    if (threadIdx.x == 0) {
+        misc[kSccFront] = misc[kSccNext];
+        misc[kSccLevels] += 1;
+    }
 }
 
 // Unassigned vertices with the wanted marks join a component: mode 0 (both
@@ -352,6 +467,26 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
     auto reset = [&](int mask) {
         hipLaunchKernelGGL(scc_reset, dim3(1), dim3(256), 0, st, s.misc, mask, w.ctr);
     };
+    // level-synchronous search from the items in front[0] (misc[kSccFront] of
+    // them); ends when a level takes nothing
+    auto search = [&](const int* color) -> hipError_t {
+        const int ge = lc.cus * 8;
+        for (int cur = 0;; cur ^= 1) {
+            hipLaunchKernelGGL(scc_scan_chunks, dim3(ge), dim3(256), 0, st, s.front[cur],
+                               g.row_off, g.rrow_off, s.pre, s.bsum, s.misc);
+            hipLaunchKernelGGL(scc_scan_sums, dim3(1), dim3(1024), 0, st, s.bsum, s.misc);
+            hipLaunchKernelGGL(scc_scan_add, dim3(ge), dim3(256), 0, st, s.pre, s.bsum, s.misc);
+            hipLaunchKernelGGL(scc_expand, dim3(ge), dim3(256), 0, st, s.front[cur], s.pre,
+                               g.row_off, g.col, g.rrow_off, g.rcol, s.live, color, s.flags,
+                               s.front[cur ^ 1], s.misc);
+            hipLaunchKernelGGL(scc_level_done, dim3(1), dim3(64), 0, st, s.misc);
+            hipError_t r = hipGetLastError();
+            if (r == hipSuccess) r = read_misc();
+            if (r != hipSuccess) return r;
+            if (host[kSccFront] == 0) break;
+        }
+        return hipSuccess;
+    };
     using clock = std::chrono::steady_clock;
     auto ms_since = [](clock::time_point t0) {
         return std::chrono::duration<double, std::milli>(clock::now() - t0).count();
@@ -383,10 +518,9 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
         reset((1 << kSccPivot) | (1 << kSccTaken));
         hipLaunchKernelGGL(scc_pivot, dim3(gv), dim3(256), 0, st, n, g.row_off, g.rrow_off, s.live,
                            s.misc);
-        hipLaunchKernelGGL(scc_seed_pivot, dim3(1), dim3(64), 0, st, s.misc, s.flags, w.q, w.ctr);
-        hipLaunchKernelGGL(scc_reach, dim3(lc.workers), dim3(256), 0, st, g.row_off, g.col,
-                           g.rrow_off, g.rcol, s.live, (const int*)nullptr, s.flags, w.q, w.ctr,
-                           s.misc);
+        hipLaunchKernelGGL(scc_seed_pivot, dim3(1), dim3(64), 0, st, s.misc, s.flags,
+                           s.front[0]);
+        if ((e = search(nullptr)) != hipSuccess) return e;
         hipLaunchKernelGGL(scc_take_marked, dim3(gv), dim3(256), 0, st, n, 0, s.live, s.flags,
                            (const int*)nullptr, label, s.assigned, s.misc);
         if ((e = hipGetLastError()) != hipSuccess || (e = read_misc()) != hipSuccess) return e;
@@ -410,12 +544,10 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
             counts->color_sweeps += 1;
             if (host[kSccChanged] == 0) break;
         }
-        reset(1 << kSccTaken);
+        reset((1 << kSccTaken) | (1 << kSccFront));
         hipLaunchKernelGGL(scc_seed_roots, dim3(gv), dim3(256), 0, st, n, s.live, s.color, s.flags,
-                           w.q, w.ctr);
-        hipLaunchKernelGGL(scc_reach, dim3(lc.workers), dim3(256), 0, st, g.row_off, g.col,
-                           g.rrow_off, g.rcol, s.live, (const int*)s.color, s.flags, w.q, w.ctr,
-                           s.misc);
+                           s.front[0], s.misc);
+        if ((e = search(s.color)) != hipSuccess) return e;
         hipLaunchKernelGGL(scc_take_marked, dim3(gv), dim3(256), 0, st, n, 1, s.live, s.flags,
                            (const int*)s.color, label, s.assigned, s.misc);
         if ((e = hipGetLastError()) != hipSuccess || (e = read_misc()) != hipSuccess) return e;
@@ -432,14 +564,11 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
     if ((e = hipGetLastError()) != hipSuccess || (e = read_misc()) != hipSuccess) return e;
     counts->n_scc = (long long)host[kSccCount];
     counts->search_edges = (long long)host[kSccEdges];
+    counts->search_levels = (int)host[kSccLevels];
+    counts->search_ors = (long long)host[kSccOrs];
     return hipSuccess;
 }
 
-int scc_max_workers_per_cu(int) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, scc_reach, 256, 0) != hipSuccess)
-        return 1;
-    return nb < 1 ? 1 : nb;
-}
+
 
 }  // namespace trim

@@ -18,15 +18,22 @@ struct SccWork {
     int* flags = nullptr;          // n: reach marks, bit 0 forward, bit 1 backward
     int* color = nullptr;          // n: max-label colours
     unsigned long long* misc = nullptr;  // kSccMisc words: pivot key, counters
+    uint32_t* front[2] = {nullptr, nullptr};  // 2n + 64 search items each (current, next)
+    uint32_t* pre = nullptr;       // 2n + 64: exclusive prefix of the frontier's list lengths
+    uint32_t* bsum = nullptr;      // per-chunk sums of the prefix scan
 };
 enum SccMisc : int { kSccPivot = 0, kSccActive = 1, kSccChanged = 2, kSccTaken = 3,
-                     kSccCount = 4, kSccEdges = 5, kSccMisc = 16 };
+                     kSccCount = 4, kSccEdges = 5, kSccFront = 6, kSccTotal = 7, kSccNext = 8,
+                     kSccLevels = 9, kSccOrs = 10, kSccMisc = 16 };
+constexpr int kScanChunk = 1024;   // frontier items per chunk of the prefix scan
 
 // Counts of one decomposition (host side).
 struct SccCounts {
     long long n_scc = 0, trimmed = 0, giant = 0;
     int trims = 0, color_rounds = 0, color_sweeps = 0;
     long long search_edges = 0;   // list entries the searches examined
+    int search_levels = 0;        // frontier levels of all searches
+    long long search_ors = 0;     // mark fetch-ors issued (marks won: at most 2 per vertex)
     double trim_ms = 0, search_ms = 0, color_ms = 0;   // host-timed phases
     bool stalled = false;   // a round made no progress (cannot happen; guarded)
 };
@@ -34,6 +41,5 @@ struct SccCounts {
 // FW-BW decomposition driven from the host (synchronises `lc.stream`).
 hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const SccWork& s,
                    const LaunchCfg& lc, int* label, SccCounts* counts);
-int scc_max_workers_per_cu(int block);
 
 }  // namespace trim

@@ -126,6 +126,10 @@ void free_scc(trim_ctx* c) {
     (void)hipFree(c->sw.flags);
     (void)hipFree(c->sw.color);
     (void)hipFree(c->sw.misc);
+    (void)hipFree(c->sw.front[0]);
+    (void)hipFree(c->sw.front[1]);
+    (void)hipFree(c->sw.pre);
+    (void)hipFree(c->sw.bsum);
     c->sw = trim::SccWork{};
     c->cap_scc = 0;
 }
@@ -140,7 +144,12 @@ int ensure_scc(trim_ctx* c, int64_t n) {
         hipMalloc((void**)&c->sw.live, words * 4) != hipSuccess ||
         hipMalloc((void**)&c->sw.flags, cap * 4) != hipSuccess ||
         hipMalloc((void**)&c->sw.color, cap * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.misc, trim::kSccMisc * 8) != hipSuccess) {
+        hipMalloc((void**)&c->sw.misc, trim::kSccMisc * 8) != hipSuccess ||
+        hipMalloc((void**)&c->sw.front[0], (2 * cap + 64) * 4) != hipSuccess ||
+        hipMalloc((void**)&c->sw.front[1], (2 * cap + 64) * 4) != hipSuccess ||
+        hipMalloc((void**)&c->sw.pre, (2 * cap + 64) * 4) != hipSuccess ||
+        hipMalloc((void**)&c->sw.bsum, ((2 * cap + 64) / trim::kScanChunk + 64) * 4) !=
+            hipSuccess) {
         (void)hipGetLastError();
         free_scc(c);
         return fail(TRIM_E_NOMEM, "cannot allocate SCC working memory for %lld vertices",
@@ -440,8 +449,9 @@ int trim_scc(trim_ctx* c, const trim_csr_t* g, const trim_opts_t* o, int32_t* la
         stats->trims = k.trims;
         stats->color_rounds = k.color_rounds;
         stats->color_sweeps = k.color_sweeps;
-        stats->reserved = 0;
+        stats->search_levels = k.search_levels;
         stats->search_edges = k.search_edges;
+        stats->search_ors = k.search_ors;
         stats->trim_ms = k.trim_ms;
         stats->search_ms = k.search_ms;
         stats->color_ms = k.color_ms;
