@@ -21,6 +21,7 @@
 #include "trim_device.h"
 #include "trim_stats.h"
 #include "trim_internal.h"
+#include "block_append.h"
 
 namespace trim {
 
@@ -71,20 +72,31 @@ __global__ void ac3_init(View g, int n, const uint32_t* preset, int* ptr, int* d
     }
 }
 
-// The first list without the preset vertices (wavefront-aggregated appends;
-// the order of the list does not matter to the rounds).
+// The first list without the preset vertices (one reservation per block and
+// step; the order of the list does not matter to the rounds).
 template <class View>
 __global__ void ac3_list_preset(View g, int n, const uint32_t* preset, int* list1, int* ctr) {
     __shared__ uint64_t lds[Stage3<View>::kWords];
+    __shared__ int s_wave[1024 / kWave], s_base;
     Stage3<View>::apply(g, lds);
-    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const int v = base + threadIdx.x;
-        const bool keep = v < n && !((preset[v >> 5] >> (v & 31)) & 1u);
-        const int slot = wave_append_slot(keep, ctr + kCnt0 + 1, nullptr);
-        if (keep) {
-            const int b = g.begin(v), e = g.end(v);
-            list1[slot] = v;
-            list1[n + slot] = b < e ? g.target(v, b, g.vctx(v)) : kNoTarget;
+    const int step = gridDim.x * blockDim.x * 4;
+    for (int base = blockIdx.x * blockDim.x * 4; base < n; base += step) {
+        int v[4], c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = base + j * blockDim.x + threadIdx.x;
+            const bool keep = x < n && !((preset[x >> 5] >> (x & 31)) & 1u);
+            v[j] = keep ? x : -1;
+            c += keep;
+        }
+        int slot = block_append_base(c, ctr + kCnt0 + 1, nullptr, s_wave, &s_base);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (v[j] < 0) continue;
+            const int b = g.begin(v[j]), e = g.end(v[j]);
+            list1[slot] = v[j];
+            list1[n + slot] = b < e ? g.target(v[j], b, g.vctx(v[j])) : kNoTarget;
+            ++slot;
         }
     }
 }
@@ -239,7 +251,7 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     }
     if (preset && n > 0) {
         Timed t(lc, "ac3_list_preset");
-        hipLaunchKernelGGL(ac3_list_preset<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
+        hipLaunchKernelGGL(ac3_list_preset<View>, dim3(grid_for(n, 1024, lc.cus * 8)), dim3(256), 0,
                            lc.stream, g, n, preset, list1, w.ctr);
     }
     if (n > 0) {

@@ -24,6 +24,7 @@
 #include "trim_device.h"
 #include "trim_stats.h"
 #include "trim_internal.h"
+#include "block_append.h"
 
 namespace trim {
 
@@ -51,13 +52,24 @@ __global__ void ac4_init(const int* row_off, const int* rrow_off, const uint32_t
     }
 }
 
+// Four vertices per thread, one shared-queue reservation per block and step.
 template <bool kTwo>
 __global__ void ac4_seed(const int* cnt, const int* dead, int n, uint32_t* q, int* ctr) {
-    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
-        const int v = base + threadIdx.x;
-        const bool d = v < n && (kTwo ? dead[v] != 0 : cnt[v] == 0);
-        const int slot = wave_append_slot(d, ctr + kQTail, ctr + kPending);
-        if (d) q[slot] = make_item(0, v);
+    __shared__ int s_wave[1024 / kWave], s_base;
+    const int step = gridDim.x * blockDim.x * 4;
+    for (int base = blockIdx.x * blockDim.x * 4; base < n; base += step) {
+        int v[4], c = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int x = base + j * blockDim.x + threadIdx.x;
+            const bool d = x < n && (kTwo ? dead[x] != 0 : cnt[x] == 0);
+            v[j] = d ? x : -1;
+            c += d;
+        }
+        int slot = block_append_base(c, ctr + kQTail, ctr + kPending, s_wave, &s_base);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (v[j] >= 0) q[slot++] = make_item(0, v[j]);
     }
 }
 
@@ -220,7 +232,7 @@ hipError_t ac4_run(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
     if (n > 0) {
         {
             Timed t(lc, kTwo ? "ac4t_seed" : "ac4_seed");
-            hipLaunchKernelGGL(ac4_seed<kTwo>, dim3(grid_for(n, B, lc.cus * 8)), dim3(B), 0,
+            hipLaunchKernelGGL(ac4_seed<kTwo>, dim3(grid_for(n, 4 * B, lc.cus * 8)), dim3(B), 0,
                                lc.stream, w.a, w.d, n, w.q, w.ctr);
         }
         {
