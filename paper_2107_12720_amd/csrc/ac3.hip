@@ -128,7 +128,9 @@ __device__ __forceinline__ void grid_barrier(int* count, int* gen) {
 }
 
 // kUnroll list entries per lane per step, their loads in flight together, and
-// one output reservation per wavefront per step.  An entry whose cursor target
+// one output reservation per workgroup per step (a reservation per wavefront
+// made the list counter a single-address hot spot: thousands of serialised
+// atomics per round).  An entry whose cursor target
 // is still live costs one random access (the target's removal round); only
 // when it has died are the cursor, the offsets and further successors read.
 constexpr int kUnroll = 4;
@@ -138,6 +140,7 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int n, int* ptr, int* 
                                                   int* list0, int* list1, int* ctr,
                                                   uint64_t* worker_edges, trim_stats_t* stats) {
     __shared__ uint64_t lds[Stage3<View>::kWords];
+    __shared__ int s_wave[256 / kWave], s_base;
     Stage3<View>::apply(g, lds);
     uint64_t edges = 0;
     int r = 1;
@@ -191,25 +194,16 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int n, int* ptr, int* 
                     st_dev(dround + v[k], r);
                 }
             }
-            uint64_t masks[kUnroll];
-            int total = 0;
+            int c = 0;
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) c += keep[k];
+            int slot = block_append_base(c, cnt_out, nullptr, s_wave, &s_base);
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
-                masks[k] = ballot(keep[k]);
-                total += popc(masks[k]);
-            }
-            if (total) {
-                int at = 0;
-                if (lane_id() == 0) at = add_dev(cnt_out, total);
-                at = __shfl(at, 0);
-#pragma unroll
-                for (int k = 0; k < kUnroll; ++k) {
-                    if (keep[k]) {
-                        const int slot = at + popc(masks[k] & lanes_below());
-                        st_dev(out + slot, v[k]);
-                        st_dev(out + n + slot, w[k]);
-                    }
-                    at += popc(masks[k]);
+                if (keep[k]) {
+                    st_dev(out + slot, v[k]);
+                    st_dev(out + n + slot, w[k]);
+                    ++slot;
                 }
             }
         }
