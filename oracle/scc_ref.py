@@ -39,6 +39,42 @@ def scc_labels(g) -> np.ndarray:
     return canonical(lab)
 
 
+def size2_pairs(g, preset=None) -> np.ndarray:
+    """Size-2 SCC trimming (the pattern check that follows size-1 trimming,
+    Section 1.1): among the vertices not preset as removed, u and v != u are
+    a pair iff each is the other's only remaining predecessor (nothing else
+    reaches the pair) or each is the other's only remaining successor (the
+    pair reaches nothing else); such a pair is a component of its own.
+    Returns partner[u] = v for paired vertices, -1 otherwise.  Plain sets,
+    one vertex at a time."""
+    n = g.n
+    alive = np.ones(n, bool) if preset is None else ~np.asarray(preset, bool)
+    ro = g.row_off.astype(np.int64)
+    rro = np.zeros(n + 1, np.int64)
+    np.add.at(rro, g.col.astype(np.int64) + 1, 1)
+    rro = np.cumsum(rro)
+    order = np.argsort(g.col, kind="stable")
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(ro))[order]
+    only_in = np.full(n, -1, np.int64)
+    only_out = np.full(n, -1, np.int64)
+    for u in range(n):
+        if not alive[u]:
+            continue
+        preds = {int(x) for x in src[rro[u]:rro[u + 1]] if alive[x]}
+        succs = {int(x) for x in g.col[ro[u]:ro[u + 1]] if alive[x]}
+        if len(preds) == 1 and u not in preds:
+            only_in[u] = preds.pop()
+        if len(succs) == 1 and u not in succs:
+            only_out[u] = succs.pop()
+    partner = np.full(n, -1, np.int64)
+    for u in range(n):
+        for only in (only_in, only_out):
+            v = only[u]
+            if v >= 0 and only[v] == u:
+                partner[u] = v
+    return partner
+
+
 def summary(labels) -> dict:
     """Number of components, of size-1 components, and the largest size."""
     labels = np.asarray(labels)

@@ -698,3 +698,61 @@ def test_scc_reference_versus_trimming(orc, gen, seed):
     on_cycle = (size > 1) | loop
     assert not (r2.live.astype(bool) == 0)[on_cycle].any()
     assert (lab[r2.live == 0] == np.flatnonzero(r2.live == 0)).all()
+
+
+def test_size2_pairs_are_components(gen):
+    """The pairs the size-2 check reports are exactly the strongly connected
+    components of two vertices, neither with a self-loop, that no other
+    remaining vertex enters or that leave to no other remaining vertex."""
+    from oracle.scc_ref import scc_labels, size2_pairs
+    rng = np.random.default_rng(11)
+    for trial in range(200):
+        n = int(rng.integers(2, 14))
+        m = int(rng.integers(1, 3 * n))
+        adj = [[] for _ in range(n)]
+        for _ in range(m):
+            adj[int(rng.integers(n))].append(int(rng.integers(n)))
+        for _ in range(int(rng.integers(0, 3))):   # plant some 2-cycles
+            a, b = rng.choice(n, 2, replace=False)
+            adj[int(a)].append(int(b))
+            adj[int(b)].append(int(a))
+        g = gen.from_adjacency(adj)
+        preset = (rng.random(n) < 0.2).astype(np.uint8)
+        alive = preset == 0
+        partner = size2_pairs(g, preset)
+        # the components of the remaining vertices
+        keep = np.flatnonzero(alive)
+        idx = np.full(n, -1)
+        idx[keep] = np.arange(keep.size)
+        sub = gen.from_adjacency([[int(idx[w]) for w in adj[v] if alive[w]] for v in keep])
+        lab = scc_labels(sub)
+        want = np.full(n, -1)
+        for comp in np.unique(lab):
+            mem = keep[lab == comp]
+            if mem.size != 2:
+                continue
+            a, b = int(mem[0]), int(mem[1])
+            if a in adj[a] or b in adj[b]:
+                continue
+            enters = any(alive[u] and u not in (a, b) and w in (a, b)
+                         for u in range(n) for w in adj[u])
+            leaves = any(w not in (a, b) and alive[w] for u in (a, b) for w in adj[u])
+            if not enters or not leaves:
+                want[a], want[b] = b, a
+        assert (partner == want).all(), (adj, preset, partner, want)
+
+
+def test_size2_pairs_hand_example(gen):
+    from oracle.scc_ref import size2_pairs
+    # 0 <-> 1 fed by 2 (not a source pair, but a sink pair: 0, 1 reach nothing
+    # else); 3 <-> 4 with 3 -> 5: a source pair (nothing enters); 6 <-> 7 with
+    # 8 -> 6 and 7 -> 8: neither
+    g = gen.from_adjacency([[1], [0], [0], [4, 5], [3], [], [7], [6, 8], [6]])
+    assert list(size2_pairs(g)) == [1, 0, -1, 4, 3, -1, -1, -1, -1]
+    # removing 5 from the start changes nothing for 3 <-> 4; removing 2 too
+    pre = np.zeros(9, np.uint8)
+    pre[[2, 5]] = 1
+    assert list(size2_pairs(g, pre)) == [1, 0, -1, 4, 3, -1, -1, -1, -1]
+    # a self-loop on 0 breaks the pair
+    g = gen.from_adjacency([[0, 1], [0]])
+    assert list(size2_pairs(g)) == [-1, -1]
