@@ -231,6 +231,8 @@ typedef struct {
     double trim_ms;        /* host-timed phases: trimming passes, */
     double search_ms;      /* the pivot's forward-backward search, */
     double color_ms;       /* colouring rounds (without their trimming) */
+    int64_t paired;        /* vertices found in components of two by the size-2 check */
+    double size2_ms;       /* host-timed size-2 check */
 } trim_scc_stats_t;
 
 /*
@@ -242,18 +244,38 @@ typedef struct {
  * colouring rounds (each unassigned vertex takes the largest id that reaches
  * it; a vertex keeping its own id is a root whose component is the vertices
  * of its colour that reach it) take out the rest, with trimming after each
- * round.  g->rrow_off and g->rcol are required and must hold the transpose.
+ * round.  Between the search and the colouring, the size-2 check of
+ * trim_size2 takes out components of two.  g->rrow_off and g->rcol are
+ * required and must hold the transpose.
  * Output: label (device, n int32): label[v] is the id of one vertex of v's
  * component, so u and v share a component iff label[u] == label[v], and
  * label[label[v]] == label[v].  stats (host, may be NULL) receives the
  * counts.  The rounds and search levels are driven from the host: the call
  * synchronises `stream` once per level and returns when the labels are final.
  * Uses 96 bytes per vertex of context memory (the two-sided trimming arrays,
- * SCC marks and colours, two search frontiers and their prefix sums).  TRIM_E_STALLED if a round made no
- * progress (a guard; the method always progresses).
+ * SCC marks and colours, two search frontiers and their prefix sums).
+ * TRIM_E_STALLED if a round made no progress (a guard; the method always
+ * progresses).
  */
 int trim_scc(trim_ctx *ctx, const trim_csr_t *g, const trim_opts_t *opts, int32_t *label,
              trim_scc_stats_t *stats, void *stream);
+
+/*
+ * Size-2 SCC trimming, the pattern check that follows size-1 trimming
+ * (Section 1.1; the paper gives no algorithm, this is the check used here):
+ * among the vertices not set in preset_dead (device bitmap as in
+ * trim_csr_preset; NULL = none removed), u and v != u form a component of
+ * two when each is the other's only remaining predecessor (nothing else
+ * reaches them) or each is the other's only remaining successor (they reach
+ * nothing else); a self-loop rules its vertex out.  Output partner (device,
+ * n int32): the other vertex for paired vertices, -1 for all others
+ * (including removed ones).  n_paired (host, may be NULL) receives the
+ * number of paired vertices; passing it synchronises `stream`.  g->rrow_off
+ * and g->rcol are required.  trim_scc runs this check once, after the
+ * forward-backward search and the trimming that follows it.
+ */
+int trim_size2(trim_ctx *ctx, const trim_csr_t *g, const uint32_t *preset_dead, int32_t *partner,
+               int64_t *n_paired, void *stream);
 
 /*
  * Trim an implicit graph (AC-6 or AC-3 only; AC-4 needs G^T and returns

@@ -30,7 +30,7 @@ STATUS = {0: "TRIM_OK", -1: "TRIM_E_INVAL", -2: "TRIM_E_NOMEM", -3: "TRIM_E_HIP"
           -4: "TRIM_E_UNSUPPORTED", -5: "TRIM_E_BADGRAPH", -6: "TRIM_E_STALLED"}
 EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destroy",
            "trim_num_workers", "trim_csr", "trim_csr_preset", "trim_csr_two_sided",
-           "trim_scc", "trim_implicit", "trim_batch",
+           "trim_scc", "trim_size2", "trim_implicit", "trim_batch",
            "trim_ctx_set_timing", "trim_ctx_kernel_times", "trim_mlp_prepare", "trim_mlp_grad",
            "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key")
 MLP_PARAMS = 1377
@@ -64,7 +64,8 @@ class SccStats(ctypes.Structure):
                 ("color_sweeps", ctypes.c_int32), ("search_levels", ctypes.c_int32),
                 ("search_edges", ctypes.c_int64), ("search_ors", ctypes.c_int64),
                 ("trim_ms", ctypes.c_double),
-                ("search_ms", ctypes.c_double), ("color_ms", ctypes.c_double)]
+                ("search_ms", ctypes.c_double), ("color_ms", ctypes.c_double),
+                ("paired", ctypes.c_int64), ("size2_ms", ctypes.c_double)]
 
 
 class ImplicitDesc(ctypes.Structure):
@@ -93,6 +94,8 @@ def lib():
                                vp, vp, vp, vp]
         L.trim_scc.argtypes = [vp, ctypes.POINTER(CsrDesc), ctypes.POINTER(Opts), vp,
                                ctypes.POINTER(SccStats), vp]
+        L.trim_size2.argtypes = [vp, ctypes.POINTER(CsrDesc), vp, vp,
+                                 ctypes.POINTER(ctypes.c_int64), vp]
         L.trim_csr_preset.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc), vp,
                                       ctypes.POINTER(Opts), vp, vp, vp, vp]
         L.trim_csr_two_sided.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc),
@@ -114,7 +117,7 @@ def lib():
         L.trim_edge_keys.argtypes = [vp, csr_p, i32, ctypes.c_uint64, vp, vp]
         L.trim_order_by_key.argtypes = [vp, csr_p, vp, f32, f32, vp, vp]
         for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_num_workers", "trim_csr",
-                  "trim_csr_preset", "trim_csr_two_sided", "trim_scc",
+                  "trim_csr_preset", "trim_csr_two_sided", "trim_scc", "trim_size2",
                   "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times",
                   "trim_mlp_prepare", "trim_mlp_grad", "trim_mlp_adam", "trim_mlp_score",
                   "trim_edge_keys", "trim_order_by_key"):
@@ -266,6 +269,25 @@ class Context:
                               _stream_handle(stream, self.device)))
         return label, {k: (float if t is ctypes.c_double else int)(getattr(st, k))
                        for k, t in SccStats._fields_}
+
+    def trim_size2(self, n, row_off, col, rrow_off, rcol, preset_dead=None, *, partner=None,
+                   stream=None):
+        """Size-2 check: (partner int32 device tensor, number of paired
+        vertices); partner[u] = v for a component {u, v} of two, else -1."""
+        import torch
+        m = int(col.numel()) if col is not None else 0
+        d = CsrDesc(int(n), m, _dev_ptr(row_off, torch.int32, "row_off"),
+                    _dev_ptr(col, torch.int32, "col") if m else None,
+                    _dev_ptr(rrow_off, torch.int32, "rrow_off"),
+                    _dev_ptr(rcol, torch.int32, "rcol") if m else None)
+        pd = _dev_ptr(preset_dead, torch.int32, "preset_dead", allow_none=True)
+        if partner is None:
+            partner = torch.empty(max(int(n), 1), dtype=torch.int32,
+                                  device=torch.device("cuda", self.device))
+        np_ = ctypes.c_int64()
+        _check(lib().trim_size2(self._h, ctypes.byref(d), pd, ctypes.c_void_p(partner.data_ptr()),
+                                ctypes.byref(np_), _stream_handle(stream, self.device)))
+        return partner, int(np_.value)
 
     def trim_csr_preset(self, algo, n, row_off, col, preset_dead, rrow_off=None, rcol=None, *,
                         live_bitmap=None, worker_edges=None, stats=None,

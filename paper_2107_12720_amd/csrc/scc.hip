@@ -19,8 +19,12 @@
 //     search inside the colour) are exactly r's component.  The largest
 //     unassigned id is always a root, so every round assigns at least one
 //     component.  Then trimming again.
-// label[v] is the id of one vertex of v's component (v itself, the pivot or
-// the root); equal labels mean one component.
+// Between 3 and 4, the size-2 check: two unassigned vertices that are each
+// other's only unassigned predecessor (or only unassigned successor) form a
+// component of two, labelled with the smaller id; trimming follows if any
+// were found.
+// label[v] is the id of one vertex of v's component (v itself, the pivot,
+// the pair's smaller id or the root); equal labels mean one component.
 //
 // The searches go level by level over a frontier of items (a vertex and a
 // direction: forward follows successors, backward predecessors).  A level
@@ -71,9 +75,11 @@ __global__ void scc_init(int n, int* label, int* flags, uint32_t* assigned,
     if (tid < kSccMisc) misc[tid] = 0;
 }
 
-// Zeroes the misc words selected by `mask` and the queue counters (one block).
+// Zeroes the misc words selected by `mask` and the queue counters, if given
+// (one block).
 __global__ void scc_reset(unsigned long long* misc, int mask, int* ctr) {
-    for (int i = threadIdx.x; i < kCtrInts; i += blockDim.x) ctr[i] = 0;
+    if (ctr)
+        for (int i = threadIdx.x; i < kCtrInts; i += blockDim.x) ctr[i] = 0;
     if (threadIdx.x < kSccMisc && ((mask >> threadIdx.x) & 1)) misc[threadIdx.x] = 0;
 }
 
@@ -394,6 +400,83 @@ __global__ __launch_bounds__(256) void scc_expand(const uint32_t* front, const u
     if (lane_id() == 0 && ors) add_misc(misc + kSccOrs, ors);
 }
 
+// Size-2 check (the pattern after size-1 trimming): the only remaining
+// neighbour of u in one list, or -1 when u has none, several, or itself.
+__device__ __forceinline__ int only_neighbour(const int* off, const int* adj, int u,
+                                              const uint32_t* live) {
+    int a = -1;
+    const int e = off[u + 1];
+    for (int p = off[u]; p < e; ++p) {
+        const int w = adj[p];
+        if (!has_bit(live, w)) continue;
+        if (w == u || (a >= 0 && w != a)) return -1;
+        a = w;
+    }
+    return a;
+}
+
+__global__ void size2_only(int n, const int* row_off, const int* col, const int* rrow_off,
+                           const int* rcol, const uint32_t* live, int* only_in, int* only_out) {
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        const bool a = has_bit(live, u);
+        only_in[u] = a ? only_neighbour(rrow_off, rcol, u, live) : -1;
+        only_out[u] = a ? only_neighbour(row_off, col, u, live) : -1;
+    }
+}
+
+// partner[u] = v when u and v are each other's only remaining predecessor
+// (nothing else reaches the pair) or only remaining successor (the pair
+// reaches nothing else): a component of two.  -1 otherwise.
+__global__ void size2_pair(int n, const int* only_in, const int* only_out, int* partner) {
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x) {
+        int p = -1;
+        const int a = only_in[u], b = only_out[u];
+        if (a >= 0 && only_in[a] == u) p = a;
+        else if (b >= 0 && only_out[b] == u) p = b;
+        partner[u] = p;
+    }
+}
+
+__global__ void size2_count(int n, const int* partner, unsigned long long* misc) {
+    __shared__ unsigned long long red[16];
+    unsigned long long c = 0;
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += gridDim.x * blockDim.x)
+        c += partner[u] >= 0;
+    c = block_total(c, red);
+    if (threadIdx.x == 0 && c) add_misc(misc + kSccCount, c);
+}
+
+// Paired vertices join their component, labelled with the pair's smaller id.
+__global__ void scc_take_pairs(int n, const uint32_t* live, const int* partner, int* label,
+                               uint32_t* assigned, unsigned long long* misc) {
+    __shared__ unsigned long long red[16];
+    const int waves = (gridDim.x * blockDim.x) / kWave;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    unsigned long long taken = 0;
+    for (int base = wid * kWave; base < n; base += waves * kWave) {
+        const int v = base + lane_id();
+        const int p = v < n && has_bit(live, v) ? partner[v] : -1;
+        if (p >= 0) label[v] = min(v, p);
+        const uint64_t m = ballot(p >= 0);
+        if (lane_id() == 0 && m) {
+            assigned[base >> 5] |= (uint32_t)m;
+            assigned[(base >> 5) + 1] |= (uint32_t)(m >> 32);
+            taken += (unsigned long long)popc(m);
+        }
+    }
+    taken = block_total(taken, red);
+    if (threadIdx.x == 0 && taken) add_misc(misc + kSccTaken, taken);
+}
+
+// live = not preset (all vertices when preset is NULL), bits past n clear.
+__global__ void scc_live_from_preset(int n, const uint32_t* preset, uint32_t* live) {
+    const int words = (n + 31) >> 5;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x) {
+        const uint32_t valid = (w == words - 1 && (n & 31)) ? ((1u << (n & 31)) - 1u) : ~0u;
+        live[w] = (preset ? ~preset[w] : ~0u) & valid;
+    }
+}
+
 // After a level: the next frontier becomes the current one.
 __global__ void scc_level_done(unsigned long long* misc) {
     if (threadIdx.x == 0) {
@@ -528,6 +611,22 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
         counts->search_ms += ms_since(t0);
         if ((e = trim_round()) != hipSuccess) return e;
     }
+    if (active > 0) {
+        // size-2 components (each the other's only remaining predecessor or
+        // successor), then trimming again if any were found
+        const auto t0 = clock::now();
+        int* partner = reinterpret_cast<int*>(s.pre);
+        reset(1 << kSccTaken);
+        hipLaunchKernelGGL(size2_only, dim3(gv), dim3(256), 0, st, n, g.row_off, g.col, g.rrow_off,
+                           g.rcol, s.live, s.flags, s.color);
+        hipLaunchKernelGGL(size2_pair, dim3(gv), dim3(256), 0, st, n, s.flags, s.color, partner);
+        hipLaunchKernelGGL(scc_take_pairs, dim3(gv), dim3(256), 0, st, n, s.live, partner, label,
+                           s.assigned, s.misc);
+        if ((e = hipGetLastError()) != hipSuccess || (e = read_misc()) != hipSuccess) return e;
+        counts->paired = (long long)host[kSccTaken];
+        counts->size2_ms += ms_since(t0);
+        if (counts->paired > 0 && (e = trim_round()) != hipSuccess) return e;
+    }
     while (active > 0) {
         // colouring round
         const auto t0 = clock::now();
@@ -570,5 +669,35 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
 }
 
 
+
+}  // namespace trim
+
+namespace trim {
+
+hipError_t size2_run(const trim_csr_t& g, const SccWork& s, const uint32_t* preset, int* partner,
+                     long long* n_paired, hipStream_t st, int cus) {
+    const int n = g.n;
+    if (n_paired) *n_paired = 0;
+    if (n == 0) return hipSuccess;
+    const int gv = grid_for(n, 256, cus * 8);
+    const int gw = grid_for((n + 31) / 32, 256, cus * 8);
+    hipLaunchKernelGGL(scc_live_from_preset, dim3(gw), dim3(256), 0, st, n, preset, s.live);
+    hipLaunchKernelGGL(size2_only, dim3(gv), dim3(256), 0, st, n, g.row_off, g.col, g.rrow_off,
+                       g.rcol, s.live, s.flags, s.color);
+    hipLaunchKernelGGL(size2_pair, dim3(gv), dim3(256), 0, st, n, s.flags, s.color, partner);
+    if (n_paired) {
+        unsigned long long c = 0;
+        hipLaunchKernelGGL(scc_reset, dim3(1), dim3(256), 0, st, s.misc, 1 << kSccCount,
+                           (int*)nullptr);
+        hipLaunchKernelGGL(size2_count, dim3(gv), dim3(256), 0, st, n, partner, s.misc);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&c, s.misc + kSccCount, sizeof c, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        *n_paired = (long long)c;
+    }
+    return hipGetLastError();
+}
 
 }  // namespace trim

@@ -34,9 +34,18 @@ struct SccCounts {
     long long search_edges = 0;   // list entries the searches examined
     int search_levels = 0;        // frontier levels of all searches
     long long search_ors = 0;     // mark fetch-ors issued (marks won: at most 2 per vertex)
+    long long paired = 0;         // vertices found in components of two by the size-2 check
+    double size2_ms = 0;
     double trim_ms = 0, search_ms = 0, color_ms = 0;   // host-timed phases
     bool stalled = false;   // a round made no progress (cannot happen; guarded)
 };
+
+// Size-2 check on the vertices not in `preset` (NULL = all): partner[u] (n
+// ints) as in trim_size2; n_paired (host, may be NULL: then no
+// synchronisation) receives the number of paired vertices.  Uses s.live,
+// s.flags, s.color and s.misc.
+hipError_t size2_run(const trim_csr_t& g, const SccWork& s, const uint32_t* preset, int* partner,
+                     long long* n_paired, hipStream_t st, int cus);
 
 // FW-BW decomposition driven from the host (synchronises `lc.stream`).
 hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const SccWork& s,

@@ -455,7 +455,30 @@ int trim_scc(trim_ctx* c, const trim_csr_t* g, const trim_opts_t* o, int32_t* la
         stats->trim_ms = k.trim_ms;
         stats->search_ms = k.search_ms;
         stats->color_ms = k.color_ms;
+        stats->paired = k.paired;
+        stats->size2_ms = k.size2_ms;
     }
+    return TRIM_OK;
+}
+
+int trim_size2(trim_ctx* c, const trim_csr_t* g, const uint32_t* preset_dead, int32_t* partner,
+               int64_t* n_paired, void* stream) {
+    if (!c || !g) return fail(TRIM_E_INVAL, "trim_size2: NULL context or graph");
+    if (g->n < 0 || g->n > (1 << 29)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
+    if (g->m < 0 || g->m >= (int64_t)1 << 31)
+        return fail(TRIM_E_INVAL, "m = %lld out of range [0, 2^31)", (long long)g->m);
+    if (!g->row_off || !g->rrow_off) return fail(TRIM_E_INVAL, "row_off or rrow_off is NULL");
+    if (g->m > 0 && (!g->col || !g->rcol)) return fail(TRIM_E_INVAL, "col or rcol is NULL");
+    if (g->n > 0 && !partner) return fail(TRIM_E_INVAL, "partner is NULL");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int rc;
+    if ((rc = ensure_scc(c, g->n))) return rc;
+    long long np = 0;
+    e = trim::size2_run(*g, c->sw, preset_dead, partner, n_paired ? &np : nullptr,
+                        (hipStream_t)stream, c->cus);
+    if (e != hipSuccess) return hip_fail(e, "size-2 check");
+    if (n_paired) *n_paired = np;
     return TRIM_OK;
 }
 

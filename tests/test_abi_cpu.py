@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     text = open(os.path.join(ROOT, "include", "trim.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(trim_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(trim_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_expected_calls():
@@ -41,6 +41,7 @@ def test_null_arguments_rejected():
     assert "NULL" in T.last_error()
     assert L.trim_csr_preset(None, 6, None, None, None, None, None, None, None) == -1
     assert L.trim_scc(None, None, None, None, None, None) == -1
+    assert L.trim_size2(None, None, None, None, None, None) == -1
     assert "NULL" in T.last_error()
     assert L.trim_ctx_destroy(None) == 0
 

@@ -130,3 +130,51 @@ def test_errors(ctx):
     with pytest.raises(T.TrimError) as e:
         ctx.trim_scc(g.n, ro, col, None, rc)
     assert e.value.code == -1
+
+
+def planted_pairs(g, k, seed):
+    """g plus k planted 2-cycles {a, b} on new vertices, fed by (or feeding) a
+    random vertex of g: after the large component is assigned they are
+    components of two that the size-2 check finds."""
+    rng = np.random.default_rng(seed)
+    src = list(np.repeat(np.arange(g.n), np.diff(g.row_off)))
+    dst = list(g.col)
+    n = g.n
+    for i in range(k):
+        a, b = n + 2 * i, n + 2 * i + 1
+        src += [a, b]
+        dst += [b, a]
+        hook = int(rng.integers(g.n))
+        if i % 2:
+            src.append(hook); dst.append(a)     # fed from the graph
+        else:
+            src.append(b); dst.append(hook)     # feeding the graph
+    return gg.from_edges(n + 2 * k, np.array(src, np.int32), np.array(dst, np.int32))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_size2_against_oracle(ctx, seed):
+    import torch
+    import paper_2107_12720_amd as T
+    from oracle.scc_ref import size2_pairs
+    rng = np.random.default_rng(seed)
+    for n, dens in ((50, 1.0), (3000, 1.2), (40001, 1.5)):
+        g = gg.uniform(n, int(dens * n), seed=seed * 7 + n)
+        g = planted_pairs(g, max(2, n // 50), seed)
+        for ratio in (1.0, 0.7):
+            preset, bm = gg.sample_vertices(g.n, ratio, seed=seed + 1)
+            say(f"  size-2 n={g.n} m={g.m} ratio={ratio}")
+            ro, col, rro, rc = upload(g, with_reverse=True)
+            pd = T.to_device(bm.view(np.int32)) if ratio < 1.0 else None
+            partner, npair = ctx.trim_size2(g.n, ro, col, rro, rc, pd)
+            torch.cuda.synchronize()
+            got = partner.cpu().numpy()[: g.n]
+            want = size2_pairs(g, preset if ratio < 1.0 else None)
+            assert np.array_equal(got, want), (n, ratio)
+            assert npair == int((want >= 0).sum())
+
+
+def test_scc_uses_size2(ctx):
+    g = planted_pairs(gg.rmat(14, 8, seed=3), 300, 5)
+    st, want = check_scc(ctx, g, name="rmat14 + 300 planted pairs")
+    assert st["paired"] >= 2 * 250, st
