@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edges/s + graphs/s: batched/learned-order AC-6 vs plain AC-6, bit-exact live set"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_FLOPS = 2.5e15   # dense BF16 matrix-core peak of MI355X
 # What the one-sided AC-6 kernels compile from: a committed counter summary of
 # one of them stays valid while these are unchanged (other kernel files are
 # separate translation units and cannot change them).
@@ -534,6 +535,23 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
     def score_order():
         col_l[0], _ = learned.learned_order(ctx, dg, indeg, src, tr.pbf)
     ms_order = ev_time(score_order, reps, 1, s)
+    # the scoring kernel alone, against both of its bounds: 2,624 flops per
+    # edge on the BF16 MFMA path (8x32 + 32x32 + 32 multiply-adds), and 28 B
+    # per edge (source and target ids, the two endpoints' precomputed
+    # features, the score) plus 20 B per vertex for the feature prepass
+    scores = torch.empty(max(g.m, 1), dtype=torch.float32, device="cuda")
+    ms_score = ev_time(lambda: ctx.mlp_score(dg, indeg, src, tr.pbf, scores), reps, 1, s)
+    fl = 2624.0 * g.m
+    by = 28.0 * g.m + 20.0 * g.n
+    mf = fl / (ms_score / 1e3) / MFMA_BF16_PEAK_FLOPS
+    hf = by / (ms_score / 1e3) / (HBM_PEAK_GBS * 1e9)
+    score_roofline = {"kernel": "mlp_score", "ms": ms_score, "flops": fl,
+                      "algorithmic_bytes": by,
+                      "achieved_TFLOPs": fl / (ms_score / 1e3) / 1e12, "mfma_frac": mf,
+                      "achieved_GBs": by / (ms_score / 1e3) / 1e9, "hbm_frac": hf,
+                      "bound": "mfma" if mf >= hf else "hbm",
+                      "peaks": {"bf16_mfma_TFLOPs": MFMA_BF16_PEAK_FLOPS / 1e12,
+                                "hbm_GBs": HBM_PEAK_GBS}}
     orders = {"learned": col_l[0], "heuristic_outdeg": learned.reference_order(ctx, dg, 0),
               "random": learned.reference_order(ctx, dg, 1, seed=5)}
     same = True
@@ -552,6 +570,7 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
             "gap_closed": (t6_plain - t6l) / max(1, t6_plain - t6_min),
             "ac6_plain_ms": ms_plain, "score_and_order_ms": ms_order,
             "end_to_end_learned_ms": ms_order + out["learned"]["ac6_ms"],
+            "score_roofline": score_roofline,
             "live_set_identical": bool(same)}
 
 
