@@ -38,6 +38,8 @@ sys.path.insert(0, ROOT)
 METRIC = "edges/s + graphs/s: batched/learned-order AC-6 vs plain AC-6, bit-exact live set"
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_FLOPS = 2.5e15   # dense BF16 matrix-core peak of MI355X
+# 32-bit integer vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+INT32_VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # What the one-sided AC-6 kernels compile from: a committed counter summary of
 # one of them stays valid while these are unchanged (other kernel files are
 # separate translation units and cannot change them).
@@ -431,11 +433,25 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
     stat = res.stats_dict()
     bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
     m = stat["graph_edges"]
+    t6 = stat["edges_total"]
+    # both bounds of the implicit path: status traffic (4 B per check, 16 B per
+    # vertex, the bitmap) and hashing on the integer ALUs (at least one hash per
+    # check and two per vertex, about 22 32-bit vector operations each)
+    b6i = 4 * t6 + 16 * n + n // 8
+    hashes = t6 + 2 * n
+    int_ops = 22 * hashes
+    hbm_frac = b6i / (ms6 / 1e3) / (HBM_PEAK_GBS * 1e9)
+    alu_frac = int_ops / (ms6 / 1e3) / INT32_VALU_PEAK_OPS
     return {"implicit": imp, "bits": bits}, {
         "workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
-        "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": stat["edges_total"],
+        "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": t6,
         "n_live": stat["n_live"],
         "kernels_ms": {k: float(np.mean(v)) for k, v in ktimes.items()},
+        "bounds": {"hbm": {"algorithmic_bytes": b6i, "GBs": b6i / (ms6 / 1e3) / 1e9,
+                           "frac": hbm_frac},
+                   "alu": {"hashes_lower_bound": hashes, "int_ops": int_ops,
+                           "peak_ops": INT32_VALU_PEAK_OPS, "frac": alu_frac},
+                   "tighter": "hbm" if hbm_frac >= alu_frac else "alu"},
         "fixpoint_check_on_samples": None}
 
 
