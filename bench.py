@@ -310,22 +310,67 @@ def bench_scc(ctx, T, graphs, reps):
     return checks, out
 
 
-def time_gpu(ctx, fn, steps, warmup):
+def time_gpu(ctx, fn, steps, warmup, per_step=None):
+    """Mean ms per call over `steps` timed calls (one event pair around all of
+    them), the per-kernel times of every call, and the last result.  With a
+    list `per_step`, each call's own event-timed duration is appended to it."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
     ktimes = {}
+    pairs = []
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
     for _ in range(steps):
+        if per_step is not None:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
         res = fn()
+        if per_step is not None:
+            b.record()
+            pairs.append((a, b))
         for name, ms in ctx.kernel_times():
             ktimes.setdefault(name, []).append(ms)
     t1.record()
     torch.cuda.synchronize()
+    if per_step is not None:
+        per_step.extend(a.elapsed_time(b) for a, b in pairs)
     return t0.elapsed_time(t1) / steps, ktimes, res
+
+
+def step_stats(times):
+    """Median, mean and a 95 % confidence interval of the mean (normal
+    approximation) of per-step times in ms."""
+    import numpy as np
+    t = np.asarray(times, dtype=np.float64)
+    if t.size == 0:
+        return None
+    half = 1.96 * t.std(ddof=1) / np.sqrt(t.size) if t.size > 1 else 0.0
+    return {"n": int(t.size), "median_ms": float(np.median(t)), "mean_ms": float(t.mean()),
+            "ci95_ms": [float(t.mean() - half), float(t.mean() + half)]}
+
+
+def copy_ceiling(nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth measured on this GPU (read + write bytes
+    per second), the practical HBM ceiling beside the 8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms / 1e3) / 1e9}
 
 
 def ev_time(fn, reps, warmup, stream):
@@ -487,6 +532,7 @@ def bench_explicit26(ctx, T, gg, reps):
         kern[dom]["traffic"] = traffic
         kern[dom]["traffic_GBs"] = traffic / (kavg[dom] / 1e3) / 1e9
         kern[dom]["traffic_frac"] = kern[dom]["traffic_GBs"] / HBM_PEAK_GBS
+        kern[dom]["amplification"] = traffic / algo[dom] if algo.get(dom) else None
     bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
     path_bytes = 8 * st["edges_total"] + 20 * n + n // 8
     out = {"workload": "rmat26_ef16", "n": n, "m": m, "ms": ms, "edges_per_s": m / (ms / 1e3),
@@ -708,7 +754,7 @@ def oracle_leg(g, checks, cpu_seconds, out):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU leg (oracle timing and the parity checks it feeds)")
@@ -766,7 +812,8 @@ def main():
         return ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=bm, worker_edges=we, stats=st_t)
 
     log(f"AC-6: warmup {args.warmup}, timed {args.steps} steps")
-    ms, ktimes, res = time_gpu(ctx, step, args.steps, args.warmup)
+    per_step = []
+    ms, ktimes, res = time_gpu(ctx, step, args.steps, args.warmup, per_step)
     st = res.stats_dict()
     value = m / (ms / 1e3)
     checks = {"ac6": {"bitmap": res.bitmap_numpy().copy(), "edges": st["edges_total"]}}
@@ -787,6 +834,7 @@ def main():
     traffic = measured_traffic(dom, "rmat22_chain", P)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
+                "amplification": traffic / algo_bytes[dom] if traffic else None,
                 "algorithmic_bytes": int(algo_bytes[dom]), "avg_ms": kavg[dom]}
     breakdown = {k: {"avg_ms": kavg[k],
                      "algorithmic_bytes": int(algo_bytes.get(k, 0)),
@@ -803,6 +851,8 @@ def main():
                    "workers": P, "block": 256, "chunk": 4096},
         "parity": None, "sweep_counts_match": sweep_ok,
         "roofline": roofline,
+        "step_stats": step_stats(per_step),
+        "hbm_copy_ceiling": copy_ceiling(),
         "breakdown": breakdown,
         "path": {"algorithmic_bytes": path_bytes,
                  "GBs": path_bytes / (ms / 1e3) / 1e9,
