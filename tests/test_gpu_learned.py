@@ -191,3 +191,59 @@ def test_training_lowers_loss_and_order_keeps_live_set(ctx):
             t6_learned = c.T6
     # what the trained network gains over plain AC-6: fewer traversed edges
     assert t6_learned < base.T6
+
+
+@pytest.mark.timeout(900)
+def test_config4_full(ctx):
+    """The learned-order workload at its full size, in the benchmark's setup:
+    trained on oracle labels of 16 R-MAT scale-20 graphs (seeds 1..16),
+    evaluated on R-MAT scale 24.  The reordered graph keeps the live set bit
+    for bit, its traversed-edge total equals the closed form on the permuted
+    lists and is below plain AC-6's; the scoring kernel matches the FP64
+    reference on 10,000 sampled edges; sampled lists are permutations."""
+    import torch
+    import paper_2107_12720_amd as T
+    from paper_2107_12720_amd import learned
+    from oracle import mlp_ref
+    say("  cfg4: 16 training graphs (R-MAT 20) with oracle labels ...")
+    train = []
+    for seed in range(1, 17):
+        g = gg.rmat(20, 16, seed=seed)
+        dg = device_graph(g)
+        indeg, src = learned.prepare(ctx, dg)
+        labels = T.to_device(oracle.bitmap(oracle.peel(g).live).view(np.int32))
+        train.append((dg, indeg, src, labels))
+    tr = learned.Trainer(ctx, seed=0, lr=5e-3)
+    losses = [float(tr.train_step(train, 1 << 14, seed=1)) for _ in range(300)]
+    say(f"  loss {losses[0]:.4f} -> {np.mean(losses[-10:]):.4f}")
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:5])
+    del train
+    say("  evaluation graph R-MAT 24 ...")
+    g = gg.rmat(24, 16, seed=0)
+    dg = device_graph(g)
+    indeg, src = learned.prepare(ctx, dg)
+    col_l, scores = learned.learned_order(ctx, dg, indeg, src, tr.pbf)
+    res = ctx.trim_csr(6, g.n, dg.row_off, col_l)
+    torch.cuda.synchronize()
+    r = oracle.peel(g)
+    base = oracle.counts(g, r)
+    assert np.array_equal(res.bitmap_numpy()[:(g.n + 31) // 32], oracle.bitmap(r.live))
+    go = gg.CSR(g.n, g.row_off, col_l.cpu().numpy())
+    c = oracle.counts(go, r)   # the levels do not depend on the order
+    st = res.stats_dict()
+    say(f"  T6 learned {c.T6}, plain {base.T6}, min {base.T6min}")
+    assert st["edges_total"] == c.T6 and base.T6min <= c.T6 < base.T6
+    rng = np.random.default_rng(24)
+    for v in rng.integers(0, g.n, 10000):
+        a, b = g.row_off[v], g.row_off[v + 1]
+        assert np.array_equal(np.sort(go.col[a:b]), np.sort(g.col[a:b])), int(v)
+    ids = rng.integers(0, g.m, 10000)
+    X, _, _ = mlp_ref.features(g.row_off.astype(np.int64), g.col,
+                               np.bincount(g.col, minlength=g.n), ids)
+    bits = tr.pbf.cpu().numpy().view(np.uint16)
+    pw = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    want = 1.0 / (1.0 + np.exp(-mlp_ref.logits(pw, X)))
+    got = scores.cpu().numpy()[ids].astype(np.float64)
+    err = np.max(np.abs(got - want))
+    say(f"  sampled scores: max |p_gpu - p_ref| = {err:.2e}")
+    assert err <= 2e-3
