@@ -253,6 +253,22 @@ hipError_t validate_csr(const trim_csr_t& g, const Work& w, hipStream_t s) {
 }
 }  // namespace trim
 
+namespace {
+// opts.validate: the device check of offsets and targets (of G^T too when
+// given), read back synchronously.
+int validate_graph(trim_ctx* c, const trim_csr_t& g, hipStream_t s) {
+    int bad = 0;
+    hipError_t e = trim::validate_csr(g, c->w, s);
+    if (e != hipSuccess) return hip_fail(e, "validate");
+    if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "validate readback");
+    if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
+    return TRIM_OK;
+}
+}  // namespace
+
 extern "C" {
 
 int trim_version(void) { return TRIM_ABI_VERSION; }
@@ -345,16 +361,7 @@ int trim_csr(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
-    if (o && o->validate) {
-        int bad = 0;
-        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate");
-        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
-                                lc.stream)) != hipSuccess ||
-            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate readback");
-        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
-    }
+    if (o && o->validate && (rc = validate_graph(c, *g, lc.stream))) return rc;
     switch (algo) {
         case TRIM_AC6: e = trim::ac6_csr(*g, c->w, lc, live_bitmap, worker_edges, stats); break;
         case TRIM_AC4: e = trim::ac4_csr(*g, c->w, lc, live_bitmap, worker_edges, stats); break;
@@ -387,16 +394,7 @@ int trim_csr_preset(trim_ctx* c, int algo, const trim_csr_t* g, const uint32_t* 
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
-    if (o && o->validate) {
-        int bad = 0;
-        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate");
-        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
-                                lc.stream)) != hipSuccess ||
-            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate readback");
-        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
-    }
+    if (o && o->validate && (rc = validate_graph(c, *g, lc.stream))) return rc;
     switch (algo) {
         case TRIM_AC6:
             e = trim::ac6_csr(*g, c->w, lc, live_bitmap, worker_edges, stats, preset_dead);
@@ -428,16 +426,7 @@ int trim_scc(trim_ctx* c, const trim_csr_t* g, const trim_opts_t* o, int32_t* la
     if ((rc = ensure(c, g->n)) || (rc = ensure2(c, g->n)) || (rc = ensure_scc(c, g->n))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, TRIM_AC6, o, stream);
     lc.timer = nullptr;   // many launches; timed as a whole by the caller
-    if (o && o->validate) {
-        int bad = 0;
-        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate");
-        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
-                                lc.stream)) != hipSuccess ||
-            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate readback");
-        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
-    }
+    if (o && o->validate && (rc = validate_graph(c, *g, lc.stream))) return rc;
     trim::SccCounts k;
     e = trim::scc_run(*g, c->w, c->w2, c->sw, lc, label, &k);
     if (e != hipSuccess) return hip_fail(e, "SCC decomposition");
@@ -504,16 +493,7 @@ int trim_csr_two_sided(trim_ctx* c, int algo, const trim_csr_t* g, const trim_op
     if ((rc = ensure(c, g->n))) return rc;
     if (algo == TRIM_AC6 && (rc = ensure2(c, g->n))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
-    if (o && o->validate) {
-        int bad = 0;
-        if ((e = trim::validate_csr(*g, c->w, lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate");
-        if ((e = hipMemcpyAsync(&bad, c->w.ctr + trim::kBad, sizeof(int), hipMemcpyDeviceToHost,
-                                lc.stream)) != hipSuccess ||
-            (e = hipStreamSynchronize(lc.stream)) != hipSuccess)
-            return hip_fail(e, "validate readback");
-        if (bad) return fail(TRIM_E_BADGRAPH, "graph validation found %d problems", bad);
-    }
+    if (o && o->validate && (rc = validate_graph(c, *g, lc.stream))) return rc;
     e = algo == TRIM_AC6
             ? trim::ac6_two_csr(*g, c->w, c->w2, lc, live_bitmap, worker_edges, stats)
             : trim::ac4_two_csr(*g, c->w, lc, live_bitmap, worker_edges, stats);
