@@ -168,11 +168,15 @@ struct WaveQueue {
     int* pending;
     int ticket;         // per lane: shared-queue slot this lane waits on, or -1
     int iter;           // wave-uniform iteration counter
+    int share_mask;     // hand-off polls every share_mask + 1 busy iterations
     int naps;           // wave-uniform idle back-off
     int hw;             // per lane: largest ring fill this lane has seen after a push
 
+    // share_every (a power of two): busy iterations between polls for lanes
+    // elsewhere that wait for work (rebalance).
     __device__ __forceinline__ void init(uint32_t* ring, int* ring_tail, uint32_t* gq,
-                                         int* ctr_qhead, int* ctr_qtail, int* ctr_pending) {
+                                         int* ctr_qhead, int* ctr_qtail, int* ctr_pending,
+                                         int share_every = kPollEvery) {
         lq = ring;
         tail_lds = ring_tail;
         if (lane_id() == 0) *tail_lds = 0;
@@ -185,6 +189,7 @@ struct WaveQueue {
         pending = ctr_pending;
         ticket = -1;
         iter = 0;
+        share_mask = share_every - 1;
         naps = 1;
         hw = 0;
     }
@@ -305,7 +310,7 @@ struct WaveQueue {
             spill_ring(fill() - kSpillAbove);
             return;
         }
-        if ((iter & (kPollEvery - 1)) != 0) return;
+        if ((iter & share_mask) != 0) return;
         const int occ = fill();
         if (occ < 2) return;
         int waiting = 0;
