@@ -89,6 +89,10 @@ def lib():
         L.or_peel2.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, i32p, i64p]
         L.or_counts2.restype = ctypes.c_int64
         L.or_counts2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i64p]
+        L.or_ac3_jacobi2.restype = ctypes.c_int64
+        L.or_ac3_jacobi2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
+        L.or_counts3two.restype = ctypes.c_int64
+        L.or_counts3two.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
         L.or_num_threads.restype = ctypes.c_int
         L.or_fin64.restype = ctypes.c_uint64
         L.or_fin64.argtypes = [ctypes.c_uint64]
@@ -191,6 +195,44 @@ def counts2(g, rrow_off, rcol, live) -> Counts2:
     if r != 0:
         raise ValueError(f"oracle counts2: live vertex {-r - 1} lacks a live neighbour")
     return Counts2(*[int(x) for x in out])
+
+
+@dataclass
+class Ac3Two:
+    live: np.ndarray    # uint8, 1 = LIVE
+    level: np.ndarray   # int32 removal round, 0 for live vertices
+    edges: int          # traversed edges (successor and predecessor checks)
+    rounds: int
+    n_live: int
+
+
+def ac3_jacobi2(g, rrow_off, rcol) -> Ac3Two:
+    """The two-sided AC-3 rounds run literally (successors first, then
+    predecessors, statuses of the round's start); G^T is (rrow_off, rcol) in
+    the order the predecessor scans use."""
+    ro, col = _csr(g)
+    rro = np.ascontiguousarray(rrow_off, dtype=np.int32)
+    rc = np.ascontiguousarray(rcol, dtype=np.int32)
+    live = np.empty(g.n, np.uint8)
+    level = np.empty(g.n, np.int32)
+    st = np.zeros(3, np.int64)
+    if lib().or_ac3_jacobi2(g.n, ro, col, rro, rc, live, level, st) < 0:
+        raise MemoryError("oracle ac3_jacobi2: allocation failed")
+    return Ac3Two(live, level, int(st[0]), int(st[1]), int(st[2]))
+
+
+def counts3two(g, rrow_off, rcol, res: PeelResult):
+    """Closed-form (total, rounds) of the two-sided AC-3 rounds from the
+    two-sided peeling result ``res`` (:func:`peel2`)."""
+    ro, col = _csr(g)
+    rro = np.ascontiguousarray(rrow_off, dtype=np.int32)
+    rc = np.ascontiguousarray(rcol, dtype=np.int32)
+    out = np.zeros(2, np.int64)
+    r = lib().or_counts3two(g.n, ro, col, rro, rc, np.ascontiguousarray(res.live, np.uint8),
+                            np.ascontiguousarray(res.level, np.int32), out)
+    if r != 0:
+        raise ValueError(f"oracle counts3two: vertex {-r - 1} inconsistent with the levels")
+    return int(out[0]), int(out[1])
 
 
 def counts(g, res: PeelResult, preset=None) -> Counts:

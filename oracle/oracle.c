@@ -38,6 +38,9 @@
  *                  check over G^T), by two counters per vertex.
  *   or_counts2     traversed-edge totals of the two-sided AC-4 algorithm and
  *                  the schedule-independent part of the two-sided AC-6 one.
+ *   or_ac3_jacobi2 / or_counts3two  the AC-3 rounds with the same two-sided
+ *                  constraint, run literally, and the closed form of their
+ *                  traversed-edge total from or_peel2's levels.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -637,5 +640,129 @@ int64_t or_counts_preset(int32_t n, const int32_t *row_off, const int32_t *col,
     out[6] = m;
     out[7] = n_live;
     free(indeg);
+    return 0;
+}
+
+/* ------------------------------------------------------ two-sided AC-3 */
+/*
+ * The AC-3 rounds (Section 4.1) with the constraint that also asks for a live
+ * predecessor: two edge_index cursors per vertex (Section 8), one over its
+ * successors and one over its predecessors, G^T given as rrow_off / rcol in
+ * the order its scans use.  Rounds read the statuses of their start: w counts
+ * as removed in round r iff it was removed in an earlier round.  In a round a
+ * LIVE vertex scans its successors first and, only if it finds one, its
+ * predecessors; a vertex that finds no successor, or then no predecessor, is
+ * removed in this round.  Every check of a neighbour counts as one traversed
+ * edge.  Outputs live[] and level[] (the removal round, 0 for live vertices);
+ * stats[0] = traversed edges, stats[1] = rounds, stats[2] = n_live.  Returns
+ * the edges, or -1 on allocation failure.
+ */
+int64_t or_ac3_jacobi2(int32_t n, const int32_t *row_off, const int32_t *col,
+                       const int32_t *rrow_off, const int32_t *rcol, uint8_t *live,
+                       int32_t *level, int64_t *stats) {
+    int64_t *co = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *ci = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *dround = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    if (!co || !ci || !dround) { free(co); free(ci); free(dround); return -1; }
+    const int64_t NEVER = INT64_MAX;
+    for (int32_t v = 0; v < n; ++v) {
+        live[v] = 1;
+        level[v] = 0;
+        co[v] = row_off[v];
+        ci[v] = rrow_off[v];
+        dround[v] = NEVER;
+    }
+    int64_t edges = 0, rounds = 0, n_live = n;
+    int change = 1;
+    while (change) {
+        change = 0;
+        rounds += 1;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!live[v]) continue;
+            int found = 0;
+            for (int64_t end = row_off[v + 1]; co[v] < end; co[v] += 1) {
+                edges += 1;
+                if (dround[col[co[v]]] >= rounds) { found = 1; break; }
+            }
+            if (found) {
+                found = 0;
+                for (int64_t end = rrow_off[v + 1]; ci[v] < end; ci[v] += 1) {
+                    edges += 1;
+                    if (dround[rcol[ci[v]]] >= rounds) { found = 1; break; }
+                }
+            }
+            if (!found) {
+                live[v] = 0;
+                level[v] = (int32_t)rounds;
+                dround[v] = rounds;
+                n_live -= 1;
+                change = 1;
+            }
+        }
+    }
+    stats[0] = edges;
+    stats[1] = rounds;
+    stats[2] = n_live;
+    free(co); free(ci); free(dround);
+    return edges;
+}
+
+/*
+ * Closed form of or_ac3_jacobi2's total from the two-sided peeling levels
+ * (or_peel2): alpha is the largest level and the rounds number R = alpha + 1.
+ * A vertex is alive at the start of round k iff it is live or its level is at
+ * least k.  fo(v, k) and fi(v, k) are the indices of v's first successor and
+ * first predecessor alive at the start of round k.  A vertex removed at level
+ * L failed on its successors iff none is alive at the start of round L, else
+ * on its predecessors.  Its cursors then account for:
+ *   failed on successors:   deg + L - 1 successor checks, and L - 1 +
+ *                           fi(v, L - 1) predecessor checks (none if L = 1);
+ *   failed on predecessors: L + fo(v, L) successor checks, indeg + L - 1
+ *                           predecessor checks;
+ *   live:                   R + fo(v, R) and R + fi(v, R).
+ * (A cursor checked in k rounds has checked k entries plus the ones it passed;
+ * one that ran off its list has checked every entry once and its last round's
+ * entry no second time.)  out[0] = total, out[1] = R.  Returns 0, or -(v+1)
+ * for a vertex whose levels are inconsistent with the graph.
+ */
+static int64_t first_alive(const int32_t *adj, int64_t b, int64_t e, const uint8_t *live,
+                           const int32_t *level, int64_t k) {
+    for (int64_t p = b; p < e; ++p)
+        if (live[adj[p]] || level[adj[p]] >= k) return p - b;
+    return -1;
+}
+int64_t or_counts3two(int32_t n, const int32_t *row_off, const int32_t *col,
+                      const int32_t *rrow_off, const int32_t *rcol, const uint8_t *live,
+                      const int32_t *level, int64_t *out) {
+    int64_t alpha = 0, total = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (!live[v] && level[v] > alpha) alpha = level[v];
+    const int64_t R = alpha + 1;
+    for (int32_t v = 0; v < n; ++v) {
+        const int64_t b = row_off[v], e = row_off[v + 1], rb = rrow_off[v], re = rrow_off[v + 1];
+        if (live[v]) {
+            const int64_t fo = first_alive(col, b, e, live, level, R);
+            const int64_t fi = first_alive(rcol, rb, re, live, level, R);
+            if (fo < 0 || fi < 0) return -((int64_t)v + 1);
+            total += R + fo + R + fi;
+            continue;
+        }
+        const int64_t L = level[v];
+        if (L < 1) return -((int64_t)v + 1);
+        const int64_t fo = first_alive(col, b, e, live, level, L);
+        if (fo < 0) {   /* no successor left at the start of round L */
+            total += (e - b) + L - 1;
+            if (L > 1) {
+                const int64_t fi = first_alive(rcol, rb, re, live, level, L - 1);
+                if (fi < 0) return -((int64_t)v + 1);
+                total += L - 1 + fi;
+            }
+        } else {
+            if (first_alive(rcol, rb, re, live, level, L) >= 0) return -((int64_t)v + 1);
+            total += L + fo + (re - rb) + L - 1;
+        }
+    }
+    out[0] = total;
+    out[1] = R;
     return 0;
 }

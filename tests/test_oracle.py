@@ -498,6 +498,59 @@ def test_two_sided_reach_and_reached_from_cycle(orc, gen, seed):
         assert c.n_live == r.n_live
 
 
+def test_two_sided_ac3_hand_example(orc, gen):
+    """Source -> cycle -> sink (0->1, 1->2, 2->1, 2->3).  Round 1: vertex 0
+    checks 1 successor and has no predecessor (1 check, removed); 1 and 2
+    check one successor and one predecessor each (4); 3 has no successor (0,
+    removed).  Round 2: 1 rechecks its successor, finds its predecessor 0
+    removed and moves on to 2 (3 checks); 2 rechecks both (2).  Nothing is
+    removed in round 2: 10 checks in 2 rounds."""
+    g = gen.from_adjacency([[1], [2], [1, 3], []])
+    rro, rcol = gen.transpose(g)
+    a = orc.ac3_jacobi2(g, rro, rcol)
+    assert (a.edges, a.rounds, a.n_live) == (10, 2, 2)
+    assert list(a.live) == [0, 1, 1, 0] and list(a.level) == [1, 0, 0, 1]
+    assert orc.counts3two(g, rro, rcol, orc.peel2(g)) == (10, 2)
+    # a path peels from both ends: alpha = 51 for 101 vertices
+    L = 101
+    g = gen.from_edges(L, np.arange(L - 1, dtype=np.int32), np.arange(1, L, dtype=np.int32))
+    rro, rcol = gen.transpose(g)
+    a = orc.ac3_jacobi2(g, rro, rcol)
+    assert a.n_live == 0 and a.rounds == 52
+    assert (a.edges, a.rounds) == orc.counts3two(g, rro, rcol, orc.peel2(g))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_two_sided_ac3_rounds_match_peeling(orc, gen, seed):
+    """The literal two-sided AC-3 rounds (statuses of each round's start)
+    remove exactly the vertices of two-sided peeling, each in the round equal
+    to its peeling step (or_peel2, an independent counter computation), take
+    alpha + 1 rounds, and check as many edges as the closed form from the
+    levels says."""
+    rng = np.random.default_rng(900 + seed)
+    for t in range(100):
+        n = int(rng.integers(1, 40))
+        m = int(rng.integers(0, 3 * n + 1))
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+        if t % 2:
+            keep = src != dst
+            src, dst = src[keep], dst[keep]
+        g = gen.from_edges(n, src, dst)
+        rro, rcol = gen.transpose(g)
+        a = orc.ac3_jacobi2(g, rro, rcol)
+        r = orc.peel2(g)
+        assert np.array_equal(a.live, r.live) and np.array_equal(a.level, r.level)
+        assert a.rounds == r.alpha + 1
+        assert (a.edges, a.rounds) == orc.counts3two(g, rro, rcol, r)
+    g = gen.rmat(12, 4, seed=seed, chain=300)
+    rro, rcol = gen.transpose(g)
+    a = orc.ac3_jacobi2(g, rro, rcol)
+    r = orc.peel2(g)
+    assert np.array_equal(a.level, r.level)
+    assert (a.edges, a.rounds) == orc.counts3two(g, rro, rcol, r)
+
+
 # ------------------------------------------------- vertices removed up front
 def literal_runs_with_preset(adj, preset):
     """The three algorithms run step by step with the preset vertices DEAD from
