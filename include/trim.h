@@ -201,16 +201,23 @@ int trim_csr_preset(trim_ctx *ctx, int algo, const trim_csr_t *g, const uint32_t
  *             both from offsets; every removed vertex walks its predecessor
  *             and successor lists once, so the sum of worker_edges is
  *             sum over removed v of (out-degree + in-degree).
- *   TRIM_AC3  TRIM_E_UNSUPPORTED.
+ *   TRIM_AC3  rounds with two edge_index cursors per vertex, one over G and
+ *             one over G^T, reading the statuses of the round's start: in
+ *             a round a vertex checks its successor cursor first and, only
+ *             if a successor is left, its predecessor cursor.  Round r
+ *             removes exactly the vertices of two-sided peeling step r, so
+ *             stats.rounds = alpha + 1 and the sum of worker_edges is fixed
+ *             (every check of a neighbour counts).  Uses the same extra
+ *             context memory as AC-6.
  * g->rrow_off and g->rcol are required (TRIM_E_INVAL without them) and must
  * hold the transpose of (row_off, col); the in-side scans follow rcol's order.
  * opts.validate checks ranges and offsets of both, not that they are
  * transposes of each other.  Outputs as for trim_csr, with worker_edges
  * sized by trim_num_workers for the same algo.  Stats: closes (AC-6) counts
  * the vertices removed after the start, i.e. those that had a successor and
- * a predecessor; n_dead all removed vertices.  AC-6 uses 48 bytes per vertex
- * of context memory beyond trim_csr (in-side lists and records, a larger
- * queue), allocated on the first call.
+ * a predecessor; n_dead all removed vertices.  AC-6 and AC-3 use 48 bytes
+ * per vertex of context memory beyond trim_csr (in-side lists and records, a
+ * larger queue), allocated on the first call of either.
  */
 int trim_csr_two_sided(trim_ctx *ctx, int algo, const trim_csr_t *g, const trim_opts_t *opts,
                        uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats,

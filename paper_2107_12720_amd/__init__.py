@@ -316,7 +316,7 @@ class Context:
                            worker_edges=None, stats=None, opts: Opts | None = None,
                            stream=None) -> TrimResult:
         """Two-sided trimming (a vertex needs a live successor and a live
-        predecessor) of the CSR graph and its transpose, algo 4 or 6."""
+        predecessor) of the CSR graph and its transpose, algo 3, 4 or 6."""
         import torch
         algo = ALGOS.get(algo, algo)
         opts = opts or Opts()
@@ -325,7 +325,7 @@ class Context:
                     _dev_ptr(col, torch.int32, "col") if m else None,
                     _dev_ptr(rrow_off, torch.int32, "rrow_off"),
                     _dev_ptr(rcol, torch.int32, "rcol") if m else None)
-        P = self.num_workers(algo, opts) if algo in (AC4, AC6) else 1
+        P = self.num_workers(algo, opts) if algo in (AC3, AC4, AC6) else 1
         lb, we, st = self._outputs((int(n) + 31) // 32, P, live_bitmap, worker_edges, stats)
         _check(lib().trim_csr_two_sided(self._h, int(algo), ctypes.byref(d), ctypes.byref(opts),
                                         ctypes.c_void_p(lb.data_ptr()),

@@ -215,6 +215,145 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int n, int* ptr, int* 
     if (stats && blockIdx.x == 0 && threadIdx.x == 0) stats->rounds = (uint64_t)r;
 }
 
+// ------------------------------------------------------------ two-sided
+// The constraint of Section 4.1 that also asks for a live predecessor: a second
+// edge_index cursor runs over G^T.  In round r a vertex checks its successors
+// first and, only if one is left, its predecessors; a vertex that finds no
+// successor, or then no predecessor, is removed in round r.  Statuses are those
+// of the round's start, so round r removes exactly the vertices of two-sided
+// peeling step r, and the rounds number alpha + 1 of two-sided peeling.  A list
+// entry carries both cursor targets, in three arrays of n ints.
+struct List3 {
+    int* v;    // vertex
+    int* wo;   // successor at its out-cursor (kNoTarget: none)
+    int* wi;   // predecessor at its in-cursor (kNoTarget: none)
+};
+
+__global__ void ac3_init2(ExplicitView out, ExplicitView in, int n, int* ptr, int* ptr_in,
+                          int* dround, List3 l1, int* ctr, uint64_t* worker_edges, int P,
+                          trim_stats_t* stats) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < kCtrInts) ctr[tid] = tid == kCnt0 + 1 ? n : 0;
+    for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
+    if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
+    for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
+        const int b = out.begin(v), e = out.end(v), rb = in.begin(v), re = in.end(v);
+        ptr[v] = b;
+        ptr_in[v] = rb;
+        dround[v] = INT_MAX;
+        l1.v[v] = v;
+        l1.wo[v] = b < e ? out.target(v, b, 0) : kNoTarget;
+        l1.wi[v] = rb < re ? in.target(v, rb, 0) : kNoTarget;
+    }
+}
+
+// The scan of one side after its cursor entry was found removed: from cursor
+// position p0 + 1 on, the first entry not removed before round r.  Returns its
+// position (the end if none) and the entry in t.
+__device__ __forceinline__ int scan_on(const ExplicitView& g, int v, int p0, int e, int r,
+                                       const int* dround, int& t) {
+    int p = p0 + 1;
+    t = kNoTarget;
+    for (; p < e; ++p) {
+        t = g.target(v, p, 0);
+        if (ld_dev(dround + t) >= r) break;
+    }
+    return p;
+}
+
+__global__ __launch_bounds__(256) void ac3_rounds2(ExplicitView out, ExplicitView in, int n,
+                                                   int* ptr, int* ptr_in, int* dround, List3 l0,
+                                                   List3 l1, int* ctr, uint64_t* worker_edges,
+                                                   trim_stats_t* stats) {
+    __shared__ int s_wave[256 / kWave], s_base;
+    uint64_t edges = 0;
+    int r = 1;
+    const int stride = gridDim.x * blockDim.x;
+    for (;; ++r) {
+        const List3 src = (r & 1) ? l1 : l0;
+        const List3 dst = (r & 1) ? l0 : l1;
+        const int cnt_in = ld_dev(ctr + kCnt0 + r % 3);
+        int* cnt_out = ctr + kCnt0 + (r + 1) % 3;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
+        for (int base = blockIdx.x * blockDim.x; base < cnt_in; base += stride * kUnroll) {
+            int v[kUnroll], wo[kUnroll], wi[kUnroll], dout[kUnroll], din[kUnroll];
+            bool keep[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                const int i = base + k * stride + threadIdx.x;
+                v[k] = -1;
+                if (i < cnt_in) {
+                    v[k] = ld_dev(src.v + i);
+                    wo[k] = ld_dev(src.wo + i);
+                    wi[k] = ld_dev(src.wi + i);
+                }
+            }
+            // both cursor entries' removal rounds in flight together (the
+            // predecessor's is only counted when a successor is left)
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                dout[k] = (v[k] >= 0 && wo[k] != kNoTarget) ? ld_dev(dround + wo[k]) : 0;
+                din[k] = (v[k] >= 0 && wi[k] != kNoTarget) ? ld_dev(dround + wi[k]) : 0;
+            }
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                keep[k] = false;
+                if (v[k] < 0) continue;
+                if (wo[k] != kNoTarget && dout[k] >= r) {   // successor cursor, checked again
+                    edges += 1;
+                } else {
+                    const int p0 = ld_dev(ptr + v[k]), e = out.end(v[k]);
+                    int t;
+                    const int p = scan_on(out, v[k], p0, e, r, dround, t);
+                    if (p >= e) {   // no successor left: removed in round r
+                        edges += (uint64_t)(e - p0);
+                        st_dev(dround + v[k], r);
+                        continue;
+                    }
+                    edges += (uint64_t)(p - p0 + 1);
+                    st_dev(ptr + v[k], p);
+                    wo[k] = t;
+                }
+                if (wi[k] != kNoTarget && din[k] >= r) {   // predecessor cursor, checked again
+                    edges += 1;
+                    keep[k] = true;
+                    continue;
+                }
+                const int p0 = ld_dev(ptr_in + v[k]), e = in.end(v[k]);
+                int t;
+                const int p = scan_on(in, v[k], p0, e, r, dround, t);
+                if (p >= e) {   // no predecessor left: removed in round r
+                    edges += (uint64_t)(e - p0);
+                    st_dev(dround + v[k], r);
+                    continue;
+                }
+                edges += (uint64_t)(p - p0 + 1);
+                st_dev(ptr_in + v[k], p);
+                wi[k] = t;
+                keep[k] = true;
+            }
+            int c = 0;
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) c += keep[k];
+            int slot = block_append_base(c, cnt_out, nullptr, s_wave, &s_base);
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+                if (keep[k]) {
+                    st_dev(dst.v + slot, v[k]);
+                    st_dev(dst.wo + slot, wo[k]);
+                    st_dev(dst.wi + slot, wi[k]);
+                    ++slot;
+                }
+            }
+        }
+        grid_barrier(ctr + kBarCount, ctr + kBarGen);
+        if (ld_dev(cnt_out) == cnt_in) break;   // no removal in round r
+    }
+    edges = wave_sum(edges);
+    if (lane_id() == 0 && edges) add_dev(worker_edges + blockIdx.x, edges);
+    if (stats && blockIdx.x == 0 && threadIdx.x == 0) stats->rounds = (uint64_t)r;
+}
+
 struct Ac3Live {
     const int* dround;
     __device__ __forceinline__ bool operator()(int v) const { return dround[v] == INT_MAX; }
@@ -272,6 +411,48 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
 
 }  // namespace
 
+// Two-sided rounds.  Working memory: cursors in w.d (successor side) and in
+// the first n ints of x.rec_in (predecessor side), removal rounds in w.c; the
+// two lists in w.a, w.b (vertex and successor entry) and x.hin (predecessor
+// entry).  Two-sided AC-6 re-initialises x.hin and writes x.rec_in before
+// reading it, so the calls can share them.
+hipError_t ac3_two_csr(const trim_csr_t& g, const Work& w, const Work2& x, const LaunchCfg& lc,
+                       uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats) {
+    const int n = g.n, P = lc.workers;
+    ExplicitView out{g.row_off, g.col}, in{g.rrow_off, g.rcol};
+    int* ptr = w.d;
+    int* ptr_in = reinterpret_cast<int*>(x.rec_in);
+    int* dround = w.c;
+    int* b = reinterpret_cast<int*>(w.b);
+    List3 l1{w.a, w.a + n, x.hin};
+    List3 l0{b, b + n, x.hin + n};
+    int pack_blocks = 0;
+    {
+        Timed t(lc, "ac3t_init");
+        hipLaunchKernelGGL(ac3_init2, dim3(grid_for(n, 256, 16384)), dim3(256), 0, lc.stream, out,
+                           in, n, ptr, ptr_in, dround, l1, w.ctr, worker_edges, P, stats);
+    }
+    if (n > 0) {
+        int nn = n;
+        void* args[] = {&out, &in, &nn, &ptr, &ptr_in, &dround, &l0, &l1, (void*)&w.ctr,
+                        &worker_edges, &stats};
+        {
+            Timed t(lc, "ac3t_rounds");
+            hipError_t e = hipLaunchCooperativeKernel((const void*)ac3_rounds2, dim3(P), dim3(256),
+                                                      args, 0, lc.stream);
+            if (e != hipSuccess) return e;
+        }
+        Timed t(lc, "ac3t_pack");
+        pack_blocks = grid_for(n, 256, lc.cus * 4);
+        hipLaunchKernelGGL(pack_bitmap<Ac3Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
+                           Ac3Live{dround}, n, bitmap, w.part);
+    }
+    if (stats)
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
+                           pack_blocks, 0, worker_edges, w.part, w.ctr, stats, 1);
+    return hipGetLastError();
+}
+
 hipError_t ac3_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
                    uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset) {
     ExplicitView v{g.row_off, g.col};
@@ -292,6 +473,9 @@ int ac3_max_workers_per_cu(int) {
         return 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, ac3_rounds<ImplicitView>, 256, 0) ==
             hipSuccess &&
+        nb2 < nb)
+        nb = nb2;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, ac3_rounds2, 256, 0) == hipSuccess &&
         nb2 < nb)
         nb = nb2;
     return nb < 1 ? 1 : nb;

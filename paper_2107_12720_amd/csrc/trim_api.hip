@@ -475,9 +475,7 @@ int trim_csr_two_sided(trim_ctx* c, int algo, const trim_csr_t* g, const trim_op
                        uint32_t* live_bitmap, uint64_t* worker_edges, trim_stats_t* stats,
                        void* stream) {
     if (!c || !g) return fail(TRIM_E_INVAL, "trim_csr_two_sided: NULL context or graph");
-    if (algo == TRIM_AC3)
-        return fail(TRIM_E_UNSUPPORTED, "two-sided trimming is built for AC-6 and AC-4");
-    if (algo != TRIM_AC4 && algo != TRIM_AC6)
+    if (algo != TRIM_AC3 && algo != TRIM_AC4 && algo != TRIM_AC6)
         return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
     if (g->n < 0 || g->n > (1 << 29)) return fail(TRIM_E_INVAL, "n = %d out of range", g->n);
     if (g->m < 0 || g->m >= (int64_t)1 << 31)
@@ -491,12 +489,12 @@ int trim_csr_two_sided(trim_ctx* c, int algo, const trim_csr_t* g, const trim_op
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n))) return rc;
-    if (algo == TRIM_AC6 && (rc = ensure2(c, g->n))) return rc;
+    if (algo != TRIM_AC4 && (rc = ensure2(c, g->n))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
     if (o && o->validate && (rc = validate_graph(c, *g, lc.stream))) return rc;
-    e = algo == TRIM_AC6
-            ? trim::ac6_two_csr(*g, c->w, c->w2, lc, live_bitmap, worker_edges, stats)
-            : trim::ac4_two_csr(*g, c->w, lc, live_bitmap, worker_edges, stats);
+    e = algo == TRIM_AC6   ? trim::ac6_two_csr(*g, c->w, c->w2, lc, live_bitmap, worker_edges, stats)
+        : algo == TRIM_AC4 ? trim::ac4_two_csr(*g, c->w, lc, live_bitmap, worker_edges, stats)
+                           : trim::ac3_two_csr(*g, c->w, c->w2, lc, live_bitmap, worker_edges, stats);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return TRIM_OK;
 }

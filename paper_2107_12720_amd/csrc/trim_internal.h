@@ -118,6 +118,8 @@ hipError_t ac3_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
                    uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset = nullptr);
 hipError_t ac3_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
                         uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
+hipError_t ac3_two_csr(const trim_csr_t& g, const Work& w, const Work2& x, const LaunchCfg& lc,
+                       uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
 int ac3_max_workers_per_cu(int block);
 
 // ------------------------------------------------------------ learned order

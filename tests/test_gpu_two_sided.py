@@ -6,7 +6,9 @@ AC-4: the edge total equals the closed form sum over removed v of
 (out-degree + in-degree).  AC-6: the live vertices' checks do not depend on
 the schedule (oracle.counts2 T6live), the removed vertices' checks lie between
 the oracle's bounds, and stats.closes counts the vertices removed after the
-start (those that had a successor and a predecessor).
+start (those that had a successor and a predecessor).  AC-3: the total equals
+the oracle's closed form of the two-sided rounds (oracle.counts3two) and the
+rounds number alpha + 1 of two-sided peeling.
 """
 import numpy as np
 import pytest
@@ -43,11 +45,12 @@ def expected_two(g):
     deg = np.diff(g.row_off.astype(np.int64))
     indeg = np.diff(rro.astype(np.int64))
     n_dead0 = int(((deg == 0) | (indeg == 0)).sum())
-    return r, c, oracle.bitmap(r.live), n_dead0
+    t3 = oracle.counts3two(g, rro, rcol, r)
+    return r, c, oracle.bitmap(r.live), n_dead0, t3
 
 
-def check_two(ctx, g, algos=(6, 4), opts=None, name="", dev=None, exp=None):
-    r, c, bm, n_dead0 = exp or expected_two(g)
+def check_two(ctx, g, algos=(6, 4, 3), opts=None, name="", dev=None, exp=None):
+    r, c, bm, n_dead0, (t3, rounds3) = exp or expected_two(g)
     dev = dev or upload(g, with_reverse=True)
     for a in algos:
         say(f"  [{name}] two-sided AC-{a} n={g.n} m={g.m}")
@@ -58,6 +61,8 @@ def check_two(ctx, g, algos=(6, 4), opts=None, name="", dev=None, exp=None):
         assert 0 <= st["q_highwater"] <= 1024, st
         if a == 4:
             assert edges == c.T4two, (edges, c)
+        elif a == 3:
+            assert edges == t3 and st["rounds"] == rounds3 == r.alpha + 1, (edges, t3, st)
         else:
             assert c.T6live + c.dead_lo <= edges <= c.T6live + c.dead_hi, (edges, c)
             assert st["closes"] == g.n - r.n_live - n_dead0, (st, n_dead0)
@@ -85,6 +90,8 @@ def test_hand_example_values(ctx):
     g = gg.from_adjacency([[1], [2], [1, 3], []])
     r, c = check_two(ctx, g, name="hand example")
     assert list(r.live) == [0, 1, 1, 0] and c.T4two == 2 and c.T6live == 5
+    # two-sided AC-3: 10 checks in 2 rounds (worked out in the oracle's pins)
+    assert oracle.counts3two(g, *gg.transpose(g), r) == (10, 2)
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -165,7 +172,7 @@ def test_schedule_perturbation(ctx, schedule):
         say(f"  schedule={schedule} {name}: 20 repeats of two-sided AC-6 and AC-4")
         for k in range(20):
             opts = T.make_opts(schedule=schedule, chunk=(64, 4096)[k % 2], workers=(0, 37)[k % 2])
-            r, c, bm, _ = exp
+            r, c, bm, _, _ = exp
             for a in (6, 4):
                 got, edges, st = run_two(ctx, g, a, opts=opts, dev=dev)
                 assert np.array_equal(got, bm), (name, a, k)
@@ -197,8 +204,8 @@ def test_errors(ctx):
     g = gg.from_adjacency([[1], [0]])
     ro, col, rro, rc = upload(g, with_reverse=True)
     with pytest.raises(T.TrimError) as e:
-        ctx.trim_csr_two_sided(3, g.n, ro, col, rro, rc)
-    assert e.value.code == -4
+        ctx.trim_csr_two_sided(5, g.n, ro, col, rro, rc)
+    assert e.value.code == -1
     with pytest.raises(T.TrimError) as e:
         ctx.trim_csr_two_sided(6, g.n, ro, col, None, rc)
     assert e.value.code == -1
