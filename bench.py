@@ -153,9 +153,10 @@ def two_sided_sweep_counts(g, rro, rcol):
     return int(checks), joins, int((alive0 & ~in_ok).sum())
 
 
-def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps):
+def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps, with_ac3=True):
     """Two-sided trimming (a live successor and a live predecessor, Section 4.1)
-    of the same graph: AC-6 and AC-4, with the kernels' algorithmic bytes."""
+    of the same graph: AC-6 and AC-4, with the kernels' algorithmic bytes, and
+    the two-sided AC-3 rounds once (alpha + 1 of them)."""
     import numpy as np
     n, m = g.n, g.m
     rro, rcl = T.to_device(rro_h), T.to_device(rcol_h)
@@ -213,6 +214,17 @@ def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps):
     checks = {"rro": rro_h, "rcol": rcol_h,
               "ac6": {"bitmap": res6.bitmap_numpy().copy(), "edges": st6["edges_total"]},
               "ac4": {"bitmap": res4.bitmap_numpy().copy(), "edges": st4["edges_total"]}}
+    if with_ac3:
+        ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr_two_sided(T.AC3, n, ro, col, rro, rcl),
+                                  1, 0)
+        st3 = res3.stats_dict()
+        out["ac3"] = {"ms": ms3, "edges_per_s": m / (ms3 / 1e3), "traversed": st3["edges_total"],
+                      "rounds": st3["rounds"], "n_live": st3["n_live"],
+                      "kernels_ms": {k: float(np.mean(v)) for k, v in kt3.items()},
+                      "parity": None}
+        out["ac6_speedup_vs_ac3"] = ms3 / ms6
+        checks["ac3"] = {"bitmap": res3.bitmap_numpy().copy(), "edges": st3["edges_total"],
+                         "rounds": st3["rounds"]}
     return checks, out
 
 
@@ -687,6 +699,12 @@ def oracle_leg(g, checks, cpu_seconds, out):
         to["ac4"]["parity"] = bool(np.array_equal(tc["ac4"]["bitmap"], bm2)
                                    and tc["ac4"]["edges"] == c2.T4two)
         to["ac4"]["T4two"] = c2.T4two
+        if "ac3" in tc:
+            t3, rounds3 = oracle.counts3two(g, tc["rro"], tc["rcol"], r2)
+            to["ac3"]["parity"] = bool(np.array_equal(tc["ac3"]["bitmap"], bm2)
+                                       and tc["ac3"]["edges"] == t3
+                                       and tc["ac3"]["rounds"] == rounds3)
+            to["ac3"]["T3J"] = t3
     if "sampling" in checks:
         sc = checks["sampling"]
         ok = True
@@ -896,9 +914,11 @@ def main():
     if not args.no_two_sided:
         if gt is None:
             gt = gg.transpose(g)
-        checks["two_sided"], out["two_sided"] = bench_two_sided(ctx, T, g, ro, col, gt[0], gt[1], 5)
+        checks["two_sided"], out["two_sided"] = bench_two_sided(ctx, T, g, ro, col, gt[0], gt[1], 5,
+                                                                with_ac3=not args.no_ac3)
         log(f"two-sided: AC-6 {out['two_sided']['ac6']['ms']:.3f} ms, "
-            f"AC-4 {out['two_sided']['ac4']['ms']:.3f} ms")
+            f"AC-4 {out['two_sided']['ac4']['ms']:.3f} ms"
+            + (f", AC-3 {out['two_sided']['ac3']['ms']:.1f} ms" if "ac3" in out["two_sided"] else ""))
     if not args.no_scc:
         if gt is None:
             gt = gg.transpose(g)
