@@ -81,6 +81,11 @@ __device__ __forceinline__ bool removes(int* dead, int u) {
 
 constexpr int kBatch = 8;
 constexpr int kCoop = 16;   // predecessor lists longer than this are walked by the wavefront
+// Busy iterations between polls for waiting lanes elsewhere: 16, as for the
+// AC-6 kernels on explicit graphs (measured at 512 workers: the 65,536-vertex
+// core+tail graph 35 % and R-MAT 22 with half of its vertices preset 12 %
+// faster than with 64, the R-MAT 22 chain workload unchanged).
+constexpr int kShareEvery4 = 16;
 
 // Phase 0 walks pre(w) over G^T and decrements out-counters (cnt[u]); with
 // kTwo, phase 1 then walks post(w) over G and decrements in-counters
@@ -95,7 +100,8 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
     __shared__ int ring_tail[256 / kWave];
     WaveQueue wq;
     const int wv = threadIdx.x / kWave;
-    wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending);
+    wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending,
+            kShareEvery4);
     uint32_t item = kNone;
     int k = 0, e = 0, ph = 0;
     bool started = false;
