@@ -16,6 +16,10 @@
 // the list of round r+1, and a grid barrier separates rounds.  List sizes
 // rotate over three counter slots so that resetting the slot of round r+2
 // never races with readers of rounds r and r+1.
+//
+// Two-sided rounds (a vertex must also keep a live predecessor, Section 4.1)
+// are ac3_init2 / ac3_rounds2 below: a second cursor over G^T, checked after
+// the successor cursor.
 #include <climits>
 
 #include "trim_device.h"
