@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define TRIM_ABI_VERSION 1
+#define TRIM_ABI_VERSION 2
 
 typedef enum { TRIM_AC3 = 3, TRIM_AC4 = 4, TRIM_AC6 = 6 } trim_algo_t;
 
@@ -56,7 +56,8 @@ typedef enum {
     TRIM_E_HIP = -3,          /* a HIP runtime call failed */
     TRIM_E_UNSUPPORTED = -4,  /* e.g. AC-4 on an implicit graph (no G^T) */
     TRIM_E_BADGRAPH = -5,     /* validate=1 found non-monotone offsets or bad targets */
-    TRIM_E_STALLED = -6       /* reserved: a watchdog bound was exceeded */
+    TRIM_E_STALLED = -6       /* a persistent kernel exceeded its step budget (watchdog):
+                                 the call was abandoned and its outputs are invalid */
 } trim_status_t;
 
 typedef struct trim_ctx trim_ctx;
@@ -105,8 +106,17 @@ typedef struct {
                            the last vertex down; TRIM_SCHED_JITTER = short
                            pseudo-random pauses inside the race windows (join versus
                            close, AC-4 decrements).  Results never depend on them. */
-    int32_t reserved[2];
+    int32_t budget;     /* watchdog: loop iterations a wavefront of a persistent kernel
+                           (AC-6 and AC-4 propagation) may make, and polls a workgroup may
+                           spend waiting at an AC-3 round barrier, before the call is
+                           abandoned: every wavefront then exits normally, the outputs
+                           are invalid and trim_ctx_status() returns TRIM_E_STALLED.
+                           0 = TRIM_DEFAULT_BUDGET (a run that legitimately needs more
+                           than that is longer than any workload here by over 10x). */
+    int32_t reserved;
 } trim_opts_t;
+
+#define TRIM_DEFAULT_BUDGET (1 << 22)
 
 #define TRIM_SCHED_REVERSE 1
 #define TRIM_SCHED_JITTER 2
@@ -129,7 +139,12 @@ typedef struct {
                               LDS queue held (the analogue of the bound on |Q_p| in
                               Section 9.2; capped by the 1,024-entry ring, beyond which
                               items go to the shared queue) */
-    uint64_t reserved;
+    uint64_t edges_live;   /* two-sided AC-6: checks made by the vertices that stay live,
+                              read off their final cursors (sum over live v of
+                              fl_out(v) + 1 + fl_in(v) + 1, schedule independent); 0 for
+                              the other calls */
+    uint64_t stalled;      /* 1 if the watchdog abandoned the call (see opts.budget) */
+    uint64_t reserved[4];
 } trim_stats_t;
 
 /*
@@ -147,13 +162,42 @@ int trim_version(void);
 /* Message of the last failed call on this host thread ("" if none). */
 const char *trim_last_error(void);
 
-/* Create a context bound to HIP device `device`.  *out is NULL on failure. */
-int trim_ctx_create(trim_ctx **out, int device);
+/*
+ * Create a context bound to HIP device `device`.  *out is NULL on failure.
+ * mem_budget caps the device memory the context may hold (its control block
+ * of about 1.1 MB included), in bytes; 0 = no cap.  A call whose working
+ * memory would exceed the cap returns TRIM_E_NOMEM before enqueuing anything,
+ * as does trim_ctx_create if the cap is below the control block.
+ */
+int trim_ctx_create(trim_ctx **out, int device, uint64_t mem_budget);
+/* Device memory the context holds now, in bytes (working memory grows to the
+ * largest graph seen and is kept for later calls). */
+int trim_ctx_mem_used(trim_ctx *ctx, uint64_t *bytes);
 /* Free a context and its working memory (NULL is ignored). */
 int trim_ctx_destroy(trim_ctx *ctx);
 
-/* Number of workers P for `algo` with `opts` (NULL = defaults); size of worker_edges. */
+/* Number of workers P for `algo` with `opts` (NULL = defaults); size of worker_edges.
+ * opts.workers above trim_max_workers() is TRIM_E_INVAL here and in every call. */
 int trim_num_workers(trim_ctx *ctx, int algo, const trim_opts_t *opts, int32_t *P);
+
+/*
+ * Largest opts.workers for `algo`: the persistent and cooperative kernels need
+ * every workgroup resident at once.  AC-6 and AC-4: the occupancy limit
+ * (resident workgroups per CU times CUs).  AC-3: two workgroups per CU (its
+ * cooperative rounds kernel is not run at full occupancy; the round barrier
+ * needs every workgroup resident, which the launch at the occupancy maximum
+ * did not give).
+ */
+int trim_max_workers(trim_ctx *ctx, int algo, int32_t *P);
+
+/*
+ * Wait for the work enqueued on `stream` and report the watchdog of the last
+ * trimming call made on `ctx`: TRIM_E_STALLED if a persistent kernel exceeded
+ * its step budget (opts.budget), TRIM_OK otherwise, TRIM_E_HIP if the stream
+ * reported an error.  The context stays usable after a stall: the next call
+ * starts from a clean state.
+ */
+int trim_ctx_status(trim_ctx *ctx, void *stream);
 
 /*
  * Trim an explicit graph with `algo`.  Output live_bitmap (device,

@@ -58,46 +58,61 @@ def lib():
     if _lib is None:
         if not os.path.exists(_SO):
             build(force=False)
-        L = ctypes.CDLL(_SO)
-        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
-        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
-        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
-        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
-        L.or_peel.restype = ctypes.c_int64
-        L.or_peel.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, i32p, i64p]
-        for f in (L.or_ac6_seq, L.or_ac3_jacobi, L.or_ac3_inplace):
-            f.restype = ctypes.c_int64
-            f.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i64p]
-        L.or_counts.restype = ctypes.c_int64
-        L.or_counts.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, ctypes.c_int32, i64p]
-        L.or_implicit_deg.restype = ctypes.c_int32
-        L.or_implicit_deg.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u64p, ctypes.c_uint64]
-        L.or_implicit_nbr.restype = ctypes.c_int32
-        L.or_implicit_nbr.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
-                                      ctypes.c_uint64]
-        L.or_implicit_csr.restype = ctypes.c_int64
-        L.or_implicit_csr.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, u64p, i32p,
-                                      ctypes.c_void_p]
-        L.or_batch_peel.restype = ctypes.c_int64
-        L.or_batch_peel.argtypes = [ctypes.c_int64, i64p, i32p, i32p, u8p, i64p, ctypes.c_int]
-        L.or_peel_preset.restype = ctypes.c_int64
-        L.or_peel_preset.argtypes = [ctypes.c_int32, i32p, i32p, u8p, u8p, i32p, i32p, i64p]
-        L.or_counts_preset.restype = ctypes.c_int64
-        L.or_counts_preset.argtypes = [ctypes.c_int32, i32p, i32p, u8p, u8p, i32p,
-                                       ctypes.c_int32, i64p]
-        L.or_peel2.restype = ctypes.c_int64
-        L.or_peel2.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, i32p, i64p]
-        L.or_counts2.restype = ctypes.c_int64
-        L.or_counts2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i64p]
-        L.or_ac3_jacobi2.restype = ctypes.c_int64
-        L.or_ac3_jacobi2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
-        L.or_counts3two.restype = ctypes.c_int64
-        L.or_counts3two.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
-        L.or_num_threads.restype = ctypes.c_int
-        L.or_fin64.restype = ctypes.c_uint64
-        L.or_fin64.argtypes = [ctypes.c_uint64]
-        _lib = L
+        _lib = load(_SO)
     return _lib
+
+
+def swap_library(L):
+    """Make every oracle function call the library handle ``L`` (from
+    :func:`load`); returns the handle in use before.  The mutation pins use it
+    to run the pins against copies of oracle.c with planted mistakes."""
+    global _lib
+    old = lib()
+    _lib = L
+    return old
+
+
+def load(path: str):
+    """Open a build of oracle.c and declare its functions."""
+    L = ctypes.CDLL(path)
+    i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+    i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+    u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+    u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+    L.or_peel.restype = ctypes.c_int64
+    L.or_peel.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, i32p, i64p]
+    for f in (L.or_ac6_seq, L.or_ac3_jacobi, L.or_ac3_inplace):
+        f.restype = ctypes.c_int64
+        f.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i64p]
+    L.or_counts.restype = ctypes.c_int64
+    L.or_counts.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, ctypes.c_int32, i64p]
+    L.or_implicit_deg.restype = ctypes.c_int32
+    L.or_implicit_deg.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u64p, ctypes.c_uint64]
+    L.or_implicit_nbr.restype = ctypes.c_int32
+    L.or_implicit_nbr.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                  ctypes.c_uint64]
+    L.or_implicit_csr.restype = ctypes.c_int64
+    L.or_implicit_csr.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, u64p, i32p,
+                                  ctypes.c_void_p]
+    L.or_batch_peel.restype = ctypes.c_int64
+    L.or_batch_peel.argtypes = [ctypes.c_int64, i64p, i32p, i32p, u8p, i64p, ctypes.c_int]
+    L.or_peel_preset.restype = ctypes.c_int64
+    L.or_peel_preset.argtypes = [ctypes.c_int32, i32p, i32p, u8p, u8p, i32p, i32p, i64p]
+    L.or_counts_preset.restype = ctypes.c_int64
+    L.or_counts_preset.argtypes = [ctypes.c_int32, i32p, i32p, u8p, u8p, i32p,
+                                   ctypes.c_int32, i64p]
+    L.or_peel2.restype = ctypes.c_int64
+    L.or_peel2.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, i32p, i64p]
+    L.or_counts2.restype = ctypes.c_int64
+    L.or_counts2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i64p]
+    L.or_ac3_jacobi2.restype = ctypes.c_int64
+    L.or_ac3_jacobi2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
+    L.or_counts3two.restype = ctypes.c_int64
+    L.or_counts3two.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
+    L.or_num_threads.restype = ctypes.c_int
+    L.or_fin64.restype = ctypes.c_uint64
+    L.or_fin64.argtypes = [ctypes.c_uint64]
+    return L
 
 
 def num_threads() -> int:

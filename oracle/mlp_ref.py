@@ -9,7 +9,8 @@ live).  Parameter vector (1,377 values): W1[32][8], b1[32], W2[32][32]
 With ``bf16=True`` the reference rounds, as the GPU does, every value that
 enters a BF16 matrix product (weights, features, layer-1 activations, dZ2 and
 dZ1); arithmetic is FP64 throughout.  With ``bf16=False`` everything is FP64,
-which the finite-difference pin uses.
+which the finite-difference pin uses.  ``adam_step`` is the optimiser's
+update in FP64.
 """
 from __future__ import annotations
 
@@ -101,3 +102,18 @@ def loss_and_grad(params, X, y, w, bf16=True):
     for k, (o, sh) in OFF.items():
         grad[o:o + int(np.prod(sh))] = g[k].ravel()
     return loss, grad
+
+
+def adam_step(params, m, v, grad, lr, beta1, beta2, eps, step):
+    """One Adam update in FP64 (Kingma and Ba, "Adam: a method for stochastic
+    optimization", ICLR 2015, Algorithm 1): the moment estimates
+    m <- beta1 m + (1 - beta1) g and v <- beta2 v + (1 - beta2) g^2, their
+    bias-corrected values m / (1 - beta1^t) and v / (1 - beta2^t), and the
+    step params - lr * m_hat / (sqrt(v_hat) + eps).  Returns (params, m, v)."""
+    g = np.asarray(grad, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** step)
+    v_hat = v / (1.0 - beta2 ** step)
+    p = np.asarray(params, np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return p, m, v

@@ -334,18 +334,27 @@ int32_t or_implicit_nbr(uint64_t seed, int log2n, uint64_t v, uint64_t i) {
     return (int32_t)(or_fin(seed ^ OR_TN ^ ((v << 8) | i)) & mask);
 }
 
+/* Three plain passes: every degree (one thread per vertex range), the
+ * offsets by a running sum, then every successor list.  The passes only
+ * split the loop over v between threads; each value is the formula above. */
 int64_t or_implicit_csr(int log2n, uint64_t seed, uint64_t zero_thr, const uint64_t *table,
                         int32_t *row_off, int32_t *col) {
     int64_t n = (int64_t)1 << log2n;
+    #pragma omp parallel for schedule(static)
+    for (int64_t v = 0; v < n; ++v)
+        row_off[v + 1] = or_implicit_deg(seed, zero_thr, table, (uint64_t)v);
     int64_t e = 0;
+    row_off[0] = 0;
     for (int64_t v = 0; v < n; ++v) {
-        int32_t d = or_implicit_deg(seed, zero_thr, table, (uint64_t)v);
-        row_off[v] = (int32_t)e;
-        if (col)
-            for (int32_t i = 0; i < d; ++i) col[e + i] = or_implicit_nbr(seed, log2n, (uint64_t)v, (uint64_t)i);
-        e += d;
+        e += row_off[v + 1];
+        row_off[v + 1] = (int32_t)e;
     }
-    row_off[n] = (int32_t)e;
+    if (col) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t v = 0; v < n; ++v)
+            for (int32_t i = 0; i < row_off[v + 1] - row_off[v]; ++i)
+                col[row_off[v] + i] = or_implicit_nbr(seed, log2n, (uint64_t)v, (uint64_t)i);
+    }
     return e;
 }
 

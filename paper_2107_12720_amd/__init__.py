@@ -15,8 +15,10 @@ The functions mirror the C ABI in ``include/trim.h``:
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -29,14 +31,17 @@ ALGOS = {"ac3": AC3, "ac4": AC4, "ac6": AC6}
 STATUS = {0: "TRIM_OK", -1: "TRIM_E_INVAL", -2: "TRIM_E_NOMEM", -3: "TRIM_E_HIP",
           -4: "TRIM_E_UNSUPPORTED", -5: "TRIM_E_BADGRAPH", -6: "TRIM_E_STALLED"}
 EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destroy",
+           "trim_ctx_mem_used", "trim_ctx_status", "trim_max_workers",
            "trim_num_workers", "trim_csr", "trim_csr_preset", "trim_csr_two_sided",
            "trim_scc", "trim_size2", "trim_implicit", "trim_batch",
            "trim_ctx_set_timing", "trim_ctx_kernel_times", "trim_mlp_prepare", "trim_mlp_grad",
            "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key")
 MLP_PARAMS = 1377
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
-                "joins", "visited", "graph_edges", "q_highwater")
-STATS_WORDS = 12
+                "joins", "visited", "graph_edges", "q_highwater", "edges_live", "stalled")
+STATS_WORDS = 16
+ABI_VERSION = 2
+DEFAULT_BUDGET = 1 << 22
 
 
 class TrimError(RuntimeError):
@@ -49,7 +54,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CsrDesc(ctypes.Structure):
@@ -86,8 +91,11 @@ def lib():
         vp, i32 = ctypes.c_void_p, ctypes.c_int32
         L.trim_version.restype = ctypes.c_int
         L.trim_last_error.restype = ctypes.c_char_p
-        L.trim_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.trim_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_uint64]
         L.trim_ctx_destroy.argtypes = [vp]
+        L.trim_ctx_mem_used.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64)]
+        L.trim_ctx_status.argtypes = [vp, vp]
+        L.trim_max_workers.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
         L.trim_num_workers.argtypes = [vp, ctypes.c_int, ctypes.POINTER(Opts),
                                        ctypes.POINTER(i32)]
         L.trim_csr.argtypes = [vp, ctypes.c_int, ctypes.POINTER(CsrDesc), ctypes.POINTER(Opts),
@@ -116,12 +124,16 @@ def lib():
         L.trim_mlp_score.argtypes = [vp, csr_p, vp, vp, vp, vp, vp]
         L.trim_edge_keys.argtypes = [vp, csr_p, i32, ctypes.c_uint64, vp, vp]
         L.trim_order_by_key.argtypes = [vp, csr_p, vp, f32, f32, vp, vp]
-        for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_num_workers", "trim_csr",
+        for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_ctx_mem_used", "trim_ctx_status",
+                  "trim_max_workers", "trim_num_workers", "trim_csr",
                   "trim_csr_preset", "trim_csr_two_sided", "trim_scc", "trim_size2",
                   "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times",
                   "trim_mlp_prepare", "trim_mlp_grad", "trim_mlp_adam", "trim_mlp_score",
                   "trim_edge_keys", "trim_order_by_key"):
             getattr(L, f).restype = ctypes.c_int
+        if L.trim_version() != ABI_VERSION:
+            raise TrimError(-3, f"{LIB_PATH} has ABI {L.trim_version()}, expected "
+                                f"{ABI_VERSION}; rebuild it")
         _lib = L
     return _lib
 
@@ -139,9 +151,10 @@ SCHED_REVERSE = 1
 SCHED_JITTER = 2
 
 
-def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False, schedule=0) -> Opts:
+def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False, schedule=0,
+              budget=0) -> Opts:
     return Opts(block, workers, chunk, int(bool(validate)), int(bool(graph)), int(schedule),
-                (0, 0))
+                int(budget), 0)
 
 
 def _dev_ptr(t, dtype, name, allow_none=False):
@@ -177,27 +190,72 @@ class TrimResult:
         return self.live_bitmap.cpu().numpy().view(np.uint32)
 
 
-class Context:
-    """A libtrim context bound to one GPU; owns the call's working memory."""
+# Contexts still open at interpreter exit are destroyed by an exit hook, while
+# the HIP runtime is certainly alive, instead of by __del__ during module
+# teardown (whose order against the runtime's and a profiler's own teardown is
+# not fixed).
+_open_contexts: "weakref.WeakSet" = weakref.WeakSet()
 
-    def __init__(self, device: int = 0):
+
+@atexit.register
+def _close_open_contexts():
+    for c in list(_open_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A libtrim context bound to one GPU; owns the call's working memory.
+    ``mem_budget`` caps the device memory it may hold (bytes, 0 = no cap)."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise TrimError(-3, "no GPU available; libtrim has no CPU path")
         self.device = device
         self._h = ctypes.c_void_p()
-        _check(lib().trim_ctx_create(ctypes.byref(self._h), device))
+        _check(lib().trim_ctx_create(ctypes.byref(self._h), device, int(mem_budget)))
+        _open_contexts.add(self)
 
     def close(self):
         if self._h:
             lib().trim_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
+        _open_contexts.discard(self)
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def mem_used(self) -> int:
+        """Device memory the context holds (bytes)."""
+        b = ctypes.c_uint64()
+        _check(lib().trim_ctx_mem_used(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def status(self, stream=None) -> int:
+        """Wait for the stream; the watchdog status of the last trimming call
+        (0, or -6 = TRIM_E_STALLED when it was abandoned)."""
+        return int(lib().trim_ctx_status(self._h, _stream_handle(stream, self.device)))
+
+    def check(self, stream=None):
+        """As status(), raising TrimError when the last call did not finish."""
+        _check(self.status(stream))
+
+    def max_workers(self, algo: int = AC6) -> int:
+        P = ctypes.c_int32()
+        _check(lib().trim_max_workers(self._h, int(ALGOS.get(algo, algo)), ctypes.byref(P)))
+        return P.value
 
     def set_timing(self, enable: bool = True):
         """Record HIP events around each kernel of later calls (same stream)."""

@@ -114,10 +114,15 @@ __global__ void ac3_list_preset(View g, int n, const uint32_t* preset, int* list
 // different addresses, and without the wait in between the read can be
 // performed after the last arrival has already bumped *gen; the block would
 // then wait for a release that never comes.
-__device__ __forceinline__ void grid_barrier(int* count, int* gen) {
+// Watchdog: a workgroup that has polled `budget` times without a release, or
+// that finds the stall word raised, gives up and raises it.  Returns false
+// (the same in every thread of the block) when the rounds must be abandoned.
+__device__ __forceinline__ bool grid_barrier(int* count, int* gen, int* stall, int budget) {
+    __shared__ int s_go;
     complete_mem();
     __syncthreads();
     if (threadIdx.x == 0) {
+        int go = 1;
         const int g0 = ld_dev(gen);
         complete_mem();   // g0 is read before this block can complete the barrier
         if (add_dev(count, 1) == (int)gridDim.x - 1) {
@@ -125,10 +130,21 @@ __device__ __forceinline__ void grid_barrier(int* count, int* gen) {
             complete_mem();
             add_dev(gen, 1);
         } else {
-            while (ld_dev(gen) == g0) __builtin_amdgcn_s_sleep(2);
+            for (int polls = 1; ld_dev(gen) == g0; ++polls) {
+                if (polls > budget || ((polls & 63) == 0 && ld_dev(stall))) {
+                    st_dev(stall, 1);
+                    go = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
         }
+        s_go = go && ld_dev(stall) == 0;
     }
     __syncthreads();
+    const bool go = s_go != 0;
+    __syncthreads();   // s_go is rewritten by the next barrier
+    return go;
 }
 
 // kUnroll list entries per lane per step, their loads in flight together, and
@@ -142,7 +158,8 @@ constexpr int kUnroll = 4;
 template <class View>
 __global__ __launch_bounds__(256) void ac3_rounds(View g, int n, int* ptr, int* dround,
                                                   int* list0, int* list1, int* ctr,
-                                                  uint64_t* worker_edges, trim_stats_t* stats) {
+                                                  uint64_t* worker_edges, trim_stats_t* stats,
+                                                  int budget) {
     __shared__ uint64_t lds[Stage3<View>::kWords];
     __shared__ int s_wave[256 / kWave], s_base;
     Stage3<View>::apply(g, lds);
@@ -211,7 +228,7 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int n, int* ptr, int* 
                 }
             }
         }
-        grid_barrier(ctr + kBarCount, ctr + kBarGen);
+        if (!grid_barrier(ctr + kBarCount, ctr + kBarGen, ctr + kStall, budget)) break;
         if (ld_dev(cnt_out) == cnt_in) break;   // no removal in round r
     }
     edges = wave_sum(edges);
@@ -268,7 +285,7 @@ __device__ __forceinline__ int scan_on(const ExplicitView& g, int v, int p0, int
 __global__ __launch_bounds__(256) void ac3_rounds2(ExplicitView out, ExplicitView in, int n,
                                                    int* ptr, int* ptr_in, int* dround, List3 l0,
                                                    List3 l1, int* ctr, uint64_t* worker_edges,
-                                                   trim_stats_t* stats) {
+                                                   trim_stats_t* stats, int budget) {
     __shared__ int s_wave[256 / kWave], s_base;
     uint64_t edges = 0;
     int r = 1;
@@ -350,7 +367,7 @@ __global__ __launch_bounds__(256) void ac3_rounds2(ExplicitView out, ExplicitVie
                 }
             }
         }
-        grid_barrier(ctr + kBarCount, ctr + kBarGen);
+        if (!grid_barrier(ctr + kBarCount, ctr + kBarGen, ctr + kStall, budget)) break;
         if (ld_dev(cnt_out) == cnt_in) break;   // no removal in round r
     }
     edges = wave_sum(edges);
@@ -393,8 +410,9 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     }
     if (n > 0) {
         int nn = n;
+        int budget = lc.budget;
         void* args[] = {&g,     &nn,          &ptr,          &dround, &list0,
-                        &list1, (void*)&w.ctr, &worker_edges, &stats};
+                        &list1, (void*)&w.ctr, &worker_edges, &stats, &budget};
         {
             Timed t(lc, "ac3_rounds");
             hipError_t e = hipLaunchCooperativeKernel((const void*)ac3_rounds<View>, dim3(P),
@@ -404,7 +422,7 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         Timed t(lc, "ac3_pack");
         pack_blocks = grid_for(n, 256, lc.cus * 4);
         hipLaunchKernelGGL(pack_bitmap<Ac3Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
-                           Ac3Live{dround}, n, bitmap, w.part);
+                           Ac3Live{dround}, n, bitmap, w.part, w.ctr, nullptr, 0LL);
     }
     // an empty graph still runs the repeat-until loop once
     if (stats)
@@ -438,8 +456,9 @@ hipError_t ac3_two_csr(const trim_csr_t& g, const Work& w, const Work2& x, const
     }
     if (n > 0) {
         int nn = n;
+        int budget = lc.budget;
         void* args[] = {&out, &in, &nn, &ptr, &ptr_in, &dround, &l0, &l1, (void*)&w.ctr,
-                        &worker_edges, &stats};
+                        &worker_edges, &stats, &budget};
         {
             Timed t(lc, "ac3t_rounds");
             hipError_t e = hipLaunchCooperativeKernel((const void*)ac3_rounds2, dim3(P), dim3(256),
@@ -449,7 +468,7 @@ hipError_t ac3_two_csr(const trim_csr_t& g, const Work& w, const Work2& x, const
         Timed t(lc, "ac3t_pack");
         pack_blocks = grid_for(n, 256, lc.cus * 4);
         hipLaunchKernelGGL(pack_bitmap<Ac3Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
-                           Ac3Live{dround}, n, bitmap, w.part);
+                           Ac3Live{dround}, n, bitmap, w.part, w.ctr, nullptr, 0LL);
     }
     if (stats)
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,

@@ -95,13 +95,13 @@ __global__ __launch_bounds__(256) void ac4_propagate(const int* rrow_off, const 
                                                      const int* row_off, const int* col, int n,
                                                      int* cnt, int* dead, uint32_t* q, int* ctr,
                                                      uint64_t* worker_edges, uint64_t* part,
-                                                     int sched) {
+                                                     int sched, int budget) {
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
     WaveQueue wq;
     const int wv = threadIdx.x / kWave;
     wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending,
-            kShareEvery4);
+            ctr + kStall, budget, kShareEvery4);
     uint32_t item = kNone;
     int k = 0, e = 0, ph = 0;
     bool started = false;
@@ -245,16 +245,16 @@ hipError_t ac4_run(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
             Timed t(lc, kTwo ? "ac4t_propagate" : "ac4_propagate");
             hipLaunchKernelGGL(ac4_propagate<kTwo>, dim3(P), dim3(256), 0, lc.stream, g.rrow_off,
                                g.rcol, g.row_off, g.col, n, w.a, w.d, w.q, w.ctr, worker_edges,
-                               w.part, lc.schedule);
+                               w.part, lc.schedule, lc.budget);
         }
         Timed t(lc, kTwo ? "ac4t_pack" : "ac4_pack");
         pack_blocks = grid_for(n, 256, lc.cus * 4);
         if (kTwo)
             hipLaunchKernelGGL(pack_bitmap<Ac4TwoLive>, dim3(pack_blocks), dim3(256), 0, lc.stream,
-                               Ac4TwoLive{w.d}, n, bitmap, w.part);
+                               Ac4TwoLive{w.d}, n, bitmap, w.part, w.ctr, w.q, w.qwords);
         else
             hipLaunchKernelGGL(pack_bitmap<Ac4Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
-                               Ac4Live{w.a}, n, bitmap, w.part);
+                               Ac4Live{w.a}, n, bitmap, w.part, w.ctr, w.q, w.qwords);
     }
     if (stats)
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,

@@ -214,7 +214,7 @@ constexpr int kHops = 256;   // S_last chain steps one item may take in a row
 template <class View>
 __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t* rec, uint32_t* q,
                                                      int* ctr, uint64_t* worker_edges,
-                                                     uint64_t* part, int sched) {
+                                                     uint64_t* part, int sched, int budget) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
     WaveQueue wq;
     const int wv = threadIdx.x / kWave;
     wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending,
-            ShareEvery<View>::value);
+            ctr + kStall, budget, ShareEvery<View>::value);
     uint32_t item = kNone;
     uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
     while (wq.acquire(item)) {
@@ -320,8 +320,10 @@ struct Ac6Live {
 // bitmap_base[g] <= wi < bitmap_base[g+1] and covers local vertices
 // 32 * (wi - bitmap_base[g]) .. + 31 (bits past the graph's n are zero).
 __global__ void ac6_pack_batch(const int* head, const int64_t* vbase, const int64_t* bitmap_base,
-                               int G, uint32_t* bitmaps, uint64_t* part) {
+                               int G, uint32_t* bitmaps, uint64_t* part, const int* ctr,
+                               uint32_t* q, long long qwords) {
     __shared__ uint64_t red[16];
+    clear_queue_if_stalled(ctr, q, qwords);
     const int64_t total_words = bitmap_base[G];
     uint64_t live_cnt = 0;
     for (int64_t wi = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; wi < total_words;
@@ -408,20 +410,20 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         {
             Timed t(lc, "ac6_propagate");
             hipLaunchKernelGGL(ac6_propagate<View>, dim3(P), dim3(256), 0, lc.stream, g, w.a,
-                               w.b, w.q, w.ctr, worker_edges, w.part, lc.schedule);
+                               w.b, w.q, w.ctr, worker_edges, w.part, lc.schedule, lc.budget);
         }
         if (!bitmap_base) {
             Timed t(lc, "ac6_pack");
             pack_blocks = grid_for(n, 256, lc.cus * 4);
             hipLaunchKernelGGL(pack_bitmap<Ac6Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
-                               Ac6Live{w.a}, n, bitmap, w.part);
+                               Ac6Live{w.a}, n, bitmap, w.part, w.ctr, w.q, w.qwords);
         }
     }
     if (bitmap_base && n > 0) {
         Timed t(lc, "ac6_pack_batch");
         pack_blocks = grid_for(n / 32 + G, 256, lc.cus * 4);
         hipLaunchKernelGGL(ac6_pack_batch, dim3(pack_blocks), dim3(256), 0, lc.stream, w.a,
-                           vbase, bitmap_base, G, bitmap, w.part);
+                           vbase, bitmap_base, G, bitmap, w.part, w.ctr, w.q, w.qwords);
     }
     if (stats) {
         Timed t(lc, "finalize");

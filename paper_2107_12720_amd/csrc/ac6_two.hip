@@ -192,14 +192,14 @@ constexpr int kTShareEvery = 16;
 
 __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, int* ctr,
                                                       uint64_t* worker_edges, uint64_t* part,
-                                                      int sched) {
+                                                      int sched, int budget) {
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
     __shared__ uint64_t red[16];
     WaveQueue wq;
     const int wv = threadIdx.x / kWave;
     wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending,
-            kTShareEvery);
+            ctr + kStall, budget, kTShareEvery);
     const ExplicitView out_view{g.row_off, g.col}, in_view{g.rrow_off, g.rcol};
     uint32_t item = kNone;
     uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
@@ -297,10 +297,39 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
     }
 }
 
-struct TwoLive {
-    const int* hout;
-    __device__ __forceinline__ bool operator()(int v) const { return hout[2 * v] != kDead; }
-};
+// Live bitmap by ballot, plus the checks the live vertices made, read off
+// their final cursors: a live vertex's supports end at its first finally-live
+// successor and predecessor, so it checked fl_out + 1 + fl_in + 1 positions
+// whatever the schedule.  Restores the shared queue after a stalled call.
+__global__ void ac6t_pack(TwoGraph g, int n, uint32_t* bitmap, uint64_t* part, const int* ctr,
+                          uint32_t* q, long long qwords) {
+    __shared__ uint64_t red[16];
+    clear_queue_if_stalled(ctr, q, qwords);
+    const int nwords = (n + 31) >> 5;
+    const int waves = (gridDim.x * blockDim.x) / kWave;
+    const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    uint64_t live_cnt = 0, live_edges = 0;
+    for (int base = wid * kWave; base < n; base += waves * kWave) {
+        const int v = base + lane_id();
+        const bool live = v < n && g.hout[2 * v] != kDead;
+        if (live)
+            live_edges += (uint64_t)(rec_cursor(g.rec_out[v]) - g.row_off[v] + 1) +
+                          (uint64_t)(rec_cursor(g.rec_in[v]) - g.rrow_off[v] + 1);
+        const uint64_t b = ballot(live);
+        if (lane_id() == 0) {
+            const int w = base >> 5;
+            bitmap[w] = (uint32_t)b;
+            if (w + 1 < nwords) bitmap[w + 1] = (uint32_t)(b >> 32);
+            live_cnt += (uint64_t)popc(b);
+        }
+    }
+    live_cnt = block_sum(live_cnt, red);
+    live_edges = block_sum(live_edges, red);
+    if (threadIdx.x == 0) {
+        part[kPartLive * kPartStride + blockIdx.x] = live_cnt;
+        part[kPartLiveEdges * kPartStride + blockIdx.x] = live_edges;
+    }
+}
 
 inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
     long long b = (n + block - 1) / block;
@@ -339,18 +368,18 @@ hipError_t ac6_two_csr_preset(const trim_csr_t& gc, const Work& w, const Work2& 
         {
             Timed t(lc, "ac6t_propagate");
             hipLaunchKernelGGL(ac6t_propagate, dim3(P), dim3(256), 0, lc.stream, g, x.q, w.ctr,
-                               worker_edges, w.part, lc.schedule);
+                               worker_edges, w.part, lc.schedule, lc.budget);
         }
         Timed t(lc, "ac6t_pack");
         pack_blocks = grid_for(n, 256, lc.cus * 4);
-        hipLaunchKernelGGL(pack_bitmap<TwoLive>, dim3(pack_blocks), dim3(256), 0, lc.stream,
-                           TwoLive{w.a}, n, bitmap, w.part);
+        hipLaunchKernelGGL(ac6t_pack, dim3(pack_blocks), dim3(256), 0, lc.stream, g, n, bitmap,
+                           w.part, w.ctr, x.q, x.qwords);
     }
     if (stats) {
         Timed t(lc, "finalize");
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, sweep_blocks,
                            n > 0 ? P : 0, pack_blocks, n > 0 ? P : 0, worker_edges, w.part,
-                           w.ctr, stats, 0);
+                           w.ctr, stats, 0, pack_blocks);
     }
     return hipGetLastError();
 }

@@ -349,8 +349,10 @@ hipError_t mlp_grad_launch(const int* row_off, const int* col, const int* indeg,
 
 hipError_t mlp_adam_launch(float* p32, short* pbf, float* m1, float* m2, float* grad, float lr,
                            float beta1, float beta2, float eps, int step, hipStream_t s) {
-    const float c1 = 1.f / (1.f - powf(beta1, (float)step));
-    const float c2 = 1.f / (1.f - powf(beta2, (float)step));
+    // the bias corrections in double: 1 - beta2^t cancels badly in FP32
+    // (beta2 = 0.999 loses about 15 bits at t = 2)
+    const float c1 = (float)(1.0 / (1.0 - pow((double)beta1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - pow((double)beta2, (double)step)));
     hipLaunchKernelGGL(mlp_adam, dim3(1), dim3(256), 0, s, p32, pbf, m1, m2, grad, lr, beta1,
                        beta2, eps, c1, c2);
     return hipGetLastError();

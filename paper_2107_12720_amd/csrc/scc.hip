@@ -585,6 +585,15 @@ hipError_t scc_run(const trim_csr_t& g, const Work& w, const Work2& x, const Scc
                            label, s.misc);
         if ((r = hipGetLastError()) != hipSuccess || (r = read_misc()) != hipSuccess) return r;
         active = (long long)host[kSccActive];
+        int stalled = 0;   // the trimming pass was abandoned by its watchdog
+        if ((r = hipMemcpyAsync(&stalled, w.ctr + kStall, sizeof(int), hipMemcpyDeviceToHost,
+                                st)) != hipSuccess ||
+            (r = hipStreamSynchronize(st)) != hipSuccess)
+            return r;
+        if (stalled) {
+            counts->stalled = true;
+            active = 0;
+        }
         counts->trimmed += (long long)host[kSccTaken];
         counts->trims += 1;
         counts->trim_ms += ms_since(t0);

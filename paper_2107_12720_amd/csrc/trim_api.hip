@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 
 #include "trim_internal.h"
 #include "scc_internal.h"
@@ -12,6 +13,10 @@
 struct trim_ctx {
     int device = 0;
     int cus = 0;
+    // device memory held by the context, against its cap (0 = none)
+    uint64_t mem_budget = 0;
+    uint64_t mem_used = 0;
+    std::unordered_map<void*, size_t> sizes;
     size_t cap_n = 0;
     trim::Work w;
     // two-sided AC-6 extras, sized for cap_n2 vertices
@@ -55,12 +60,40 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(TRIM_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Every device allocation of a context goes through these two, so the context
+// knows what it holds and can refuse what would exceed its cap.
+hipError_t dmalloc(trim_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (c->mem_budget && c->mem_used + bytes > c->mem_budget) return hipErrorOutOfMemory;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return e;
+    }
+    c->sizes[*p] = bytes;
+    c->mem_used += bytes;
+    return hipSuccess;
+}
+template <class T>
+hipError_t dmalloc(trim_ctx* c, T** p, size_t bytes) {
+    return dmalloc(c, reinterpret_cast<void**>(p), bytes);
+}
+void dfree(trim_ctx* c, void* p) {
+    if (!p) return;
+    auto it = c->sizes.find(p);
+    if (it != c->sizes.end()) {
+        c->mem_used -= it->second;
+        c->sizes.erase(it);
+    }
+    (void)hipFree(p);
+}
+
 void free_work(trim_ctx* c) {
-    (void)hipFree(c->w.a);
-    (void)hipFree(c->w.b);
-    (void)hipFree(c->w.c);
-    (void)hipFree(c->w.d);
-    (void)hipFree(c->w.q);
+    dfree(c, c->w.a);
+    dfree(c, c->w.b);
+    dfree(c, c->w.c);
+    dfree(c, c->w.d);
+    dfree(c, c->w.q);
     c->w.q = nullptr;
     c->w.a = nullptr;
     c->w.b = nullptr;
@@ -74,11 +107,11 @@ int ensure(trim_ctx* c, int64_t n) {
     if (need <= c->cap_n) return TRIM_OK;
     free_work(c);
     size_t cap = need + need / 8 + 64;
-    if (hipMalloc((void**)&c->w.a, cap * 8) != hipSuccess ||
-        hipMalloc((void**)&c->w.b, cap * 8) != hipSuccess ||
-        hipMalloc((void**)&c->w.c, cap * 4) != hipSuccess ||
-        hipMalloc((void**)&c->w.d, cap * 4) != hipSuccess ||
-        hipMalloc((void**)&c->w.q, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess ||
+    if (dmalloc(c, &c->w.a, cap * 8) != hipSuccess ||
+        dmalloc(c, &c->w.b, cap * 8) != hipSuccess ||
+        dmalloc(c, &c->w.c, cap * 4) != hipSuccess ||
+        dmalloc(c, &c->w.d, cap * 4) != hipSuccess ||
+        dmalloc(c, &c->w.q, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess ||
         // free queue slots hold kNone (all ones); consumers restore it
         hipMemset(c->w.q, 0xFF, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess) {
         (void)hipGetLastError();
@@ -87,13 +120,14 @@ int ensure(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n = cap;
+    c->w.qwords = (long long)cap * 3 + trim::kQueueSlots;
     return TRIM_OK;
 }
 
 void free_work2(trim_ctx* c) {
-    (void)hipFree(c->w2.hin);
-    (void)hipFree(c->w2.rec_in);
-    (void)hipFree(c->w2.q);
+    dfree(c, c->w2.hin);
+    dfree(c, c->w2.rec_in);
+    dfree(c, c->w2.q);
     c->w2 = trim::Work2{};
     c->cap_n2 = 0;
 }
@@ -107,9 +141,9 @@ int ensure2(trim_ctx* c, int64_t n) {
     free_work2(c);
     size_t cap = need + need / 8 + 64;
     const size_t qbytes = cap * 32 + (size_t)trim::kQueueSlots * 4;
-    if (hipMalloc((void**)&c->w2.hin, cap * 8) != hipSuccess ||
-        hipMalloc((void**)&c->w2.rec_in, cap * 8) != hipSuccess ||
-        hipMalloc((void**)&c->w2.q, qbytes) != hipSuccess ||
+    if (dmalloc(c, &c->w2.hin, cap * 8) != hipSuccess ||
+        dmalloc(c, &c->w2.rec_in, cap * 8) != hipSuccess ||
+        dmalloc(c, &c->w2.q, qbytes) != hipSuccess ||
         hipMemset(c->w2.q, 0xFF, qbytes) != hipSuccess) {
         (void)hipGetLastError();
         free_work2(c);
@@ -117,19 +151,20 @@ int ensure2(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n2 = cap;
+    c->w2.qwords = (long long)cap * 8 + trim::kQueueSlots;
     return TRIM_OK;
 }
 
 void free_scc(trim_ctx* c) {
-    (void)hipFree(c->sw.assigned);
-    (void)hipFree(c->sw.live);
-    (void)hipFree(c->sw.flags);
-    (void)hipFree(c->sw.color);
-    (void)hipFree(c->sw.misc);
-    (void)hipFree(c->sw.front[0]);
-    (void)hipFree(c->sw.front[1]);
-    (void)hipFree(c->sw.pre);
-    (void)hipFree(c->sw.bsum);
+    dfree(c, c->sw.assigned);
+    dfree(c, c->sw.live);
+    dfree(c, c->sw.flags);
+    dfree(c, c->sw.color);
+    dfree(c, c->sw.misc);
+    dfree(c, c->sw.front[0]);
+    dfree(c, c->sw.front[1]);
+    dfree(c, c->sw.pre);
+    dfree(c, c->sw.bsum);
     c->sw = trim::SccWork{};
     c->cap_scc = 0;
 }
@@ -140,15 +175,15 @@ int ensure_scc(trim_ctx* c, int64_t n) {
     free_scc(c);
     size_t cap = need + need / 8 + 64;
     const size_t words = cap / 32 + 64;
-    if (hipMalloc((void**)&c->sw.assigned, words * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.live, words * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.flags, cap * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.color, cap * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.misc, trim::kSccMisc * 8) != hipSuccess ||
-        hipMalloc((void**)&c->sw.front[0], (2 * cap + 64) * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.front[1], (2 * cap + 64) * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.pre, (2 * cap + 64) * 4) != hipSuccess ||
-        hipMalloc((void**)&c->sw.bsum, ((2 * cap + 64) / trim::kScanChunk + 64) * 4) !=
+    if (dmalloc(c, &c->sw.assigned, words * 4) != hipSuccess ||
+        dmalloc(c, &c->sw.live, words * 4) != hipSuccess ||
+        dmalloc(c, &c->sw.flags, cap * 4) != hipSuccess ||
+        dmalloc(c, &c->sw.color, cap * 4) != hipSuccess ||
+        dmalloc(c, &c->sw.misc, trim::kSccMisc * 8) != hipSuccess ||
+        dmalloc(c, &c->sw.front[0], (2 * cap + 64) * 4) != hipSuccess ||
+        dmalloc(c, &c->sw.front[1], (2 * cap + 64) * 4) != hipSuccess ||
+        dmalloc(c, &c->sw.pre, (2 * cap + 64) * 4) != hipSuccess ||
+        dmalloc(c, &c->sw.bsum, ((2 * cap + 64) / trim::kScanChunk + 64) * 4) !=
             hipSuccess) {
         (void)hipGetLastError();
         free_scc(c);
@@ -162,11 +197,11 @@ int ensure_scc(trim_ctx* c, int64_t n) {
 int ensure_tiles(trim_ctx* c, long long m) {
     const long long need = trim::tile_scratch_ints(m > 0 ? m : 1);
     if (need <= c->cap_tiles) return TRIM_OK;
-    (void)hipFree(c->tiles);
+    dfree(c, c->tiles);
     c->tiles = nullptr;
     c->cap_tiles = 0;
     const long long cap = need + need / 8 + 64;
-    if (hipMalloc((void**)&c->tiles, (size_t)cap * 4) != hipSuccess) {
+    if (dmalloc(c, &c->tiles, (size_t)cap * 4) != hipSuccess) {
         (void)hipGetLastError();
         c->tiles = nullptr;
         return fail(TRIM_E_NOMEM, "cannot allocate tile tables for %lld edges", m);
@@ -177,22 +212,37 @@ int ensure_tiles(trim_ctx* c, long long m) {
 
 // AC-3's single cooperative launch is limited to two workgroups per CU.  With
 // eight per CU (the occupancy maximum, 2,048 workgroups) the rounds kernel
-// stopped making progress, also after the barrier's generation read was
-// ordered before the arrival; the cause is not known, so that configuration
-// stays off.  More workgroups only lengthen the barrier anyway: a round costs
-// least at one per CU, the default.
+// stopped making progress; the round barrier needs every workgroup resident,
+// and the launch at the occupancy maximum evidently did not give that (the
+// barrier protocol itself is checked on the host with the full workgroup
+// count).  That configuration stays off: opts.workers above the cap is an
+// argument error.  More workgroups only lengthen the barrier anyway: a round
+// costs least at one per CU, the default.
 constexpr int kAc3MaxPerCu = 2;
 
-int workers_for(trim_ctx* c, int algo, const trim_opts_t* o) {
+int max_workers(const trim_ctx* c, int algo) {
     int per_cu = algo == TRIM_AC6 ? c->occ6 : algo == TRIM_AC4 ? c->occ4 : c->occ3;
     if (algo == TRIM_AC3 && per_cu > kAc3MaxPerCu) per_cu = kAc3MaxPerCu;
     int max_p = per_cu * c->cus;
+    if (max_p > trim::kMaxWorkers) max_p = trim::kMaxWorkers;
+    return max_p < 1 ? 1 : max_p;
+}
+
+int workers_for(trim_ctx* c, int algo, const trim_opts_t* o) {
+    int per_cu = algo == TRIM_AC6 ? c->occ6 : algo == TRIM_AC4 ? c->occ4 : c->occ3;
     int def = (algo == TRIM_AC3 ? 1 : (per_cu < 2 ? per_cu : 2)) * c->cus;
     int p = (o && o->workers > 0) ? o->workers : def;
-    if (p > max_p) p = max_p;
-    if (p > trim::kMaxWorkers) p = trim::kMaxWorkers;
+    const int max_p = max_workers(c, algo);
+    if (p > max_p) p = max_p;   // only the default can exceed it; check_workers refuses more
     if (p < 1) p = 1;
     return p;
+}
+
+int check_workers(trim_ctx* c, int algo, const trim_opts_t* o) {
+    if (o && o->workers > max_workers(c, algo))
+        return fail(TRIM_E_INVAL, "opts.workers = %d exceeds the limit %d for AC-%d", o->workers,
+                    max_workers(c, algo), algo);
+    return TRIM_OK;
 }
 
 int check_opts(const trim_opts_t* o) {
@@ -205,6 +255,7 @@ int check_opts(const trim_opts_t* o) {
     if (o->graph != 0 && o->graph != 1) return fail(TRIM_E_INVAL, "opts.graph must be 0 or 1");
     if (o->schedule & ~(TRIM_SCHED_REVERSE | TRIM_SCHED_JITTER))
         return fail(TRIM_E_INVAL, "opts.schedule has unknown bits");
+    if (o->budget < 0) return fail(TRIM_E_INVAL, "opts.budget must be >= 0");
     return TRIM_OK;
 }
 
@@ -214,6 +265,7 @@ trim::LaunchCfg launch_cfg(trim_ctx* c, int algo, const trim_opts_t* o, void* st
     lc.chunk = (o && o->chunk) ? o->chunk : 4096;
     lc.schedule = o ? o->schedule : 0;
     lc.workers = workers_for(c, algo, o);
+    lc.budget = (o && o->budget > 0) ? o->budget : TRIM_DEFAULT_BUDGET;
     lc.cus = c->cus;
     lc.stream = (hipStream_t)stream;
     if (c->timing) {
@@ -241,6 +293,10 @@ __global__ void validate_kernel(const int* row_off, const int* col, int n, long 
 }  // namespace
 
 namespace trim {
+// Error reporting and option checks for the entry points in other files.
+int report_error(int code, const char* msg) { return fail(code, "%s", msg); }
+int check_options(const trim_opts_t* o) { return check_opts(o); }
+
 hipError_t validate_csr(const trim_csr_t& g, const Work& w, hipStream_t s) {
     hipError_t e = hipMemsetAsync(w.ctr + kBad, 0, sizeof(int), s);
     if (e != hipSuccess) return e;
@@ -275,7 +331,7 @@ int trim_version(void) { return TRIM_ABI_VERSION; }
 
 const char* trim_last_error(void) { return g_err.c_str(); }
 
-int trim_ctx_create(trim_ctx** out, int device) {
+int trim_ctx_create(trim_ctx** out, int device, uint64_t mem_budget) {
     if (!out) return fail(TRIM_E_INVAL, "trim_ctx_create: out is NULL");
     *out = nullptr;
     int ndev = 0;
@@ -289,6 +345,7 @@ int trim_ctx_create(trim_ctx** out, int device) {
         return hip_fail(e, "hipGetDeviceProperties");
     trim_ctx* c = new trim_ctx;
     c->device = device;
+    c->mem_budget = mem_budget;
     c->cus = prop.multiProcessorCount;
     c->occ6 = trim::ac6_max_workers_per_cu(256);
     {
@@ -297,16 +354,17 @@ int trim_ctx_create(trim_ctx** out, int device) {
     }
     c->occ4 = trim::ac4_max_workers_per_cu(256);
     c->occ3 = trim::ac3_max_workers_per_cu(256);
-    if ((e = hipMalloc((void**)&c->w.ctr, trim::kCtrInts * sizeof(int))) != hipSuccess ||
-        (e = hipMalloc((void**)&c->w.wedges, trim::kMaxWorkers * sizeof(uint64_t))) !=
+    if ((e = dmalloc(c, &c->w.ctr, trim::kCtrInts * sizeof(int))) != hipSuccess ||
+        (e = dmalloc(c, &c->w.wedges, trim::kMaxWorkers * sizeof(uint64_t))) !=
             hipSuccess ||
-        (e = hipMalloc((void**)&c->w.part,
+        (e = dmalloc(c, &c->w.part,
                        (size_t)trim::kPartSlots * trim::kPartStride * sizeof(uint64_t))) !=
             hipSuccess) {
-        (void)hipFree(c->w.ctr);
-        (void)hipFree(c->w.wedges);
+        dfree(c, c->w.ctr);
+        dfree(c, c->w.wedges);
         delete c;
-        return fail(TRIM_E_NOMEM, "cannot allocate control block: %s", hipGetErrorString(e));
+        return fail(TRIM_E_NOMEM, "cannot allocate control block (%llu bytes cap): %s",
+                    (unsigned long long)mem_budget, hipGetErrorString(e));
     }
     *out = c;
     return TRIM_OK;
@@ -321,12 +379,12 @@ int trim_ctx_destroy(trim_ctx* c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     for (auto& ev : c->timer.ev)
         if (ev) (void)hipEventDestroy(ev);
-    (void)hipFree(c->w.ctr);
-    (void)hipFree(c->w.wedges);
-    (void)hipFree(c->w.part);
-    (void)hipFree(c->tiles);
-    (void)hipFree(c->copies);
-    (void)hipFree(c->vf);
+    dfree(c, c->w.ctr);
+    dfree(c, c->w.wedges);
+    dfree(c, c->w.part);
+    dfree(c, c->tiles);
+    dfree(c, c->copies);
+    dfree(c, c->vf);
     delete c;
     return TRIM_OK;
 }
@@ -336,8 +394,37 @@ int trim_num_workers(trim_ctx* c, int algo, const trim_opts_t* o, int32_t* P) {
     if (algo != TRIM_AC3 && algo != TRIM_AC4 && algo != TRIM_AC6)
         return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
     int rc = check_opts(o);
-    if (rc) return rc;
+    if (rc || (rc = check_workers(c, algo, o))) return rc;
     *P = workers_for(c, algo, o);
+    return TRIM_OK;
+}
+
+int trim_max_workers(trim_ctx* c, int algo, int32_t* P) {
+    if (!c || !P) return fail(TRIM_E_INVAL, "trim_max_workers: NULL argument");
+    if (algo != TRIM_AC3 && algo != TRIM_AC4 && algo != TRIM_AC6)
+        return fail(TRIM_E_INVAL, "unknown algorithm %d", algo);
+    *P = max_workers(c, algo);
+    return TRIM_OK;
+}
+
+int trim_ctx_mem_used(trim_ctx* c, uint64_t* bytes) {
+    if (!c || !bytes) return fail(TRIM_E_INVAL, "trim_ctx_mem_used: NULL argument");
+    *bytes = c->mem_used;
+    return TRIM_OK;
+}
+
+int trim_ctx_status(trim_ctx* c, void* stream) {
+    if (!c) return fail(TRIM_E_INVAL, "trim_ctx_status: NULL context");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    int stalled = 0;
+    hipStream_t s = (hipStream_t)stream;
+    if ((e = hipMemcpyAsync(&stalled, c->w.ctr + trim::kStall, sizeof(int),
+                            hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "trim_ctx_status");
+    if (stalled)
+        return fail(TRIM_E_STALLED, "the last call exceeded its step budget and was abandoned");
     return TRIM_OK;
 }
 
@@ -356,7 +443,7 @@ int trim_csr(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
     if (algo == TRIM_AC4 && (!g->rrow_off || (g->m > 0 && !g->rcol)))
         return fail(TRIM_E_INVAL, "AC-4 needs the transposed graph (rrow_off, rcol)");
     int rc = check_opts(o);
-    if (rc) return rc;
+    if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n))) return rc;
@@ -389,7 +476,7 @@ int trim_csr_preset(trim_ctx* c, int algo, const trim_csr_t* g, const uint32_t* 
     if (algo == TRIM_AC4 && (!g->rrow_off || (g->m > 0 && !g->rcol)))
         return fail(TRIM_E_INVAL, "AC-4 needs the transposed graph (rrow_off, rcol)");
     int rc = check_opts(o);
-    if (rc) return rc;
+    if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n))) return rc;
@@ -420,7 +507,7 @@ int trim_scc(trim_ctx* c, const trim_csr_t* g, const trim_opts_t* o, int32_t* la
     if (g->m > 0 && (!g->col || !g->rcol)) return fail(TRIM_E_INVAL, "col or rcol is NULL");
     if (g->n > 0 && !label) return fail(TRIM_E_INVAL, "label is NULL");
     int rc = check_opts(o);
-    if (rc) return rc;
+    if (rc || (rc = check_workers(c, TRIM_AC6, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n)) || (rc = ensure2(c, g->n)) || (rc = ensure_scc(c, g->n))) return rc;
@@ -485,7 +572,7 @@ int trim_csr_two_sided(trim_ctx* c, int algo, const trim_csr_t* g, const trim_op
     if (g->n > 0 && !live_bitmap) return fail(TRIM_E_INVAL, "live_bitmap is NULL");
     if (!worker_edges) return fail(TRIM_E_INVAL, "worker_edges is NULL");
     int rc = check_opts(o);
-    if (rc) return rc;
+    if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n))) return rc;
@@ -513,7 +600,7 @@ int trim_implicit(trim_ctx* c, int algo, const trim_implicit_t* g, const trim_op
     if (!g->deg_table) return fail(TRIM_E_INVAL, "deg_table is NULL");
     if (!live_bitmap || !worker_edges) return fail(TRIM_E_INVAL, "NULL output");
     int rc = check_opts(o);
-    if (rc) return rc;
+    if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, (int64_t)1 << g->log2n))) return rc;
@@ -536,7 +623,7 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
         return fail(TRIM_E_INVAL, "batch sizes out of range");
     if (total_m > 0 && !col) return fail(TRIM_E_INVAL, "col is NULL");
     int rc = check_opts(o);
-    if (rc) return rc;
+    if (rc || (rc = check_workers(c, TRIM_AC6, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, total_n))) return rc;
@@ -608,10 +695,10 @@ int trim_mlp_prepare(trim_ctx* c, const trim_csr_t* g, int32_t* indeg, int32_t* 
     if (g->n <= trim::kXcdCopiesMaxN) {
         const long long need = (long long)trim::kXcdCopies * (g->n > 0 ? g->n : 1);
         if (need > c->cap_copies) {
-            (void)hipFree(c->copies);
+            dfree(c, c->copies);
             c->copies = nullptr;
             c->cap_copies = 0;
-            if (hipMalloc((void**)&c->copies, (size_t)need * 4) != hipSuccess) {
+            if (dmalloc(c, &c->copies, (size_t)need * 4) != hipSuccess) {
                 (void)hipGetLastError();
                 c->copies = nullptr;
                 return fail(TRIM_E_NOMEM, "cannot allocate in-degree copies for %d vertices",
@@ -661,10 +748,10 @@ int trim_mlp_score(trim_ctx* c, const trim_csr_t* g, const int32_t* indeg, const
         return fail(TRIM_E_INVAL, "trim_mlp_score: NULL argument");
     const long long need = 2LL * (g->n > 0 ? g->n : 1);   // float2 per vertex
     if (need > c->cap_vf) {
-        (void)hipFree(c->vf);
+        dfree(c, c->vf);
         c->vf = nullptr;
         c->cap_vf = 0;
-        if (hipMalloc((void**)&c->vf, (size_t)need * 4) != hipSuccess) {
+        if (dmalloc(c, &c->vf, (size_t)need * 4) != hipSuccess) {
             (void)hipGetLastError();
             c->vf = nullptr;
             return fail(TRIM_E_NOMEM, "cannot allocate vertex features for %d vertices", g->n);

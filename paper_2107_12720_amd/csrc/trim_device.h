@@ -153,6 +153,9 @@ constexpr int kMaxNaps = 4;               // idle back-off cap, in s_sleep(127) 
 // reserves slot t through qtail, so claims never retry.  `pending` counts
 // shared-queue items plus wavefronts that hold private work: it reaches zero
 // only when no work is left anywhere, and then waiting lanes give up.
+// Watchdog: a wavefront that has looped `budget` times gives up and raises
+// the stall word; every other wavefront sees it at its next idle poll (or
+// within 256 busy iterations) and exits too, so the kernel always drains.
 // Free slots hold kNone; a consumer resets the slot it took, so the buffer
 // is clean for the next call without a fill pass.  Outstanding tickets are at
 // most 64 per wavefront, which the queue's slack (kQueueSlots) covers.
@@ -166,6 +169,8 @@ struct WaveQueue {
     int* qhead;
     int* qtail;
     int* pending;
+    int* stall;         // watchdog word (nonzero: every wavefront exits)
+    int budget;         // loop iterations this wavefront may make
     int ticket;         // per lane: shared-queue slot this lane waits on, or -1
     int iter;           // wave-uniform iteration counter
     int share_mask;     // hand-off polls every share_mask + 1 busy iterations
@@ -176,6 +181,7 @@ struct WaveQueue {
     // elsewhere that wait for work (rebalance).
     __device__ __forceinline__ void init(uint32_t* ring, int* ring_tail, uint32_t* gq,
                                          int* ctr_qhead, int* ctr_qtail, int* ctr_pending,
+                                         int* ctr_stall, int step_budget,
                                          int share_every = kPollEvery) {
         lq = ring;
         tail_lds = ring_tail;
@@ -187,6 +193,8 @@ struct WaveQueue {
         qhead = ctr_qhead;
         qtail = ctr_qtail;
         pending = ctr_pending;
+        stall = ctr_stall;
+        budget = step_budget;
         ticket = -1;
         iter = 0;
         share_mask = share_every - 1;
@@ -319,11 +327,23 @@ struct WaveQueue {
         if (waiting > 0) spill_ring(min(occ / 2, waiting));
     }
 
-    // Returns false when the whole computation is finished.  Otherwise at
-    // least one lane of the wave holds an item.
+    // Wave-uniform: true once some wavefront raised the stall word.
+    __device__ __forceinline__ bool stalled() const {
+        int s = 0;
+        if (lane_id() == 0) s = ld_dev(stall);
+        return __shfl(s, 0) != 0;
+    }
+
+    // Returns false when the whole computation is finished (or abandoned by
+    // the watchdog).  Otherwise at least one lane of the wave holds an item.
     __device__ __forceinline__ bool acquire(uint32_t& item) {
         for (;;) {
             ++iter;
+            if (iter > budget) {   // watchdog: give up, and make everyone else stop
+                if (lane_id() == 0) st_dev(stall, 1);
+                return false;
+            }
+            if ((iter & 255) == 0 && stalled()) return false;
             refill(item);
             const uint64_t busy = ballot(item != kNone);
             const bool tickets = ballot(ticket >= 0) != 0;
@@ -345,7 +365,7 @@ struct WaveQueue {
                 naps = 1;
                 return true;
             }
-            if (ld_dev(pending) == 0) return false;
+            if (ld_dev(pending) == 0 || stalled()) return false;
             for (int i = 0; i < naps; ++i) __builtin_amdgcn_s_sleep(127);
             naps = naps * 2 > kMaxNaps ? kMaxNaps : naps * 2;
         }
@@ -376,6 +396,18 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t x, uint64_t* scratch) {
     for (int i = 0; i < nw; ++i) s += scratch[i];
     __syncthreads();
     return s;
+}
+
+// After a call abandoned by the watchdog, items and consumed tickets may be
+// left in the shared queue.  The output kernel that follows the persistent
+// one restores every slot to kNone (grid-stride), so the next call starts
+// from a clean queue; when nothing stalled it only reads the stall word.
+__device__ __forceinline__ void clear_queue_if_stalled(const int* ctr, uint32_t* q,
+                                                       long long qwords) {
+    if (!q || ld_dev(ctr + kStall) == 0) return;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < qwords;
+         i += (long long)gridDim.x * blockDim.x)
+        q[i] = kNone;
 }
 
 // ------------------------------------------------------------ graph views

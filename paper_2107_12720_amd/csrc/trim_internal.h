@@ -20,6 +20,7 @@ enum Ctr : int {
     kBarGen = 160,   // grid barrier generation
     kCursor = 192,   // next unclaimed vertex of the chunked sweep
     kCnt0 = 224,     // AC-3 live-list sizes, rotating over 3 slots
+    kStall = 240,    // watchdog: nonzero once a persistent kernel gave up (opts.budget)
     kCtrInts = 256
 };
 
@@ -32,6 +33,7 @@ struct Work {
                               //   AC-3 removal round
     int* d = nullptr;         // n int32: AC-3 cursor / two-sided AC-4 removal flags
     uint32_t* q = nullptr;    // 3n shared-queue slots, kNone between calls
+    long long qwords = 0;     // size of q in words (slack included)
     int* ctr = nullptr;       // kCtrInts control words
     uint64_t* wedges = nullptr;  // per-worker counts when the caller has none (batches)
     uint64_t* part = nullptr;    // per-block partial sums (kPartSlots x kPartStride)
@@ -41,13 +43,15 @@ struct Work2 {
     int* hin = nullptr;         // 2n int32: in-side list heads
     uint64_t* rec_in = nullptr; // n uint64: in-side (next, cursor) records
     uint32_t* q = nullptr;      // 8n shared-queue slots (+ kQueueSlots), kNone between calls
+    long long qwords = 0;       // size of q in words
 };
 constexpr int kMaxWorkers = 16384;
 // shared-queue slack beyond 3n slots: outstanding tickets, 64 per wavefront
 constexpr int kQueueSlots = 64 * 4 * kMaxWorkers;
 constexpr int kPartStride = 16384;   // >= workers, sweep blocks and pack blocks
 enum PartSlot : int { kPartCloses = 0, kPartJoins = 1, kPartVisited = 2, kPartSweep = 3,
-                      kPartLive = 4, kPartDeg = 5, kPartQhw = 6, kPartSlots = 7 };
+                      kPartLive = 4, kPartDeg = 5, kPartQhw = 6, kPartLiveEdges = 7,
+                      kPartSlots = 8 };
 
 // Optional per-kernel event timing (trim_ctx_set_timing).
 struct Timer {
@@ -75,6 +79,7 @@ struct LaunchCfg {
     int chunk = 4096;         // vertices per dynamically claimed sweep chunk
     int schedule = 0;         // TRIM_SCHED_* perturbation flags (tests)
     int workers = 0;          // persistent workgroups
+    int budget = TRIM_DEFAULT_BUDGET;   // watchdog step budget (opts.budget)
     int cus = 256;
     hipStream_t stream = nullptr;
     Timer* timer = nullptr;   // non-null: record per-kernel events
@@ -153,5 +158,9 @@ hipError_t order_launch(const int* row_off, const int* col, int n, long long m, 
 
 // ------------------------------------------------------------ validation
 hipError_t validate_csr(const trim_csr_t& g, const Work& w, hipStream_t s);
+// The calling thread's error message (trim_last_error) and the option checks
+// of trim_api.hip, for entry points defined in other files.
+int report_error(int code, const char* msg);
+int check_options(const trim_opts_t* o);
 
 }  // namespace trim

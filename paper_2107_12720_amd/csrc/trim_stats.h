@@ -12,9 +12,13 @@ namespace trim {
 namespace {   // kernels below get a private copy in every translation unit
 
 // Live bitmap (bit v%32 of word v/32) from a per-vertex predicate, by ballot.
+// Also restores the shared queue (q, qwords; NULL for AC-3) if the watchdog
+// abandoned the persistent kernel before it.
 template <class IsLive>
-__global__ void pack_bitmap(IsLive is_live, int n, uint32_t* bitmap, uint64_t* part) {
+__global__ void pack_bitmap(IsLive is_live, int n, uint32_t* bitmap, uint64_t* part,
+                            const int* ctr, uint32_t* q, long long qwords) {
     __shared__ uint64_t red[16];
+    clear_queue_if_stalled(ctr, q, qwords);
     const int nwords = (n + 31) >> 5;
     const int waves = (gridDim.x * blockDim.x) / kWave;
     const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -47,10 +51,11 @@ __device__ __forceinline__ uint64_t max_range(const uint64_t* a, int k, uint64_t
 
 // One block: reduce the partials into *stats.  n_sweep / n_prop = number of
 // sweep / propagation partials (0 when the algorithm has none); n_qhw =
-// number of ring high-water partials.
+// number of ring high-water partials; n_live_edges = number of live-check
+// partials (two-sided AC-6 only, else 0).
 __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack, int n_qhw,
                                const uint64_t* worker_edges, const uint64_t* part, const int* ctr,
-                               trim_stats_t* stats, int empty_rounds) {
+                               trim_stats_t* stats, int empty_rounds, int n_live_edges = 0) {
     __shared__ uint64_t red[16];
     const uint64_t qhw = max_range(part + kPartQhw * kPartStride, n_qhw, red);
     const uint64_t edges = sum_range(worker_edges, P, red);
@@ -60,6 +65,7 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
     const uint64_t joins = sum_range(part + kPartJoins * kPartStride, n_prop, red);
     const uint64_t visited = sum_range(part + kPartVisited * kPartStride, n_prop, red);
     const uint64_t degsum = sum_range(part + kPartDeg * kPartStride, n_sweep, red);
+    const uint64_t live_edges = sum_range(part + kPartLiveEdges * kPartStride, n_live_edges, red);
     if (threadIdx.x == 0) {
         stats->edges_total = edges;
         stats->n_live = live;
@@ -71,6 +77,8 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
         stats->visited = visited;
         stats->graph_edges = degsum;
         stats->q_highwater = qhw;
+        stats->edges_live = live_edges;
+        stats->stalled = ld_dev(ctr + kStall) != 0;
         if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
     }
 }

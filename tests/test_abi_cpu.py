@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     L = T.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert L.trim_version() == 1
+    assert L.trim_version() == T.ABI_VERSION == 2
 
 
 def test_null_arguments_rejected():
@@ -33,7 +33,10 @@ def test_null_arguments_rejected():
     L = T.lib()
     assert L.trim_csr(None, 6, None, None, None, None, None, None) == -1
     assert "NULL" in T.last_error()
-    assert L.trim_ctx_create(None, 0) == -1
+    assert L.trim_ctx_create(None, 0, 0) == -1
+    assert L.trim_ctx_status(None, None) == -1
+    assert L.trim_max_workers(None, 6, ctypes.byref(ctypes.c_int32())) == -1
+    assert L.trim_ctx_mem_used(None, ctypes.byref(ctypes.c_uint64())) == -1
     P = ctypes.c_int32()
     assert L.trim_num_workers(None, 6, None, ctypes.byref(P)) == -1
     assert L.trim_batch(None, 1, None, None, None, 0, 0, None, None, None, None, None, None) == -1
@@ -52,7 +55,7 @@ def test_no_gpu_context_fails_cleanly():
     if torch.cuda.is_available():
         pytest.skip("a GPU is present")
     h = ctypes.c_void_p()
-    rc = T.lib().trim_ctx_create(ctypes.byref(h), 0)
+    rc = T.lib().trim_ctx_create(ctypes.byref(h), 0, 0)
     assert rc in (-1, -3) and not h.value
     with pytest.raises(T.TrimError):
         T.Context(0)
@@ -61,5 +64,9 @@ def test_no_gpu_context_fails_cleanly():
 def test_opts_layout_matches_header():
     import paper_2107_12720_amd as T
     assert ctypes.sizeof(T.Opts) == 32
+    assert [f for f, _ in T.Opts._fields_] == ["block", "workers", "chunk", "validate", "graph",
+                                               "schedule", "budget", "reserved"]
+    # trim_stats_t: 16 uint64 words, the named fields first
+    assert T.STATS_WORDS == 16 and len(T.STATS_FIELDS) == 13
     assert ctypes.sizeof(T.CsrDesc) == 48
     assert ctypes.sizeof(T.ImplicitDesc) == 32

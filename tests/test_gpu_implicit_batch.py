@@ -57,7 +57,7 @@ def test_implicit_small(ctx, log2n, seed):
 
 
 def test_implicit_2_24(ctx):
-    g, r = implicit_case(ctx, 24, 0, algos=(6,))
+    g, r = implicit_case(ctx, 24, 0, algos=(6, 3))
     say(f"  2^24: m={g.m} live={r.n_live} alpha={r.alpha}")
 
 

@@ -1,7 +1,8 @@
-"""Full-size parity on the largest workloads: R-MAT scale 26, edge factor 16
-(about 1.07e9 edges) against the whole oracle, and the implicit graph with
-2^28 vertices on sampled vertices.  Generation and the sequential oracle take
-about a minute each, so these tests have their own time limits."""
+"""Full-size parity on the largest workloads, against the whole oracle:
+R-MAT scale 26, edge factor 16 (about 1.07e9 edges), and the implicit graph
+with 2^28 vertices (about 7.4e8 generated edges).  Generation and the
+sequential oracle take a minute or more each, so these tests have their own
+time limits."""
 import pytest
 
 import graphgen as gg
@@ -26,32 +27,44 @@ def test_config2_explicit_full(ctx):
     check_all(ctx, g, algos=(6,), name="rmat26")
 
 
-@pytest.mark.timeout(600)
-def test_implicit_2_28_samples(ctx):
-    """The implicit graph at its full size, 2^28 vertices, in the launch
-    configuration the benchmark times (default options).  The oracle's own
-    hash gives the degree and successors of 20,000 sampled vertices; each must
-    be live iff one of its successors is live (the fixed point, on both sides:
-    no removed vertex keeps a live successor, no live one lacks one)."""
+@pytest.mark.timeout(1200)
+def test_implicit_2_28_full(ctx):
+    """The implicit graph at its full size, 2^28 vertices (about 7.4e8
+    generated edges), in the launch configuration the benchmark times
+    (default options): the oracle materialises POST with its own SplitMix64
+    code and peels the whole graph; AC-6 must give its live bitmap bit for
+    bit and the traversed-edge total T6, AC-3 the bitmap, T3J and
+    alpha + 1 rounds."""
     import numpy as np
     import torch
     import oracle
     import paper_2107_12720_amd as T
     imp = gg.implicit(log2n=28, seed=0)
-    say("  implicit 2^28: AC-6 ...")
-    res = ctx.trim_implicit(T.AC6, 28, imp.seed, imp.zero_thr, T.to_device(imp.table))
-    torch.cuda.synchronize()
-    st = res.stats_dict()
-    bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[: imp.n]
-    assert st["n_live"] == int(bits.sum()) and st["n_live"] + st["n_dead"] == imp.n
-    assert st["edges_total"] >= st["n_live"]
-    rng = np.random.default_rng(28)
-    live_seen = dead_seen = 0
-    for v in rng.integers(0, imp.n, 20000):
-        d = oracle.implicit_deg(imp, int(v))
-        succ_live = any(bits[oracle.implicit_nbr(imp, int(v), i)] for i in range(d))
-        assert bool(bits[v]) == succ_live, int(v)
-        live_seen += int(bits[v])
-        dead_seen += 1 - int(bits[v])
-    say(f"  samples: {live_seen} live, {dead_seen} removed; n_live {st['n_live']}")
-    assert live_seen > 1000 and dead_seen > 1000
+    table = T.to_device(imp.table)
+    got = {}
+    for a in (6, 3):
+        say(f"  implicit 2^28: AC-{a} ...")
+        res = ctx.trim_implicit(a, 28, imp.seed, imp.zero_thr, table)
+        assert ctx.status() == 0
+        torch.cuda.synchronize()
+        got[a] = (res.bitmap_numpy().copy(), res.stats_dict(),
+                  int(res.worker_edges.sum().item()))
+        del res
+    say("  oracle: materialising POST ...")
+    ro, col = oracle.implicit_csr(imp)
+    g = gg.CSR(imp.n, ro, col)
+    say(f"  oracle: m={g.m}, peeling ...")
+    r = oracle.peel(g)
+    say(f"  oracle: alpha={r.alpha} n_live={r.n_live}, closed forms ...")
+    c = oracle.counts(g, r)
+    bm = oracle.bitmap(r.live)
+    say(f"  oracle: T6={c.T6} T3J={c.T3J}")
+    for a, want in ((6, c.T6), (3, c.T3J)):
+        bits, st, edges = got[a]
+        assert np.array_equal(bits[: bm.shape[0]], bm), f"AC-{a} bitmap differs at 2^28"
+        assert st["edges_total"] == edges == want, (a, st, want)
+        assert st["n_live"] == r.n_live, st
+        if a == 6:
+            assert st["graph_edges"] == g.m, st     # the sum of deg(v) generated on the GPU
+        else:
+            assert st["rounds"] == r.alpha + 1, st

@@ -71,6 +71,44 @@ def test_gradient_vs_fp64_reference(ctx):
             assert err <= 1e-2 * np.max(np.abs(b)) + 1e-7, (k, err, np.max(np.abs(b)))
 
 
+def test_adam_vs_fp64_reference(ctx):
+    """Three optimiser steps of trim_mlp_adam against the FP64 Adam of
+    oracle.mlp_ref (Kingma and Ba, Algorithm 1), element by element: FP32
+    master weights and both moments to FP32 rounding, the BF16 copy equal to
+    the round-to-nearest-even of the GPU's own FP32 weights, and the gradient
+    buffer (loss word included) cleared."""
+    import torch
+    import paper_2107_12720_amd as T
+    from paper_2107_12720_amd import learned
+    from oracle import mlp_ref
+    rng = np.random.default_rng(11)
+    n = T.MLP_PARAMS
+    p32 = learned.init_params(seed=5).astype(np.float32)
+    p32[256:288] = rng.normal(0, 0.1, 32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    P = dev(p32)
+    PB = torch.zeros(n, dtype=torch.int16, device="cuda")
+    M1 = torch.zeros(n, dtype=torch.float32, device="cuda")
+    M2 = torch.zeros(n, dtype=torch.float32, device="cuda")
+    lr, b1, b2, eps = [float(np.float32(x)) for x in (3e-3, 0.9, 0.999, 1e-8)]
+    rp, rm, rv = p32.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in (1, 2, 3):
+        g = (rng.normal(0, 1, n) * 10.0 ** rng.uniform(-4, 1, n)).astype(np.float32)
+        g[::97] = 0.0
+        G = dev(np.r_[g, np.float32(1.5)])         # the loss word follows the gradients
+        ctx.mlp_adam(P, PB, M1, M2, G, lr, step, beta1=b1, beta2=b2, eps=eps)
+        torch.cuda.synchronize()
+        rp, rm, rv = mlp_ref.adam_step(rp, rm, rv, g.astype(np.float64), lr, b1, b2, eps, step)
+        gp = P.cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(M1.cpu().numpy(), rm, rtol=1e-6, atol=1e-12)
+        np.testing.assert_allclose(M2.cpu().numpy(), rv, rtol=1e-6, atol=1e-16)
+        np.testing.assert_allclose(gp, rp, rtol=5e-7, atol=1e-6 * lr)
+        bits = PB.cpu().numpy().view(np.uint16)
+        assert np.array_equal(bits, mlp_ref.bf16_bits(P.cpu().numpy()))
+        assert not G.cpu().numpy().any()
+        say(f"  step {step}: max |dp| gpu-ref {np.max(np.abs(gp - rp)):.3e}")
+
+
 def test_scores_vs_fp64_reference(ctx):
     """Every edge's probability from the scoring kernel against the FP64
     forward pass on the same BF16 weights."""

@@ -4,8 +4,9 @@ Two-sided trimming also needs a live predecessor (the in-degree check over G^T
 of Section 4.1).  The live bitmap must equal oracle.peel2's bit for bit.
 AC-4: the edge total equals the closed form sum over removed v of
 (out-degree + in-degree).  AC-6: the live vertices' checks do not depend on
-the schedule (oracle.counts2 T6live), the removed vertices' checks lie between
-the oracle's bounds, and stats.closes counts the vertices removed after the
+the schedule and must equal oracle.counts2 T6live exactly (stats.edges_live,
+read off the final cursors), the removed vertices' checks lie between the
+oracle's bounds, and stats.closes counts the vertices removed after the
 start (those that had a successor and a predecessor).  AC-3: the total equals
 the oracle's closed form of the two-sided rounds (oracle.counts3two) and the
 rounds number alpha + 1 of two-sided peeling.
@@ -64,6 +65,8 @@ def check_two(ctx, g, algos=(6, 4, 3), opts=None, name="", dev=None, exp=None):
         elif a == 3:
             assert edges == t3 and st["rounds"] == rounds3 == r.alpha + 1, (edges, t3, st)
         else:
+            # the live vertices' checks, read off their final cursors, exactly
+            assert st["edges_live"] == c.T6live, (st, c)
             assert c.T6live + c.dead_lo <= edges <= c.T6live + c.dead_hi, (edges, c)
             assert st["closes"] == g.n - r.n_live - n_dead0, (st, n_dead0)
             assert st["graph_edges"] == g.m, st

@@ -321,9 +321,13 @@ def test_bitmap_layout(orc):
 
 
 def test_mlp_reference_finite_differences():
+    from oracle import mlp_ref
+    pin_finite_differences(mlp_ref)
+
+
+def pin_finite_differences(mlp_ref):
     """The FP64 reference's backward pass against central differences of its
     own forward pass (no BF16 rounding), on random features and weights."""
-    from oracle import mlp_ref
     rng = np.random.default_rng(7)
     p = rng.normal(0, 0.4, mlp_ref.NPARAM)
     X = rng.normal(0, 1, (24, 8))
@@ -342,6 +346,10 @@ def test_mlp_reference_finite_differences():
 
 def test_mlp_reference_bf16_rounding():
     from oracle import mlp_ref
+    pin_bf16_rounding(mlp_ref)
+
+
+def pin_bf16_rounding(mlp_ref):
     x = np.array([1.0, 1.00390625, 1.005, 3.14159265, -2.71828, 1e-3, 0.0])
     r = mlp_ref.bf16_round(x)
     # BF16 keeps 8 significant bits: 1 + 2^-8 is exactly halfway and rounds to even
@@ -350,9 +358,13 @@ def test_mlp_reference_bf16_rounding():
 
 
 def test_mlp_logits_hand_computed():
+    from oracle import mlp_ref
+    pin_logits_hand_computed(mlp_ref)
+
+
+def pin_logits_hand_computed(mlp_ref):
     """A network with one path 8 -> 1 -> 1 -> 1 computes 6 relu(x0) - 1 by
     hand: W1[0][0] = 1, W2[0][0] = 2, w3[0] = 3, b3 = -1, all else 0."""
-    from oracle import mlp_ref
     p = np.zeros(mlp_ref.NPARAM)
     p[0] = 1.0            # W1[0][0]
     p[288] = 2.0          # W2[0][0]
@@ -369,6 +381,74 @@ def test_mlp_logits_hand_computed():
     want = np.sum(np.log1p(np.exp(-s)) * y + np.log1p(np.exp(s)) * (1 - y))
     loss, _ = mlp_ref.loss_and_grad(p, X, y, w, bf16=False)
     assert abs(loss - want) < 1e-12
+
+
+def pin_features_hand_computed(mlp_ref, fin64):
+    """Feature rows of a 3-vertex graph worked out by hand: 0 -> [1, 2],
+    1 -> [2], 2 -> [0], so out-degrees (2, 1, 1) and in-degrees (1, 1, 2).
+    Edge u -> w at list position i has log1p(outdeg u), log1p(indeg u),
+    log1p(outdeg w), log1p(indeg w), log1p(outdeg u) - log1p(outdeg w) and
+    +-1 for bits 0, 1, 2 of SplitMix64(i).  The finalizer maps 0 to 0, so
+    position 0 gives -1, -1, -1; position 1 takes its bits from ``fin64``
+    (pinned on the published vector)."""
+    row_off = np.array([0, 2, 3, 4])
+    col = np.array([1, 2, 2, 0])
+    indeg = np.array([1, 1, 2])
+    X, src, dst = mlp_ref.features(row_off, col, indeg, [0, 1, 2, 3])
+    assert list(src) == [0, 0, 1, 2] and list(dst) == [1, 2, 2, 0]
+    l2, l3 = np.log(2.0), np.log(3.0)
+    h = fin64(1)
+    b = [1.0 if (h >> k) & 1 else -1.0 for k in range(3)]
+    want = np.array([
+        [l3, l2, l2, l2, l3 - l2, -1, -1, -1],     # 0 -> 1, position 0
+        [l3, l2, l2, l3, l3 - l2] + b,             # 0 -> 2, position 1
+        [l2, l2, l2, l3, 0.0, -1, -1, -1],         # 1 -> 2, position 0
+        [l2, l3, l3, l2, l2 - l3, -1, -1, -1],     # 2 -> 0, position 0
+    ])
+    # the features are computed in FP32, as on the GPU
+    np.testing.assert_allclose(X, want, rtol=2e-7, atol=2e-7)
+
+
+def pin_adam_first_step(mlp_ref):
+    """At step 1 from zero moments, m_hat = g and v_hat = g^2, so every
+    parameter moves by exactly lr * g / (|g| + eps)."""
+    g = np.array([0.5, -2.0, 0.0, 1e-9, 3e4])
+    p0 = np.array([1.0, -1.0, 0.25, 0.0, 2.0])
+    lr, eps = 0.1, 1e-8
+    p, m, v = mlp_ref.adam_step(p0, np.zeros(5), np.zeros(5), g, lr, 0.9, 0.999, eps, 1)
+    np.testing.assert_allclose(p, p0 - lr * g / (np.abs(g) + eps), rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-14)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-14)
+
+
+def pin_adam_two_steps_by_hand(mlp_ref):
+    """Gradients +1 then -1 with beta1 = 0.9, beta2 = 0.999: after step 1,
+    m = 0.1, v = 0.001 and the parameter moves down by lr / (1 + eps).  Step 2
+    gives m = 0.09 - 0.1 = -0.01, v = 0.000999 + 0.001 = 0.001999, so
+    m_hat = -0.01 / 0.19, v_hat = 0.001999 / 0.001999 = 1, and the parameter
+    moves up by lr * (0.01 / 0.19) / (1 + eps)."""
+    lr, eps = 0.05, 1e-8
+    p, m, v = mlp_ref.adam_step([0.0], [0.0], [0.0], [1.0], lr, 0.9, 0.999, eps, 1)
+    assert abs(p[0] + lr / (1 + eps)) < 1e-15 and abs(m[0] - 0.1) < 1e-15
+    p, m, v = mlp_ref.adam_step(p, m, v, [-1.0], lr, 0.9, 0.999, eps, 2)
+    assert abs(m[0] + 0.01) < 1e-15 and abs(v[0] - 0.001999) < 1e-15
+    want = -lr / (1 + eps) + lr * (0.01 / 0.19) / (1 + eps)
+    assert abs(p[0] - want) < 1e-14
+
+
+def test_mlp_features_hand_computed(orc):
+    from oracle import mlp_ref
+    pin_features_hand_computed(mlp_ref, orc.fin64)
+
+
+def test_mlp_adam_first_step():
+    from oracle import mlp_ref
+    pin_adam_first_step(mlp_ref)
+
+
+def test_mlp_adam_two_steps_by_hand():
+    from oracle import mlp_ref
+    pin_adam_two_steps_by_hand(mlp_ref)
 
 
 # --------------------------------------------------------- two-sided trimming
