@@ -73,16 +73,23 @@ def test_gradient_vs_fp64_reference(ctx):
 
 def test_adam_vs_fp64_reference(ctx):
     """Three optimiser steps of trim_mlp_adam against the FP64 Adam of
-    oracle.mlp_ref (Kingma and Ba, Algorithm 1), element by element: FP32
-    master weights and both moments to FP32 rounding, the BF16 copy equal to
+    oracle.mlp_ref (Kingma and Ba, Algorithm 1), element by element, within
+    a first-order FP32 error budget carried through the steps: each FP32
+    operation rounds with relative error at most u = 2^-24, so a moment
+    m = b1 m' + (1 - b1) g is off by at most 3u (b1 |m'| + (1 - b1) |g|) plus
+    b1 times the previous error (the two terms may cancel, so the bound is on
+    the terms, not on m); the weight step lr m_hat / (sqrt(v_hat) + eps)
+    inherits the moments' errors through its partial derivatives, plus 6u of
+    its own, and the new weight rounds once more.  The BF16 copy must equal
     the round-to-nearest-even of the GPU's own FP32 weights, and the gradient
-    buffer (loss word included) cleared."""
+    buffer (loss word included) must be cleared."""
     import torch
     import paper_2107_12720_amd as T
     from paper_2107_12720_amd import learned
     from oracle import mlp_ref
     rng = np.random.default_rng(11)
     n = T.MLP_PARAMS
+    u = 2.0 ** -24
     p32 = learned.init_params(seed=5).astype(np.float32)
     p32[256:288] = rng.normal(0, 0.1, 32)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
@@ -92,21 +99,33 @@ def test_adam_vs_fp64_reference(ctx):
     M2 = torch.zeros(n, dtype=torch.float32, device="cuda")
     lr, b1, b2, eps = [float(np.float32(x)) for x in (3e-3, 0.9, 0.999, 1e-8)]
     rp, rm, rv = p32.astype(np.float64), np.zeros(n), np.zeros(n)
+    em, ev, ep = np.zeros(n), np.zeros(n), np.zeros(n)
     for step in (1, 2, 3):
         g = (rng.normal(0, 1, n) * 10.0 ** rng.uniform(-4, 1, n)).astype(np.float32)
         g[::97] = 0.0
         G = dev(np.r_[g, np.float32(1.5)])         # the loss word follows the gradients
         ctx.mlp_adam(P, PB, M1, M2, G, lr, step, beta1=b1, beta2=b2, eps=eps)
         torch.cuda.synchronize()
-        rp, rm, rv = mlp_ref.adam_step(rp, rm, rv, g.astype(np.float64), lr, b1, b2, eps, step)
-        gp = P.cpu().numpy().astype(np.float64)
-        np.testing.assert_allclose(M1.cpu().numpy(), rm, rtol=1e-6, atol=1e-12)
-        np.testing.assert_allclose(M2.cpu().numpy(), rv, rtol=1e-6, atol=1e-16)
-        np.testing.assert_allclose(gp, rp, rtol=5e-7, atol=1e-6 * lr)
+        g64 = g.astype(np.float64)
+        em = b1 * em + 3 * u * (b1 * np.abs(rm) + (1 - b1) * np.abs(g64))
+        ev = b2 * ev + 4 * u * (b2 * rv + (1 - b2) * g64 * g64)
+        rp, rm, rv = mlp_ref.adam_step(rp, rm, rv, g64, lr, b1, b2, eps, step)
+        c1, c2 = 1 / (1 - b1 ** step), 1 / (1 - b2 ** step)
+        den = np.sqrt(rv * c2) + eps
+        step_ = lr * rm * c1 / den
+        d_dm = lr * c1 / den
+        d_dv = 0.5 * lr * np.abs(rm) * c1 * np.sqrt(c2) / (den * den * np.sqrt(np.maximum(rv, 1e-300)))
+        ep = ep + d_dm * em + d_dv * ev + 6 * u * np.abs(step_) + u * np.abs(rp)
+        gm, gv, gp = (t.cpu().numpy().astype(np.float64) for t in (M1, M2, P))
+        for name, got, ref, bud in (("m", gm, rm, em), ("v", gv, rv, ev), ("p", gp, rp, ep)):
+            bad = np.abs(got - ref) > bud * 1.01 + 1e-30
+            assert not bad.any(), (step, name, np.flatnonzero(bad)[:5], (got - ref)[bad][:5],
+                                   bud[bad][:5])
         bits = PB.cpu().numpy().view(np.uint16)
         assert np.array_equal(bits, mlp_ref.bf16_bits(P.cpu().numpy()))
         assert not G.cpu().numpy().any()
-        say(f"  step {step}: max |dp| gpu-ref {np.max(np.abs(gp - rp)):.3e}")
+        say(f"  step {step}: max |dp| gpu-ref {np.max(np.abs(gp - rp)):.3e}, "
+            f"max budget {np.max(ep):.3e}")
 
 
 def test_scores_vs_fp64_reference(ctx):

@@ -151,7 +151,7 @@ def test_schedule_invariance(ctx):
     exp = expected_two(g)
     dev = upload(g, with_reverse=True)
     for block, chunk, workers in ((64, 64, 1), (256, 4096, 7), (1024, 65536, 0), (128, 1, 3),
-                                  (512, 300, 2048)):
+                                  (512, 300, 512)):
         opts = T.make_opts(block=block, chunk=chunk, workers=workers)
         check_two(ctx, g, opts=opts, dev=dev, exp=exp,
                   name=f"block={block} chunk={chunk} workers={workers}")
