@@ -354,6 +354,26 @@ int trim_batch(trim_ctx *ctx, int32_t G, const int64_t *vbase, const int32_t *ro
                trim_stats_t *stats, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, hosts that forbid hipMalloc): AC-6 on an
+ * explicit graph exactly as trim_csr with TRIM_AC6, with no context and no
+ * allocation of any kind.  The working memory is a fixed array inside the
+ * library, one copy per GPU (about 30 MB, held until the process ends), on
+ * the calling thread's current device.  The caller passes inputs and outputs
+ * as for trim_csr; worker_edges needs opts.workers entries, or
+ * TRIM_NOALLOC_WORKERS when opts.workers is 0.  g->rrow_off / g->rcol are
+ * ignored.  TRIM_E_INVAL for n > TRIM_NOALLOC_MAX_N, opts.workers >
+ * TRIM_NOALLOC_WORKERS or opts.graph != 0.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (two streams, two threads) race
+ * and must be serialised by the caller.  The watchdog (opts.budget) works as
+ * for trim_csr; a stall shows in stats.stalled (no context to query).
+ */
+#define TRIM_NOALLOC_MAX_N (1 << 20)
+#define TRIM_NOALLOC_WORKERS 512
+int trim_csr_noalloc(const trim_csr_t *g, const trim_opts_t *opts, uint32_t *live_bitmap,
+                     uint64_t *worker_edges, trim_stats_t *stats, void *stream);
+
+/*
  * Learned successor order (AC-6 checks successors in list order; a live
  * vertex costs the index of its first live successor + 1 checks, Section 6.1
  * and the edge_index of Section 8).  A small network scores each edge u -> w

@@ -35,7 +35,8 @@ EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destr
            "trim_num_workers", "trim_csr", "trim_csr_preset", "trim_csr_two_sided",
            "trim_scc", "trim_size2", "trim_implicit", "trim_batch",
            "trim_ctx_set_timing", "trim_ctx_kernel_times", "trim_mlp_prepare", "trim_mlp_grad",
-           "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key")
+           "trim_mlp_adam", "trim_mlp_score", "trim_edge_keys", "trim_order_by_key",
+           "trim_csr_noalloc")
 MLP_PARAMS = 1377
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
                 "joins", "visited", "graph_edges", "q_highwater", "edges_live", "stalled")
@@ -124,12 +125,13 @@ def lib():
         L.trim_mlp_score.argtypes = [vp, csr_p, vp, vp, vp, vp, vp]
         L.trim_edge_keys.argtypes = [vp, csr_p, i32, ctypes.c_uint64, vp, vp]
         L.trim_order_by_key.argtypes = [vp, csr_p, vp, f32, f32, vp, vp]
+        L.trim_csr_noalloc.argtypes = [csr_p, ctypes.POINTER(Opts), vp, vp, vp, vp]
         for f in ("trim_ctx_create", "trim_ctx_destroy", "trim_ctx_mem_used", "trim_ctx_status",
                   "trim_max_workers", "trim_num_workers", "trim_csr",
                   "trim_csr_preset", "trim_csr_two_sided", "trim_scc", "trim_size2",
                   "trim_implicit", "trim_batch", "trim_ctx_set_timing", "trim_ctx_kernel_times",
                   "trim_mlp_prepare", "trim_mlp_grad", "trim_mlp_adam", "trim_mlp_score",
-                  "trim_edge_keys", "trim_order_by_key"):
+                  "trim_edge_keys", "trim_order_by_key", "trim_csr_noalloc"):
             getattr(L, f).restype = ctypes.c_int
         if L.trim_version() != ABI_VERSION:
             raise TrimError(-3, f"{LIB_PATH} has ABI {L.trim_version()}, expected "
@@ -429,6 +431,37 @@ class Context:
                                 ctypes.c_void_p(ge.data_ptr()), ctypes.c_void_p(st.data_ptr()),
                                 _stream_handle(stream, self.device)))
         return TrimResult(lb, ge, st)
+
+
+NOALLOC_MAX_N = 1 << 20
+NOALLOC_WORKERS = 512
+
+
+def trim_csr_noalloc(n, row_off, col, *, live_bitmap=None, worker_edges=None, stats=None,
+                     opts: Opts | None = None, stream=None, device: int = 0) -> TrimResult:
+    """AC-6 through trim_csr_noalloc: no context, working memory in the
+    library's fixed per-GPU array (n <= NOALLOC_MAX_N).  Outputs that are not
+    given are allocated here by torch, before the call."""
+    import torch
+    opts = opts or Opts()
+    m = int(col.numel()) if col is not None else 0
+    d = CsrDesc(int(n), m, _dev_ptr(row_off, torch.int32, "row_off"),
+                _dev_ptr(col, torch.int32, "col") if m else None, None, None)
+    dev = torch.device("cuda", device)
+    P = opts.workers if opts.workers > 0 else NOALLOC_WORKERS
+    if live_bitmap is None:
+        live_bitmap = torch.empty(max((int(n) + 31) // 32, 1), dtype=torch.int32, device=dev)
+    if worker_edges is None:
+        worker_edges = torch.empty(max(P, 1), dtype=torch.int64, device=dev)
+    if stats is None:
+        stats = torch.empty(STATS_WORDS, dtype=torch.int64, device=dev)
+    with torch.cuda.device(device):
+        _check(lib().trim_csr_noalloc(ctypes.byref(d), ctypes.byref(opts),
+                                      ctypes.c_void_p(live_bitmap.data_ptr()),
+                                      ctypes.c_void_p(worker_edges.data_ptr()),
+                                      ctypes.c_void_p(stats.data_ptr()),
+                                      _stream_handle(stream, device)))
+    return TrimResult(live_bitmap, worker_edges, stats)
 
 
 class DeviceGraph:
