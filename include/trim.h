@@ -113,8 +113,20 @@ typedef struct {
                            are invalid and trim_ctx_status() returns TRIM_E_STALLED.
                            0 = TRIM_DEFAULT_BUDGET (a run that legitimately needs more
                            than that is longer than any workload here by over 10x). */
-    int32_t reserved;
+    int32_t flags;      /* TRIM_FLAG_* bits (0 = defaults) */
 } trim_opts_t;
+
+/*
+ * AC-6 (trim_csr, trim_csr_preset, trim_implicit, trim_batch,
+ * trim_csr_noalloc): after the first sweep, a vertex whose support is its last
+ * successor is removed exactly when that support is, so these links form a
+ * forest whose trees fall with their roots.  By default every tree whose root
+ * the first sweep already removed is taken out at once, by pointer jumping in
+ * O(log depth) rounds, before the propagation starts; the successor checks
+ * are the same.  TRIM_FLAG_STEPWISE instead propagates those removals one at a
+ * time through the support lists, as the paper's waiting sets do.
+ */
+#define TRIM_FLAG_STEPWISE 1
 
 #define TRIM_DEFAULT_BUDGET (1 << 22)
 
@@ -130,8 +142,8 @@ typedef struct {
     uint64_t rounds;       /* AC-3: sweeps run (alpha + 1); 0 otherwise */
     uint64_t queued;       /* AC-6/AC-4: work items that went through the shared queue */
     uint64_t edges_sweep;  /* AC-6: successor checks made by the first sweep */
-    uint64_t closes;       /* AC-6: removed vertices whose support lists were closed
-                              after the first sweep */
+    uint64_t closes;       /* AC-6: removed vertices whose support lists the propagation
+                              closed (the forest collapse counts in `forest`) */
     uint64_t joins;        /* AC-6: support-list joins after the first sweep */
     uint64_t visited;      /* AC-6: support-list members handed back */
     uint64_t graph_edges;  /* AC-6: sum of out-degrees as generated or read (m) */
@@ -144,7 +156,12 @@ typedef struct {
                               fl_out(v) + 1 + fl_in(v) + 1, schedule independent); 0 for
                               the other calls */
     uint64_t stalled;      /* 1 if the watchdog abandoned the call (see opts.budget) */
-    uint64_t reserved[4];
+    uint64_t forest;       /* AC-6: vertices removed by the forest collapse after the first
+                              sweep (the vertices it left without a live successor, plus the
+                              members of their last-successor trees); 0 with
+                              TRIM_FLAG_STEPWISE */
+    uint64_t jump_rounds;  /* AC-6: pointer-jumping rounds the forest collapse ran */
+    uint64_t reserved[2];
 } trim_stats_t;
 
 /*
@@ -358,7 +375,7 @@ int trim_batch(trim_ctx *ctx, int32_t G, const int64_t *vbase, const int32_t *ro
  * capture, tight serving loops, hosts that forbid hipMalloc): AC-6 on an
  * explicit graph exactly as trim_csr with TRIM_AC6, with no context and no
  * allocation of any kind.  The working memory is a fixed array inside the
- * library, one copy per GPU (about 30 MB, held until the process ends), on
+ * library, one copy per GPU (about 42 MB, held until the process ends), on
  * the calling thread's current device.  The caller passes inputs and outputs
  * as for trim_csr; worker_edges needs opts.workers entries, or
  * TRIM_NOALLOC_WORKERS when opts.workers is 0.  g->rrow_off / g->rcol are

@@ -39,7 +39,8 @@ EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destr
            "trim_csr_noalloc")
 MLP_PARAMS = 1377
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
-                "joins", "visited", "graph_edges", "q_highwater", "edges_live", "stalled")
+                "joins", "visited", "graph_edges", "q_highwater", "edges_live", "stalled",
+                "forest", "jump_rounds")
 STATS_WORDS = 16
 ABI_VERSION = 2
 DEFAULT_BUDGET = 1 << 22
@@ -55,7 +56,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("budget", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("budget", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class CsrDesc(ctypes.Structure):
@@ -153,10 +154,13 @@ SCHED_REVERSE = 1
 SCHED_JITTER = 2
 
 
+FLAG_STEPWISE = 1
+
+
 def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False, schedule=0,
-              budget=0) -> Opts:
+              budget=0, flags=0) -> Opts:
     return Opts(block, workers, chunk, int(bool(validate)), int(bool(graph)), int(schedule),
-                int(budget), 0)
+                int(budget), int(flags))
 
 
 def _dev_ptr(t, dtype, name, allow_none=False):

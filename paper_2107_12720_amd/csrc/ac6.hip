@@ -41,6 +41,19 @@
 //                  its sinks bit is clear, and joining is a plain exchange (no
 //                  CAS retry storms on hub vertices).  Vertices without a live
 //                  successor are queued as close items.
+//   ac6_jump       (forest collapse, the default) after the sweep, a vertex
+//                  whose support is its last successor is removed exactly
+//                  when that support is: these links form a forest, and every
+//                  tree whose root the sweep left without a live successor is
+//                  removed at once.  Pointer jumping over the tree members
+//                  (one round per launch, in place, O(log depth) rounds)
+//                  finds each member's root; a member whose root is removed
+//                  is removed (both heads exchanged with kDead) and its S_more
+//                  list handed to the propagation.  Its S_last list holds only
+//                  members of its own tree, removed by the same rounds, so it
+//                  is not walked.  No successor is checked here.  A round in
+//                  which no member found its root leaves only members whose
+//                  links run into a cycle: they stay live, and the rounds stop.
 //   ac6_propagate  persistent workers (the paper's Trim_p) run close and walk
 //                  items (see below) through per-wavefront LDS rings
 //                  (WaveQueue); a lane follows an S_last chain for up to
@@ -50,6 +63,8 @@
 #include "trim_stats.h"
 #include "trim_internal.h"
 #include "ac6_support.h"
+#include "block_append.h"
+#include "grid_barrier.h"
 
 namespace trim {
 
@@ -115,11 +130,20 @@ __global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, const uint32
 }
 
 constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-queue append
+// Forest-collapse list entries: a vertex id, with this bit for the vertices the
+// sweep left without a live successor (the removed roots).
+constexpr uint32_t kRootBit = 0x80000000u;
 
+// With jp (the forest collapse): jp[v] = the target of v's support if that is
+// v's last successor (v is a tree member, listed in jlist), v itself if v has
+// successors left after its support (a root whose fate is open), and ~v (< 0)
+// if v has no live successor (a removed root, listed with kRootBit).  Without
+// jp, the vertices without a live successor are queued as close items.
 template <class View>
 __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* sinks,
                           const uint32_t* preset, uint64_t* rec, uint32_t* q, int* ctr,
-                          uint64_t* worker_edges, int P, uint64_t* part, int sched) {
+                          uint64_t* worker_edges, int P, uint64_t* part, int sched, int* jp,
+                          uint32_t* jlist) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t cas[kCasBuf];
     __shared__ int s_chunk, s_ncas, s_base;
@@ -127,17 +151,23 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
     Stage<View>::apply(g, lds);
     if (threadIdx.x == 0) s_ncas = 0;
     uint64_t edges = 0, degsum = 0;
-    // move the buffered casualties to the shared queue with one reservation
+    // move the buffered entries to the shared queue (close items) or to the
+    // forest list, with one reservation
     auto flush = [&]() {
         __syncthreads();
         const int k = s_ncas;
         if (k > 0) {
             if (threadIdx.x == 0) {
-                add_dev(ctr + kPending, k);
-                s_base = add_dev(ctr + kQTail, k);
+                if (jp) {
+                    s_base = add_dev(ctr + kJCnt0, k);
+                } else {
+                    add_dev(ctr + kPending, k);
+                    s_base = add_dev(ctr + kQTail, k);
+                }
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < k; i += blockDim.x) q[s_base + i] = cas[i];
+            uint32_t* dst = jp ? jlist : q;
+            for (int i = threadIdx.x; i < k; i += blockDim.x) dst[s_base + i] = cas[i];
             __syncthreads();
             if (threadIdx.x == 0) s_ncas = 0;
         }
@@ -155,7 +185,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
         const int ce = cb + chunk < n ? cb + chunk : n;
         for (int base = cb; base < ce; base += blockDim.x) {
             const int v = base + threadIdx.x;
-            bool casualty = false;
+            bool casualty = false, member = false;
             uint64_t mine = 0;
             int gi = 0;
             if (v < ce) {
@@ -174,19 +204,27 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
                         const int old = xchg_dev(head + 2 * w + (p + 1 == e), v);
                         rec[v] = pack_rec(old, p);
                         mine = (uint64_t)(p - b + 1);
+                        if (jp) {
+                            member = p + 1 == e;
+                            jp[v] = member ? w : v;
+                        }
                     } else {
                         casualty = true;
+                        if (jp) jp[v] = ~v;
                         mine = (uint64_t)(e - b);
                     }
                 }
             }
             edges += mine;
-            const uint64_t mask = ballot(casualty);
+            const bool put = casualty || member;
+            const uint64_t mask = ballot(put);
             if (mask) {
                 int wbase = 0;
                 if (lane_id() == 0) wbase = atomicAdd(&s_ncas, popc(mask));
                 wbase = __shfl(wbase, 0);
-                if (casualty) cas[wbase + popc(mask & lanes_below())] = make_item(0, v);
+                if (put)
+                    cas[wbase + popc(mask & lanes_below())] =
+                        jp ? ((uint32_t)v | (casualty ? kRootBit : 0u)) : make_item(0, v);
             }
             __syncthreads();
             if (s_ncas > kCasBuf - (int)blockDim.x) flush();
@@ -206,10 +244,20 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
 //   CLOSE(x)       x found no live successor: close both of its lists;
 //   CLOSE_LAST(x)  the same for a member x of some S_last(p): x is removed with
 //                  p, and x's record links to the next member of S_last(p);
-//   WMORE(x)       x is a member of a closed S_more list: resume its DoPost
-//                  and walk on to the next member.
-enum : uint32_t { kClose = 0, kCloseLast = 1, kWalkMore = 2 };
+//   WALK(x)        x heads (the rest of) a closed S_more list: follow the links
+//                  and hand each member out as a RESCAN item, up to kWalk
+//                  members in a row.  The walk only loads links (one memory
+//                  round trip per member), so a long list -- a hub's -- is not
+//                  walked at the pace of its members' rescans;
+//   RESCAN(x)      x was in a closed S_more list: resume its DoPost after its
+//                  old support (edge_index, Section 8).
+// RESCAN items go to the wave-local ring: the other lanes of the walking
+// wave rescan while the walker goes on, and the shared queue never holds
+// them (it has room for three items per vertex; hand-backs are only bounded
+// by the number of joins).  A full local ring stops the walk until it drains.
+enum : uint32_t { kClose = 0, kCloseLast = 1, kWalkMore = 2, kRescan = 3 };
 constexpr int kHops = 256;   // S_last chain steps one item may take in a row
+constexpr int kWalk = 32;    // S_more members one WALK item hands out in a row
 
 template <class View>
 __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t* rec, uint32_t* q,
@@ -218,12 +266,14 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
+    __shared__ uint32_t local_rings[256 / kWave][kLocalP];
+    __shared__ int local_tail[256 / kWave];
     __shared__ uint64_t red[16];
     Stage<View>::apply(g, lds);
     WaveQueue wq;
     const int wv = threadIdx.x / kWave;
     wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending,
-            ctr + kStall, budget, ShareEvery<View>::value);
+            ctr + kStall, budget, ShareEvery<View>::value, local_rings[wv], &local_tail[wv]);
     uint32_t item = kNone;
     uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
     while (wq.acquire(item)) {
@@ -237,24 +287,45 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
         if (item != kNone) {
             const int x = item_vertex(item);
             const uint32_t kind = item_kind(item);
+            int rx = -1, cont = -1;   // a member rescanned by this lane now; the rest of its list
             if (kind == kWalkMore) {
-                // read x's list link before x re-joins (which rewrites rec[x])
-                const uint64_t r = ld_dev(rec + x);
-                const int nx = rec_next(r);
-                visited += 1;
-                if (sched & TRIM_SCHED_JITTER) jitter_nap(x);
-                if (resume(g, x, rec_cursor(r) + 1, head, rec, edges, sched)) {
-                    joins += 1;
-                    if (nx >= 0) keep = make_item(kWalkMore, nx);
-                } else {
-                    if (nx >= 0) wq.push1(make_item(kWalkMore, nx));
-                    close_now = true;
-                    cx = x;
+                // Each link is read before its member is handed out (a rescan
+                // that re-joins rewrites the member's record).  The last
+                // member of a burst, and any member the full local ring does
+                // not take, is rescanned by the walker itself, so every
+                // iteration makes progress.
+                int y = x;
+                for (int h = 0;; ++h) {
+                    const int ny = ld_dev(rec_link(rec, y));
+                    visited += 1;
+                    if (h + 1 < kWalk && wq.push_local(make_item(kRescan, y))) {
+                        if (ny < 0) break;
+                        y = ny;
+                        continue;
+                    }
+                    rx = y;
+                    cont = ny;
+                    break;
                 }
+            } else if (kind == kRescan) {
+                rx = x;
             } else {
                 close_now = true;
                 cx = x;
                 member = kind == kCloseLast;
+            }
+            if (rx >= 0) {
+                // rx is in no list until it joins again: its record is stable
+                const uint64_t r = ld_dev(rec + rx);
+                if (sched & TRIM_SCHED_JITTER) jitter_nap(rx);
+                if (resume(g, rx, rec_cursor(r) + 1, head, rec, edges, sched)) {
+                    joins += 1;
+                    if (cont >= 0) keep = make_item(kWalkMore, cont);
+                } else {
+                    if (cont >= 0) wq.push1(make_item(kWalkMore, cont));
+                    close_now = true;
+                    cx = rx;
+                }
             }
         }
         if (close_now) {
@@ -309,6 +380,124 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
         part[kPartVisited * kPartStride + blockIdx.x] = visited;
         part[kPartQhw * kPartStride + blockIdx.x] = (uint64_t)qhw;
     }
+}
+
+// The forest collapse (see the file comment) in one launch of at most two
+// workgroups per CU, all resident at once: round r reads the list of round r
+// (sizes rotate over three counters, like the AC-3 lists), resolves what it
+// can, appends the members still without a root to the list of round r + 1,
+// and a grid barrier ends the round.  The links are updated in place; every
+// value a later round reads (links, lists) is written and read with
+// device-coherent accesses, so it is visible across XCDs after the barrier.
+// Stop rule: the unresolved member nearest its root always resolves in the
+// next round (its link points at a resolved vertex or a root), so a round
+// that resolves nothing leaves only members whose links run into a cycle.
+constexpr int kJumpUnroll = 8;
+constexpr int kJumpPerCu = 2;   // resident workgroups per CU of the jump launch
+
+template <class View>
+__global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint32_t* l0,
+                                                uint32_t* l1, uint32_t* q, int* ctr,
+                                                int max_rounds, int budget) {
+    __shared__ uint32_t buf[kCasBuf];   // S_more heads of removed vertices: walk items
+    __shared__ int s_nbuf, s_base, s_wave[256 / kWave];
+    __shared__ uint64_t red[16];
+    if (threadIdx.x == 0) s_nbuf = 0;
+    __syncthreads();
+    auto flush = [&]() {
+        __syncthreads();
+        const int k = s_nbuf;
+        if (k > 0) {
+            if (threadIdx.x == 0) {
+                add_dev(ctr + kPending, k);
+                s_base = add_dev(ctr + kQTail, k);
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < k; i += blockDim.x) q[s_base + i] = buf[i];
+            __syncthreads();
+            if (threadIdx.x == 0) s_nbuf = 0;
+        }
+        __syncthreads();
+    };
+    uint64_t killed = 0;
+    for (int r = 0; r < max_rounds; ++r) {
+        const uint32_t* lin = (r & 1) ? l1 : l0;
+        uint32_t* lout = (r & 1) ? l0 : l1;
+        const int cnt = ld_dev(ctr + kJCnt0 + r % 3);
+        if (cnt == 0 || (r > 0 && ld_dev(ctr + kJDone0 + (r - 1) % 3) == 0)) break;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st_dev(ctr + kJCnt0 + (r + 2) % 3, 0);
+            st_dev(ctr + kJDone0 + (r + 1) % 3, 0);
+            add_dev(ctr + kJRounds, 1);
+        }
+        uint64_t done = 0;
+        const int step = gridDim.x * blockDim.x * kJumpUnroll;
+        for (int base = blockIdx.x * blockDim.x * kJumpUnroll; base < cnt; base += step) {
+            int v[kJumpUnroll], x[kJumpUnroll], y[kJumpUnroll];
+            uint32_t ent[kJumpUnroll];
+#pragma unroll
+            for (int k = 0; k < kJumpUnroll; ++k) {
+                const int i = base + k * blockDim.x + threadIdx.x;
+                ent[k] = i < cnt ? (uint32_t)ld_dev((const int*)lin + i) : kNone;
+            }
+#pragma unroll
+            for (int k = 0; k < kJumpUnroll; ++k) {
+                v[k] = (int)(ent[k] & ~kRootBit);
+                x[k] = (ent[k] != kNone && !(ent[k] & kRootBit)) ? ld_dev(jp + v[k]) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < kJumpUnroll; ++k) y[k] = x[k] >= 0 ? ld_dev(jp + x[k]) : 0;
+            int c = 0;
+            uint32_t item[kJumpUnroll];
+            bool keep[kJumpUnroll];
+#pragma unroll
+            for (int k = 0; k < kJumpUnroll; ++k) {
+                item[k] = kNone;
+                keep[k] = false;
+                bool kill = false;
+                if (ent[k] == kNone) {
+                    // past the end of the list
+                } else if (ent[k] & kRootBit) {
+                    kill = true;                 // a removed root
+                } else if (y[k] < 0) {           // the ancestor's root is removed, so v's is
+                    st_dev(jp + v[k], y[k]);
+                    kill = true;
+                    done += 1;
+                } else if (y[k] == x[k]) {       // the ancestor is a root whose fate is open
+                    done += 1;
+                } else {
+                    st_dev(jp + v[k], y[k]);
+                    keep[k] = true;
+                    c += 1;
+                }
+                if (kill) {
+                    const int2 ab = xchg2_dev(head + 2 * v[k], kDead, kDead);
+                    if (ab.x >= 0) item[k] = make_item(kWalkMore, ab.x);
+                    killed += 1;
+                }
+            }
+            int slot = block_append_base(c, ctr + kJCnt0 + (r + 1) % 3, nullptr, s_wave, &s_base);
+#pragma unroll
+            for (int k = 0; k < kJumpUnroll; ++k) {
+                if (keep[k]) st_dev((int*)lout + slot++, v[k]);
+                const uint64_t mask = ballot(item[k] != kNone);
+                if (mask) {
+                    int wbase = 0;
+                    if (lane_id() == 0) wbase = atomicAdd(&s_nbuf, popc(mask));
+                    wbase = __shfl(wbase, 0);
+                    if (item[k] != kNone) buf[wbase + popc(mask & lanes_below())] = item[k];
+                }
+            }
+            __syncthreads();
+            if (s_nbuf > kCasBuf - (int)blockDim.x * kJumpUnroll) flush();
+        }
+        done = block_sum(done, red);
+        if (threadIdx.x == 0 && done) add_dev(ctr + kJDone0 + r % 3, (int)done);
+        if (!grid_barrier(ctr + kBarCount, ctr + kBarGen, ctr + kStall, budget)) break;
+    }
+    flush();
+    killed = block_sum(killed, red);
+    if (threadIdx.x == 0 && killed) add_dev(ctr + kJKilled, (int)killed);
 }
 
 struct Ac6Live {
@@ -405,7 +594,15 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
             Timed t(lc, "ac6_sweep");
             hipLaunchKernelGGL(ac6_sweep<View>, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n,
                                chunk, w.a, reinterpret_cast<const uint32_t*>(w.c), preset, w.b,
-                               w.q, w.ctr, worker_edges, P, w.part, lc.schedule);
+                               w.q, w.ctr, worker_edges, P, w.part, lc.schedule,
+                               lc.forest ? w.jp : nullptr, lc.forest ? w.e : nullptr);
+        }
+        if (lc.forest) {
+            Timed t(lc, "ac6_jump");
+            int rounds = 2;   // ceil(log2 n) + 1 rounds resolve any depth
+            while ((1LL << (rounds - 1)) < (long long)n) ++rounds;
+            hipLaunchKernelGGL(ac6_jump<View>, dim3(lc.cus * kJumpPerCu), dim3(256), 0, lc.stream,
+                               g, w.jp, w.a, w.e, w.e + n, w.q, w.ctr, rounds, lc.budget);
         }
         {
             Timed t(lc, "ac6_propagate");

@@ -12,8 +12,9 @@
 // n <= TRIM_NOALLOC_MAX_N and at most TRIM_NOALLOC_WORKERS workers:
 //   list heads   2n int32        records   n uint64
 //   sinks bitmap n/32 + 2 words  queue     3n + 64 * 4 * workers uint32
+//   forest links n int32         forest lists 2n uint32
 //   control      kCtrInts int32  partials  kPartSlots * kPartStride uint64
-// about 30 MB in all.  Every call overwrites what it reads before reading it,
+// about 42 MB in all.  Every call overwrites what it reads before reading it,
 // except the queue, whose free slots must hold kNone: the first call on a
 // device fills it with a kernel, and every later call leaves it that way
 // (consumers restore each slot they take; a call abandoned by the watchdog
@@ -38,7 +39,9 @@ constexpr long long kOffHead = 0;
 constexpr long long kOffRec = kOffHead + round256(kMaxN);             // 2n int32
 constexpr long long kOffSinks = kOffRec + round256(kMaxN);            // n uint64
 constexpr long long kOffQueue = kOffSinks + round256(kMaxN / 64 + 2); // n/32 + 2 (+1) uint32
-constexpr long long kOffCtr = kOffQueue + round256((kQueueWordsU32 + 1) / 2);
+constexpr long long kOffJp = kOffQueue + round256((kQueueWordsU32 + 1) / 2);   // n int32
+constexpr long long kOffLists = kOffJp + round256(kMaxN / 2);                     // 2n uint32
+constexpr long long kOffCtr = kOffLists + round256(kMaxN);
 constexpr long long kOffPart = kOffCtr + round256(kCtrInts / 2);
 constexpr long long kScratchWords = kOffPart + round256((long long)kPartSlots * kPartStride);
 
@@ -135,6 +138,8 @@ extern "C" int trim_csr_noalloc(const trim_csr_t* g, const trim_opts_t* o,
     w.b = d->base + kOffRec;
     w.c = reinterpret_cast<int*>(d->base + kOffSinks);
     w.q = reinterpret_cast<uint32_t*>(d->base + kOffQueue);
+    w.jp = reinterpret_cast<int*>(d->base + kOffJp);
+    w.e = reinterpret_cast<uint32_t*>(d->base + kOffLists);
     w.qwords = kQueueWordsU32;
     w.ctr = reinterpret_cast<int*>(d->base + kOffCtr);
     w.part = d->base + kOffPart;
@@ -144,6 +149,7 @@ extern "C" int trim_csr_noalloc(const trim_csr_t* g, const trim_opts_t* o,
     lc.schedule = o ? o->schedule : 0;
     lc.workers = (o && o->workers > 0) ? o->workers : TRIM_NOALLOC_WORKERS;
     lc.budget = (o && o->budget > 0) ? o->budget : TRIM_DEFAULT_BUDGET;
+    lc.forest = !(o && (o->flags & TRIM_FLAG_STEPWISE));
     lc.cus = d->cus;
     lc.stream = s;
     if (o && o->validate) {

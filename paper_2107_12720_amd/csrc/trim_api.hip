@@ -28,7 +28,7 @@ struct trim_ctx {
     int occ6 = 0, occ4 = 0, occ3 = 0;   // resident workgroups per CU (occ6: both AC-6 forms)
     // captured launch sequence of trim_batch and the arguments it was made for
     hipGraphExec_t gexec = nullptr;
-    uint64_t gkey[23] = {};
+    uint64_t gkey[25] = {};
     bool timing = false;
     trim::Timer timer;
     // tile tables of the preprocessing and reordering kernels
@@ -94,7 +94,10 @@ void free_work(trim_ctx* c) {
     dfree(c, c->w.c);
     dfree(c, c->w.d);
     dfree(c, c->w.q);
+    dfree(c, c->w.e);
     c->w.q = nullptr;
+    c->w.e = nullptr;
+    c->w.jp = nullptr;
     c->w.a = nullptr;
     c->w.b = nullptr;
     c->w.c = nullptr;
@@ -111,6 +114,7 @@ int ensure(trim_ctx* c, int64_t n) {
         dmalloc(c, &c->w.b, cap * 8) != hipSuccess ||
         dmalloc(c, &c->w.c, cap * 4) != hipSuccess ||
         dmalloc(c, &c->w.d, cap * 4) != hipSuccess ||
+        dmalloc(c, &c->w.e, cap * 12) != hipSuccess ||
         dmalloc(c, &c->w.q, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess ||
         // free queue slots hold kNone (all ones); consumers restore it
         hipMemset(c->w.q, 0xFF, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess) {
@@ -120,6 +124,7 @@ int ensure(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n = cap;
+    c->w.jp = reinterpret_cast<int*>(c->w.e + 2 * cap);   // after the two lists
     c->w.qwords = (long long)cap * 3 + trim::kQueueSlots;
     return TRIM_OK;
 }
@@ -256,6 +261,7 @@ int check_opts(const trim_opts_t* o) {
     if (o->schedule & ~(TRIM_SCHED_REVERSE | TRIM_SCHED_JITTER))
         return fail(TRIM_E_INVAL, "opts.schedule has unknown bits");
     if (o->budget < 0) return fail(TRIM_E_INVAL, "opts.budget must be >= 0");
+    if (o->flags & ~TRIM_FLAG_STEPWISE) return fail(TRIM_E_INVAL, "opts.flags has unknown bits");
     return TRIM_OK;
 }
 
@@ -266,6 +272,7 @@ trim::LaunchCfg launch_cfg(trim_ctx* c, int algo, const trim_opts_t* o, void* st
     lc.schedule = o ? o->schedule : 0;
     lc.workers = workers_for(c, algo, o);
     lc.budget = (o && o->budget > 0) ? o->budget : TRIM_DEFAULT_BUDGET;
+    lc.forest = !(o && (o->flags & TRIM_FLAG_STEPWISE));
     lc.cus = c->cus;
     lc.stream = (hipStream_t)stream;
     if (c->timing) {
@@ -636,14 +643,15 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
         return TRIM_OK;
     }
     if (!stream) return fail(TRIM_E_INVAL, "opts.graph needs a non-NULL stream");
-    const uint64_t key[23] = {(uint64_t)G, (uint64_t)vbase, (uint64_t)row_off, (uint64_t)col,
+    const uint64_t key[25] = {(uint64_t)G, (uint64_t)vbase, (uint64_t)row_off, (uint64_t)col,
                               (uint64_t)total_n, (uint64_t)total_m, (uint64_t)bitmap_base,
                               (uint64_t)live_bitmaps, (uint64_t)graph_edges, (uint64_t)stats,
                               (uint64_t)stream, (uint64_t)lc.block,
                               (uint64_t)lc.chunk | ((uint64_t)lc.schedule << 32),
                               (uint64_t)lc.workers, (uint64_t)c->w.a, (uint64_t)c->w.b,
                               (uint64_t)c->w.c, (uint64_t)c->w.d, (uint64_t)c->w.q,
-                              (uint64_t)c->w.part, (uint64_t)c->w.ctr, (uint64_t)c->w.wedges, 1};
+                              (uint64_t)c->w.part, (uint64_t)c->w.ctr, (uint64_t)c->w.wedges,
+                              (uint64_t)c->w.e, (uint64_t)lc.forest | ((uint64_t)lc.budget << 1), 1};
     if (!c->gexec || memcmp(key, c->gkey, sizeof key) != 0) {
         if (c->gexec) {
             (void)hipGraphExecDestroy(c->gexec);

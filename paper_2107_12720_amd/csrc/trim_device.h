@@ -141,6 +141,7 @@ __device__ __forceinline__ uint32_t item_kind(uint32_t it) { return it >> 30; }
 __device__ __forceinline__ int item_vertex(uint32_t it) { return (int)(it & kIdMask); }
 
 constexpr int kLocalQ = 1024;             // LDS ring entries per wavefront
+constexpr int kLocalP = 256;              // entries of the wave-local ring (never shared)
 constexpr int kSpillAbove = kLocalQ / 2;  // ring fill that triggers a bulk hand-off
 constexpr int kPollEvery = 64;            // busy iterations between shared-queue polls
 constexpr int kMaxNaps = 4;               // idle back-off cap, in s_sleep(127) naps
@@ -169,6 +170,9 @@ struct WaveQueue {
     int* qhead;
     int* qtail;
     int* pending;
+    uint32_t* lp;       // optional wave-local ring: items that never leave the wave
+    int* ptail_lds;     // its tail in LDS
+    int phead;          // wave-uniform head
     int* stall;         // watchdog word (nonzero: every wavefront exits)
     int budget;         // loop iterations this wavefront may make
     int ticket;         // per lane: shared-queue slot this lane waits on, or -1
@@ -182,10 +186,18 @@ struct WaveQueue {
     __device__ __forceinline__ void init(uint32_t* ring, int* ring_tail, uint32_t* gq,
                                          int* ctr_qhead, int* ctr_qtail, int* ctr_pending,
                                          int* ctr_stall, int step_budget,
-                                         int share_every = kPollEvery) {
+                                         int share_every = kPollEvery,
+                                         uint32_t* local_ring = nullptr,
+                                         int* local_tail = nullptr) {
         lq = ring;
         tail_lds = ring_tail;
-        if (lane_id() == 0) *tail_lds = 0;
+        lp = local_ring;
+        ptail_lds = local_tail;
+        phead = 0;
+        if (lane_id() == 0) {
+            *tail_lds = 0;
+            if (ptail_lds) *ptail_lds = 0;
+        }
         __builtin_amdgcn_wave_barrier();
         head = 0;
         holding = false;
@@ -207,8 +219,37 @@ struct WaveQueue {
     }
     __device__ __forceinline__ int fill() const { return tail() - head; }
 
-    // Idle lanes take items from the LDS ring.
+    // One item into the wave-local ring, from any lane, also from divergent
+    // code.  Returns false (nothing pushed) when that ring is full.  Its items
+    // are taken by idle lanes of this wave before any other work and never go
+    // to the shared queue, so they need no room there.
+    __device__ __forceinline__ bool push_local(uint32_t it) {
+        int t = __hip_atomic_load(ptail_lds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        for (;;) {
+            if (t - phead >= kLocalP) return false;
+            if (__hip_atomic_compare_exchange_strong(ptail_lds, &t, t + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WAVEFRONT)) {
+                lp[t & (kLocalP - 1)] = it;
+                return true;
+            }
+        }
+    }
+
+    // Idle lanes take items from the wave-local ring, then from the LDS ring.
     __device__ __forceinline__ void refill(uint32_t& item) {
+        if (lp) {
+            const uint64_t idle = ballot(item == kNone);
+            const int avail =
+                __hip_atomic_load(ptail_lds, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) -
+                phead;
+            if (idle && avail > 0) {
+                const int take = min(popc(idle), avail);
+                const int rank = popc(idle & lanes_below());
+                if (item == kNone && rank < take) item = lp[(phead + rank) & (kLocalP - 1)];
+                phead += take;
+            }
+        }
         const uint64_t idle = ballot(item == kNone);
         const int avail = tail() - head;
         if (idle && avail > 0) {

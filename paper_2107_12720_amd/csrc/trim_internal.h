@@ -19,6 +19,11 @@ enum Ctr : int {
     kBarCount = 128, // grid barrier arrivals
     kBarGen = 160,   // grid barrier generation
     kCursor = 192,   // next unclaimed vertex of the chunked sweep
+    kJCnt0 = 200,    // AC-6 forest collapse: list sizes, rotating over 3 slots
+    kJDone0 = 204,   // vertices whose root was found, per round, rotating over 3 slots
+    kJStop = 208,    // nonzero once the pointer-jumping rounds are over
+    kJRounds = 209,  // rounds run
+    kJKilled = 210,  // vertices removed by the collapse
     kCnt0 = 224,     // AC-3 live-list sizes, rotating over 3 slots
     kStall = 240,    // watchdog: nonzero once a persistent kernel gave up (opts.budget)
     kCtrInts = 256
@@ -31,7 +36,10 @@ struct Work {
     uint64_t* b = nullptr;    // n uint64: AC-6 (out-side) records / AC-3 list
     int* c = nullptr;         // n int32: AC-6 bitmap of vertices removed at the start /
                               //   AC-3 removal round
-    int* d = nullptr;         // n int32: AC-3 cursor / two-sided AC-4 removal flags
+    int* d = nullptr;         // n int32: AC-3 cursor / two-sided AC-4 removal flags /
+                              //   batch: first vertex of each vertex's graph
+    uint32_t* e = nullptr;    // 2n uint32: AC-6 forest-collapse lists (two of n)
+    int* jp = nullptr;        // n int32: AC-6 forest links
     uint32_t* q = nullptr;    // 3n shared-queue slots, kNone between calls
     long long qwords = 0;     // size of q in words (slack included)
     int* ctr = nullptr;       // kCtrInts control words
@@ -80,6 +88,7 @@ struct LaunchCfg {
     int schedule = 0;         // TRIM_SCHED_* perturbation flags (tests)
     int workers = 0;          // persistent workgroups
     int budget = TRIM_DEFAULT_BUDGET;   // watchdog step budget (opts.budget)
+    bool forest = true;       // AC-6: collapse the last-successor forest after the sweep
     int cus = 256;
     hipStream_t stream = nullptr;
     Timer* timer = nullptr;   // non-null: record per-kernel events

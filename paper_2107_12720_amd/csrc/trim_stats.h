@@ -79,6 +79,8 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
         stats->q_highwater = qhw;
         stats->edges_live = live_edges;
         stats->stalled = ld_dev(ctr + kStall) != 0;
+        stats->forest = (uint64_t)ld_dev(ctr + kJKilled);
+        stats->jump_rounds = (uint64_t)ld_dev(ctr + kJRounds);
         if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
     }
 }

@@ -65,8 +65,8 @@ def test_opts_layout_matches_header():
     import paper_2107_12720_amd as T
     assert ctypes.sizeof(T.Opts) == 32
     assert [f for f, _ in T.Opts._fields_] == ["block", "workers", "chunk", "validate", "graph",
-                                               "schedule", "budget", "reserved"]
+                                               "schedule", "budget", "flags"]
     # trim_stats_t: 16 uint64 words, the named fields first
-    assert T.STATS_WORDS == 16 and len(T.STATS_FIELDS) == 13
+    assert T.STATS_WORDS == 16 and len(T.STATS_FIELDS) == 15
     assert ctypes.sizeof(T.CsrDesc) == 48
     assert ctypes.sizeof(T.ImplicitDesc) == 32

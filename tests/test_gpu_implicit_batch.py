@@ -9,7 +9,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from gpu_common import say, sweep_counts
+from gpu_common import check_ac6_counters, say
 
 pytestmark = pytest.mark.gpu
 
@@ -45,9 +45,7 @@ def implicit_case(ctx, log2n, seed, algos=(6, 3)):
         if a == 3:
             assert st["rounds"] == r.alpha + 1
         if a == 6:
-            checks, joins, _ = sweep_counts(g)
-            assert st["edges_sweep"] == checks
-            assert st["visited"] == joins + st["joins"] - r.n_live
+            check_ac6_counters(g, r, st)
     return g, r
 
 

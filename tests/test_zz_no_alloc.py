@@ -14,7 +14,7 @@ from gpu_common import say, upload
 
 pytestmark = pytest.mark.gpu
 
-FIXED = ("edges_total", "n_live", "n_dead", "edges_sweep", "closes", "graph_edges")
+FIXED = ("edges_total", "n_live", "n_dead", "edges_sweep", "closes", "graph_edges", "forest")
 
 
 @pytest.fixture(scope="module")
