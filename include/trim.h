@@ -161,8 +161,12 @@ typedef struct {
                               members of their last-successor trees); 0 with
                               TRIM_FLAG_STEPWISE */
     uint64_t jump_rounds;  /* AC-6: pointer-jumping rounds the forest collapse ran */
-    uint64_t reserved[2];
-} trim_stats_t;
+    uint64_t work_items;   /* AC-6: list entries the forest-collapse rounds processed;
+                              AC-3: live-list entries processed over all rounds */
+    uint64_t phases;       /* AC-6: level-synchronous phases of the propagation before its
+                              asynchronous tail */
+    uint64_t reserved;
+} trim_stats_t;   /* 18 words */
 
 /*
  * Per-kernel timing of the last call made on `ctx` (for benchmarks).  With

@@ -40,8 +40,8 @@ EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destr
 MLP_PARAMS = 1377
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
                 "joins", "visited", "graph_edges", "q_highwater", "edges_live", "stalled",
-                "forest", "jump_rounds")
-STATS_WORDS = 16
+                "forest", "jump_rounds", "work_items", "phases")
+STATS_WORDS = 18
 ABI_VERSION = 2
 DEFAULT_BUDGET = 1 << 22
 

@@ -130,7 +130,10 @@ __global__ __launch_bounds__(256) void ac3_rounds(View g, int n, int* ptr, int* 
         int* out = (r & 1) ? list0 : list1;
         const int cnt_in = ld_dev(ctr + kCnt0 + r % 3);
         int* cnt_out = ctr + kCnt0 + (r + 1) % 3;
-        if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
+            add_dev(ctr + kAcWork, cnt_in);
+        }
         for (int base = blockIdx.x * blockDim.x; base < cnt_in; base += stride * kUnroll) {
             int v[kUnroll], w[kUnroll], d[kUnroll];
             bool keep[kUnroll];
@@ -254,7 +257,10 @@ __global__ __launch_bounds__(256) void ac3_rounds2(ExplicitView out, ExplicitVie
         const List3 dst = (r & 1) ? l0 : l1;
         const int cnt_in = ld_dev(ctr + kCnt0 + r % 3);
         int* cnt_out = ctr + kCnt0 + (r + 1) % 3;
-        if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st_dev(ctr + kCnt0 + (r + 2) % 3, 0);
+            add_dev(ctr + kAcWork, cnt_in);
+        }
         for (int base = blockIdx.x * blockDim.x; base < cnt_in; base += stride * kUnroll) {
             int v[kUnroll], wo[kUnroll], wi[kUnroll], dout[kUnroll], din[kUnroll];
             bool keep[kUnroll];

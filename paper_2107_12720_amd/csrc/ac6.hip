@@ -382,6 +382,155 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
     }
 }
 
+// Level-synchronous propagation: the bulk of the work after the first sweep
+// (and the forest collapse) runs in phases, the frontier form of Table
+// trim-2.  A phase processes every item of its list -- CLOSE(x): exchange
+// both of x's list heads with kDead and hand back both lists; RESCAN(x):
+// resume x's DoPost after its old support, and close x if it finds none;
+// WALK(x): hand back the S_more list headed by x -- and writes the items it
+// creates to the next phase's list: a CLOSE for every S_last member (it has
+// no successor left) and a RESCAN for every S_more member.  The lists are
+// walked in lockstep, one link per lane per step; created items are staged
+// per wavefront in LDS and reserved in the next list with one fetch-add per
+// flush.  A grid barrier ends each phase.  Nothing here touches the shared
+// ticket queue, whose few counters every wavefront would otherwise contend
+// for.  Once a phase's list is shorter than kTailItems (a deep, narrow
+// remainder, such as a chain), its items go to the shared queue and the
+// asynchronous kernel finishes: it follows a chain at one memory round trip
+// per removal, where a phase costs a barrier.  Launched with at most two
+// workgroups per CU, all resident at once.
+constexpr int kTailItems = 256;
+constexpr int kStage = 256;   // items staged per wavefront before one reservation
+constexpr int kLevelsPerCu = 2;
+
+template <class View>
+__global__ __launch_bounds__(256) void ac6_levels(View g, int* head, uint64_t* rec, uint32_t* q,
+                                                  uint32_t* l0, uint32_t* l1, int* ctr,
+                                                  uint64_t* worker_edges, int P, uint64_t* part,
+                                                  int sched, int budget) {
+    __shared__ uint64_t lds[Stage<View>::kWords];
+    __shared__ uint32_t stage[256 / kWave][kStage];
+    __shared__ int stage_n[256 / kWave];
+    __shared__ uint64_t red[16];
+    Stage<View>::apply(g, lds);
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == 0) stage_n[wv] = 0;
+    __builtin_amdgcn_wave_barrier();
+    uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
+    const int stride = gridDim.x * blockDim.x;
+    int* out_cnt = nullptr;
+    uint32_t* out = nullptr;
+    // move this wavefront's staged items to the next list (wave-uniform)
+    auto flush = [&]() {
+        const int k = stage_n[wv];
+        if (k == 0) return;
+        int base = 0;
+        if (lane_id() == 0) base = add_dev(out_cnt, k);
+        base = __shfl(base, 0);
+        for (int i = lane_id(); i < k; i += kWave) st_dev((int*)out + base + i, (int)stage[wv][i]);
+        __builtin_amdgcn_wave_barrier();
+        if (lane_id() == 0) stage_n[wv] = 0;
+        __builtin_amdgcn_wave_barrier();
+    };
+    // stage this lane's item, if any (wave-uniform)
+    auto emit = [&](uint32_t e) {
+        const uint64_t mk = ballot(e != kNone);
+        const int k = popc(mk);
+        if (k == 0) return;
+        if (stage_n[wv] + k > kStage) flush();
+        const int base = stage_n[wv];
+        if (e != kNone) stage[wv][base + popc(mk & lanes_below())] = e;
+        __builtin_amdgcn_wave_barrier();
+        if (lane_id() == 0) stage_n[wv] = base + k;
+        __builtin_amdgcn_wave_barrier();
+    };
+    const int n0 = ld_dev(ctr + kQTail);   // the first phase's items, in the shared queue
+    for (int ph = 0;; ++ph) {
+        const uint32_t* in = ph == 0 ? q : ((ph & 1) ? l0 : l1);
+        const int cnt = ph == 0 ? n0 : ld_dev(ctr + kLvCnt0 + ph % 3);
+        if (cnt < kTailItems) {
+            // the rest goes to the asynchronous kernel, through the shared queue
+            if (ph > 0) {
+                for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
+                    st_dev((int*)q + i, ld_dev((const int*)in + i));
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    st_dev(ctr + kQHead, 0);
+                    st_dev(ctr + kQTail, cnt);
+                    st_dev(ctr + kPending, cnt);
+                }
+            }
+            break;
+        }
+        out = (ph & 1) ? l1 : l0;
+        out_cnt = ctr + kLvCnt0 + (ph + 1) % 3;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st_dev(ctr + kLvCnt0 + (ph + 2) % 3, 0);
+            add_dev(ctr + kLvPhases, 1);
+        }
+        for (int base = blockIdx.x * blockDim.x; base < cnt; base += stride) {
+            const int i = base + threadIdx.x;
+            uint32_t it = kNone;
+            if (i < cnt) {
+                it = (uint32_t)ld_dev((const int*)in + i);
+                if (ph == 0) st_dev((int*)q + i, (int)kNone);   // the slot is free again
+            }
+            int walk_last = -1, walk_more = -1, cx = -1;
+            if (it != kNone) {
+                const int x = item_vertex(it);
+                const uint32_t kind = item_kind(it);
+                if (kind == kWalkMore) {
+                    walk_more = x;
+                } else if (kind == kRescan) {
+                    // x is in no list until it joins again: its record is stable
+                    const uint64_t r = ld_dev(rec + x);
+                    if (sched & TRIM_SCHED_JITTER) jitter_nap(x);
+                    if (resume(g, x, rec_cursor(r) + 1, head, rec, edges, sched))
+                        joins += 1;
+                    else
+                        cx = x;
+                } else {
+                    cx = x;   // a close (the first phase's items are closes or walks)
+                }
+            }
+            if (cx >= 0) {
+                if (sched & TRIM_SCHED_JITTER) jitter_nap((uint64_t)cx << 8);
+                const int2 ab = xchg2_dev(head + 2 * cx, kDead, kDead);
+                closes += 1;
+                walk_more = ab.x;
+                walk_last = ab.y;
+            }
+            // a member's link is read before its item exists: its own processing,
+            // in the next phase, is the only thing that can change its record
+            while (ballot(walk_last >= 0 || walk_more >= 0)) {
+                uint32_t e = kNone;
+                if (walk_last >= 0) {
+                    const int nx = ld_dev(rec_link(rec, walk_last));
+                    e = make_item(kClose, walk_last);
+                    walk_last = nx;
+                } else if (walk_more >= 0) {
+                    const int nx = ld_dev(rec_link(rec, walk_more));
+                    e = make_item(kRescan, walk_more);
+                    walk_more = nx;
+                }
+                visited += e != kNone;
+                emit(e);
+            }
+        }
+        flush();
+        if (!grid_barrier(ctr + kBarCount, ctr + kBarGen, ctr + kStall, budget)) break;
+    }
+    edges = block_sum(edges, red);
+    closes = block_sum(closes, red);
+    joins = block_sum(joins, red);
+    visited = block_sum(visited, red);
+    if (threadIdx.x == 0) {
+        if (edges) add_dev(worker_edges + (blockIdx.x % P), edges);
+        part[kPartLvCloses * kPartStride + blockIdx.x] = closes;
+        part[kPartLvJoins * kPartStride + blockIdx.x] = joins;
+        part[kPartLvVisited * kPartStride + blockIdx.x] = visited;
+    }
+}
+
 // The forest collapse (see the file comment) in one launch of at most two
 // workgroups per CU, all resident at once: round r reads the list of round r
 // (sizes rotate over three counters, like the AC-3 lists), resolves what it
@@ -429,6 +578,7 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint
             st_dev(ctr + kJCnt0 + (r + 2) % 3, 0);
             st_dev(ctr + kJDone0 + (r + 1) % 3, 0);
             add_dev(ctr + kJRounds, 1);
+            add_dev(ctr + kJWork, cnt);
         }
         uint64_t done = 0;
         const int step = gridDim.x * blockDim.x * kJumpUnroll;
@@ -604,6 +754,13 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
             hipLaunchKernelGGL(ac6_jump<View>, dim3(lc.cus * kJumpPerCu), dim3(256), 0, lc.stream,
                                g, w.jp, w.a, w.e, w.e + n, w.q, w.ctr, rounds, lc.budget);
         }
+        const int level_blocks = lc.cus * kLevelsPerCu;
+        {
+            Timed t(lc, "ac6_levels");
+            hipLaunchKernelGGL(ac6_levels<View>, dim3(level_blocks), dim3(256), 0, lc.stream, g,
+                               w.a, w.b, w.q, w.e, w.e + n, w.ctr, worker_edges, P, w.part,
+                               lc.schedule, lc.budget);
+        }
         {
             Timed t(lc, "ac6_propagate");
             hipLaunchKernelGGL(ac6_propagate<View>, dim3(P), dim3(256), 0, lc.stream, g, w.a,
@@ -626,7 +783,7 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         Timed t(lc, "finalize");
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, sweep_blocks,
                            n > 0 ? P : 0, pack_blocks, n > 0 ? P : 0, worker_edges, w.part,
-                           w.ctr, stats, 0);
+                           w.ctr, stats, 0, 0, n > 0 ? lc.cus * kLevelsPerCu : 0);
     }
     return hipGetLastError();
 }

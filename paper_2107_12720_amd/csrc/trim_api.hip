@@ -10,6 +10,9 @@
 #include "trim_internal.h"
 #include "scc_internal.h"
 
+static_assert(sizeof(trim_stats_t) == 18 * sizeof(uint64_t), "trim_stats_t layout");
+static_assert(sizeof(trim_opts_t) == 8 * sizeof(int32_t), "trim_opts_t layout");
+
 struct trim_ctx {
     int device = 0;
     int cus = 0;

@@ -24,6 +24,10 @@ enum Ctr : int {
     kJStop = 208,    // nonzero once the pointer-jumping rounds are over
     kJRounds = 209,  // rounds run
     kJKilled = 210,  // vertices removed by the collapse
+    kJWork = 211,    // list entries the collapse rounds processed
+    kLvCnt0 = 212,   // AC-6 level-synchronous phases: list sizes, rotating over 3 slots
+    kLvPhases = 215, // phases run
+    kAcWork = 216,   // AC-3: live-list entries processed over all rounds
     kCnt0 = 224,     // AC-3 live-list sizes, rotating over 3 slots
     kStall = 240,    // watchdog: nonzero once a persistent kernel gave up (opts.budget)
     kCtrInts = 256
@@ -59,7 +63,8 @@ constexpr int kQueueSlots = 64 * 4 * kMaxWorkers;
 constexpr int kPartStride = 16384;   // >= workers, sweep blocks and pack blocks
 enum PartSlot : int { kPartCloses = 0, kPartJoins = 1, kPartVisited = 2, kPartSweep = 3,
                       kPartLive = 4, kPartDeg = 5, kPartQhw = 6, kPartLiveEdges = 7,
-                      kPartSlots = 8 };
+                      kPartLvCloses = 8, kPartLvJoins = 9, kPartLvVisited = 10,
+                      kPartSlots = 11 };
 
 // Optional per-kernel event timing (trim_ctx_set_timing).
 struct Timer {

@@ -52,18 +52,24 @@ __device__ __forceinline__ uint64_t max_range(const uint64_t* a, int k, uint64_t
 // One block: reduce the partials into *stats.  n_sweep / n_prop = number of
 // sweep / propagation partials (0 when the algorithm has none); n_qhw =
 // number of ring high-water partials; n_live_edges = number of live-check
-// partials (two-sided AC-6 only, else 0).
+// partials (two-sided AC-6 only, else 0); n_levels = number of partials of
+// the level-synchronous propagation phases (AC-6, else 0).
 __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack, int n_qhw,
                                const uint64_t* worker_edges, const uint64_t* part, const int* ctr,
-                               trim_stats_t* stats, int empty_rounds, int n_live_edges = 0) {
+                               trim_stats_t* stats, int empty_rounds, int n_live_edges = 0,
+                               int n_levels = 0) {
     __shared__ uint64_t red[16];
     const uint64_t qhw = max_range(part + kPartQhw * kPartStride, n_qhw, red);
     const uint64_t edges = sum_range(worker_edges, P, red);
     const uint64_t live = sum_range(part + kPartLive * kPartStride, n_pack, red);
     const uint64_t sweep = sum_range(part + kPartSweep * kPartStride, n_sweep, red);
-    const uint64_t closes = sum_range(part + kPartCloses * kPartStride, n_prop, red);
-    const uint64_t joins = sum_range(part + kPartJoins * kPartStride, n_prop, red);
-    const uint64_t visited = sum_range(part + kPartVisited * kPartStride, n_prop, red);
+    // the propagation's counts: its level-synchronous phases and its asynchronous tail
+    const uint64_t closes = sum_range(part + kPartCloses * kPartStride, n_prop, red) +
+                            sum_range(part + kPartLvCloses * kPartStride, n_levels, red);
+    const uint64_t joins = sum_range(part + kPartJoins * kPartStride, n_prop, red) +
+                           sum_range(part + kPartLvJoins * kPartStride, n_levels, red);
+    const uint64_t visited = sum_range(part + kPartVisited * kPartStride, n_prop, red) +
+                             sum_range(part + kPartLvVisited * kPartStride, n_levels, red);
     const uint64_t degsum = sum_range(part + kPartDeg * kPartStride, n_sweep, red);
     const uint64_t live_edges = sum_range(part + kPartLiveEdges * kPartStride, n_live_edges, red);
     if (threadIdx.x == 0) {
@@ -81,6 +87,9 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
         stats->stalled = ld_dev(ctr + kStall) != 0;
         stats->forest = (uint64_t)ld_dev(ctr + kJKilled);
         stats->jump_rounds = (uint64_t)ld_dev(ctr + kJRounds);
+        stats->work_items = (uint64_t)(uint32_t)ld_dev(ctr + kJWork) +
+                            (uint64_t)(uint32_t)ld_dev(ctr + kAcWork);
+        stats->phases = (uint64_t)ld_dev(ctr + kLvPhases);
         if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
     }
 }

@@ -66,7 +66,12 @@ def test_opts_layout_matches_header():
     assert ctypes.sizeof(T.Opts) == 32
     assert [f for f, _ in T.Opts._fields_] == ["block", "workers", "chunk", "validate", "graph",
                                                "schedule", "budget", "flags"]
-    # trim_stats_t: 16 uint64 words, the named fields first
-    assert T.STATS_WORDS == 16 and len(T.STATS_FIELDS) == 15
+    # trim_stats_t: the header's uint64 words, the named fields first, in order
+    text = open(os.path.join(ROOT, "include", "trim.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} trim_stats_t;", text).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"uint64_t\s+(\w+)(?:\[(\d+)\])?;", body)
+    assert sum(int(k or 1) for _, k in fields) == T.STATS_WORDS == 18
+    assert tuple(f for f, _ in fields if f != "reserved") == T.STATS_FIELDS
     assert ctypes.sizeof(T.CsrDesc) == 48
     assert ctypes.sizeof(T.ImplicitDesc) == 32
