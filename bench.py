@@ -91,27 +91,73 @@ def measured_traffic(kernel, workload, workers=None):
 
 
 def prop_bytes(st, t6):
-    """Algorithmic bytes of one ac6_propagate launch: 8 B per successor check
-    (target id + target status), 16 B per close (two list-head exchanges),
-    16 B per join (record store + head CAS), 8 B per list member handed back
-    (its record)."""
+    """Algorithmic bytes of the propagation after the first sweep (its
+    level-synchronous phases and its asynchronous tail together): 8 B per
+    successor check (target id + target status), 16 B per close (two list-head
+    exchanges), 16 B per join (record store + head CAS), 8 B per list member
+    handed back (its record)."""
     return (8 * (t6 - st["edges_sweep"]) + 16 * st["closes"] + 16 * st["joins"]
             + 8 * st["visited"])
 
 
-def sweep_counts(g):
-    """(checks, joins, casualties) of the first sweep.  Only out-degree-0
-    vertices are removed while it runs, so v joins the list of its first
-    successor with out-degree > 0, or is queued for removal if it has none."""
+def jump_bytes(st):
+    """Algorithmic bytes of the forest collapse: per list entry and round its
+    entry, its link and its ancestor's link read, and one link or list entry
+    written (16 B); per removed vertex an 8-byte head exchange and a 4-byte
+    walk item."""
+    return 16 * st["work_items"] + 12 * st["forest"]
+
+
+def kernel_bytes(n, st, sw):
+    """Algorithmic bytes of every AC-6 kernel of one trim (sw = the sweep's
+    host counts: checks, joins, casualties, last-successor members).  The
+    propagation's two kernels share one count: both get the combined bytes
+    under the name 'propagation'."""
+    checks, joins, cas, members = sw
+    forest = st["forest"] > 0
+    return {"ac6_init": 4 * (n + 1) + 8 * n + n // 8,
+            "ac6_sweep": sweep_bytes(n, checks, joins, cas)
+            + (4 * (joins + cas) + 4 * (members + cas) if forest else 0),
+            "ac6_jump": jump_bytes(st),
+            "propagation": prop_bytes(st, st["edges_total"]),
+            "ac6_pack": 8 * n + n // 8}
+
+
+def group_times(kavg):
+    """Per-kernel average ms, with the propagation's two kernels summed."""
+    out = {k: v for k, v in kavg.items() if k not in ("ac6_levels", "ac6_propagate")}
+    out["propagation"] = kavg.get("ac6_levels", 0.0) + kavg.get("ac6_propagate", 0.0)
+    return out
+
+
+def sweep_counts(g, chunk=1 << 22):
+    """(checks, joins, casualties, last-successor members) of the first sweep.
+    Only out-degree-0 vertices are removed while it runs, so v joins the list
+    of its first successor with out-degree > 0 (the S_last list if that is its
+    last successor), or is left without a live successor if it has none.
+    Counted over vertex ranges, so the largest graphs fit in host memory."""
     import numpy as np
-    deg = np.diff(g.row_off.astype(np.int64))
-    ok = np.flatnonzero(deg[g.col] > 0)
-    start = g.row_off[:-1].astype(np.int64)
-    j = np.searchsorted(ok, start)
-    first = np.where(j < ok.size, ok[np.minimum(j, ok.size - 1)], -1)
-    has = (deg > 0) & (first >= start) & (first < g.row_off[1:])
-    checks = np.where(has, first - start + 1, deg).sum()
-    return int(checks), int(has.sum()), int(((deg > 0) & ~has).sum())
+    ro = g.row_off
+    nz = np.diff(ro) > 0
+    tot = [0, 0, 0, 0]
+    for v0 in range(0, g.n, chunk):
+        v1 = min(g.n, v0 + chunk)
+        e0, e1 = int(ro[v0]), int(ro[v1])
+        deg = np.diff(ro[v0:v1 + 1].astype(np.int64))
+        if e1 == e0:
+            continue
+        ok = np.flatnonzero(nz[g.col[e0:e1]]) + e0
+        start = ro[v0:v1].astype(np.int64)
+        j = np.searchsorted(ok, start)
+        first = np.where(j < ok.size, ok[np.minimum(j, max(ok.size - 1, 0))] if ok.size else -1,
+                         -1)
+        end = ro[v0 + 1:v1 + 1].astype(np.int64)
+        has = (deg > 0) & (first >= start) & (first < end)
+        tot[0] += int(np.where(has, first - start + 1, deg).sum())
+        tot[1] += int(has.sum())
+        tot[2] += int(((deg > 0) & ~has).sum())
+        tot[3] += int((has & (first == end - 1)).sum())
+    return tuple(tot)
 
 
 def sweep_bytes(n, checks, joins, casualties):
@@ -212,7 +258,8 @@ def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps, with_ac3=True):
            "ac6_speedup_vs_ac4": ms4 / ms6,
            "depth": {"chain_hop_us": ms_chain * 1e3 / (L - 1), "chain_live_ok": chain_ok}}
     checks = {"rro": rro_h, "rcol": rcol_h,
-              "ac6": {"bitmap": res6.bitmap_numpy().copy(), "edges": st6["edges_total"]},
+              "ac6": {"bitmap": res6.bitmap_numpy().copy(), "edges": st6["edges_total"],
+                      "edges_live": st6["edges_live"]},
               "ac4": {"bitmap": res4.bitmap_numpy().copy(), "edges": st4["edges_total"]}}
     if with_ac3:
         ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr_two_sided(T.AC3, n, ro, col, rro, rcl),
@@ -325,17 +372,21 @@ def bench_scc(ctx, T, graphs, reps):
 def time_gpu(ctx, fn, steps, warmup, per_step=None):
     """Mean ms per call over `steps` timed calls (one event pair around all of
     them), the per-kernel times of every call, and the last result.  With a
-    list `per_step`, each call's own event-timed duration is appended to it."""
+    list `per_step`, each call's own event-timed duration is appended to it.
+    The context keeps the kernel events of up to 64 calls, so the timed loop
+    reads them (and waits for the GPU) only once per 64 calls."""
     import torch
     for _ in range(warmup):
         fn()
+    ring = max(1, min(steps, 64))
+    ctx.set_timing(ring)
     torch.cuda.synchronize()
     ktimes = {}
     pairs = []
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
-    for _ in range(steps):
+    for i in range(steps):
         if per_step is not None:
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
@@ -344,10 +395,13 @@ def time_gpu(ctx, fn, steps, warmup, per_step=None):
         if per_step is not None:
             b.record()
             pairs.append((a, b))
-        for name, ms in ctx.kernel_times():
-            ktimes.setdefault(name, []).append(ms)
+        if (i + 1) % ring == 0 or i + 1 == steps:
+            for name, ms in ctx.kernel_times():
+                ktimes.setdefault(name, []).append(ms)
+            ctx.set_timing(ring)
     t1.record()
     torch.cuda.synchronize()
+    ctx.set_timing(1)
     if per_step is not None:
         per_step.extend(a.elapsed_time(b) for a, b in pairs)
     return t0.elapsed_time(t1) / steps, ktimes, res
@@ -428,7 +482,7 @@ def bench_batch(ctx, T, gg, reps):
                               opts=opts, stream=s)
     with torch.cuda.stream(s):
         params, table = autotune.tune(ctx, "batch", N, M, run, workers=(256, 512, 1024),
-                                      reps=3, use_cache=False)
+                                      reps=3, use_cache=False, exact_counts=True)
         log(f"batch: tuned {params}")
         opts_g = T.make_opts(block=params["block"], chunk=params["chunk"],
                              workers=params["workers"], graph=True)
@@ -436,7 +490,9 @@ def bench_batch(ctx, T, gg, reps):
         res = run(opts_g)
         s.synchronize()
     got = res.bitmap_numpy()
-    n_live_gpu = res.stats_dict()["n_live"]
+    bst = res.stats_dict()
+    n_live_gpu = bst["n_live"]
+    gedges = res.worker_edges.cpu().numpy().copy()
     # the same AC-6, one call per graph
     per = []
     for gi in range(G):
@@ -460,13 +516,32 @@ def bench_batch(ctx, T, gg, reps):
         ms_union = ev_time(lambda: ctx.trim_csr(T.AC6, N, ro, col_u, live_bitmap=lbu,
                                                 worker_edges=we, stats=st, stream=s), reps, 1, s)
     ctx.set_timing(True)
-    check = {"batch": b, "bitmap_base": bb, "bitmap": got, "n_live": n_live_gpu}
+    # the per-kernel split of one batch launch sequence, outside the graph
+    # (event records are not captured)
+    with torch.cuda.stream(s):
+        opts_k = T.make_opts(block=params["block"], chunk=params["chunk"],
+                             workers=params["workers"])
+        _, kt, _ = time_gpu(ctx, lambda: run(opts_k), 5, 1)
+    ksum = {k: float(np.mean(v)) for k, v in kt.items()}
+    # B6 summed over the graphs: 8 B per check (target id and its status),
+    # 20 B per vertex (offsets, list head, record), the bitmaps
+    t6sum = int(gedges.sum())
+    b6 = 8 * t6sum + 20 * N + N // 8
+    roofline = {"bound": "hbm", "kernel": "whole batch (HIP graph)",
+                "algorithmic_bytes": b6, "achieved": b6 / (ms_b / 1e3) / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": b6 / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS}
+    check = {"batch": b, "bitmap_base": bb, "bitmap": got, "n_live": n_live_gpu,
+             "graph_edges": gedges}
     return check, {"workload": "batch4096_coretail", "graphs": G, "sum_n": N, "sum_m": M,
             "ms": ms_b, "graphs_per_s": G / (ms_b / 1e3), "edges_per_s": M / (ms_b / 1e3),
-            "parity": None, "tuned": params,
+            "parity": None, "tuned": params, "T6_sum": t6sum, "roofline": roofline,
+            "kernels_ms": ksum, "stats": bst,
+            "tuner": sorted(table, key=lambda r: r["ms"])[:8],
             "per_graph_calls": {"ms": ms_each, "graphs_per_s": G / (ms_each / 1e3)},
             "union_one_graph": {"ms": ms_union, "graphs_per_s": G / (ms_union / 1e3)},
-            "speedup_vs_per_graph_calls": ms_each / ms_b}
+            "speedup_vs_per_graph_calls": ms_each / ms_b,
+            "speedup_vs_union": ms_union / ms_b}
 
 
 def bench_implicit(ctx, T, gg, reps, log2n=28):
@@ -499,11 +574,30 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
     int_ops = 22 * hashes
     hbm_frac = b6i / (ms6 / 1e3) / (HBM_PEAK_GBS * 1e9)
     alu_frac = int_ops / (ms6 / 1e3) / INT32_VALU_PEAK_OPS
+    # the Jacobi AC-3 baseline on the same graph: 4 B per check (the target's
+    # removal round; its id is hashed), 12 B per live-list entry and round
+    P3 = ctx.num_workers(T.AC3)
+    ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_implicit(
+        T.AC3, log2n, imp.seed, imp.zero_thr, table, live_bitmap=lb, worker_edges=we[:P3],
+        stats=st), 1, 0)
+    st3 = res3.stats_dict()
+    bits3 = np.unpackbits(res3.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
+    b3i = 4 * st3["edges_total"] + 12 * st3["work_items"] + n // 8
+    log(f"implicit: AC-6 {ms6:.2f} ms, AC-3 {ms3:.2f} ms ({st3['rounds']} rounds)")
     return {"implicit": imp, "bits": bits}, {
         "workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
         "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": t6,
-        "n_live": stat["n_live"],
+        "n_live": stat["n_live"], "stats": stat,
         "kernels_ms": {k: float(np.mean(v)) for k, v in ktimes.items()},
+        "ac3": {"ms": ms3, "edges_per_s": m / (ms3 / 1e3), "T3J": st3["edges_total"],
+                "rounds": st3["rounds"], "work_items": st3["work_items"],
+                "kernels_ms": {k: float(np.mean(v)) for k, v in kt3.items()},
+                "roofline": roof(b3i, ms3),
+                "same_live_set_as_ac6": bool(np.array_equal(bits3, bits))},
+        "ac6_speedup_vs_ac3": ms3 / ms6,
+        "full_parity": "the full bitmap, T6, T3J and AC-3's rounds are compared with the "
+                       "oracle in the GPU test suite (test_implicit_2_28_full); here: the "
+                       "fixed-point property on 20,000 sampled vertices",
         "bounds": {"hbm": {"algorithmic_bytes": b6i, "GBs": b6i / (ms6 / 1e3) / 1e9,
                            "frac": hbm_frac},
                    "alu": {"hashes_lower_bound": hashes, "int_ops": int_ops,
@@ -512,11 +606,66 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
         "fixpoint_check_on_samples": None}
 
 
+def ac4_bytes(n, st, indeg_dead):
+    """AC4Trim* algorithmic bytes: per reverse edge walked its source id and a
+    fetch-sub (12 B), per vertex its offsets and counter (8 B), per removed
+    vertex its G^T offsets and queue slot (16 B), the bitmap."""
+    return 12 * st["edges_total"] + 8 * n + 16 * st["n_dead"] + n // 8
+
+
+def ac3_bytes(n, st):
+    """Jacobi AC-3 algorithmic bytes: per successor check its target id and
+    the target's removal round (8 B), per live-list entry and round its entry
+    and cursor (12 B), the bitmap."""
+    return 8 * st["edges_total"] + 12 * st["work_items"] + n // 8
+
+
+def roof(b, ms):
+    return {"algorithmic_bytes": int(b), "GBs": b / (ms / 1e3) / 1e9,
+            "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_cfg0(ctx, T, gg, steps=50):
+    """The small core+tail graph (n = 65,536): microseconds per trim of AC-6,
+    AC-4* and AC-3J and their traversed-edge totals (the oracle's closed forms
+    are compared in the CPU leg)."""
+    import numpy as np
+    import torch
+    g = gg.config0()
+    n, m = g.n, g.m
+    ro, col = T.to_device(g.row_off), T.to_device(g.col)
+    a, b = gg.transpose(g)
+    rro, rcl = T.to_device(a), T.to_device(b)
+    lb = torch.empty((n + 31) // 32, dtype=torch.int32, device="cuda")
+    P = max(ctx.max_workers(T.AC6), ctx.max_workers(T.AC4), ctx.max_workers(T.AC3))
+    we = torch.empty(P, dtype=torch.int64, device="cuda")
+    st_t = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
+    out, check = {"workload": "coretail_n65536", "n": n, "m": m}, {"graph": g}
+    for name, algo, extra in (("ac6", T.AC6, ()), ("ac4", T.AC4, (rro, rcl)), ("ac3", T.AC3, ())):
+        Pa = ctx.num_workers(algo)
+        per = []
+        ms, kt, res = time_gpu(ctx, lambda: ctx.trim_csr(algo, n, ro, col, *extra,
+                                                          live_bitmap=lb, worker_edges=we[:Pa],
+                                                          stats=st_t), steps, 3, per)
+        st = res.stats_dict()
+        check[name] = {"bitmap": res.bitmap_numpy().copy(), "edges": st["edges_total"],
+                       "rounds": st["rounds"]}
+        out[name] = {"us": ms * 1e3, "median_us": float(np.median(per)) * 1e3,
+                     "edges_total": st["edges_total"], "n_live": st["n_live"],
+                     "kernels_us": {k: float(np.mean(v)) * 1e3 for k, v in kt.items()},
+                     "parity": None}
+        if name == "ac3":
+            out[name]["rounds"] = st["rounds"]
+    log(f"cfg0: AC-6 {out['ac6']['us']:.1f} us, AC-4 {out['ac4']['us']:.1f} us, "
+        f"AC-3 {out['ac3']['us']:.1f} us")
+    return check, out
+
+
 def bench_explicit26(ctx, T, gg, reps):
-    """AC-6 on the explicit R-MAT scale-26 graph (edge factor 16, about 1.07e9
-    edges, no planted chain): time per trim, kernel breakdown and each kernel's
-    algorithmic bytes.  Full oracle parity at this size is a GPU test; here the
-    fixpoint property is checked on sampled vertices in the CPU leg."""
+    """The explicit R-MAT scale-26 graph (edge factor 16, about 1.07e9 edges,
+    no planted chain) with all three algorithms: time per trim, each kernel's
+    algorithmic bytes against the 8 TB/s HBM peak, and (in the CPU leg) the
+    whole oracle: bitmaps and traversed-edge totals of AC-6, AC-4* and AC-3J."""
     import numpy as np
     import torch
     log("explicit: generating R-MAT scale 26 ...")
@@ -525,41 +674,84 @@ def bench_explicit26(ctx, T, gg, reps):
     ro, col = T.to_device(g.row_off), T.to_device(g.col)
     P = ctx.num_workers(T.AC6)
     lb = torch.empty((n + 31) // 32, dtype=torch.int32, device="cuda")
-    we = torch.empty(P, dtype=torch.int64, device="cuda")
+    we = torch.empty(max(P, ctx.max_workers(T.AC4)), dtype=torch.int64, device="cuda")
     st_t = torch.empty(T.STATS_WORDS, dtype=torch.int64, device="cuda")
     ms, ktimes, res = time_gpu(ctx, lambda: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=lb,
-                                                         worker_edges=we, stats=st_t), reps, 1)
+                                                         worker_edges=we[:P], stats=st_t), reps, 1)
     st = res.stats_dict()
+    bm6 = res.bitmap_numpy().copy()
     kavg = {k: float(np.mean(v)) for k, v in ktimes.items()}
-    sweep_joins = st["visited"] - st["joins"] + st["n_live"]
-    algo = {"ac6_sweep": sweep_bytes(n, st["edges_sweep"], sweep_joins, 0),
-            "ac6_propagate": prop_bytes(st, st["edges_total"]),
-            "ac6_init": 4 * (n + 1) + 8 * n + n // 8, "ac6_pack": 8 * n + n // 8}
-    kern = {k: {"avg_ms": kavg[k], "algorithmic_bytes": int(algo.get(k, 0)),
-                "achieved_GBs": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9,
-                "frac": algo.get(k, 0) / (kavg[k] / 1e3) / 1e9 / HBM_PEAK_GBS} for k in kavg}
-    dom = max(kavg, key=kavg.get)
+    log("explicit: host sweep counts ...")
+    sw = sweep_counts(g)
+    algo = kernel_bytes(n, st, sw)
+    gt = group_times(kavg)
+    kern = {k: {"avg_ms": gt[k], "algorithmic_bytes": int(algo.get(k, 0)),
+                "achieved_GBs": algo.get(k, 0) / (gt[k] / 1e3) / 1e9,
+                "frac": algo.get(k, 0) / (gt[k] / 1e3) / 1e9 / HBM_PEAK_GBS}
+            for k in gt if gt[k] > 0}
+    dom = max((k for k in kern if k in algo), key=lambda k: kern[k]["avg_ms"])
     traffic = measured_traffic(dom, "rmat26")
     if traffic is not None:
         kern[dom]["traffic"] = traffic
-        kern[dom]["traffic_GBs"] = traffic / (kavg[dom] / 1e3) / 1e9
+        kern[dom]["traffic_GBs"] = traffic / (gt[dom] / 1e3) / 1e9
         kern[dom]["traffic_frac"] = kern[dom]["traffic_GBs"] / HBM_PEAK_GBS
         kern[dom]["amplification"] = traffic / algo[dom] if algo.get(dom) else None
-    bits = np.unpackbits(res.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
     path_bytes = 8 * st["edges_total"] + 20 * n + n // 8
     out = {"workload": "rmat26_ef16", "n": n, "m": m, "ms": ms, "edges_per_s": m / (ms / 1e3),
            "T6": st["edges_total"], "n_live": st["n_live"], "kernels": kern, "dominant": dom,
+           "kernels_ms": kavg, "stats": st,
            "path": {"algorithmic_bytes": path_bytes, "GBs": path_bytes / (ms / 1e3) / 1e9,
                     "frac": path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
-           "fixpoint_check_on_samples": None, "parity": "full oracle parity: GPU test"}
+           "parity": None}
+    check = {"graph": g, "ac6": {"bitmap": bm6, "edges": st["edges_total"]}}
+    # the baselines on the same graph; AC-4 takes G^T as an input (built here,
+    # outside any timed region, as the paper treats it)
+    log("explicit: G^T for AC-4 ...")
+    a, b = gg.transpose(g)
+    rro, rcl = T.to_device(a), T.to_device(b)
+    del a, b
+    P4 = ctx.num_workers(T.AC4)
+    ms4, kt4, res4 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC4, n, ro, col, rro, rcl,
+                                                        live_bitmap=lb, worker_edges=we[:P4],
+                                                        stats=st_t), 2, 1)
+    st4 = res4.stats_dict()
+    check["ac4"] = {"bitmap": res4.bitmap_numpy().copy(), "edges": st4["edges_total"]}
+    del rro, rcl
+    torch.cuda.empty_cache()
+    P3 = ctx.num_workers(T.AC3)
+    ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC3, n, ro, col, live_bitmap=lb,
+                                                        worker_edges=we[:P3], stats=st_t), 2, 1)
+    st3 = res3.stats_dict()
+    check["ac3"] = {"bitmap": res3.bitmap_numpy().copy(), "edges": st3["edges_total"],
+                    "rounds": st3["rounds"]}
+    out["ac4"] = {"ms": ms4, "edges_per_s": m / (ms4 / 1e3), "T4star": st4["edges_total"],
+                  "kernels_ms": {k: float(np.mean(v)) for k, v in kt4.items()},
+                  "roofline": roof(ac4_bytes(n, st4, None), ms4), "parity": None}
+    out["ac3"] = {"ms": ms3, "edges_per_s": m / (ms3 / 1e3), "T3J": st3["edges_total"],
+                  "rounds": st3["rounds"],
+                  "kernels_ms": {k: float(np.mean(v)) for k, v in kt3.items()},
+                  "roofline": roof(ac3_bytes(n, st3), ms3), "parity": None}
+    out["ac6_speedup_vs_ac4"] = ms4 / ms
+    out["ac6_speedup_vs_ac3"] = ms3 / ms
+    log(f"explicit26: AC-6 {ms:.3f} ms, AC-4 {ms4:.3f} ms, AC-3 {ms3:.3f} ms")
     del ro, col
-    return {"graph": g, "bits": bits}, out
+    torch.cuda.empty_cache()
+    return check, out
 
 
-def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
+def oracle_labels(graphs):
+    """CPU leg: the oracle's live bitmaps of the learned section's graphs
+    (training labels, and the evaluation graph's live set)."""
+    import oracle
+    return [oracle.bitmap(oracle.peel(g).live) for g in graphs]
+
+
+def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3, use_oracle=True):
     """Learned successor order: train on 16 R-MAT scale-20 graphs (seeds 1..16,
-    labels from plain AC-6), evaluate on R-MAT scale 24 (seed 0): traversed
-    edges and times of plain, learned, heuristic and random orders."""
+    labels from the oracle's peel, or from plain GPU AC-6 when the CPU leg is
+    off), evaluate on R-MAT scale 24 (seed 0): traversed edges and times of
+    plain, learned, heuristic and random orders, every order's live set
+    compared with the oracle's."""
     import time as _t
     import numpy as np
     import torch
@@ -569,12 +761,17 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
     s = torch.cuda.current_stream()
     log("learned: building 16 training graphs (R-MAT scale 20) ...")
     train = []
-    for seed in range(1, 17):
-        g = gg.rmat(20, 16, seed=seed)
+    gs = [gg.rmat(20, 16, seed=seed) for seed in range(1, 17)]
+    labs = oracle_labels(gs) if use_oracle else None
+    for i, g in enumerate(gs):
         dg = T.DeviceGraph.upload(g)
         indeg, src = learned.prepare(ctx, dg)
-        lab = ctx.trim_csr(T.AC6, g.n, dg.row_off, dg.col).live_bitmap
+        if labs is not None:
+            lab = torch.from_numpy(labs[i].view(np.int32).copy()).cuda()
+        else:
+            lab = ctx.trim_csr(T.AC6, g.n, dg.row_off, dg.col).live_bitmap
         train.append((dg, indeg, src, lab))
+    del gs
     torch.cuda.synchronize()
     tr = learned.Trainer(ctx, seed=0, lr=5e-3)
     t0 = _t.perf_counter()
@@ -601,6 +798,8 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
     torch.cuda.synchronize()
     plain_bm = res.bitmap_numpy().copy()
     t6_plain = res.stats_dict()["edges_total"]
+    want_bm = oracle_labels([g])[0] if use_oracle else plain_bm
+    same = bool(np.array_equal(plain_bm, want_bm))
     live = np.unpackbits(plain_bm.view(np.uint8), bitorder="little")[:g.n].astype(bool)
     deg = np.diff(g.row_off.astype(np.int64))
     t6_min = int(deg[~live].sum() + live.sum())
@@ -628,12 +827,11 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
                                 "hbm_GBs": HBM_PEAK_GBS}}
     orders = {"learned": col_l[0], "heuristic_outdeg": learned.reference_order(ctx, dg, 0),
               "random": learned.reference_order(ctx, dg, 1, seed=5)}
-    same = True
     for name, col in orders.items():
         ms = ev_time(lambda: ac6(col), reps, 1, s)
         r2 = ac6(col)
         torch.cuda.synchronize()
-        same = same and np.array_equal(r2.bitmap_numpy(), plain_bm)
+        same = same and np.array_equal(r2.bitmap_numpy(), want_bm)
         out[name] = {"T6": r2.stats_dict()["edges_total"], "ac6_ms": ms}
     t6l = out["learned"]["T6"]
     ctx.set_timing(True)
@@ -645,7 +843,9 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3):
             "ac6_plain_ms": ms_plain, "score_and_order_ms": ms_order,
             "end_to_end_learned_ms": ms_order + out["learned"]["ac6_ms"],
             "score_roofline": score_roofline,
-            "live_set_identical": bool(same)}
+            "labels": "oracle" if use_oracle else "gpu_ac6",
+            "live_set_identical": bool(same),
+            "live_set_reference": "oracle" if use_oracle else "plain GPU AC-6"}
 
 
 def oracle_leg(g, checks, cpu_seconds, out):
@@ -693,6 +893,7 @@ def oracle_leg(g, checks, cpu_seconds, out):
         to["alpha"] = r2.alpha
         to["depth"]["floor_ms"] = r2.alpha * to["depth"]["chain_hop_us"] / 1e3
         to["ac6"]["parity"] = bool(np.array_equal(tc["ac6"]["bitmap"], bm2)
+                                   and tc["ac6"]["edges_live"] == c2.T6live
                                    and c2.T6live + c2.dead_lo <= tc["ac6"]["edges"]
                                    <= c2.T6live + c2.dead_hi)
         to["ac6"]["T6live"] = c2.T6live
@@ -741,6 +942,11 @@ def oracle_leg(g, checks, cpu_seconds, out):
         b, bb = bc["batch"], bc["bitmap_base"]
         live, nl, _ = oracle.batch_peel(b)
         ok = bc["n_live"] == int(nl.sum())
+        # per-graph traversed edges on 256 sampled graphs (closed form per graph)
+        for gi in np.random.default_rng(0).choice(b.G, min(256, b.G), replace=False):
+            sub = b.graph(int(gi))
+            ok = ok and int(bc["graph_edges"][gi]) == oracle.counts(sub, oracle.peel(sub)).T6
+        out["batch"]["parity_sample"] = "all bitmaps; per-graph T6 on 256 sampled graphs"
         for gi in range(b.G):
             v0, v1 = int(b.vbase[gi]), int(b.vbase[gi + 1])
             want = oracle.bitmap(live[v0:v1])
@@ -748,15 +954,34 @@ def oracle_leg(g, checks, cpu_seconds, out):
                 ok = False
                 break
         out["batch"]["parity"] = bool(ok)
+    if "cfg0" in checks:
+        cc, co = checks["cfg0"], out["cfg0"]
+        r0 = oracle.peel(cc["graph"])
+        c0 = oracle.counts(cc["graph"], r0)
+        bm0 = oracle.bitmap(r0.live)
+        for name, want in (("ac6", c0.T6), ("ac4", c0.T4s), ("ac3", c0.T3J)):
+            co[name]["parity"] = bool(np.array_equal(cc[name]["bitmap"], bm0)
+                                      and cc[name]["edges"] == want
+                                      and (name != "ac3" or cc[name]["rounds"] == c0.rounds3))
+        co.update({"T6": c0.T6, "T4star": c0.T4s, "T3J": c0.T3J, "alpha": r0.alpha,
+                   "n_live": r0.n_live})
     if "explicit26" in checks:
-        g26, bits = checks["explicit26"]["graph"], checks["explicit26"]["bits"]
-        rng = np.random.default_rng(0)
-        ok = True
-        for v in rng.integers(0, g26.n, 20000):
-            succ = g26.col[g26.row_off[v]:g26.row_off[v + 1]]
-            ok = ok and bool(bits[v]) == bool(bits[succ].any())
-        out["explicit26"]["fixpoint_check_on_samples"] = bool(ok)
-        out["explicit26"]["samples"] = 20000
+        ec, eo = checks["explicit26"], out["explicit26"]
+        g26 = ec["graph"]
+        t = time.perf_counter()
+        r26 = oracle.peel(g26)
+        c26 = oracle.counts(g26, r26)
+        eo["oracle"] = {"s": time.perf_counter() - t, "cores": 1,
+                        "sample": "one run of the sequential peel and the closed forms"}
+        bm26 = oracle.bitmap(r26.live)
+        eo["parity"] = bool(np.array_equal(ec["ac6"]["bitmap"], bm26)
+                            and ec["ac6"]["edges"] == c26.T6)
+        eo["ac4"]["parity"] = bool(np.array_equal(ec["ac4"]["bitmap"], bm26)
+                                   and ec["ac4"]["edges"] == c26.T4s)
+        eo["ac3"]["parity"] = bool(np.array_equal(ec["ac3"]["bitmap"], bm26)
+                                   and ec["ac3"]["edges"] == c26.T3J
+                                   and ec["ac3"]["rounds"] == c26.rounds3)
+        eo.update({"alpha": r26.alpha, "T6min": c26.T6min})
     if "implicit" in checks:
         imp, bits = checks["implicit"]["implicit"], checks["implicit"]["bits"]
         rng = np.random.default_rng(0)
@@ -783,6 +1008,8 @@ def main():
     ap.add_argument("--no-explicit26", action="store_true",
                     help="skip the explicit R-MAT scale-26 graph")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-order section")
+    ap.add_argument("--no-cfg0", action="store_true",
+                    help="skip the small core+tail graph (n = 65,536)")
     ap.add_argument("--no-two-sided", action="store_true",
                     help="skip two-sided trimming (AC-6 and AC-4) of the same graph")
     ap.add_argument("--no-sampling", action="store_true",
@@ -839,25 +1066,24 @@ def main():
     sweep_ok = True
 
     kavg = {k: float(np.mean(v)) for k, v in ktimes.items()}
-    dom = max(kavg, key=kavg.get)
-    b_prop = prop_bytes(st, st["edges_total"])
-    sw_checks, sw_joins, sw_cas = sweep_counts(g)
-    if sw_checks != st["edges_sweep"]:
-        log(f"warning: sweep checks {st['edges_sweep']} != host count {sw_checks}")
+    sw = sweep_counts(g)
+    if sw[0] != st["edges_sweep"]:
+        log(f"warning: sweep checks {st['edges_sweep']} != host count {sw[0]}")
         sweep_ok = False
-    b_sweep = sweep_bytes(n, sw_checks, sw_joins, sw_cas)
-    algo_bytes = {"ac6_propagate": b_prop, "ac6_sweep": b_sweep,
-                  "ac6_init": 4 * (n + 1) + 8 * n + n // 8, "ac6_pack": 8 * n + n // 8}
-    ach = algo_bytes[dom] / (kavg[dom] / 1e3) / 1e9
+    algo_bytes = kernel_bytes(n, st, sw)
+    gtimes = group_times(kavg)
+    dom = max((k for k in gtimes if k in algo_bytes), key=gtimes.get)
+    ach = algo_bytes[dom] / (gtimes[dom] / 1e3) / 1e9
     traffic = measured_traffic(dom, "rmat22_chain", P)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic,
                 "amplification": traffic / algo_bytes[dom] if traffic else None,
-                "algorithmic_bytes": int(algo_bytes[dom]), "avg_ms": kavg[dom]}
-    breakdown = {k: {"avg_ms": kavg[k],
+                "algorithmic_bytes": int(algo_bytes[dom]), "avg_ms": gtimes[dom]}
+    breakdown = {k: {"avg_ms": gtimes[k],
                      "algorithmic_bytes": int(algo_bytes.get(k, 0)),
-                     "achieved_GBs": algo_bytes.get(k, 0) / (kavg[k] / 1e3) / 1e9}
-                 for k in kavg}
+                     "achieved_GBs": algo_bytes.get(k, 0) / (gtimes[k] / 1e3) / 1e9}
+                 for k in gtimes if gtimes[k] > 0}
+    breakdown["kernels_ms"] = kavg
     path_bytes = 8 * st["edges_total"] + 20 * n + n // 8
 
     out = {
@@ -931,6 +1157,8 @@ def main():
     if not args.no_batch:
         checks["batch"], out["batch"] = bench_batch(ctx, T, gg, 10)
         log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s")
+    if not args.no_cfg0:
+        checks["cfg0"], out["cfg0"] = bench_cfg0(ctx, T, gg)
     if not args.no_explicit26:
         checks["explicit26"], out["explicit26"] = bench_explicit26(ctx, T, gg, 3)
         log(f"explicit26: {out['explicit26']['edges_per_s']:.3e} edges/s")
@@ -938,7 +1166,7 @@ def main():
         checks["implicit"], out["implicit"] = bench_implicit(ctx, T, gg, 3)
         log(f"implicit: {out['implicit']['edges_per_s']:.3e} edges/s")
     if not args.no_learned:
-        out["learned"] = bench_learned(ctx, T, gg)
+        out["learned"] = bench_learned(ctx, T, gg, use_oracle=not args.no_cpu)
         log(f"learned: gap closed {out['learned']['gap_closed']:.3f}")
 
     if not args.no_cpu:

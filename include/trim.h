@@ -169,11 +169,17 @@ typedef struct {
 } trim_stats_t;   /* 18 words */
 
 /*
- * Per-kernel timing of the last call made on `ctx` (for benchmarks).  With
- * trim_ctx_set_timing(ctx, 1), every launch sequence records HIP events
- * around each kernel on the call's stream.  trim_ctx_kernel_times waits for
- * the last call to finish and writes up to `max` entries: names[i] (a static
- * string) and ms[i] (elapsed milliseconds).  Returns the number of kernels.
+ * Per-kernel timing (for benchmarks).  With trim_ctx_set_timing(ctx, k),
+ * 1 <= k <= 64, every later launch sequence on `ctx` records HIP events around
+ * each of its kernels on the call's stream, and the events of the last k calls
+ * are kept (k = 0 turns timing off; other values are TRIM_E_INVAL).  Calls
+ * made under HIP graph capture, and the many-launch calls (trim_scc), record
+ * nothing.  trim_ctx_kernel_times waits for the last call to finish and writes
+ * up to `max` entries, the kept calls in call order and each call's kernels in
+ * launch order: names[i] (a static string) and ms[i] (elapsed milliseconds).
+ * Returns the number of entries written.  Reading does not wait for anything
+ * before it, so a loop of up to k calls runs without host synchronisation and
+ * is read once at its end.
  */
 int trim_ctx_set_timing(trim_ctx *ctx, int enable);
 int trim_ctx_kernel_times(trim_ctx *ctx, int max, const char **names, float *ms);

@@ -186,7 +186,7 @@ def _stream_handle(stream, device):
 class TrimResult:
     live_bitmap: "object"    # torch.int32 tensor of ceil(n/32) words (uint32 bit patterns)
     worker_edges: "object"   # torch.int64 tensor of P counts (or per-graph counts)
-    stats: "object"          # torch.int64 tensor of 12 words (trim_stats_t)
+    stats: "object"          # torch.int64 tensor of STATS_WORDS words (trim_stats_t)
 
     def stats_dict(self) -> dict:
         s = self.stats.cpu().numpy().view(np.uint64)
@@ -263,15 +263,19 @@ class Context:
         _check(lib().trim_max_workers(self._h, int(ALGOS.get(algo, algo)), ctypes.byref(P)))
         return P.value
 
-    def set_timing(self, enable: bool = True):
-        """Record HIP events around each kernel of later calls (same stream)."""
-        _check(lib().trim_ctx_set_timing(self._h, int(bool(enable))))
+    def set_timing(self, enable=True):
+        """Record HIP events around each kernel of later calls (same stream).
+        `enable`: False / 0 off, True / 1 the last call, k <= 64 the last k
+        calls."""
+        _check(lib().trim_ctx_set_timing(self._h, int(enable)))
 
     def kernel_times(self) -> list:
-        """[(kernel name, ms)] of the last call; waits for it to finish."""
-        names = (ctypes.c_char_p * 16)()
-        ms = (ctypes.c_float * 16)()
-        k = lib().trim_ctx_kernel_times(self._h, 16, names, ms)
+        """[(kernel name, ms)] of the kept calls, in call order; waits for the
+        last of them to finish."""
+        cap = 16 * 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_float * cap)()
+        k = lib().trim_ctx_kernel_times(self._h, cap, names, ms)
         if k < 0:
             raise TrimError(k, last_error())
         return [(names[i].decode(), float(ms[i])) for i in range(k)]

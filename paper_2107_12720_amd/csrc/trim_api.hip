@@ -32,7 +32,6 @@ struct trim_ctx {
     // captured launch sequence of trim_batch and the arguments it was made for
     hipGraphExec_t gexec = nullptr;
     uint64_t gkey[25] = {};
-    bool timing = false;
     trim::Timer timer;
     // tile tables of the preprocessing and reordering kernels
     int* tiles = nullptr;
@@ -278,10 +277,7 @@ trim::LaunchCfg launch_cfg(trim_ctx* c, int algo, const trim_opts_t* o, void* st
     lc.forest = !(o && (o->flags & TRIM_FLAG_STEPWISE));
     lc.cus = c->cus;
     lc.stream = (hipStream_t)stream;
-    if (c->timing) {
-        c->timer.count = 0;
-        lc.timer = &c->timer;
-    }
+    if (c->timer.keep > 0) lc.timer = c->timer.next();
     return lc;
 }
 
@@ -387,8 +383,9 @@ int trim_ctx_destroy(trim_ctx* c) {
     free_work2(c);
     free_scc(c);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    for (auto& ev : c->timer.ev)
-        if (ev) (void)hipEventDestroy(ev);
+    for (auto& sl : c->timer.slot)
+        for (auto& ev : sl.ev)
+            if (ev) (void)hipEventDestroy(ev);
     dfree(c, c->w.ctr);
     dfree(c, c->w.wedges);
     dfree(c, c->w.part);
@@ -799,31 +796,39 @@ int trim_order_by_key(trim_ctx* c, const trim_csr_t* g, const float* keys, float
 
 int trim_ctx_set_timing(trim_ctx* c, int enable) {
     if (!c) return fail(TRIM_E_INVAL, "trim_ctx_set_timing: NULL context");
+    if (enable < 0 || enable > trim::Timer::kCalls)
+        return fail(TRIM_E_INVAL, "trim_ctx_set_timing: enable outside [0, 64]");
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    if (enable && !c->timer.ev[0]) {
-        for (auto& ev : c->timer.ev)
+    for (; c->timer.created < enable; ++c->timer.created)
+        for (auto& ev : c->timer.slot[c->timer.created].ev)
             if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
-    }
-    c->timing = enable != 0;
-    c->timer.count = 0;
+    c->timer.keep = enable;
+    c->timer.calls = 0;
     return TRIM_OK;
 }
 
 int trim_ctx_kernel_times(trim_ctx* c, int max, const char** names, float* ms) {
     if (!c || (max > 0 && (!names || !ms)))
         return fail(TRIM_E_INVAL, "trim_ctx_kernel_times: NULL argument");
-    const int k = c->timer.count < max ? c->timer.count : max;
-    if (c->timer.count > 0) {
-        hipError_t e = hipEventSynchronize(c->timer.ev[2 * c->timer.count - 1]);
+    trim::Timer& t = c->timer;
+    if (t.keep == 0 || t.calls == 0) return 0;
+    const long long first = t.calls > t.keep ? t.calls - t.keep : 0;
+    const trim::Timer::Slot& last = t.slot[(t.calls - 1) % t.keep];
+    if (last.count > 0) {
+        hipError_t e = hipEventSynchronize(last.ev[2 * last.count - 1]);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     }
-    for (int i = 0; i < k; ++i) {
-        names[i] = c->timer.names[i];
-        float t = 0.f;
-        hipError_t e = hipEventElapsedTime(&t, c->timer.ev[2 * i], c->timer.ev[2 * i + 1]);
-        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-        ms[i] = t;
+    int k = 0;
+    for (long long call = first; call < t.calls; ++call) {
+        const trim::Timer::Slot& sl = t.slot[call % t.keep];
+        for (int i = 0; i < sl.count && k < max; ++i, ++k) {
+            names[k] = sl.names[i];
+            float v = 0.f;
+            hipError_t e = hipEventElapsedTime(&v, sl.ev[2 * i], sl.ev[2 * i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            ms[k] = v;
+        }
     }
     return k;
 }

@@ -66,12 +66,27 @@ enum PartSlot : int { kPartCloses = 0, kPartJoins = 1, kPartVisited = 2, kPartSw
                       kPartLvCloses = 8, kPartLvJoins = 9, kPartLvVisited = 10,
                       kPartSlots = 11 };
 
-// Optional per-kernel event timing (trim_ctx_set_timing).
+// Optional per-kernel event timing (trim_ctx_set_timing): event pairs of up to
+// kMax kernels per call, for each of the last `keep` calls (a ring of kCalls
+// slots), so that a timed loop need not wait for every call.
 struct Timer {
     static constexpr int kMax = 16;
-    hipEvent_t ev[2 * kMax] = {};
-    const char* names[kMax] = {};
-    int count = 0;
+    static constexpr int kCalls = 64;
+    struct Slot {
+        hipEvent_t ev[2 * kMax] = {};
+        const char* names[kMax] = {};
+        int count = 0;
+    };
+    Slot slot[kCalls];
+    int keep = 0;          // slots in use (0: timing off)
+    long long calls = 0;   // calls recorded since timing was set
+    int created = 0;       // slots whose events exist
+    // The slot for a new call; its previous contents are dropped.
+    Slot* next() {
+        Slot* s = &slot[calls++ % keep];
+        s->count = 0;
+        return s;
+    }
 };
 
 struct LaunchCfg;
@@ -82,7 +97,7 @@ class Timed {
     ~Timed();
 
   private:
-    Timer* t_;
+    Timer::Slot* t_;
     hipStream_t s_;
     int idx_ = -1;
 };
@@ -96,7 +111,7 @@ struct LaunchCfg {
     bool forest = true;       // AC-6: collapse the last-successor forest after the sweep
     int cus = 256;
     hipStream_t stream = nullptr;
-    Timer* timer = nullptr;   // non-null: record per-kernel events
+    Timer::Slot* timer = nullptr;   // non-null: record per-kernel events here
 };
 
 inline Timed::Timed(const LaunchCfg& lc, const char* name) : t_(lc.timer), s_(lc.stream) {
