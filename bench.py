@@ -459,8 +459,9 @@ def ev_time(fn, reps, warmup, stream):
 
 def bench_batch(ctx, T, gg, reps):
     """4,096 core+tail graphs: one autotuned, HIP-graph-captured launch sequence
-    (graphs/s), against the same AC-6 called once per graph and against the
-    disjoint union trimmed as one graph."""
+    (graphs/s; one workgroup per graph), against the union path of trim_batch,
+    the same AC-6 called once per graph, and the disjoint union trimmed as one
+    graph."""
     import numpy as np
     import torch
 
@@ -481,8 +482,12 @@ def bench_batch(ctx, T, gg, reps):
         return ctx.trim_batch(vb, ro, col, bbd, N, M, live_bitmaps=lb, graph_edges=ge, stats=st,
                               opts=opts, stream=s)
     with torch.cuda.stream(s):
-        params, table = autotune.tune(ctx, "batch", N, M, run, workers=(256, 512, 1024),
-                                      reps=3, use_cache=False, exact_counts=True)
+        # one workgroup per graph: the block size is the tuning knob (the
+        # chunk has no meaning there; workers 0 = one workgroup per slot the
+        # occupancy allows)
+        params, table = autotune.tune(ctx, "batch", N, M, run, workers=(0,),
+                                      blocks=(256, 512, 1024), chunks=(0,), reps=3,
+                                      use_cache=False, exact_counts=True)
         log(f"batch: tuned {params}")
         opts_g = T.make_opts(block=params["block"], chunk=params["chunk"],
                              workers=params["workers"], graph=True)
@@ -508,6 +513,14 @@ def bench_batch(ctx, T, gg, reps):
                          stream=s)
     with torch.cuda.stream(s):
         ms_each = ev_time(each, 1, 1, s)
+    # the same batch through the union path of trim_batch (device-wide kernels)
+    opts_u = T.make_opts(flags=T.FLAG_BATCH_UNION, graph=True)
+    with torch.cuda.stream(s):
+        ms_bu = ev_time(lambda: run(opts_u), reps, 2, s)
+        res_u = run(opts_u)
+        s.synchronize()
+    union_path_same = bool(np.array_equal(res_u.bitmap_numpy(), got)
+                           and np.array_equal(res_u.worker_edges.cpu().numpy(), gedges))
     # the disjoint union as one graph (global target ids)
     col_u = T.to_device((b.col.astype(np.int64) + np.repeat(b.vbase[:-1], np.diff(b.ebase)))
                         .astype(np.int32))
@@ -540,6 +553,8 @@ def bench_batch(ctx, T, gg, reps):
             "tuner": sorted(table, key=lambda r: r["ms"])[:8],
             "per_graph_calls": {"ms": ms_each, "graphs_per_s": G / (ms_each / 1e3)},
             "union_one_graph": {"ms": ms_union, "graphs_per_s": G / (ms_union / 1e3)},
+            "batch_union_path": {"ms": ms_bu, "graphs_per_s": G / (ms_bu / 1e3),
+                                 "same_result": union_path_same},
             "speedup_vs_per_graph_calls": ms_each / ms_b,
             "speedup_vs_union": ms_union / ms_b}
 
@@ -1092,7 +1107,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": "rmat22_ef16_chain100k", "algo": "ac6", "n": n, "m": m,
-                   "workers": P, "block": 256, "chunk": 4096},
+                   "workers": P, "block": 256, "chunk": "auto (4096 at this n)"},
         "parity": None, "sweep_counts_match": sweep_ok,
         "roofline": roofline,
         "step_stats": step_stats(per_step),

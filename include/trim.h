@@ -96,7 +96,8 @@ typedef struct {
     int32_t workers;    /* persistent workgroups P (0 = sized from occupancy) */
     int32_t chunk;      /* AC-6: vertices claimed per dynamic work chunk of the first
                            sweep (Section 8, schedule(dynamic, s)); rounded up to a
-                           multiple of block; 0 = 4096 */
+                           multiple of block; 0 = automatic: 4096, or less for graphs
+                           with fewer than 4096 * 4 vertices per CU (at least 256) */
     int32_t validate;   /* 1 = check offsets/targets on the device first (synchronises) */
     int32_t graph;      /* trim_batch only: 1 = capture the launch sequence into a HIP
                            graph on the first call and replay it while every argument
@@ -120,13 +121,23 @@ typedef struct {
  * AC-6 (trim_csr, trim_csr_preset, trim_implicit, trim_batch,
  * trim_csr_noalloc): after the first sweep, a vertex whose support is its last
  * successor is removed exactly when that support is, so these links form a
- * forest whose trees fall with their roots.  By default every tree whose root
- * the first sweep already removed is taken out at once, by pointer jumping in
- * O(log depth) rounds, before the propagation starts; the successor checks
- * are the same.  TRIM_FLAG_STEPWISE instead propagates those removals one at a
- * time through the support lists, as the paper's waiting sets do.
+ * forest whose trees fall with their roots.  By default (explicit graphs)
+ * every tree whose root the first sweep already removed is taken out at once,
+ * by pointer jumping in O(log depth) rounds, before the propagation starts;
+ * the successor checks are the same.  TRIM_FLAG_STEPWISE instead propagates
+ * those removals one at a time through the support lists, as the paper's
+ * waiting sets do.  trim_implicit propagates stepwise unless TRIM_FLAG_FOREST
+ * is given: the jump visits every tree member, also those under a root that
+ * stays, which on a wide, shallow forest costs more than it saves (on the
+ * 2^28-vertex hashed graph: 7.4 ms of jumping to save 3.3 ms of phases).
+ * Deep, narrow trees (long chains) are what the collapse is for.
  */
 #define TRIM_FLAG_STEPWISE 1
+/* trim_implicit: collapse the forest (see above); ignored with STEPWISE. */
+#define TRIM_FLAG_FOREST 4
+/* trim_batch: trim the batch as one disjoint union (device-wide kernels)
+ * instead of one workgroup per graph. */
+#define TRIM_FLAG_BATCH_UNION 2
 
 #define TRIM_DEFAULT_BUDGET (1 << 22)
 
@@ -366,6 +377,12 @@ int trim_implicit(trim_ctx *ctx, int algo, const trim_implicit_t *g, const trim_
 
 /*
  * AC-6 on G independent graphs packed into one CSR, in one launch sequence.
+ * By default each graph is trimmed whole by one workgroup (graphs claimed
+ * largest first; a graph's phases end at workgroup barriers, so graphs never
+ * wait for each other), which suits many small and mid-sized graphs.  With
+ * TRIM_FLAG_BATCH_UNION in opts.flags the batch is trimmed as one disjoint
+ * union by the device-wide kernels of trim_csr, which suits a few large
+ * graphs.  Both give the same bitmaps and per-graph totals.
  * Graph g owns vertices [vbase[g], vbase[g+1]) and their out-edges;
  * row_off (device, vbase[G]+1 entries) is absolute into col; col (device)
  * holds graph-local target ids in [0, vbase[g+1]-vbase[g]).  vbase and

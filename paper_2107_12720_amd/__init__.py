@@ -155,6 +155,8 @@ SCHED_JITTER = 2
 
 
 FLAG_STEPWISE = 1
+FLAG_BATCH_UNION = 2
+FLAG_FOREST = 4
 
 
 def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False, schedule=0,

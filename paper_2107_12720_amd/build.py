@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libtrim.so")
 SOURCES = ["ac6.hip", "ac6_two.hip", "scc.hip", "ac4.hip", "ac3.hip", "mlp.hip", "order.hip",
-           "trim_api.hip", "noalloc.hip"]
+           "trim_api.hip", "noalloc.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          # no packed-fp32 instruction selection (hazard on these parts)

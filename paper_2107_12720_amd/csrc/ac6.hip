@@ -129,7 +129,8 @@ __global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, const uint32
     }
 }
 
-constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-queue append
+constexpr int kCasBuf = 4096;   // entries buffered in LDS before one shared-queue append
+constexpr int kSweepUnroll = 4; // vertices per lane in flight in the first sweep
 // Forest-collapse list entries: a vertex id, with this bit for the vertices the
 // sweep left without a live successor (the removed roots).
 constexpr uint32_t kRootBit = 0x80000000u;
@@ -139,11 +140,21 @@ constexpr uint32_t kRootBit = 0x80000000u;
 // successors left after its support (a root whose fate is open), and ~v (< 0)
 // if v has no live successor (a removed root, listed with kRootBit).  Without
 // jp, the vertices without a live successor are queued as close items.
+//
+// Each lane keeps kSweepUnroll vertices in flight, blockDim apart (so every
+// load of a step is coalesced across the wavefront): the offsets of all of
+// them, then their first targets and those targets' sinks bits, then their
+// joins, are issued before any result is waited for.  The first successor is
+// almost always the support (a sink is rarely anyone's first target), so the
+// serial scan past sinks is the exception.  The join's exchange returns the
+// old head, which goes into the joiner's record: with several joins in flight
+// their round trips overlap instead of adding up.
 template <class View>
 __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* sinks,
                           const uint32_t* preset, uint64_t* rec, uint32_t* q, int* ctr,
                           uint64_t* worker_edges, int P, uint64_t* part, int sched, int* jp,
                           uint32_t* jlist) {
+    constexpr int U = kSweepUnroll;
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t cas[kCasBuf];
     __shared__ int s_chunk, s_ncas, s_base;
@@ -183,51 +194,85 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
         int cb = claim;
         if (sched & TRIM_SCHED_REVERSE) cb = ((n + chunk - 1) / chunk - 1 - claim / chunk) * chunk;
         const int ce = cb + chunk < n ? cb + chunk : n;
-        for (int base = cb; base < ce; base += blockDim.x) {
-            const int v = base + threadIdx.x;
-            bool casualty = false, member = false;
-            uint64_t mine = 0;
-            int gi = 0;
-            if (v < ce) {
-                const int b = g.begin(v), e = g.end(v);
-                degsum += (uint64_t)(e - b);
-                // a preset vertex is removed already: no DoPost
-                if (b < e && !(preset && ((preset[v >> 5] >> (v & 31)) & 1u))) {
-                    gi = g.vctx(v);
-                    int p = b, w = 0;
-                    for (; p < e; ++p) {
-                        w = g.target(v, p, gi);
-                        if (!((sinks[w >> 5] >> (w & 31)) & 1u)) break;
-                    }
-                    if (p < e) {
-                        if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)blockIdx.x << 32) ^ v);
-                        const int old = xchg_dev(head + 2 * w + (p + 1 == e), v);
-                        rec[v] = pack_rec(old, p);
-                        mine = (uint64_t)(p - b + 1);
-                        if (jp) {
-                            member = p + 1 == e;
-                            jp[v] = member ? w : v;
-                        }
-                    } else {
-                        casualty = true;
-                        if (jp) jp[v] = ~v;
-                        mine = (uint64_t)(e - b);
-                    }
+        for (int base = cb; base < ce; base += U * blockDim.x) {
+            int v[U], b[U], e[U], gi[U], p[U], w[U];
+            bool ok[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                v[k] = base + k * blockDim.x + threadIdx.x;
+                b[k] = e[k] = 0;
+                gi[k] = 0;
+                if (v[k] < ce) {
+                    b[k] = g.begin(v[k]);
+                    e[k] = g.end(v[k]);
                 }
             }
-            edges += mine;
-            const bool put = casualty || member;
-            const uint64_t mask = ballot(put);
-            if (mask) {
-                int wbase = 0;
-                if (lane_id() == 0) wbase = atomicAdd(&s_ncas, popc(mask));
-                wbase = __shfl(wbase, 0);
-                if (put)
-                    cas[wbase + popc(mask & lanes_below())] =
-                        jp ? ((uint32_t)v | (casualty ? kRootBit : 0u)) : make_item(0, v);
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                degsum += (uint64_t)(e[k] - b[k]);
+                // a preset vertex is removed already: no DoPost
+                if (preset && b[k] < e[k] && ((preset[v[k] >> 5] >> (v[k] & 31)) & 1u))
+                    e[k] = b[k];
+                p[k] = b[k];
+                w[k] = 0;
+                if (b[k] < e[k]) {
+                    gi[k] = g.vctx(v[k]);
+                    w[k] = g.target(v[k], b[k], gi[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                ok[k] = b[k] < e[k] && !((sinks[w[k] >> 5] >> (w[k] & 31)) & 1u);
+            }
+            // the rare serial scan past sinks
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (b[k] < e[k] && !ok[k]) {
+                    for (++p[k]; p[k] < e[k]; ++p[k]) {
+                        w[k] = g.target(v[k], p[k], gi[k]);
+                        if (!((sinks[w[k] >> 5] >> (w[k] & 31)) & 1u)) break;
+                    }
+                    ok[k] = p[k] < e[k];
+                }
+            }
+            int old[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (ok[k]) {
+                    if (sched & TRIM_SCHED_JITTER)
+                        jitter_nap(((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k]);
+                    old[k] = xchg_dev(head + 2 * w[k] + (p[k] + 1 == e[k]), v[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                bool casualty = false, member = false;
+                if (ok[k]) {
+                    rec[v[k]] = pack_rec(old[k], p[k]);
+                    edges += (uint64_t)(p[k] - b[k] + 1);
+                    if (jp) {
+                        member = p[k] + 1 == e[k];
+                        jp[v[k]] = member ? w[k] : v[k];
+                    }
+                } else if (b[k] < e[k]) {
+                    casualty = true;
+                    if (jp) jp[v[k]] = ~v[k];
+                    edges += (uint64_t)(e[k] - b[k]);
+                }
+                const bool put = casualty || member;
+                const uint64_t mask = ballot(put);
+                if (mask) {
+                    int wbase = 0;
+                    if (lane_id() == 0) wbase = atomicAdd(&s_ncas, popc(mask));
+                    wbase = __shfl(wbase, 0);
+                    if (put)
+                        cas[wbase + popc(mask & lanes_below())] =
+                            jp ? ((uint32_t)v[k] | (casualty ? kRootBit : 0u))
+                               : make_item(0, v[k]);
+                }
             }
             __syncthreads();
-            if (s_ncas > kCasBuf - (int)blockDim.x) flush();
+            if (s_ncas > kCasBuf - U * (int)blockDim.x) flush();
         }
     }
     flush();
@@ -738,7 +783,7 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
                            w.ctr, worker_edges, P, stats);
     }
     if (n > 0) {
-        const int chunk = ((lc.chunk + B - 1) / B) * B;
+        const int chunk = sweep_chunk(lc, n, B);
         sweep_blocks = grid_for(n, chunk, lc.cus * 8);
         {
             Timed t(lc, "ac6_sweep");

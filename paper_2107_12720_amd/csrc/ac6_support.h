@@ -9,8 +9,9 @@ namespace trim {
 // Resume DoPost of u from cursor position p0 of its list in `g` (successors,
 // or predecessors when `g` views G^T).  Returns true if u joined the support
 // list of the first live neighbour found; `edges` receives the positions
-// checked.
-template <class View>
+// checked.  S: memory scope of the record store and the join (agent scope
+// unless one workgroup owns the whole graph).
+template <class View, int S = __HIP_MEMORY_SCOPE_AGENT>
 __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, uint64_t* rec,
                                        uint64_t& edges, int sched) {
     // kScan successors at a time: their targets, then their list heads, each
@@ -32,10 +33,10 @@ __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, 
             int* slot = head + 2 * w[j] + (p + j + 1 == e);
             int hj = h[j];
             while (hj != kDead) {
-                st_dev(rec + u, pack_rec(hj, p + j));
+                st_s<S>(rec + u, pack_rec(hj, p + j));
                 complete_mem();
                 if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)u << 24) ^ (p + j));
-                if (cas_dev(slot, hj, u)) {
+                if (cas_s<S>(slot, hj, u)) {
                     edges += (uint64_t)(p + j - p0 + 1);
                     return true;
                 }

@@ -358,7 +358,7 @@ hipError_t ac6_two_csr_preset(const trim_csr_t& gc, const Work& w, const Work2& 
                            n, dead0, preset, w.ctr, worker_edges, P, stats);
     }
     if (n > 0) {
-        const int chunk = ((lc.chunk + B - 1) / B) * B;
+        const int chunk = sweep_chunk(lc, n, B);
         sweep_blocks = grid_for(n, chunk, lc.cus * 8);
         {
             Timed t(lc, "ac6t_sweep");

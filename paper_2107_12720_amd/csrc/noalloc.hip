@@ -141,11 +141,12 @@ extern "C" int trim_csr_noalloc(const trim_csr_t* g, const trim_opts_t* o,
     w.jp = reinterpret_cast<int*>(d->base + kOffJp);
     w.e = reinterpret_cast<uint32_t*>(d->base + kOffLists);
     w.qwords = kQueueWordsU32;
+    w.cap = kMaxN;
     w.ctr = reinterpret_cast<int*>(d->base + kOffCtr);
     w.part = d->base + kOffPart;
     LaunchCfg lc;
     lc.block = (o && o->block) ? o->block : 256;
-    lc.chunk = (o && o->chunk) ? o->chunk : 4096;
+    lc.chunk = o ? o->chunk : 0;
     lc.schedule = o ? o->schedule : 0;
     lc.workers = (o && o->workers > 0) ? o->workers : TRIM_NOALLOC_WORKERS;
     lc.budget = (o && o->budget > 0) ? o->budget : TRIM_DEFAULT_BUDGET;

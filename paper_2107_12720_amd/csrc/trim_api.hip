@@ -126,6 +126,7 @@ int ensure(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n = cap;
+    c->w.cap = (long long)cap;
     c->w.jp = reinterpret_cast<int*>(c->w.e + 2 * cap);   // after the two lists
     c->w.qwords = (long long)cap * 3 + trim::kQueueSlots;
     return TRIM_OK;
@@ -263,14 +264,15 @@ int check_opts(const trim_opts_t* o) {
     if (o->schedule & ~(TRIM_SCHED_REVERSE | TRIM_SCHED_JITTER))
         return fail(TRIM_E_INVAL, "opts.schedule has unknown bits");
     if (o->budget < 0) return fail(TRIM_E_INVAL, "opts.budget must be >= 0");
-    if (o->flags & ~TRIM_FLAG_STEPWISE) return fail(TRIM_E_INVAL, "opts.flags has unknown bits");
+    if (o->flags & ~(TRIM_FLAG_STEPWISE | TRIM_FLAG_BATCH_UNION | TRIM_FLAG_FOREST))
+        return fail(TRIM_E_INVAL, "opts.flags has unknown bits");
     return TRIM_OK;
 }
 
 trim::LaunchCfg launch_cfg(trim_ctx* c, int algo, const trim_opts_t* o, void* stream) {
     trim::LaunchCfg lc;
     lc.block = (o && o->block) ? o->block : 256;
-    lc.chunk = (o && o->chunk) ? o->chunk : 4096;
+    lc.chunk = o ? o->chunk : 0;
     lc.schedule = o ? o->schedule : 0;
     lc.workers = workers_for(c, algo, o);
     lc.budget = (o && o->budget > 0) ? o->budget : TRIM_DEFAULT_BUDGET;
@@ -612,6 +614,8 @@ int trim_implicit(trim_ctx* c, int algo, const trim_implicit_t* g, const trim_op
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, (int64_t)1 << g->log2n))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
+    // implicit graphs: the forest collapse only on request (see the header)
+    lc.forest = o && (o->flags & TRIM_FLAG_FOREST) && !(o->flags & TRIM_FLAG_STEPWISE);
     e = algo == TRIM_AC6 ? trim::ac6_implicit(*g, c->w, lc, live_bitmap, worker_edges, stats)
                          : trim::ac3_implicit(*g, c->w, lc, live_bitmap, worker_edges, stats);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -633,12 +637,21 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
     if (rc || (rc = check_workers(c, TRIM_AC6, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    if ((rc = ensure(c, total_n))) return rc;
+    if ((rc = ensure(c, total_n > G ? total_n : G))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, TRIM_AC6, o, stream);
     if (o && o->graph) lc.timer = nullptr;   // no event records inside a captured graph
+    const bool uni = o && (o->flags & TRIM_FLAG_BATCH_UNION);
+    // the owned path sizes its grid from its own occupancy unless workers are given
+    trim::LaunchCfg lco = lc;
+    lco.workers = (o && o->workers > 0) ? o->workers : 0;
+    auto run = [&]() {
+        return uni ? trim::ac6_batch(G, vbase, row_off, col, total_n, bitmap_base, c->w, lc,
+                                     live_bitmaps, graph_edges, stats)
+                   : trim::ac6_batch_owned(G, vbase, row_off, col, total_n, bitmap_base, c->w,
+                                           lco, live_bitmaps, graph_edges, stats);
+    };
     if (!(o && o->graph)) {
-        e = trim::ac6_batch(G, vbase, row_off, col, total_n, bitmap_base, c->w, lc, live_bitmaps,
-                            graph_edges, stats);
+        e = run();
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         return TRIM_OK;
     }
@@ -651,7 +664,8 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
                               (uint64_t)lc.workers, (uint64_t)c->w.a, (uint64_t)c->w.b,
                               (uint64_t)c->w.c, (uint64_t)c->w.d, (uint64_t)c->w.q,
                               (uint64_t)c->w.part, (uint64_t)c->w.ctr, (uint64_t)c->w.wedges,
-                              (uint64_t)c->w.e, (uint64_t)lc.forest | ((uint64_t)lc.budget << 1), 1};
+                              (uint64_t)c->w.e, (uint64_t)lc.forest | ((uint64_t)lc.budget << 1),
+                              1u | ((uint64_t)uni << 1)};
     if (!c->gexec || memcmp(key, c->gkey, sizeof key) != 0) {
         if (c->gexec) {
             (void)hipGraphExecDestroy(c->gexec);
@@ -660,8 +674,7 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
         hipGraph_t graph = nullptr;
         if ((e = hipStreamBeginCapture(lc.stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = trim::ac6_batch(G, vbase, row_off, col, total_n, bitmap_base, c->w, lc,
-                                        live_bitmaps, graph_edges, stats);
+        hipError_t le = run();
         e = hipStreamEndCapture(lc.stream, &graph);
         if (le != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);

@@ -75,6 +75,38 @@ __device__ __forceinline__ unsigned add_dev(unsigned* p, unsigned v) {
 __device__ __forceinline__ uint64_t add_dev(uint64_t* p, uint64_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// The same operations at a chosen memory scope (a __HIP_MEMORY_SCOPE_* value):
+// data that only one workgroup touches needs workgroup scope only, which the
+// workgroup's own L2 serves.
+template <int S>
+__device__ __forceinline__ int ld_s(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, S);
+}
+template <int S>
+__device__ __forceinline__ uint64_t ld_s(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, S);
+}
+template <int S>
+__device__ __forceinline__ void st_s(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, S);
+}
+template <int S>
+__device__ __forceinline__ int xchg_s(int* p, int v) {
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, S);
+}
+template <int S>
+__device__ __forceinline__ int2 xchg2_s(int* p, int v0, int v1) {
+    const uint64_t v = ((uint64_t)(uint32_t)v1 << 32) | (uint32_t)v0;
+    const uint64_t old =
+        __hip_atomic_exchange(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED, S);
+    return make_int2((int)(uint32_t)old, (int)(uint32_t)(old >> 32));
+}
+template <int S>
+__device__ __forceinline__ bool cas_s(int* p, int& expected, int desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED,
+                                                __ATOMIC_RELAXED, S);
+}
+
 // Wait until every vector memory operation this wave issued has completed.
 __device__ __forceinline__ void complete_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 

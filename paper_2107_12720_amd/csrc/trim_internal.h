@@ -41,14 +41,16 @@ struct Work {
     int* c = nullptr;         // n int32: AC-6 bitmap of vertices removed at the start /
                               //   AC-3 removal round
     int* d = nullptr;         // n int32: AC-3 cursor / two-sided AC-4 removal flags /
-                              //   batch: first vertex of each vertex's graph
-    uint32_t* e = nullptr;    // 2n uint32: AC-6 forest-collapse lists (two of n)
+                              //   batch: first vertex of each vertex's graph (union
+                              //   path) or the graphs' claim order (owned path)
+    uint32_t* e = nullptr;    // 2n uint32: AC-6 forest-collapse lists / phase lists (two of n)
     int* jp = nullptr;        // n int32: AC-6 forest links
     uint32_t* q = nullptr;    // 3n shared-queue slots, kNone between calls
     long long qwords = 0;     // size of q in words (slack included)
     int* ctr = nullptr;       // kCtrInts control words
     uint64_t* wedges = nullptr;  // per-worker counts when the caller has none (batches)
     uint64_t* part = nullptr;    // per-block partial sums (kPartSlots x kPartStride)
+    long long cap = 0;           // vertices the per-vertex buffers hold
 };
 // Extra working memory of two-sided AC-6 (allocated on its first use).
 struct Work2 {
@@ -104,7 +106,7 @@ class Timed {
 
 struct LaunchCfg {
     int block = 256;          // sweep block size
-    int chunk = 4096;         // vertices per dynamically claimed sweep chunk
+    int chunk = 0;            // vertices per dynamically claimed sweep chunk (0 = automatic)
     int schedule = 0;         // TRIM_SCHED_* perturbation flags (tests)
     int workers = 0;          // persistent workgroups
     int budget = TRIM_DEFAULT_BUDGET;   // watchdog step budget (opts.budget)
@@ -113,6 +115,19 @@ struct LaunchCfg {
     hipStream_t stream = nullptr;
     Timer::Slot* timer = nullptr;   // non-null: record per-kernel events here
 };
+
+// Vertices per dynamically claimed chunk of a first sweep: opts.chunk when
+// given, else 4096 (the paper's s, Section 8) cut down for small graphs so
+// that there are at least four chunks per CU, but never below 256; rounded up
+// to a multiple of the block size.
+inline int sweep_chunk(const LaunchCfg& lc, long long n, int block) {
+    long long c = lc.chunk;
+    if (c <= 0) {
+        c = n / (4LL * (lc.cus > 0 ? lc.cus : 1));
+        c = c < 256 ? 256 : (c > 4096 ? 4096 : c);
+    }
+    return (int)((c + block - 1) / block * block);
+}
 
 inline Timed::Timed(const LaunchCfg& lc, const char* name) : t_(lc.timer), s_(lc.stream) {
     if (t_ && t_->count < Timer::kMax) {
@@ -131,6 +146,12 @@ hipError_t ac6_csr(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
                    uint64_t* worker_edges, trim_stats_t* stats, const uint32_t* preset = nullptr);
 hipError_t ac6_implicit(const trim_implicit_t& g, const Work& w, const LaunchCfg& lc,
                         uint32_t* bitmap, uint64_t* worker_edges, trim_stats_t* stats);
+// trim_batch with one workgroup per graph (batch.hip); the default.
+hipError_t ac6_batch_owned(int G, const int64_t* vbase, const int32_t* row_off,
+                           const int32_t* col, int64_t total_n, const int64_t* bitmap_base,
+                           const Work& w, const LaunchCfg& lc, uint32_t* bitmaps,
+                           uint64_t* graph_edges, trim_stats_t* stats);
+int ac6_owned_blocks_per_cu(int block);
 hipError_t ac6_batch(int G, const int64_t* vbase, const int32_t* row_off, const int32_t* col,
                      int64_t total_n, const int64_t* bitmap_base, const Work& w,
                      const LaunchCfg& lc, uint32_t* bitmaps, uint64_t* graph_edges,

@@ -13,7 +13,7 @@ def test_sweep_counts_by_loop(gen):
     for seed in range(3):
         g = gen.uniform(2000, 2600, seed=seed + 20)
         deg = np.diff(g.row_off)
-        checks = joins = cas = 0
+        checks = joins = cas = members = 0
         for v in range(g.n):
             succ = g.col[g.row_off[v]:g.row_off[v + 1]]
             if succ.size == 0:
@@ -25,7 +25,10 @@ def test_sweep_counts_by_loop(gen):
             else:
                 checks += k + 1
                 joins += 1
-        assert bench.sweep_counts(g) == (checks, joins, cas)
+                members += k == succ.size - 1
+        assert bench.sweep_counts(g) == (checks, joins, cas, members)
+        # the chunked count is the same for any chunk size
+        assert bench.sweep_counts(g, chunk=97) == (checks, joins, cas, members)
 
 
 def test_two_sided_sweep_counts_by_loop(gen):

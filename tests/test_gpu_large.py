@@ -42,13 +42,16 @@ def test_implicit_2_28_full(ctx):
     imp = gg.implicit(log2n=28, seed=0)
     table = T.to_device(imp.table)
     got = {}
-    for a in (6, 3):
-        say(f"  implicit 2^28: AC-{a} ...")
-        res = ctx.trim_implicit(a, 28, imp.seed, imp.zero_thr, table)
+    # the default (stepwise AC-6, as the benchmark runs it), the forest
+    # collapse on request, and AC-3
+    for key, a, flags in (("6", 6, 0), ("6f", 6, T.FLAG_FOREST), ("3", 3, 0)):
+        say(f"  implicit 2^28: AC-{a} flags={flags} ...")
+        res = ctx.trim_implicit(a, 28, imp.seed, imp.zero_thr, table,
+                                opts=T.make_opts(flags=flags))
         assert ctx.status() == 0
         torch.cuda.synchronize()
-        got[a] = (res.bitmap_numpy().copy(), res.stats_dict(),
-                  int(res.worker_edges.sum().item()))
+        got[key] = (res.bitmap_numpy().copy(), res.stats_dict(),
+                    int(res.worker_edges.sum().item()))
         del res
     say("  oracle: materialising POST ...")
     ro, col = oracle.implicit_csr(imp)
@@ -59,8 +62,8 @@ def test_implicit_2_28_full(ctx):
     c = oracle.counts(g, r)
     bm = oracle.bitmap(r.live)
     say(f"  oracle: T6={c.T6} T3J={c.T3J}")
-    for a, want in ((6, c.T6), (3, c.T3J)):
-        bits, st, edges = got[a]
+    for key, a, want in (("6", 6, c.T6), ("6f", 6, c.T6), ("3", 3, c.T3J)):
+        bits, st, edges = got[key]
         assert np.array_equal(bits[: bm.shape[0]], bm), f"AC-{a} bitmap differs at 2^28"
         assert st["edges_total"] == edges == want, (a, st, want)
         assert st["n_live"] == r.n_live, st
