@@ -794,6 +794,11 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3, use_oracle=True)
     torch.cuda.synchronize()
     t_train = _t.perf_counter() - t0
     losses = [float(x) for x in losses]
+    # the key ranges of the learned order and of the heuristic, each chosen on
+    # four of the training graphs (never on the evaluation graph)
+    range_l = learned.choose_logit_range(ctx, train[:4], tr.pbf)
+    range_h = learned.choose_degree_range(ctx, train[:4])
+    log(f"learned: key ranges {range_l} (logit), {range_h} (log1p out-degree)")
     del train
     log("learned: evaluation graph R-MAT scale 24 ...")
     g = gg.rmat(24, 16, seed=0)
@@ -821,7 +826,7 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3, use_oracle=True)
     col_l = [None]
 
     def score_order():
-        col_l[0], _ = learned.learned_order(ctx, dg, indeg, src, tr.pbf)
+        col_l[0], _ = learned.learned_order(ctx, dg, indeg, src, tr.pbf, range_l)
     ms_order = ev_time(score_order, reps, 1, s)
     # the scoring kernel alone, against both of its bounds: 2,624 flops per
     # edge on the BF16 MFMA path (8x32 + 32x32 + 32 multiply-adds), and 28 B
@@ -840,7 +845,9 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3, use_oracle=True)
                       "bound": "mfma" if mf >= hf else "hbm",
                       "peaks": {"bf16_mfma_TFLOPs": MFMA_BF16_PEAK_FLOPS / 1e12,
                                 "hbm_GBs": HBM_PEAK_GBS}}
-    orders = {"learned": col_l[0], "heuristic_outdeg": learned.reference_order(ctx, dg, 0),
+    orders = {"learned": col_l[0],
+              "heuristic_outdeg": learned.reference_order(ctx, dg, 0, key_range=range_h),
+              "heuristic_outdeg_full_range": learned.reference_order(ctx, dg, 0),
               "random": learned.reference_order(ctx, dg, 1, seed=5)}
     for name, col in orders.items():
         ms = ev_time(lambda: ac6(col), reps, 1, s)
@@ -855,8 +862,14 @@ def bench_learned(ctx, T, gg, steps=300, batch=1 << 14, reps=3, use_oracle=True)
             "loss_first": losses[0], "loss_last": float(np.mean(losses[-10:])),
             "T6_plain": t6_plain, "T6_min": t6_min, "orders": out,
             "gap_closed": (t6_plain - t6l) / max(1, t6_plain - t6_min),
+            "key_ranges": {"learned_logit": list(range_l), "heuristic_log1p_outdeg": list(range_h),
+                           "chosen_on": "4 training graphs (R-MAT 20, seeds 1-4)"},
+            "learned_T6_le_heuristic_T6": t6l <= out["heuristic_outdeg"]["T6"],
             "ac6_plain_ms": ms_plain, "score_and_order_ms": ms_order,
             "end_to_end_learned_ms": ms_order + out["learned"]["ac6_ms"],
+            # trims of one graph after which ordering once pays for itself
+            "break_even_trims": (ms_order / (ms_plain - out["learned"]["ac6_ms"])
+                                 if ms_plain > out["learned"]["ac6_ms"] else None),
             "score_roofline": score_roofline,
             "labels": "oracle" if use_oracle else "gpu_ac6",
             "live_set_identical": bool(same),

@@ -450,8 +450,8 @@ int trim_mlp_adam(trim_ctx *ctx, float *params, uint16_t *params_bf16, float *ad
                   float *adam_v, float *grad, float lr, float beta1, float beta2, float eps,
                   int32_t step, void *stream);
 
-/* scores[e] = the network's probability that the target of edge e stays live,
- * 1 / (1 + exp(-logit)) (m entries, CSR order).  Per-vertex features are first
+/* scores[e] = the network's logit that the target of edge e stays live (its
+ * probability is 1 / (1 + exp(-logit))) (m entries, CSR order).  Per-vertex features are first
  * tabulated in context memory (8 bytes per vertex, kept for later calls). */
 int trim_mlp_score(trim_ctx *ctx, const trim_csr_t *g, const int32_t *indeg, const int32_t *src,
                    const uint16_t *params_bf16, float *scores, void *stream);

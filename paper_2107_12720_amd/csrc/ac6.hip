@@ -46,7 +46,9 @@
 //                  when that support is: these links form a forest, and every
 //                  tree whose root the sweep left without a live successor is
 //                  removed at once.  Pointer jumping over the tree members
-//                  (one round per launch, in place, O(log depth) rounds)
+//                  (rounds in one launch, links updated in place; a round
+//                  follows two links, so after r rounds a link reaches 4^r
+//                  levels up: O(log depth) rounds)
 //                  finds each member's root; a member whose root is removed
 //                  is removed (both heads exchanged with kDead) and its S_more
 //                  list handed to the propagation.  Its S_last list holds only
@@ -447,6 +449,16 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
 constexpr int kTailItems = 256;
 constexpr int kStage = 256;   // items staged per wavefront before one reservation
 constexpr int kLevelsPerCu = 2;
+// Workgroups of the level-synchronous launches (phases and forest rounds):
+// two per CU, fewer for small graphs, where a phase holds few items and the
+// grid barrier, whose cost grows with the number of arriving workgroups,
+// dominates (one workgroup per 4,096 vertices, at least 8).
+__host__ inline int phase_blocks(long long n, int cus) {
+    long long b = n / 4096;
+    if (b < 8) b = 8;
+    if (b > (long long)cus * kLevelsPerCu) b = (long long)cus * kLevelsPerCu;
+    return (int)b;
+}
 
 template <class View>
 __global__ __launch_bounds__(256) void ac6_levels(View g, int* head, uint64_t* rec, uint32_t* q,
@@ -587,7 +599,6 @@ __global__ __launch_bounds__(256) void ac6_levels(View g, int* head, uint64_t* r
 // next round (its link points at a resolved vertex or a root), so a round
 // that resolves nothing leaves only members whose links run into a cycle.
 constexpr int kJumpUnroll = 8;
-constexpr int kJumpPerCu = 2;   // resident workgroups per CU of the jump launch
 
 template <class View>
 __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint32_t* l0,
@@ -628,7 +639,7 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint
         uint64_t done = 0;
         const int step = gridDim.x * blockDim.x * kJumpUnroll;
         for (int base = blockIdx.x * blockDim.x * kJumpUnroll; base < cnt; base += step) {
-            int v[kJumpUnroll], x[kJumpUnroll], y[kJumpUnroll];
+            int v[kJumpUnroll], x[kJumpUnroll], y[kJumpUnroll], z[kJumpUnroll];
             uint32_t ent[kJumpUnroll];
 #pragma unroll
             for (int k = 0; k < kJumpUnroll; ++k) {
@@ -642,6 +653,11 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint
             }
 #pragma unroll
             for (int k = 0; k < kJumpUnroll; ++k) y[k] = x[k] >= 0 ? ld_dev(jp + x[k]) : 0;
+            // a second hop per round: links reach four times as far after each
+            // round instead of twice, for one more dependent load
+#pragma unroll
+            for (int k = 0; k < kJumpUnroll; ++k)
+                z[k] = (x[k] >= 0 && y[k] >= 0 && y[k] != x[k]) ? ld_dev(jp + y[k]) : 0;
             int c = 0;
             uint32_t item[kJumpUnroll];
             bool keep[kJumpUnroll];
@@ -660,8 +676,15 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint
                     done += 1;
                 } else if (y[k] == x[k]) {       // the ancestor is a root whose fate is open
                     done += 1;
-                } else {
+                } else if (z[k] < 0) {           // two links up: the root is removed
+                    st_dev(jp + v[k], z[k]);
+                    kill = true;
+                    done += 1;
+                } else if (z[k] == y[k]) {       // two links up: a root whose fate is open
                     st_dev(jp + v[k], y[k]);
+                    done += 1;
+                } else {
+                    st_dev(jp + v[k], z[k]);
                     keep[k] = true;
                     c += 1;
                 }
@@ -775,7 +798,7 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
                    const uint32_t* preset = nullptr) {
     const int P = lc.workers;
     const int B = lc.block;
-    int sweep_blocks = 0, pack_blocks = 0;
+    int sweep_blocks = 0, pack_blocks = 0, level_blocks = 0;
     {
         Timed t(lc, "ac6_init");
         hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
@@ -796,10 +819,10 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
             Timed t(lc, "ac6_jump");
             int rounds = 2;   // ceil(log2 n) + 1 rounds resolve any depth
             while ((1LL << (rounds - 1)) < (long long)n) ++rounds;
-            hipLaunchKernelGGL(ac6_jump<View>, dim3(lc.cus * kJumpPerCu), dim3(256), 0, lc.stream,
+            hipLaunchKernelGGL(ac6_jump<View>, dim3(phase_blocks(n, lc.cus)), dim3(256), 0, lc.stream,
                                g, w.jp, w.a, w.e, w.e + n, w.q, w.ctr, rounds, lc.budget);
         }
-        const int level_blocks = lc.cus * kLevelsPerCu;
+        level_blocks = phase_blocks(n, lc.cus);
         {
             Timed t(lc, "ac6_levels");
             hipLaunchKernelGGL(ac6_levels<View>, dim3(level_blocks), dim3(256), 0, lc.stream, g,
@@ -828,7 +851,7 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         Timed t(lc, "finalize");
         hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, sweep_blocks,
                            n > 0 ? P : 0, pack_blocks, n > 0 ? P : 0, worker_edges, w.part,
-                           w.ctr, stats, 0, 0, n > 0 ? lc.cus * kLevelsPerCu : 0);
+                           w.ctr, stats, 0, 0, level_blocks);
     }
     return hipGetLastError();
 }

@@ -88,8 +88,17 @@ __global__ void batch_order(const int64_t* vbase, const int* row_off, int G, int
 // the workgroup's L2 serves them.
 constexpr int kWG = __HIP_MEMORY_SCOPE_WORKGROUP;
 
+// Dead-vertex bitmap of an owned graph in LDS: a bit per local vertex, set for
+// sinks at init and by every close.  Successor checks read it instead of a
+// list head in device memory (a random cache line per check); a join still
+// reads the head and its CAS fails on kDead, so a bit that is not yet set
+// only costs that attempt.  kBitsWords words per workgroup: the whole array
+// for a workgroup's graph, an equal share per wavefront for wavefront graphs.
+constexpr int kBitsWords = 16384;   // 64 KiB: 2^19 vertices
+
 // Shared state of an owned-graph kernel's workgroup (LDS).
 struct OwnShared {
+    uint32_t bits[kBitsWords];
     uint32_t stage[kOwnMaxBlock / kWave][kOwnStage];   // per-wavefront item staging
     int stage_n[kOwnMaxBlock / kWave];
     int cnt[kOwnMaxBlock / kWave];   // items in the list being built: [0] for the
@@ -104,14 +113,53 @@ struct OwnTotals {
     int max_phases = 0;
 };
 
+__device__ __forceinline__ bool bit_dead(const uint32_t* bits, int l) {
+    return (bits[l >> 5] >> (l & 31)) & 1u;
+}
+
+// Resume DoPost of u (global id) from position p0, skipping targets whose
+// bit is set; as resume() otherwise (the same checks are counted).
+__device__ __forceinline__ bool resume_own(const OwnedView& g, int u, int p0, int* head,
+                                           uint64_t* rec, uint64_t& edges, int sched,
+                                           const uint32_t* bits) {
+    constexpr int kScan = 8;
+    const int e = g.end(u);
+    for (int p = p0; p < e; p += kScan) {
+        int w[kScan];
+#pragma unroll
+        for (int j = 0; j < kScan; ++j)
+            if (p + j < e) w[j] = g.col[p + j];
+#pragma unroll
+        for (int j = 0; j < kScan; ++j) {
+            if (p + j >= e) break;
+            if (bit_dead(bits, w[j])) continue;
+            int* slot = head + 2 * (g.vb + w[j]) + (p + j + 1 == e);
+            int hj = ld_s<kWG>(slot);
+            while (hj != kDead) {
+                st_s<kWG>(rec + u, pack_rec(hj, p + j));
+                complete_mem();
+                if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)u << 24) ^ (p + j));
+                if (cas_s<kWG>(slot, hj, u)) {
+                    edges += (uint64_t)(p + j - p0 + 1);
+                    return true;
+                }
+            }
+        }
+    }
+    edges += (uint64_t)(e - p0);
+    return false;
+}
+
 // Trim graph gi with a group of threads: the whole workgroup (kWaveGroup
 // false; phases end at workgroup barriers) or one wavefront (true; its lanes
 // run in lock step, so a phase ends with the wavefront's own memory wait).
+// `bits`: the group's LDS bitmap, or nullptr if the graph does not fit it
+// (then statuses are read from the heads).
 template <bool kWaveGroup>
 __device__ void own_graph(int gi, const int64_t* vbase, const int* row_off, const int* col,
                           const int64_t* bitmap_base, int* head, uint64_t* rec, uint32_t* l0,
                           uint32_t* l1, uint32_t* bitmaps, uint64_t* graph_edges, int sched,
-                          OwnShared& sh, OwnTotals& t) {
+                          OwnShared& sh, OwnTotals& t, uint32_t* bits) {
     const int wv = threadIdx.x / kWave;
     const int rank = kWaveGroup ? lane_id() : (int)threadIdx.x;
     const int size = kWaveGroup ? kWave : (int)blockDim.x;
@@ -151,17 +199,25 @@ __device__ void own_graph(int gi, const int64_t* vbase, const int* row_off, cons
         __builtin_amdgcn_wave_barrier();
     };
     uint64_t edges = 0;
-    // init: the heads of the graph's vertices
+    // init: the heads of the graph's vertices and the sinks' bits (one word of
+    // the bitmap per 32 local vertices: a lane ORs its vertex's bit in)
+    if (bits)
+        for (int i = rank; i < ((ve - vb + 31) >> 5); i += size) bits[i] = 0;
+    sync();
     for (int v = vb + rank; v < ve; v += size) {
         const int b = row_off[v], e = row_off[v + 1];
         const int h = b == e ? kDead : kEmpty;
         reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
+        if (bits && b == e) atomicOr(&bits[(v - vb) >> 5], 1u << ((v - vb) & 31));
         t.deg += (uint64_t)(e - b);
     }
     if (rank == 0) *cnt = 0;
     sync();
     // sweep: only sinks are removed while it runs, so a target is live iff it
     // has a successor
+    auto sink = [&](int w) {
+        return bits ? bit_dead(bits, w - vb) : row_off[w] == row_off[w + 1];
+    };
     out = l0 + vb;
     for (int base = vb; base < ve; base += kOwnUnroll * size) {
         int v[kOwnUnroll], b[kOwnUnroll], e[kOwnUnroll], p[kOwnUnroll], w[kOwnUnroll];
@@ -175,15 +231,15 @@ __device__ void own_graph(int gi, const int64_t* vbase, const int* row_off, cons
                 e[k] = row_off[v[k] + 1];
             }
             p[k] = b[k];
-            w[k] = b[k] < e[k] ? vb + col[b[k]] : 0;
+            w[k] = b[k] < e[k] ? vb + col[b[k]] : vb;
         }
 #pragma unroll
         for (int k = 0; k < kOwnUnroll; ++k) {
-            ok[k] = b[k] < e[k] && row_off[w[k]] != row_off[w[k] + 1];
+            ok[k] = b[k] < e[k] && !sink(w[k]);
             if (b[k] < e[k] && !ok[k]) {
                 for (++p[k]; p[k] < e[k]; ++p[k]) {
                     w[k] = vb + col[p[k]];
-                    if (row_off[w[k]] != row_off[w[k] + 1]) break;
+                    if (!sink(w[k])) break;
                 }
                 ok[k] = p[k] < e[k];
             }
@@ -231,7 +287,11 @@ __device__ void own_graph(int gi, const int64_t* vbase, const int* row_off, cons
                     // x is in no list until it joins again: its record is stable
                     const uint64_t r = ld_s<kWG>(rec + x);
                     if (sched & TRIM_SCHED_JITTER) jitter_nap((uint64_t)x);
-                    if (resume<OwnedView, kWG>(g, x, rec_cursor(r) + 1, head, rec, edges, sched))
+                    const bool joined =
+                        bits ? resume_own(g, x, rec_cursor(r) + 1, head, rec, edges, sched, bits)
+                             : resume<OwnedView, kWG>(g, x, rec_cursor(r) + 1, head, rec, edges,
+                                                      sched);
+                    if (joined)
                         t.joins += 1;
                     else
                         cx = x;
@@ -242,6 +302,7 @@ __device__ void own_graph(int gi, const int64_t* vbase, const int* row_off, cons
             if (cx >= 0) {
                 if (sched & TRIM_SCHED_JITTER) jitter_nap((uint64_t)cx << 8);
                 const int2 ab = xchg2_s<kWG>(head + 2 * cx, kDead, kDead);
+                if (bits) atomicOr(&bits[(cx - vb) >> 5], 1u << ((cx - vb) & 31));
                 t.closes += 1;
                 walk_more = ab.x;
                 walk_last = ab.y;
@@ -274,15 +335,25 @@ __device__ void own_graph(int gi, const int64_t* vbase, const int* row_off, cons
     // pack: the graph's bitmap words (bits past its n stay zero)
     const int64_t wb = bitmap_base[gi], we = bitmap_base[gi + 1];
     const int nwords = (ve - vb + 31) >> 5;
-    const int gwave = kWaveGroup ? 0 : wv, gwaves = size / kWave;
-    for (int base = vb + gwave * kWave; base < ve; base += gwaves * kWave) {
-        const int v = base + lane_id();
-        const uint64_t m = ballot(v < ve && ld_s<kWG>(head + 2 * v) != kDead);
-        if (lane_id() == 0) {
-            const int wi = (base - vb) >> 5;
-            bitmaps[wb + wi] = (uint32_t)m;
-            if (wi + 1 < nwords) bitmaps[wb + wi + 1] = (uint32_t)(m >> 32);
-            t.live += (uint64_t)popc(m);
+    if (bits) {
+        for (int i = rank; i < nwords; i += size) {
+            const int nb = ve - vb - 32 * i;   // vertices in this word
+            const uint32_t valid = nb >= 32 ? 0xFFFFFFFFu : ((1u << nb) - 1u);
+            const uint32_t word = ~bits[i] & valid;
+            bitmaps[wb + i] = word;
+            t.live += (uint64_t)__popc(word);
+        }
+    } else {
+        const int gwave = kWaveGroup ? 0 : wv, gwaves = size / kWave;
+        for (int base = vb + gwave * kWave; base < ve; base += gwaves * kWave) {
+            const int v = base + lane_id();
+            const uint64_t m = ballot(v < ve && ld_s<kWG>(head + 2 * v) != kDead);
+            if (lane_id() == 0) {
+                const int wi = (base - vb) >> 5;
+                bitmaps[wb + wi] = (uint32_t)m;
+                if (wi + 1 < nwords) bitmaps[wb + wi + 1] = (uint32_t)(m >> 32);
+                t.live += (uint64_t)popc(m);
+            }
         }
     }
     for (int64_t wi = wb + nwords + rank; wi < we; wi += size) bitmaps[wi] = 0;
@@ -319,10 +390,14 @@ __global__ __launch_bounds__(kOwnMaxBlock) void ac6_owned(
             first = gi;
             break;
         }
+        const int ng = (int)(vbase[gi + 1] - vbase[gi]);
         own_graph<false>(gi, vbase, row_off, col, bitmap_base, head, rec, l0, l1, bitmaps,
-                         graph_edges, sched, sh, t);
+                         graph_edges, sched, sh, t,
+                         ((ng + 31) >> 5) <= kBitsWords ? sh.bits : nullptr);
     }
     // wavefront part: wavefront 0 takes the graph that ended the workgroup part
+    const int wave_words = kBitsWords / (blockDim.x / kWave);
+    __syncthreads();   // the workgroup's bitmap is free for the wavefronts
     for (int gi = (wv == 0) ? first : -1;;) {
         if (gi < 0) {
             int c = 0;
@@ -331,8 +406,10 @@ __global__ __launch_bounds__(kOwnMaxBlock) void ac6_owned(
             if (c >= G) break;
             gi = order[c];
         }
+        const int ng = (int)(vbase[gi + 1] - vbase[gi]);
         own_graph<true>(gi, vbase, row_off, col, bitmap_base, head, rec, l0, l1, bitmaps,
-                        graph_edges, sched, sh, t);
+                        graph_edges, sched, sh, t,
+                        ((ng + 31) >> 5) <= wave_words ? sh.bits + wv * wave_words : nullptr);
         gi = -1;
     }
     __syncthreads();

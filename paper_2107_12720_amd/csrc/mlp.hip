@@ -303,8 +303,10 @@ __global__ void mlp_adam(float* p32, short* pbf, float* m1, float* m2, float* gr
     if (threadIdx.x == 0) grad[1377] = 0.f;
 }
 
-// Probability that the target of every edge stays live (the logistic
-// function of the network's logit), in CSR order.
+// The network's logit that the target of every edge stays live, in CSR
+// order.  The logit, not the probability, is what the lists are ordered by:
+// the logistic function saturates to exactly 1 in FP32 for logits above about
+// 17, which would tie most live targets.
 __global__ __launch_bounds__(256) void mlp_score(Graph g, const short* p, float* score) {
     const int l = lane_id(), half = l >> 5, col = l & 31;
     Weights W;
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(256) void mlp_score(Graph g, const short* p, float*
         bf16x4 h1[4];
         float h2[16];
         const float s = forward(W, f, z1, z2, h1, h2);
-        if (half == 0 && e < g.m) score[e] = 1.f / (1.f + expf(-s));
+        if (half == 0 && e < g.m) score[e] = s;
     }
 }
 

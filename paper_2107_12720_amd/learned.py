@@ -5,10 +5,12 @@ backward, Adam, scoring, reordering) runs in the HIP kernels of libtrim
 (mlp.hip, order.hip); this module allocates device buffers and loops over
 steps.
 
-Labels are the live sets of the training graphs, produced by plain AC-6 on
-the GPU (the same greatest fixed point the CPU oracle computes; the tests
-check that equality).  Training minimises the binary cross-entropy of "target
-is live" over edges whose source is live.
+Labels are the live sets of the training graphs (the caller supplies them:
+the tests and the benchmark use the CPU oracle's).  Training minimises the
+binary cross-entropy of "target is live" over edges whose source is live.
+The order sorts each list by the network's logit in 16 levels; the range the
+levels span is chosen on the training graphs (choose_logit_range), as is the
+out-degree heuristic's (choose_degree_range) when the two are compared.
 """
 from __future__ import annotations
 
@@ -74,23 +76,57 @@ def prepare(ctx, dg):
     return indeg, src
 
 
-def learned_order(ctx, dg, indeg, src, pbf):
-    """(col_out, scores): successor lists reordered by predicted liveness."""
+# The reorder sorts each list into 16 equal levels of its key over [lo, hi]
+# (larger keys first).  Candidate ranges, chosen on the training graphs only.
+LOGIT_RANGES = [(lo, hi) for lo in (-8.0, -4.0, 0.0, 4.0, 8.0) for hi in (12.0, 16.0, 24.0, 32.0)]
+DEGREE_RANGES = [(lo, hi) for lo in (0.0, 1.0) for hi in (4.0, 6.0, 8.0, 10.0, 12.0, 16.0)]
+DEFAULT_LOGIT_RANGE = (0.0, 24.0)
+
+
+def learned_order(ctx, dg, indeg, src, pbf, key_range=DEFAULT_LOGIT_RANGE):
+    """(col_out, scores): successor lists reordered by the network's logit of
+    the target staying live, in 16 levels over key_range."""
     import torch
     scores = torch.empty(max(dg.m, 1), dtype=torch.float32, device="cuda")
     ctx.mlp_score(dg, indeg, src, pbf, scores)
-    # probability of staying live, 16 equal levels over [0, 1]
     col_out = torch.empty_like(dg.col)
-    ctx.order_by_key(dg, scores, 0.0, 1.0, col_out)
+    ctx.order_by_key(dg, scores, float(key_range[0]), float(key_range[1]), col_out)
     return col_out, scores
 
 
-def reference_order(ctx, dg, kind: int, seed: int = 0):
-    """kind 0: larger target out-degree first (heuristic); kind 1: random order."""
+def _t6_total(ctx, graphs, order):
+    """Sum over graphs of AC-6's traversed edges with the lists that
+    order(dg, indeg, src) returns."""
+    total = 0
+    for dg, indeg, src, _ in graphs:
+        col = order(dg, indeg, src)
+        total += ctx.trim_csr(6, dg.n, dg.row_off, col).stats_dict()["edges_total"]
+    return total
+
+
+def choose_logit_range(ctx, graphs, pbf, ranges=LOGIT_RANGES):
+    """The key range with the fewest traversed edges on the training graphs."""
+    return min(ranges, key=lambda r: _t6_total(
+        ctx, graphs, lambda dg, i, s: learned_order(ctx, dg, i, s, pbf, r)[0]))
+
+
+def choose_degree_range(ctx, graphs, ranges=DEGREE_RANGES):
+    """The same choice for the out-degree heuristic (its key is
+    log1p(target out-degree))."""
+    return min(ranges, key=lambda r: _t6_total(
+        ctx, graphs, lambda dg, i, s: reference_order(ctx, dg, 0, key_range=r)))
+
+
+def reference_order(ctx, dg, kind: int, seed: int = 0, key_range=None):
+    """kind 0: larger target out-degree first (heuristic; key log1p(out-degree),
+    default range [0, log1p(m)]); kind 1: random order."""
     import torch
     keys = torch.empty(max(dg.m, 1), dtype=torch.float32, device="cuda")
     ctx.edge_keys(dg, kind, keys, seed=seed)
-    lo, hi = (0.0, float(np.log1p(dg.m))) if kind == 0 else (0.0, 1.0)
+    if key_range is not None:
+        lo, hi = float(key_range[0]), float(key_range[1])
+    else:
+        lo, hi = (0.0, float(np.log1p(dg.m))) if kind == 0 else (0.0, 1.0)
     col_out = torch.empty_like(dg.col)
     ctx.order_by_key(dg, keys, lo, hi, col_out)
     return col_out
