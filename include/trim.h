@@ -402,7 +402,7 @@ int trim_batch(trim_ctx *ctx, int32_t G, const int64_t *vbase, const int32_t *ro
  * capture, tight serving loops, hosts that forbid hipMalloc): AC-6 on an
  * explicit graph exactly as trim_csr with TRIM_AC6, with no context and no
  * allocation of any kind.  The working memory is a fixed array inside the
- * library, one copy per GPU (about 42 MB, held until the process ends), on
+ * library, one copy per GPU (about 69 MB, held until the process ends), on
  * the calling thread's current device.  The caller passes inputs and outputs
  * as for trim_csr; worker_edges needs opts.workers entries, or
  * TRIM_NOALLOC_WORKERS when opts.workers is 0.  g->rrow_off / g->rcol are

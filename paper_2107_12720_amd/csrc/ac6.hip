@@ -110,8 +110,9 @@ struct ShareEvery<ImplicitView> {
 // 64); the last wavefront may write one word past ceil(n/32), which the
 // buffer has.
 template <class View>
-__global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, const uint32_t* preset,
-                         int* ctr, uint64_t* worker_edges, int P, trim_stats_t* stats) {
+__global__ void ac6_init(View g, int n, int* head, int* ext, uint32_t* sinks,
+                         const uint32_t* preset, int* ctr, uint64_t* worker_edges, int P,
+                         trim_stats_t* stats) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     Stage<View>::apply(g, lds);
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,6 +124,8 @@ __global__ void ac6_init(View g, int n, int* head, uint32_t* sinks, const uint32
             g.end(v) == g.begin(v) || (preset && ((preset[v >> 5] >> (v & 31)) & 1u));
         const int h = sink ? kDead : kEmpty;
         reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
+        if (ext)
+            for (int j = 0; j < kMoreLists - 1; ++j) ext[(kMoreLists - 1) * (long long)v + j] = h;
         const uint64_t m = ballot(sink);
         if (lane_id() == 0) {
             sinks[v >> 5] = (uint32_t)m;
@@ -152,7 +155,7 @@ constexpr uint32_t kRootBit = 0x80000000u;
 // old head, which goes into the joiner's record: with several joins in flight
 // their round trips overlap instead of adding up.
 template <class View>
-__global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* sinks,
+__global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const uint32_t* sinks,
                           const uint32_t* preset, uint64_t* rec, uint32_t* q, int* ctr,
                           uint64_t* worker_edges, int P, uint64_t* part, int sched, int* jp,
                           uint32_t* jlist) {
@@ -243,7 +246,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, const uint32_t* s
                 if (ok[k]) {
                     if (sched & TRIM_SCHED_JITTER)
                         jitter_nap(((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k]);
-                    old[k] = xchg_dev(head + 2 * w[k] + (p[k] + 1 == e[k]), v[k]);
+                    old[k] = xchg_dev(join_slot(head, ext, w[k], p[k] + 1 == e[k], v[k]), v[k]);
                 }
             }
 #pragma unroll
@@ -307,9 +310,10 @@ constexpr int kHops = 256;   // S_last chain steps one item may take in a row
 constexpr int kWalk = 32;    // S_more members one WALK item hands out in a row
 
 template <class View>
-__global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t* rec, uint32_t* q,
-                                                     int* ctr, uint64_t* worker_edges,
-                                                     uint64_t* part, int sched, int budget) {
+__global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, int* ext, uint64_t* rec,
+                                                     uint32_t* q, int* ctr,
+                                                     uint64_t* worker_edges, uint64_t* part,
+                                                     int sched, int budget) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
@@ -365,7 +369,7 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
                 // rx is in no list until it joins again: its record is stable
                 const uint64_t r = ld_dev(rec + rx);
                 if (sched & TRIM_SCHED_JITTER) jitter_nap(rx);
-                if (resume(g, rx, rec_cursor(r) + 1, head, rec, edges, sched)) {
+                if (resume(g, rx, rec_cursor(r) + 1, head, rec, edges, sched, ext)) {
                     joins += 1;
                     if (cont >= 0) keep = make_item(kWalkMore, cont);
                 } else {
@@ -385,13 +389,14 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
             // loaded: a 32-bit load, so no register of an in-flight load is
             // reused by the pushes below.
             int link = member ? ld_dev(rec_link(rec, cx)) : -1;
-            int2 ab = xchg2_dev(head + 2 * cx, kDead, kDead);   // S_more(cx), S_last(cx)
+            ClosedLists cl = close_lists(head, ext, cx);   // S_more(cx), S_last(cx)
             int fill = 0;   // ring fill read after the previous step's pushes
             for (int hop = 0;; ++hop) {
                 closes += 1;
                 // a dying vertex never joins a list again, so its record is stable
                 const int sib = member ? link : -1;
-                const int a = ab.x, b = ab.y;
+                const ClosedLists cur = cl;
+                const int b = cur.last;
                 // depth first: into S_last(c) if it has members, else on to the
                 // next member of the list c was in
                 const int next = b >= 0 ? b : sib;
@@ -400,9 +405,11 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, uint64_t
                 if (go) {
                     if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)next << 8) ^ hop);
                     link = ld_dev(rec_link(rec, next));
-                    ab = xchg2_dev(head + 2 * next, kDead, kDead);
+                    cl = close_lists(head, ext, next);
                 }
-                if (a >= 0) wq.push1(make_item(kWalkMore, a));
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j)
+                    if (cur.more[j] >= 0) wq.push1(make_item(kWalkMore, cur.more[j]));
                 if (b >= 0 && sib >= 0) wq.push1(make_item(kCloseLast, sib));
                 fill = wq.fill();
                 if (!go) {
@@ -461,7 +468,7 @@ __host__ inline int phase_blocks(long long n, int cus) {
 }
 
 template <class View>
-__global__ __launch_bounds__(256) void ac6_levels(View g, int* head, uint64_t* rec, uint32_t* q,
+__global__ __launch_bounds__(256) void ac6_levels(View g, int* head, int* ext, uint64_t* rec, uint32_t* q,
                                                   uint32_t* l0, uint32_t* l1, int* ctr,
                                                   uint64_t* worker_edges, int P, uint64_t* part,
                                                   int sched, int budget) {
@@ -531,17 +538,22 @@ __global__ __launch_bounds__(256) void ac6_levels(View g, int* head, uint64_t* r
                 it = (uint32_t)ld_dev((const int*)in + i);
                 if (ph == 0) st_dev((int*)q + i, (int)kNone);   // the slot is free again
             }
-            int walk_last = -1, walk_more = -1, cx = -1;
+            // the chains this lane walks: S_last (CLOSE items) and the S_more
+            // lists (RESCAN items), all advanced together
+            int walk_last = -1, cx = -1;
+            int walk_more[kMoreLists];
+#pragma unroll
+            for (int j = 0; j < kMoreLists; ++j) walk_more[j] = -1;
             if (it != kNone) {
                 const int x = item_vertex(it);
                 const uint32_t kind = item_kind(it);
                 if (kind == kWalkMore) {
-                    walk_more = x;
+                    walk_more[0] = x;
                 } else if (kind == kRescan) {
                     // x is in no list until it joins again: its record is stable
                     const uint64_t r = ld_dev(rec + x);
                     if (sched & TRIM_SCHED_JITTER) jitter_nap(x);
-                    if (resume(g, x, rec_cursor(r) + 1, head, rec, edges, sched))
+                    if (resume(g, x, rec_cursor(r) + 1, head, rec, edges, sched, ext))
                         joins += 1;
                     else
                         cx = x;
@@ -551,26 +563,35 @@ __global__ __launch_bounds__(256) void ac6_levels(View g, int* head, uint64_t* r
             }
             if (cx >= 0) {
                 if (sched & TRIM_SCHED_JITTER) jitter_nap((uint64_t)cx << 8);
-                const int2 ab = xchg2_dev(head + 2 * cx, kDead, kDead);
+                const ClosedLists cl = close_lists(head, ext, cx);
                 closes += 1;
-                walk_more = ab.x;
-                walk_last = ab.y;
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j) walk_more[j] = cl.more[j];
+                walk_last = cl.last;
             }
             // a member's link is read before its item exists: its own processing,
             // in the next phase, is the only thing that can change its record
-            while (ballot(walk_last >= 0 || walk_more >= 0)) {
-                uint32_t e = kNone;
-                if (walk_last >= 0) {
-                    const int nx = ld_dev(rec_link(rec, walk_last));
-                    e = make_item(kClose, walk_last);
-                    walk_last = nx;
-                } else if (walk_more >= 0) {
-                    const int nx = ld_dev(rec_link(rec, walk_more));
-                    e = make_item(kRescan, walk_more);
-                    walk_more = nx;
+            auto active = [&]() {
+                bool a = walk_last >= 0;
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j) a = a || walk_more[j] >= 0;
+                return a;
+            };
+            while (ballot(active())) {
+                int nl = -1, nm[kMoreLists];
+                if (walk_last >= 0) nl = ld_dev(rec_link(rec, walk_last));
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j)
+                    nm[j] = walk_more[j] >= 0 ? ld_dev(rec_link(rec, walk_more[j])) : -1;
+                visited += walk_last >= 0;
+                emit(walk_last >= 0 ? make_item(kClose, walk_last) : kNone);
+                walk_last = nl;
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j) {
+                    visited += walk_more[j] >= 0;
+                    emit(walk_more[j] >= 0 ? make_item(kRescan, walk_more[j]) : kNone);
+                    walk_more[j] = nm[j];
                 }
-                visited += e != kNone;
-                emit(e);
             }
         }
         flush();
@@ -598,13 +619,20 @@ __global__ __launch_bounds__(256) void ac6_levels(View g, int* head, uint64_t* r
 // Stop rule: the unresolved member nearest its root always resolves in the
 // next round (its link points at a resolved vertex or a root), so a round
 // that resolves nothing leaves only members whose links run into a cycle.
-constexpr int kJumpUnroll = 8;
+// Entries per thread per step: more would leave most workgroups idle when a
+// round's list is short.
+constexpr int kJumpUnroll = 2;
+
+// WALK items of one round step buffered in LDS: up to kMoreLists per removed
+// vertex, kJumpUnroll vertices per thread, plus what is left from before.
+constexpr int kJumpStep = 256 * kJumpUnroll * kMoreLists;
+constexpr int kJumpBuf = kJumpStep + 4096;
 
 template <class View>
-__global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint32_t* l0,
+__global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, int* ext, uint32_t* l0,
                                                 uint32_t* l1, uint32_t* q, int* ctr,
                                                 int max_rounds, int budget) {
-    __shared__ uint32_t buf[kCasBuf];   // S_more heads of removed vertices: walk items
+    __shared__ uint32_t buf[kJumpBuf];   // S_more heads of removed vertices: walk items
     __shared__ int s_nbuf, s_base, s_wave[256 / kWave];
     __shared__ uint64_t red[16];
     if (threadIdx.x == 0) s_nbuf = 0;
@@ -659,11 +687,12 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint
             for (int k = 0; k < kJumpUnroll; ++k)
                 z[k] = (x[k] >= 0 && y[k] >= 0 && y[k] != x[k]) ? ld_dev(jp + y[k]) : 0;
             int c = 0;
-            uint32_t item[kJumpUnroll];
+            uint32_t item[kJumpUnroll][kMoreLists];
             bool keep[kJumpUnroll];
 #pragma unroll
             for (int k = 0; k < kJumpUnroll; ++k) {
-                item[k] = kNone;
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j) item[k][j] = kNone;
                 keep[k] = false;
                 bool kill = false;
                 if (ent[k] == kNone) {
@@ -689,8 +718,10 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint
                     c += 1;
                 }
                 if (kill) {
-                    const int2 ab = xchg2_dev(head + 2 * v[k], kDead, kDead);
-                    if (ab.x >= 0) item[k] = make_item(kWalkMore, ab.x);
+                    const ClosedLists cl = close_lists(head, ext, v[k]);
+#pragma unroll
+                    for (int j = 0; j < kMoreLists; ++j)
+                        if (cl.more[j] >= 0) item[k][j] = make_item(kWalkMore, cl.more[j]);
                     killed += 1;
                 }
             }
@@ -698,16 +729,20 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, uint
 #pragma unroll
             for (int k = 0; k < kJumpUnroll; ++k) {
                 if (keep[k]) st_dev((int*)lout + slot++, v[k]);
-                const uint64_t mask = ballot(item[k] != kNone);
-                if (mask) {
-                    int wbase = 0;
-                    if (lane_id() == 0) wbase = atomicAdd(&s_nbuf, popc(mask));
-                    wbase = __shfl(wbase, 0);
-                    if (item[k] != kNone) buf[wbase + popc(mask & lanes_below())] = item[k];
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j) {
+                    const uint64_t mask = ballot(item[k][j] != kNone);
+                    if (mask) {
+                        int wbase = 0;
+                        if (lane_id() == 0) wbase = atomicAdd(&s_nbuf, popc(mask));
+                        wbase = __shfl(wbase, 0);
+                        if (item[k][j] != kNone)
+                            buf[wbase + popc(mask & lanes_below())] = item[k][j];
+                    }
                 }
             }
             __syncthreads();
-            if (s_nbuf > kCasBuf - (int)blockDim.x * kJumpUnroll) flush();
+            if (s_nbuf > kJumpBuf - kJumpStep) flush();
         }
         done = block_sum(done, red);
         if (threadIdx.x == 0 && done) add_dev(ctr + kJDone0 + r % 3, (int)done);
@@ -799,10 +834,13 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     const int P = lc.workers;
     const int B = lc.block;
     int sweep_blocks = 0, pack_blocks = 0, level_blocks = 0;
+    // split S_more lists for graphs up to kSplitMaxN vertices (their extra
+    // heads exist only then)
+    int* ext = (w.ext && n <= kSplitMaxN) ? w.ext : nullptr;
     {
         Timed t(lc, "ac6_init");
         hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           lc.stream, g, n, w.a, reinterpret_cast<uint32_t*>(w.c), preset,
+                           lc.stream, g, n, w.a, ext, reinterpret_cast<uint32_t*>(w.c), preset,
                            w.ctr, worker_edges, P, stats);
     }
     if (n > 0) {
@@ -811,7 +849,7 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         {
             Timed t(lc, "ac6_sweep");
             hipLaunchKernelGGL(ac6_sweep<View>, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n,
-                               chunk, w.a, reinterpret_cast<const uint32_t*>(w.c), preset, w.b,
+                               chunk, w.a, ext, reinterpret_cast<const uint32_t*>(w.c), preset, w.b,
                                w.q, w.ctr, worker_edges, P, w.part, lc.schedule,
                                lc.forest ? w.jp : nullptr, lc.forest ? w.e : nullptr);
         }
@@ -820,19 +858,19 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
             int rounds = 2;   // ceil(log2 n) + 1 rounds resolve any depth
             while ((1LL << (rounds - 1)) < (long long)n) ++rounds;
             hipLaunchKernelGGL(ac6_jump<View>, dim3(phase_blocks(n, lc.cus)), dim3(256), 0, lc.stream,
-                               g, w.jp, w.a, w.e, w.e + n, w.q, w.ctr, rounds, lc.budget);
+                               g, w.jp, w.a, ext, w.e, w.e + n, w.q, w.ctr, rounds, lc.budget);
         }
         level_blocks = phase_blocks(n, lc.cus);
         {
             Timed t(lc, "ac6_levels");
             hipLaunchKernelGGL(ac6_levels<View>, dim3(level_blocks), dim3(256), 0, lc.stream, g,
-                               w.a, w.b, w.q, w.e, w.e + n, w.ctr, worker_edges, P, w.part,
+                               w.a, ext, w.b, w.q, w.e, w.e + n, w.ctr, worker_edges, P, w.part,
                                lc.schedule, lc.budget);
         }
         {
             Timed t(lc, "ac6_propagate");
             hipLaunchKernelGGL(ac6_propagate<View>, dim3(P), dim3(256), 0, lc.stream, g, w.a,
-                               w.b, w.q, w.ctr, worker_edges, w.part, lc.schedule, lc.budget);
+                               ext, w.b, w.q, w.ctr, worker_edges, w.part, lc.schedule, lc.budget);
         }
         if (!bitmap_base) {
             Timed t(lc, "ac6_pack");

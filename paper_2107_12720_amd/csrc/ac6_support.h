@@ -6,14 +6,45 @@
 
 namespace trim {
 
+// Split S_more lists: with `ext` (3 ints per vertex), S_more(w) is four
+// lists -- head[2w] and ext[3w .. 3w+2] -- and joiner u goes to list u & 3,
+// so a closed hub's supporters come back as four chains that are walked side
+// by side.  S_last(w) stays one list (head[2w+1]).  ext == nullptr: one list.
+constexpr int kMoreLists = 4;
+__device__ __forceinline__ int* join_slot(int* head, int* ext, int w, bool last, int u) {
+    if (last) return head + 2 * w + 1;
+    const int s = u & (kMoreLists - 1);
+    return (s == 0 || !ext) ? head + 2 * w : ext + (kMoreLists - 1) * w + (s - 1);
+}
+// The heads of a closed vertex's lists: more[0..3] (kEmpty = none), last.
+struct ClosedLists {
+    int more[kMoreLists];
+    int last;
+};
+// Close x: exchange every list head of x with kDead (the exchanges are
+// independent, so their round trips overlap).  Each list, on its own, is
+// closed with the guarantee of the unsplit close: nobody joins it after its
+// exchange, and every earlier joiner comes back in the returned chain.
+__device__ __forceinline__ ClosedLists close_lists(int* head, int* ext, int x) {
+    ClosedLists c;
+    const int2 ab = xchg2_dev(head + 2 * x, kDead, kDead);
+    c.more[0] = ab.x;
+    c.last = ab.y;
+#pragma unroll
+    for (int j = 1; j < kMoreLists; ++j)
+        c.more[j] = ext ? xchg_dev(ext + (kMoreLists - 1) * x + (j - 1), kDead) : kEmpty;
+    return c;
+}
+
 // Resume DoPost of u from cursor position p0 of its list in `g` (successors,
 // or predecessors when `g` views G^T).  Returns true if u joined the support
 // list of the first live neighbour found; `edges` receives the positions
 // checked.  S: memory scope of the record store and the join (agent scope
-// unless one workgroup owns the whole graph).
+// unless one workgroup owns the whole graph).  ext: the split S_more lists,
+// or nullptr.
 template <class View, int S = __HIP_MEMORY_SCOPE_AGENT>
 __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, uint64_t* rec,
-                                       uint64_t& edges, int sched) {
+                                       uint64_t& edges, int sched, int* ext = nullptr) {
     // kScan successors at a time: their targets, then their list heads, each
     // group of loads in flight together, then the joins in list order.
     constexpr int kScan = 4;
@@ -26,11 +57,11 @@ __device__ __forceinline__ bool resume(const View& g, int u, int p0, int* head, 
             if (p + j < e) w[j] = g.target(u, p + j, ctx);
 #pragma unroll
         for (int j = 0; j < kScan; ++j)
-            if (p + j < e) h[j] = ld_cached(head + 2 * w[j] + (p + j + 1 == e));
+            if (p + j < e) h[j] = ld_cached(join_slot(head, ext, w[j], p + j + 1 == e, u));
 #pragma unroll
         for (int j = 0; j < kScan; ++j) {
             if (p + j >= e) break;
-            int* slot = head + 2 * w[j] + (p + j + 1 == e);
+            int* slot = join_slot(head, ext, w[j], p + j + 1 == e, u);
             int hj = h[j];
             while (hj != kDead) {
                 st_s<S>(rec + u, pack_rec(hj, p + j));

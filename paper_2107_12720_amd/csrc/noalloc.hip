@@ -11,10 +11,11 @@
 // device and passed to the kernels.  Layout (256-byte aligned pieces), for
 // n <= TRIM_NOALLOC_MAX_N and at most TRIM_NOALLOC_WORKERS workers:
 //   list heads   2n int32        records   n uint64
-//   sinks bitmap n/32 + 2 words  queue     3n + 64 * 4 * workers uint32
+//   sinks bitmap n/32 + 2 words  queue     6n + 64 * 4 * workers uint32
 //   forest links n int32         forest lists 2n uint32
+//   split S_more heads 3n int32
 //   control      kCtrInts int32  partials  kPartSlots * kPartStride uint64
-// about 42 MB in all.  Every call overwrites what it reads before reading it,
+// about 69 MB in all.  Every call overwrites what it reads before reading it,
 // except the queue, whose free slots must hold kNone: the first call on a
 // device fills it with a kernel, and every later call leaves it that way
 // (consumers restore each slot they take; a call abandoned by the watchdog
@@ -33,7 +34,8 @@ constexpr long long round256(long long words) {
     return (words + kWords256 - 1) / kWords256 * kWords256;
 }
 constexpr long long kMaxN = TRIM_NOALLOC_MAX_N;
-constexpr long long kQueueWordsU32 = 3 * kMaxN + 64LL * 4 * TRIM_NOALLOC_WORKERS;
+static_assert(kMaxN <= kSplitMaxN, "the fixed array holds the split S_more heads");
+constexpr long long kQueueWordsU32 = 6 * kMaxN + 64LL * 4 * TRIM_NOALLOC_WORKERS;
 // offsets in uint64 words
 constexpr long long kOffHead = 0;
 constexpr long long kOffRec = kOffHead + round256(kMaxN);             // 2n int32
@@ -41,7 +43,8 @@ constexpr long long kOffSinks = kOffRec + round256(kMaxN);            // n uint6
 constexpr long long kOffQueue = kOffSinks + round256(kMaxN / 64 + 2); // n/32 + 2 (+1) uint32
 constexpr long long kOffJp = kOffQueue + round256((kQueueWordsU32 + 1) / 2);   // n int32
 constexpr long long kOffLists = kOffJp + round256(kMaxN / 2);                     // 2n uint32
-constexpr long long kOffCtr = kOffLists + round256(kMaxN);
+constexpr long long kOffExt = kOffLists + round256(kMaxN);                     // 3n int32
+constexpr long long kOffCtr = kOffExt + round256((3 * kMaxN + 1) / 2);
 constexpr long long kOffPart = kOffCtr + round256(kCtrInts / 2);
 constexpr long long kScratchWords = kOffPart + round256((long long)kPartSlots * kPartStride);
 
@@ -140,6 +143,7 @@ extern "C" int trim_csr_noalloc(const trim_csr_t* g, const trim_opts_t* o,
     w.q = reinterpret_cast<uint32_t*>(d->base + kOffQueue);
     w.jp = reinterpret_cast<int*>(d->base + kOffJp);
     w.e = reinterpret_cast<uint32_t*>(d->base + kOffLists);
+    w.ext = reinterpret_cast<int*>(d->base + kOffExt);
     w.qwords = kQueueWordsU32;
     w.cap = kMaxN;
     w.ctr = reinterpret_cast<int*>(d->base + kOffCtr);

@@ -97,8 +97,10 @@ void free_work(trim_ctx* c) {
     dfree(c, c->w.d);
     dfree(c, c->w.q);
     dfree(c, c->w.e);
+    dfree(c, c->w.ext);
     c->w.q = nullptr;
     c->w.e = nullptr;
+    c->w.ext = nullptr;
     c->w.jp = nullptr;
     c->w.a = nullptr;
     c->w.b = nullptr;
@@ -112,14 +114,19 @@ int ensure(trim_ctx* c, int64_t n) {
     if (need <= c->cap_n) return TRIM_OK;
     free_work(c);
     size_t cap = need + need / 8 + 64;
+    // the split S_more lists (and the queue room they need) for graphs that
+    // use them
+    const bool split = (long long)need <= trim::kSplitMaxN;
+    const size_t qslots = cap * (split ? 6 : 3) + (size_t)trim::kQueueSlots;
     if (dmalloc(c, &c->w.a, cap * 8) != hipSuccess ||
         dmalloc(c, &c->w.b, cap * 8) != hipSuccess ||
         dmalloc(c, &c->w.c, cap * 4) != hipSuccess ||
         dmalloc(c, &c->w.d, cap * 4) != hipSuccess ||
         dmalloc(c, &c->w.e, cap * 12) != hipSuccess ||
-        dmalloc(c, &c->w.q, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess ||
+        (split && dmalloc(c, &c->w.ext, cap * 12) != hipSuccess) ||
+        dmalloc(c, &c->w.q, qslots * 4) != hipSuccess ||
         // free queue slots hold kNone (all ones); consumers restore it
-        hipMemset(c->w.q, 0xFF, cap * 12 + (size_t)trim::kQueueSlots * 4) != hipSuccess) {
+        hipMemset(c->w.q, 0xFF, qslots * 4) != hipSuccess) {
         (void)hipGetLastError();
         free_work(c);
         return fail(TRIM_E_NOMEM, "cannot allocate working memory for %lld vertices",
@@ -128,7 +135,7 @@ int ensure(trim_ctx* c, int64_t n) {
     c->cap_n = cap;
     c->w.cap = (long long)cap;
     c->w.jp = reinterpret_cast<int*>(c->w.e + 2 * cap);   // after the two lists
-    c->w.qwords = (long long)cap * 3 + trim::kQueueSlots;
+    c->w.qwords = (long long)qslots;
     return TRIM_OK;
 }
 
