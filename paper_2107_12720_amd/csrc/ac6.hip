@@ -47,8 +47,8 @@
 //                  tree whose root the sweep left without a live successor is
 //                  removed at once.  Pointer jumping over the tree members
 //                  (rounds in one launch, links updated in place; a round
-//                  follows two links, so after r rounds a link reaches 4^r
-//                  levels up: O(log depth) rounds)
+//                  follows kJumpHops links, so after r rounds a link spans
+//                  kJumpHops^r levels: O(log depth) rounds)
 //                  finds each member's root; a member whose root is removed
 //                  is removed (both heads exchanged with kDead) and its S_more
 //                  list handed to the propagation.  Its S_last list holds only
@@ -622,6 +622,9 @@ __global__ __launch_bounds__(256) void ac6_levels(View g, int* head, int* ext, u
 // Entries per thread per step: more would leave most workgroups idle when a
 // round's list is short.
 constexpr int kJumpUnroll = 2;
+// Links an entry follows per round (at least 2): a link that spans d levels
+// spans kJumpHops * d after the round (2 is classic pointer doubling).
+constexpr int kJumpHops = 8;
 
 // WALK items of one round step buffered in LDS: up to kMoreLists per removed
 // vertex, kJumpUnroll vertices per thread, plus what is left from before.
@@ -667,7 +670,8 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, int*
         uint64_t done = 0;
         const int step = gridDim.x * blockDim.x * kJumpUnroll;
         for (int base = blockIdx.x * blockDim.x * kJumpUnroll; base < cnt; base += step) {
-            int v[kJumpUnroll], x[kJumpUnroll], y[kJumpUnroll], z[kJumpUnroll];
+            // anc[k][h]: where v[k]'s link leads after h + 1 links
+            int v[kJumpUnroll], anc[kJumpUnroll][kJumpHops];
             uint32_t ent[kJumpUnroll];
 #pragma unroll
             for (int k = 0; k < kJumpUnroll; ++k) {
@@ -677,15 +681,18 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, int*
 #pragma unroll
             for (int k = 0; k < kJumpUnroll; ++k) {
                 v[k] = (int)(ent[k] & ~kRootBit);
-                x[k] = (ent[k] != kNone && !(ent[k] & kRootBit)) ? ld_dev(jp + v[k]) : -1;
+                anc[k][0] = (ent[k] != kNone && !(ent[k] & kRootBit)) ? ld_dev(jp + v[k]) : -1;
             }
+            // further links, each one more dependent load; a link is followed
+            // only from a member (a root's link is itself or < 0)
 #pragma unroll
-            for (int k = 0; k < kJumpUnroll; ++k) y[k] = x[k] >= 0 ? ld_dev(jp + x[k]) : 0;
-            // a second hop per round: links reach four times as far after each
-            // round instead of twice, for one more dependent load
+            for (int h = 1; h < kJumpHops; ++h)
 #pragma unroll
-            for (int k = 0; k < kJumpUnroll; ++k)
-                z[k] = (x[k] >= 0 && y[k] >= 0 && y[k] != x[k]) ? ld_dev(jp + y[k]) : 0;
+                for (int k = 0; k < kJumpUnroll; ++k) {
+                    const int a = anc[k][h - 1];
+                    const bool member = a >= 0 && (h < 2 || a != anc[k][h - 2]);
+                    anc[k][h] = member ? ld_dev(jp + a) : a;
+                }
             int c = 0;
             uint32_t item[kJumpUnroll][kMoreLists];
             bool keep[kJumpUnroll];
@@ -699,23 +706,35 @@ __global__ __launch_bounds__(256) void ac6_jump(View g, int* jp, int* head, int*
                     // past the end of the list
                 } else if (ent[k] & kRootBit) {
                     kill = true;                 // a removed root
-                } else if (y[k] < 0) {           // the ancestor's root is removed, so v's is
-                    st_dev(jp + v[k], y[k]);
-                    kill = true;
-                    done += 1;
-                } else if (y[k] == x[k]) {       // the ancestor is a root whose fate is open
-                    done += 1;
-                } else if (z[k] < 0) {           // two links up: the root is removed
-                    st_dev(jp + v[k], z[k]);
-                    kill = true;
-                    done += 1;
-                } else if (z[k] == y[k]) {       // two links up: a root whose fate is open
-                    st_dev(jp + v[k], y[k]);
-                    done += 1;
                 } else {
-                    st_dev(jp + v[k], z[k]);
-                    keep[k] = true;
-                    c += 1;
+                    // the first link that is a removed root's mark (< 0) or an
+                    // open root (its link is itself) settles v; else v keeps
+                    // the farthest ancestor
+                    int prev = anc[k][0], outcome = 0, to = anc[k][kJumpHops - 1];
+#pragma unroll
+                    for (int h = 1; h < kJumpHops; ++h) {
+                        const int a = anc[k][h];
+                        if (outcome == 0 && a < 0) {
+                            outcome = 1;
+                            to = a;
+                        } else if (outcome == 0 && a == prev) {
+                            outcome = 2;
+                            to = prev;
+                        }
+                        prev = a;
+                    }
+                    if (outcome == 1) {          // the root is removed, so v is
+                        st_dev(jp + v[k], to);
+                        kill = true;
+                        done += 1;
+                    } else if (outcome == 2) {   // the root's fate is open
+                        if (to != anc[k][0]) st_dev(jp + v[k], to);
+                        done += 1;
+                    } else {
+                        st_dev(jp + v[k], to);
+                        keep[k] = true;
+                        c += 1;
+                    }
                 }
                 if (kill) {
                     const ClosedLists cl = close_lists(head, ext, v[k]);

@@ -6,17 +6,17 @@
 
 namespace trim {
 
-// Split S_more lists: with `ext` (3 ints per vertex), S_more(w) is four
-// lists -- head[2w] and ext[3w .. 3w+2] -- and joiner u goes to list u & 3,
-// so a closed hub's supporters come back as four chains that are walked side
-// by side.  S_last(w) stays one list (head[2w+1]).  ext == nullptr: one list.
-constexpr int kMoreLists = 4;
+// Split S_more lists: with `ext` (kMoreLists - 1 ints per vertex), S_more(w)
+// is kMoreLists lists -- head[2w] and ext[(kMoreLists - 1) w ..] -- and
+// joiner u goes to list u % kMoreLists, so a closed hub's supporters come
+// back as that many chains, walked side by side.  S_last(w) stays one list
+// (head[2w+1]).  ext == nullptr: one list.
 __device__ __forceinline__ int* join_slot(int* head, int* ext, int w, bool last, int u) {
     if (last) return head + 2 * w + 1;
     const int s = u & (kMoreLists - 1);
     return (s == 0 || !ext) ? head + 2 * w : ext + (kMoreLists - 1) * w + (s - 1);
 }
-// The heads of a closed vertex's lists: more[0..3] (kEmpty = none), last.
+// The heads of a closed vertex's lists: more[] (kEmpty = none), last.
 struct ClosedLists {
     int more[kMoreLists];
     int last;

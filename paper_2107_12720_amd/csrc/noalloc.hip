@@ -35,7 +35,8 @@ constexpr long long round256(long long words) {
 }
 constexpr long long kMaxN = TRIM_NOALLOC_MAX_N;
 static_assert(kMaxN <= kSplitMaxN, "the fixed array holds the split S_more heads");
-constexpr long long kQueueWordsU32 = 6 * kMaxN + 64LL * 4 * TRIM_NOALLOC_WORKERS;
+constexpr long long kQueueWordsU32 =
+    kQueuePerVertexSplit * kMaxN + 64LL * 4 * TRIM_NOALLOC_WORKERS;
 // offsets in uint64 words
 constexpr long long kOffHead = 0;
 constexpr long long kOffRec = kOffHead + round256(kMaxN);             // 2n int32
@@ -43,8 +44,8 @@ constexpr long long kOffSinks = kOffRec + round256(kMaxN);            // n uint6
 constexpr long long kOffQueue = kOffSinks + round256(kMaxN / 64 + 2); // n/32 + 2 (+1) uint32
 constexpr long long kOffJp = kOffQueue + round256((kQueueWordsU32 + 1) / 2);   // n int32
 constexpr long long kOffLists = kOffJp + round256(kMaxN / 2);                     // 2n uint32
-constexpr long long kOffExt = kOffLists + round256(kMaxN);                     // 3n int32
-constexpr long long kOffCtr = kOffExt + round256((3 * kMaxN + 1) / 2);
+constexpr long long kOffExt = kOffLists + round256(kMaxN);   // (kMoreLists - 1) n int32
+constexpr long long kOffCtr = kOffExt + round256(((kMoreLists - 1) * kMaxN + 1) / 2);
 constexpr long long kOffPart = kOffCtr + round256(kCtrInts / 2);
 constexpr long long kScratchWords = kOffPart + round256((long long)kPartSlots * kPartStride);
 

@@ -117,13 +117,14 @@ int ensure(trim_ctx* c, int64_t n) {
     // the split S_more lists (and the queue room they need) for graphs that
     // use them
     const bool split = (long long)need <= trim::kSplitMaxN;
-    const size_t qslots = cap * (split ? 6 : 3) + (size_t)trim::kQueueSlots;
+    const size_t qslots =
+        cap * (split ? trim::kQueuePerVertexSplit : 3) + (size_t)trim::kQueueSlots;
     if (dmalloc(c, &c->w.a, cap * 8) != hipSuccess ||
         dmalloc(c, &c->w.b, cap * 8) != hipSuccess ||
         dmalloc(c, &c->w.c, cap * 4) != hipSuccess ||
         dmalloc(c, &c->w.d, cap * 4) != hipSuccess ||
         dmalloc(c, &c->w.e, cap * 12) != hipSuccess ||
-        (split && dmalloc(c, &c->w.ext, cap * 12) != hipSuccess) ||
+        (split && dmalloc(c, &c->w.ext, cap * 4 * (trim::kMoreLists - 1)) != hipSuccess) ||
         dmalloc(c, &c->w.q, qslots * 4) != hipSuccess ||
         // free queue slots hold kNone (all ones); consumers restore it
         hipMemset(c->w.q, 0xFF, qslots * 4) != hipSuccess) {

@@ -45,9 +45,10 @@ struct Work {
                               //   path) or the graphs' claim order (owned path)
     uint32_t* e = nullptr;    // 2n uint32: AC-6 forest-collapse lists / phase lists (two of n)
     int* jp = nullptr;        // n int32: AC-6 forest links
-    int* ext = nullptr;       // 3n int32: the split S_more heads of AC-6 (allocated only
-                              //   for capacities up to kSplitMaxN vertices)
-    uint32_t* q = nullptr;    // 3n shared-queue slots (6n with ext), kNone between calls
+    int* ext = nullptr;       // (kMoreLists - 1) n int32: the split S_more heads of AC-6
+                              //   (allocated only for capacities up to kSplitMaxN)
+    uint32_t* q = nullptr;    // 3n shared-queue slots ((2 + kMoreLists) n with ext), kNone
+                              //   between calls
     long long qwords = 0;     // size of q in words (slack included)
     int* ctr = nullptr;       // kCtrInts control words
     uint64_t* wedges = nullptr;  // per-worker counts when the caller has none (batches)
@@ -62,10 +63,12 @@ struct Work2 {
     long long qwords = 0;       // size of q in words
 };
 constexpr int kMaxWorkers = 16384;
-// AC-6 splits S_more lists four ways for graphs up to this many vertices; a
-// close can then queue up to four S_more heads, so the shared queue needs
-// room for six items per vertex instead of three.
+// AC-6 splits S_more lists kMoreLists ways for graphs up to kSplitMaxN
+// vertices; a close can then queue up to kMoreLists S_more heads, so the
+// shared queue needs room for 2 + kMoreLists items per vertex instead of 3.
+constexpr int kMoreLists = 4;
 constexpr long long kSplitMaxN = 1LL << 25;
+constexpr int kQueuePerVertexSplit = 2 + kMoreLists;
 // shared-queue slack beyond 3n slots: outstanding tickets, 64 per wavefront
 constexpr int kQueueSlots = 64 * 4 * kMaxWorkers;
 constexpr int kPartStride = 16384;   // >= workers, sweep blocks and pack blocks
