@@ -262,8 +262,9 @@ def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps, with_ac3=True):
                       "edges_live": st6["edges_live"]},
               "ac4": {"bitmap": res4.bitmap_numpy().copy(), "edges": st4["edges_total"]}}
     if with_ac3:
+        # one call of about 5 s: no second call for a per-kernel split
         ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr_two_sided(T.AC3, n, ro, col, rro, rcl),
-                                  1, 0)
+                                  1, 0, breakdown_steps=0)
         st3 = res3.stats_dict()
         out["ac3"] = {"ms": ms3, "edges_per_s": m / (ms3 / 1e3), "traversed": st3["edges_total"],
                       "rounds": st3["rounds"], "n_live": st3["n_live"],
@@ -369,42 +370,52 @@ def bench_scc(ctx, T, graphs, reps):
     return checks, out
 
 
-def time_gpu(ctx, fn, steps, warmup, per_step=None):
-    """Mean ms per call over `steps` timed calls (one event pair around all of
-    them), the per-kernel times of every call, and the last result.  With a
-    list `per_step`, each call's own event-timed duration is appended to it.
-    The context keeps the kernel events of up to 64 calls, so the timed loop
-    reads them (and waits for the GPU) only once per 64 calls."""
+def time_gpu(ctx, fn, steps, warmup, per_step=None, breakdown_steps=None):
+    """Mean ms per call over `steps` timed calls with nothing recorded inside
+    the timed region but one event pair around all of them; the per-kernel
+    times of `breakdown_steps` further calls (default min(steps, 20); 0 = none)
+    timed with the library's per-kernel events (those cost about 7 us per
+    kernel of stream time, about 50 us per AC-6 trim, so they stay out of
+    the calls the mean comes from; a kernel's own duration is the same); and
+    the last result.  With a list `per_step`, a third loop of `steps` calls
+    appends each call's own event-timed duration to it."""
     import torch
     for _ in range(warmup):
         fn()
-    ring = max(1, min(steps, 64))
-    ctx.set_timing(ring)
+    ctx.set_timing(0)
     torch.cuda.synchronize()
-    ktimes = {}
-    pairs = []
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
-    for i in range(steps):
-        if per_step is not None:
+    for _ in range(steps):
+        res = fn()
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    ktimes = {}
+    nb = min(steps, 20) if breakdown_steps is None else breakdown_steps
+    if nb > 0:
+        ring = max(1, min(nb, 64))
+        ctx.set_timing(ring)
+        for i in range(nb):
+            res = fn()
+            if (i + 1) % ring == 0 or i + 1 == nb:
+                for name, kms in ctx.kernel_times():
+                    ktimes.setdefault(name, []).append(kms)
+                ctx.set_timing(ring)
+    ctx.set_timing(1)
+    if per_step is not None:
+        pairs = []
+        for _ in range(steps):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-        res = fn()
-        if per_step is not None:
+            res = fn()
             b.record()
             pairs.append((a, b))
-        if (i + 1) % ring == 0 or i + 1 == steps:
-            for name, ms in ctx.kernel_times():
-                ktimes.setdefault(name, []).append(ms)
-            ctx.set_timing(ring)
-    t1.record()
-    torch.cuda.synchronize()
-    ctx.set_timing(1)
-    if per_step is not None:
+        torch.cuda.synchronize()
         per_step.extend(a.elapsed_time(b) for a, b in pairs)
-    return t0.elapsed_time(t1) / steps, ktimes, res
+    return ms, ktimes, res
 
 
 def step_stats(times):
@@ -1087,7 +1098,8 @@ def main():
 
     log(f"AC-6: warmup {args.warmup}, timed {args.steps} steps")
     per_step = []
-    ms, ktimes, res = time_gpu(ctx, step, args.steps, args.warmup, per_step)
+    ms, ktimes, res = time_gpu(ctx, step, args.steps, args.warmup, per_step,
+                               breakdown_steps=args.steps)
     st = res.stats_dict()
     value = m / (ms / 1e3)
     checks = {"ac6": {"bitmap": res.bitmap_numpy().copy(), "edges": st["edges_total"]}}
@@ -1125,6 +1137,11 @@ def main():
         "parity": None, "sweep_counts_match": sweep_ok,
         "roofline": roofline,
         "step_stats": step_stats(per_step),
+        "timing": {"value_loop": f"{args.steps} steps, one event pair around all, no "
+                                 "per-kernel events",
+                   "kernel_times": f"{args.steps} more steps with the library's per-kernel "
+                                   "events (about 50 us of stream time per step)",
+                   "step_stats": f"{args.steps} more steps, one event pair each"},
         "hbm_copy_ceiling": copy_ceiling(),
         "breakdown": breakdown,
         "path": {"algorithmic_bytes": path_bytes,
@@ -1160,7 +1177,9 @@ def main():
             "ac6_speedup_vs_ac4": ms4 / ms,
         }
         if not args.no_ac3:
-            ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC3, n, ro, col), 1, 0)
+            # one call of about 4 s: no second call for a per-kernel split
+            ms3, kt3, res3 = time_gpu(ctx, lambda: ctx.trim_csr(T.AC3, n, ro, col), 1, 0,
+                                      breakdown_steps=0)
             st3 = res3.stats_dict()
             checks["ac3"] = {"bitmap": res3.bitmap_numpy().copy(), "edges": st3["edges_total"],
                              "rounds": st3["rounds"]}

@@ -391,7 +391,7 @@ hipError_t ac3_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     }
     // an empty graph still runs the repeat-until loop once
     if (stats)
-        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(1024), 0, lc.stream, n, P, 0, 0,
                            pack_blocks, 0, worker_edges, w.part, w.ctr, stats, 1);
     return hipGetLastError();
 }
@@ -436,7 +436,7 @@ hipError_t ac3_two_csr(const trim_csr_t& g, const Work& w, const Work2& x, const
                            Ac3Live{dround}, n, bitmap, w.part, w.ctr, nullptr, 0LL);
     }
     if (stats)
-        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(1024), 0, lc.stream, n, P, 0, 0,
                            pack_blocks, 0, worker_edges, w.part, w.ctr, stats, 1);
     return hipGetLastError();
 }

@@ -257,7 +257,7 @@ hipError_t ac4_run(const trim_csr_t& g, const Work& w, const LaunchCfg& lc, uint
                                Ac4Live{w.a}, n, bitmap, w.part, w.ctr, w.q, w.qwords);
     }
     if (stats)
-        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, 0, 0,
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(1024), 0, lc.stream, n, P, 0, 0,
                            pack_blocks, n > 0 ? P : 0, worker_edges, w.part, w.ctr, stats, 0);
     return hipGetLastError();
 }

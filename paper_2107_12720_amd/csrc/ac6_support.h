@@ -25,14 +25,15 @@ struct ClosedLists {
 // independent, so their round trips overlap).  Each list, on its own, is
 // closed with the guarantee of the unsplit close: nobody joins it after its
 // exchange, and every earlier joiner comes back in the returned chain.
+template <int S = __HIP_MEMORY_SCOPE_AGENT>
 __device__ __forceinline__ ClosedLists close_lists(int* head, int* ext, int x) {
     ClosedLists c;
-    const int2 ab = xchg2_dev(head + 2 * x, kDead, kDead);
+    const int2 ab = xchg2_s<S>(head + 2 * x, kDead, kDead);
     c.more[0] = ab.x;
     c.last = ab.y;
 #pragma unroll
     for (int j = 1; j < kMoreLists; ++j)
-        c.more[j] = ext ? xchg_dev(ext + (kMoreLists - 1) * x + (j - 1), kDead) : kEmpty;
+        c.more[j] = ext ? xchg_s<S>(ext + (kMoreLists - 1) * x + (j - 1), kDead) : kEmpty;
     return c;
 }
 

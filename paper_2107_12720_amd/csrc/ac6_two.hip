@@ -377,7 +377,7 @@ hipError_t ac6_two_csr_preset(const trim_csr_t& gc, const Work& w, const Work2& 
     }
     if (stats) {
         Timed t(lc, "finalize");
-        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, n, P, sweep_blocks,
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(1024), 0, lc.stream, n, P, sweep_blocks,
                            n > 0 ? P : 0, pack_blocks, n > 0 ? P : 0, worker_edges, w.part,
                            w.ctr, stats, 0, pack_blocks);
     }

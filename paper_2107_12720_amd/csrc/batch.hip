@@ -463,7 +463,7 @@ hipError_t ac6_batch_owned(int G, const int64_t* vbase, const int32_t* row_off,
     }
     if (stats) {
         Timed t(lc, "finalize");
-        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(256), 0, lc.stream, (int)total_n, W, W,
+        hipLaunchKernelGGL(finalize_stats, dim3(1), dim3(1024), 0, lc.stream, (int)total_n, W, W,
                            0, W, 0, w.wedges, w.part, w.ctr, stats, 0, 0, W);
     }
     return hipGetLastError();

@@ -37,53 +37,78 @@ __global__ void pack_bitmap(IsLive is_live, int n, uint32_t* bitmap, uint64_t* p
     if (threadIdx.x == 0) part[kPartLive * kPartStride + blockIdx.x] = live_cnt;
 }
 
-__device__ __forceinline__ uint64_t sum_range(const uint64_t* a, int k, uint64_t* red) {
-    uint64_t s = 0;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) s += a[i];
-    return block_sum(s, red);
-}
-
-__device__ __forceinline__ uint64_t max_range(const uint64_t* a, int k, uint64_t* red) {
-    int m = 0;
-    for (int i = threadIdx.x; i < k; i += blockDim.x) m = max(m, (int)a[i]);
-    return (uint64_t)block_max(m, reinterpret_cast<int*>(red));
-}
-
 // One block: reduce the partials into *stats.  n_sweep / n_prop = number of
 // sweep / propagation partials (0 when the algorithm has none); n_qhw =
 // number of ring high-water partials; n_live_edges = number of live-check
 // partials (two-sided AC-6 only, else 0); n_levels = number of partials of
-// the level-synchronous propagation phases (AC-6, else 0).
+// the level-synchronous propagation phases (AC-6, else 0).  Every thread
+// sums its share of all quantities in one pass, and one reduction combines
+// them (a reduction per quantity would cost a barrier pair each).
 __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack, int n_qhw,
                                const uint64_t* worker_edges, const uint64_t* part, const int* ctr,
                                trim_stats_t* stats, int empty_rounds, int n_live_edges = 0,
                                int n_levels = 0) {
-    __shared__ uint64_t red[16];
-    const uint64_t qhw = max_range(part + kPartQhw * kPartStride, n_qhw, red);
-    const uint64_t edges = sum_range(worker_edges, P, red);
-    const uint64_t live = sum_range(part + kPartLive * kPartStride, n_pack, red);
-    const uint64_t sweep = sum_range(part + kPartSweep * kPartStride, n_sweep, red);
-    // the propagation's counts: its level-synchronous phases and its asynchronous tail
-    const uint64_t closes = sum_range(part + kPartCloses * kPartStride, n_prop, red) +
-                            sum_range(part + kPartLvCloses * kPartStride, n_levels, red);
-    const uint64_t joins = sum_range(part + kPartJoins * kPartStride, n_prop, red) +
-                           sum_range(part + kPartLvJoins * kPartStride, n_levels, red);
-    const uint64_t visited = sum_range(part + kPartVisited * kPartStride, n_prop, red) +
-                             sum_range(part + kPartLvVisited * kPartStride, n_levels, red);
-    const uint64_t degsum = sum_range(part + kPartDeg * kPartStride, n_sweep, red);
-    const uint64_t live_edges = sum_range(part + kPartLiveEdges * kPartStride, n_live_edges, red);
+    enum { kEdges, kLive, kSweep, kCloses, kJoins, kVisited, kDeg, kLiveE, kQhw, kN };
+    __shared__ uint64_t red[kN][16];
+    uint64_t acc[kN] = {};
+    const auto P_ = [&](int slot, int i) { return part[slot * kPartStride + i]; };
+    int most = P;
+    for (int k : {n_sweep, n_prop, n_pack, n_qhw, n_live_edges, n_levels}) most = k > most ? k : most;
+    for (int i = threadIdx.x; i < most; i += blockDim.x) {
+        if (i < P) acc[kEdges] += worker_edges[i];
+        if (i < n_pack) acc[kLive] += P_(kPartLive, i);
+        if (i < n_sweep) {
+            acc[kSweep] += P_(kPartSweep, i);
+            acc[kDeg] += P_(kPartDeg, i);
+        }
+        if (i < n_prop) {
+            acc[kCloses] += P_(kPartCloses, i);
+            acc[kJoins] += P_(kPartJoins, i);
+            acc[kVisited] += P_(kPartVisited, i);
+        }
+        if (i < n_levels) {
+            acc[kCloses] += P_(kPartLvCloses, i);
+            acc[kJoins] += P_(kPartLvJoins, i);
+            acc[kVisited] += P_(kPartLvVisited, i);
+        }
+        if (i < n_live_edges) acc[kLiveE] += P_(kPartLiveEdges, i);
+        if (i < n_qhw) {
+            const uint64_t h = P_(kPartQhw, i);
+            acc[kQhw] = h > acc[kQhw] ? h : acc[kQhw];
+        }
+    }
+    const int w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+#pragma unroll
+    for (int q = 0; q < kN; ++q) {
+        uint64_t x = acc[q];
+        if (q == kQhw) {
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint64_t y = ((uint64_t)__shfl_xor((unsigned)(x >> 32), off) << 32) |
+                                   __shfl_xor((unsigned)x, off);
+                x = y > x ? y : x;
+            }
+        } else {
+            x = wave_sum(x);
+        }
+        if (lane_id() == 0) red[q][w] = x;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        stats->edges_total = edges;
-        stats->n_live = live;
-        stats->n_dead = (uint64_t)n - live;
+        uint64_t tot[kN] = {};
+        for (int q = 0; q < kN; ++q)
+            for (int i = 0; i < nw; ++i)
+                tot[q] = q == kQhw ? (red[q][i] > tot[q] ? red[q][i] : tot[q]) : tot[q] + red[q][i];
+        stats->edges_total = tot[kEdges];
+        stats->n_live = tot[kLive];
+        stats->n_dead = (uint64_t)n - tot[kLive];
         stats->queued = (uint64_t)ctr[kQTail];
-        stats->edges_sweep = sweep;
-        stats->closes = closes;
-        stats->joins = joins;
-        stats->visited = visited;
-        stats->graph_edges = degsum;
-        stats->q_highwater = qhw;
-        stats->edges_live = live_edges;
+        stats->edges_sweep = tot[kSweep];
+        stats->closes = tot[kCloses];
+        stats->joins = tot[kJoins];
+        stats->visited = tot[kVisited];
+        stats->graph_edges = tot[kDeg];
+        stats->q_highwater = tot[kQhw];
+        stats->edges_live = tot[kLiveE];
         stats->stalled = ld_dev(ctr + kStall) != 0;
         stats->forest = (uint64_t)ld_dev(ctr + kJKilled);
         stats->jump_rounds = (uint64_t)ld_dev(ctr + kJRounds);
