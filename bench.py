@@ -182,10 +182,12 @@ def first_ok(row_off, col, ok):
 
 
 def two_sided_sweep_counts(g, rro, rcol):
-    """(checks, joins, casualties) of the two-sided first sweep.  Vertices
-    without a successor or a predecessor are the only ones removed while it
-    runs; every other vertex scans its successors for the first one not
-    removed, and only if it finds one, its predecessors likewise."""
+    """(checks, joins, casualties, members, scanned) of the two-sided first
+    sweep.  Vertices without a successor or a predecessor are the only ones
+    removed while it runs; every other vertex (scanned) scans its successors
+    for the first one not removed, and only if it finds one, its predecessors
+    likewise.  Members: vertices that found both and whose out-support is
+    their last successor (the forest collapse's tree members)."""
     import numpy as np
     deg = np.diff(g.row_off.astype(np.int64))
     indeg = np.diff(rro.astype(np.int64))
@@ -196,7 +198,8 @@ def two_sided_sweep_counts(g, rro, rcol):
     in_ok = out_ok & (fi >= 0)
     checks = np.where(out_ok, fo + 1, deg)[alive0].sum() + np.where(fi >= 0, fi + 1, indeg)[out_ok].sum()
     joins = int(out_ok.sum() + in_ok.sum())
-    return int(checks), joins, int((alive0 & ~in_ok).sum())
+    members = int((in_ok & (fo == deg - 1)).sum())
+    return int(checks), joins, int((alive0 & ~in_ok).sum()), members, int(alive0.sum())
 
 
 def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps, with_ac3=True):
@@ -223,12 +226,19 @@ def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps, with_ac3=True):
     dc = [T.to_device(x) for x in (gc.row_off, gc.col, rc_t[0], rc_t[1])]
     ms_chain, _, res_c = time_gpu(ctx, lambda: ctx.trim_csr_two_sided(T.AC6, L, *dc), 3, 1)
     chain_ok = res_c.stats_dict()["n_live"] == 1
-    sc, sj, scas = two_sided_sweep_counts(g, rro_h, rcol_h)
+    sc, sj, scas, smem, sscan = two_sided_sweep_counts(g, rro_h, rcol_h)
+    forest = st6["forest"] > 0
     # bytes per unit: 4 B per read or write, 8 B per 4-byte atomic, 16 B per
-    # 8-byte exchange (the paper's per-edge and per-vertex terms, both sides)
+    # 8-byte exchange (the paper's per-edge and per-vertex terms, both sides);
+    # with the forest collapse the sweep also writes a link per scanned vertex
+    # and a list entry per member and casualty, and the collapse reads and
+    # writes 16 B per list entry and round, and exchanges both pairs (32 B)
+    # and queues an item (4 B) per removal
     algo = {
         "ac6t_init": 8 * (n + 1) + 16 * n + n // 8,
-        "ac6t_sweep": 8 * (n + 1) + n // 8 + 4 * sc + 16 * sj + 4 * scas,
+        "ac6t_sweep": 8 * (n + 1) + n // 8 + 4 * sc + 16 * sj + 4 * scas
+        + (4 * sscan + 4 * (smem + scas) if forest else 0),
+        "ac6t_jump": 16 * st6["work_items"] + 36 * st6["forest"],
         "ac6t_propagate": (8 * (st6["edges_total"] - st6["edges_sweep"]) + 32 * st6["closes"]
                            + 16 * st6["joins"] + 8 * st6["visited"]),
         "ac6t_pack": 8 * n + n // 8,
@@ -244,6 +254,7 @@ def bench_two_sided(ctx, T, g, ro, col, rro_h, rcol_h, reps, with_ac3=True):
     out = {"workload": "rmat22_ef16_chain100k", "n": n, "m": m,
            "ac6": {"ms": ms6, "edges_per_s": m / (ms6 / 1e3), "traversed": st6["edges_total"],
                    "n_live": st6["n_live"], "closes": st6["closes"], "joins": st6["joins"],
+                   "forest": st6["forest"], "jump_rounds": st6["jump_rounds"],
                    "sweep_checks_match": sc == st6["edges_sweep"],
                    "kernels": kernels, "dominant": dom,
                    "roofline": {"bound": "hbm", "kernel": dom,

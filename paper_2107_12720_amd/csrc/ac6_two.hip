@@ -30,13 +30,17 @@
 // Kernels, in stream order: ac6t_init (list heads, the bitmap of vertices
 // without successors or predecessors, counters), ac6t_sweep (both support
 // searches per vertex; only that bitmap's vertices are removed while it runs,
-// so joining is a plain exchange), ac6t_propagate (persistent workers on
-// per-wavefront LDS rings), pack.
+// so joining is a plain exchange), ac6_jump (the forest collapse of the
+// one-sided kernels over the out-side S_last links; the default, off with
+// TRIM_FLAG_STEPWISE: a chain that ends in a vertex without successors falls
+// in O(log length) rounds instead of one removal after another),
+// ac6t_propagate (persistent workers on per-wavefront LDS rings), pack.
 #include "trim_device.h"
 #include "trim_stats.h"
 #include "trim_internal.h"
 #include "ac6_support.h"
 #include "scc_internal.h"
+#include "forest_jump.h"
 
 namespace trim {
 
@@ -78,32 +82,35 @@ __global__ void ac6t_init(TwoGraph g, int n, uint32_t* dead0, const uint32_t* pr
 
 __device__ __forceinline__ bool bit(const uint32_t* bm, int v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
 
-// First scan of one side of v over [b, e): the first neighbour outside dead0,
-// joined by exchange.  Returns false if there is none; `checks` receives the
-// positions checked.
-__device__ __forceinline__ bool first_join(const int* adj, int b, int e, const uint32_t* dead0,
-                                           int* head, uint64_t* rec, int v, uint64_t& checks,
-                                           int sched, uint64_t salt) {
-    int p = b, w = 0;
-    for (; p < e; ++p) {
-        w = __builtin_nontemporal_load(adj + p);
-        if (!bit(dead0, w)) break;
-    }
-    if (p == e) {
-        checks += (uint64_t)(e - b);
-        return false;
-    }
-    if (sched & TRIM_SCHED_JITTER) jitter_nap(salt);
-    const int old = xchg_dev(head + 2 * w + (p + 1 == e), v);
-    rec[v] = pack_rec(old, p);
-    checks += (uint64_t)(p - b + 1);
-    return true;
-}
+constexpr int kTSweepUnroll = 4;   // vertices per lane in flight in the first sweep
+// entries buffered in LDS before one shared append: room for one step of the
+// largest workgroup (1,024 lanes x kTSweepUnroll)
+constexpr int kCasBuf = 1024 * kTSweepUnroll;
 
-constexpr int kCasBuf = 2048;   // casualties buffered in LDS before one shared-queue append
-
+// The first sweep: for every vertex v outside dead0, the first successor
+// outside dead0 (its out-support) and, only if there is one, the first
+// predecessor outside dead0 (its in-support), each joined by exchange; v is a
+// casualty if either is missing.  Only dead0's vertices are removed while
+// this kernel runs, so a neighbour is live iff its dead0 bit is clear.
+//
+// Each lane keeps kTSweepUnroll vertices in flight, blockDim apart: their
+// offsets on both sides, then their first successors and first predecessors
+// and those neighbours' dead0 bits, then their joins, are issued before any
+// result is waited for.  The in-side loads are issued whatever the out-side
+// finds (a load is no check); the in-side scan past dead0 and the in-side
+// join happen only for a vertex that found its out-support, so the checks
+// counted are those of the one-vertex-at-a-time reading.
+//
+// With jp (the forest collapse over the out-side S_last links, forest_jump.h):
+// jp[v] = v's out-support if that is v's last successor and v keeps an
+// in-support (a tree member, listed in jlist), ~v if v found no live
+// successor or no live predecessor (a removed root, listed with kRootBit),
+// v itself otherwise.  Without jp, the vertices that found none are queued as
+// close items.
 __global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, uint32_t* q,
-                           int* ctr, uint64_t* worker_edges, int P, uint64_t* part, int sched) {
+                           int* ctr, uint64_t* worker_edges, int P, uint64_t* part, int sched,
+                           int* jp, uint32_t* jlist) {
+    constexpr int U = kTSweepUnroll;
     __shared__ uint32_t cas[kCasBuf];
     __shared__ int s_chunk, s_ncas, s_base;
     __shared__ uint64_t red[16];
@@ -114,11 +121,16 @@ __global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, 
         const int k = s_ncas;
         if (k > 0) {
             if (threadIdx.x == 0) {
-                add_dev(ctr + kPending, k);
-                s_base = add_dev(ctr + kQTail, k);
+                if (jp) {
+                    s_base = add_dev(ctr + kJCnt0, k);
+                } else {
+                    add_dev(ctr + kPending, k);
+                    s_base = add_dev(ctr + kQTail, k);
+                }
             }
             __syncthreads();
-            for (int i = threadIdx.x; i < k; i += blockDim.x) q[s_base + i] = cas[i];
+            uint32_t* dst = jp ? jlist : q;
+            for (int i = threadIdx.x; i < k; i += blockDim.x) dst[s_base + i] = cas[i];
             __syncthreads();
             if (threadIdx.x == 0) s_ncas = 0;
         }
@@ -133,32 +145,102 @@ __global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, 
         int cb = claim;
         if (sched & TRIM_SCHED_REVERSE) cb = ((n + chunk - 1) / chunk - 1 - claim / chunk) * chunk;
         const int ce = cb + chunk < n ? cb + chunk : n;
-        for (int base = cb; base < ce; base += blockDim.x) {
-            const int v = base + threadIdx.x;
-            bool casualty = false;
-            uint64_t mine = 0;
-            if (v < ce) {
-                const int b = g.row_off[v], e = g.row_off[v + 1];
-                const int rb = g.rrow_off[v], re = g.rrow_off[v + 1];
-                degsum += (uint64_t)(e - b);
-                if (!bit(dead0, v)) {   // has both lists and is not preset
-                    const uint64_t salt = ((uint64_t)blockIdx.x << 32) ^ v;
-                    casualty = !first_join(g.col, b, e, dead0, g.hout, g.rec_out, v, mine, sched,
-                                           salt) ||
-                               !first_join(g.rcol, rb, re, dead0, g.hin, g.rec_in, v, mine, sched,
-                                           salt ^ 1);
+        for (int base = cb; base < ce; base += U * blockDim.x) {
+            int v[U], b[U], e[U], rb[U], re[U], po[U], pi[U], wo[U], wi[U];
+            bool live[U], oko[U], oki[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                v[k] = base + k * blockDim.x + threadIdx.x;
+                b[k] = e[k] = rb[k] = re[k] = 0;
+                if (v[k] < ce) {
+                    b[k] = g.row_off[v[k]];
+                    e[k] = g.row_off[v[k] + 1];
+                    rb[k] = g.rrow_off[v[k]];
+                    re[k] = g.rrow_off[v[k] + 1];
                 }
             }
-            edges += mine;
-            const uint64_t mask = ballot(casualty);
-            if (mask) {
-                int wbase = 0;
-                if (lane_id() == 0) wbase = atomicAdd(&s_ncas, popc(mask));
-                wbase = __shfl(wbase, 0);
-                if (casualty) cas[wbase + popc(mask & lanes_below())] = (uint32_t)v;
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                degsum += (uint64_t)(e[k] - b[k]);
+                // dead0 holds every vertex without successors or predecessors
+                live[k] = v[k] < ce && !bit(dead0, v[k]);
+                po[k] = b[k];
+                pi[k] = rb[k];
+                wo[k] = wi[k] = 0;
+                if (b[k] < e[k]) wo[k] = __builtin_nontemporal_load(g.col + b[k]);
+                if (rb[k] < re[k]) wi[k] = __builtin_nontemporal_load(g.rcol + rb[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                oko[k] = live[k] && !bit(dead0, wo[k]);
+                oki[k] = live[k] && !bit(dead0, wi[k]);
+            }
+            // the rare serial scans past dead0
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (live[k] && !oko[k]) {
+                    for (++po[k]; po[k] < e[k]; ++po[k]) {
+                        wo[k] = __builtin_nontemporal_load(g.col + po[k]);
+                        if (!bit(dead0, wo[k])) break;
+                    }
+                    oko[k] = po[k] < e[k];
+                }
+                if (oko[k] && !oki[k]) {
+                    for (++pi[k]; pi[k] < re[k]; ++pi[k]) {
+                        wi[k] = __builtin_nontemporal_load(g.rcol + pi[k]);
+                        if (!bit(dead0, wi[k])) break;
+                    }
+                    oki[k] = pi[k] < re[k];
+                }
+            }
+            int oldo[U], oldi[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint64_t salt = ((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k];
+                if (oko[k]) {
+                    if (sched & TRIM_SCHED_JITTER) jitter_nap(salt);
+                    oldo[k] = xchg_dev(g.hout + 2 * wo[k] + (po[k] + 1 == e[k]), v[k]);
+                }
+                if (oko[k] && oki[k]) {
+                    if (sched & TRIM_SCHED_JITTER) jitter_nap(salt ^ 1);
+                    oldi[k] = xchg_dev(g.hin + 2 * wi[k] + (pi[k] + 1 == re[k]), v[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                bool casualty = false, member = false;
+                if (live[k]) {
+                    if (oko[k]) {
+                        g.rec_out[v[k]] = pack_rec(oldo[k], po[k]);
+                        edges += (uint64_t)(po[k] - b[k] + 1);
+                        if (oki[k]) {
+                            g.rec_in[v[k]] = pack_rec(oldi[k], pi[k]);
+                            edges += (uint64_t)(pi[k] - rb[k] + 1);
+                        } else {
+                            edges += (uint64_t)(re[k] - rb[k]);
+                        }
+                    } else {
+                        edges += (uint64_t)(e[k] - b[k]);
+                    }
+                    casualty = !(oko[k] && oki[k]);
+                    if (jp) {
+                        member = !casualty && po[k] + 1 == e[k];
+                        jp[v[k]] = casualty ? ~v[k] : member ? wo[k] : v[k];
+                    }
+                }
+                const bool put = casualty || member;
+                const uint64_t mask = ballot(put);
+                if (mask) {
+                    int wbase = 0;
+                    if (lane_id() == 0) wbase = atomicAdd(&s_ncas, popc(mask));
+                    wbase = __shfl(wbase, 0);
+                    if (put)
+                        cas[wbase + popc(mask & lanes_below())] =
+                            (uint32_t)v[k] | (jp && casualty ? kRootBit : 0u);
+                }
             }
             __syncthreads();
-            if (s_ncas > kCasBuf - (int)blockDim.x) flush();
+            if (s_ncas > kCasBuf - U * (int)blockDim.x) flush();
         }
     }
     flush();
@@ -176,10 +258,21 @@ __global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, 
 //   LAST_OUT(x)     x is a member of a closed S_last list on the out-side (its
 //                   last successor died): remove it; rec_out[x] links to the
 //                   next member;  LAST_IN(x) the same on the in-side;
-//   MORE_OUT(x)     x is a member of a closed S_more list on the out-side:
-//                   resume its out-scan (unless it is already removed), then
-//                   walk on to the next member;  MORE_IN(x) likewise.
-enum : uint32_t { kTClose = 0, kTLastOut = 1, kTLastIn = 2, kTMoreOut = 3, kTMoreIn = 4 };
+//   MORE_OUT(x)     x heads (the rest of) a closed S_more list on the
+//                   out-side: follow the links and hand each member out as a
+//                   RESCAN_OUT item, up to kTWalk members in a row;
+//                   MORE_IN(x) likewise on the in-side;
+//   RESCAN_OUT(x)   resume x's out-scan after its old support, unless x is
+//                   already removed;  RESCAN_IN(x) likewise on the in-side.
+// The walk only loads links, one memory round trip per member, so a hub's
+// long list is not walked at the pace of its members' scans: the rescans go
+// to the wave-local ring, where the other lanes of the walking wave take
+// them (never to the shared queue, whose room is counted per vertex).
+enum : uint32_t {
+    kTClose = 0, kTLastOut = 1, kTLastIn = 2, kTMoreOut = 3, kTMoreIn = 4, kTRescanOut = 5,
+    kTRescanIn = 6
+};
+constexpr int kTWalk = 32;   // S_more members one MORE item hands out in a row
 constexpr uint32_t kTIdMask = 0x1FFFFFFFu;
 __device__ __forceinline__ uint32_t titem(uint32_t kind, int v) { return (kind << 29) | (uint32_t)v; }
 __device__ __forceinline__ uint32_t last_kind(int side) { return side ? kTLastIn : kTLastOut; }
@@ -195,11 +288,13 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
                                                       int sched, int budget) {
     __shared__ uint32_t rings[256 / kWave][kLocalQ];
     __shared__ int ring_tail[256 / kWave];
+    __shared__ uint32_t local_rings[256 / kWave][kLocalP];
+    __shared__ int local_tail[256 / kWave];
     __shared__ uint64_t red[16];
     WaveQueue wq;
     const int wv = threadIdx.x / kWave;
     wq.init(rings[wv], &ring_tail[wv], q, ctr + kQHead, ctr + kQTail, ctr + kPending,
-            ctr + kStall, budget, kTShareEvery);
+            ctr + kStall, budget, kTShareEvery, local_rings[wv], &local_tail[wv]);
     const ExplicitView out_view{g.row_off, g.col}, in_view{g.rrow_off, g.rcol};
     uint32_t item = kNone;
     uint64_t edges = 0, closes = 0, joins = 0, visited = 0;
@@ -212,25 +307,52 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
             const int x = (int)(item & kTIdMask);
             const uint32_t kind = item >> 29;
             if (kind >= kTMoreOut) {
-                const bool in = kind == kTMoreIn;
-                // read x's link before x can re-join (which rewrites its record)
-                const uint64_t r = ld_dev((in ? g.rec_in : g.rec_out) + x);
-                const int nx = rec_next(r);
-                visited += 1;
-                bool stays = true;   // a removed member is skipped
-                if (ld_dev(g.hout + 2 * x) != kDead) {
-                    if (sched & TRIM_SCHED_JITTER) jitter_nap(x);
-                    stays = in ? resume(in_view, x, rec_cursor(r) + 1, g.hin, g.rec_in, edges, sched)
-                               : resume(out_view, x, rec_cursor(r) + 1, g.hout, g.rec_out, edges,
-                                        sched);
-                    joins += stays;
-                }
-                if (stays) {
-                    if (nx >= 0) keep = titem(kind, nx);
+                const bool in = kind == kTMoreIn || kind == kTRescanIn;
+                uint64_t* rec = in ? g.rec_in : g.rec_out;
+                const uint32_t walk = in ? kTMoreIn : kTMoreOut;
+                int rx = -1, cont = -1;   // a member rescanned by this lane now; the rest
+                if (kind <= kTMoreIn) {
+                    // Each link is read before its member is handed out (a
+                    // rescan that re-joins rewrites the member's record).  The
+                    // last member of a burst, and any member the full local
+                    // ring does not take, is rescanned by the walker itself.
+                    int y = x;
+                    for (int h = 0;; ++h) {
+                        const int ny = ld_dev(rec_link(rec, y));
+                        visited += 1;
+                        if (h + 1 < kTWalk &&
+                            wq.push_local(titem(in ? kTRescanIn : kTRescanOut, y))) {
+                            if (ny < 0) break;
+                            y = ny;
+                            continue;
+                        }
+                        rx = y;
+                        cont = ny;
+                        break;
+                    }
                 } else {
-                    if (nx >= 0) wq.push1(titem(kind, nx));
-                    close_now = true;
-                    cx = x;
+                    rx = x;
+                }
+                if (rx >= 0) {
+                    // rx is in no list of this side until it joins again: its
+                    // record is stable
+                    const uint64_t r = ld_dev(rec + rx);
+                    bool stays = true;   // a removed member is skipped
+                    if (ld_dev(g.hout + 2 * rx) != kDead) {
+                        if (sched & TRIM_SCHED_JITTER) jitter_nap(rx);
+                        stays = in ? resume(in_view, rx, rec_cursor(r) + 1, g.hin, g.rec_in, edges,
+                                            sched)
+                                   : resume(out_view, rx, rec_cursor(r) + 1, g.hout, g.rec_out,
+                                            edges, sched);
+                        joins += stays;
+                    }
+                    if (stays) {
+                        if (cont >= 0) keep = titem(walk, cont);
+                    } else {
+                        if (cont >= 0) wq.push1(titem(walk, cont));
+                        close_now = true;
+                        cx = rx;
+                    }
                 }
             } else {
                 close_now = true;
@@ -296,6 +418,24 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
         part[kPartQhw * kPartStride + blockIdx.x] = (uint64_t)qhw;
     }
 }
+
+// The forest collapse's removal (forest_jump.h): both pairs of v exchanged
+// with kDead; its out-side and in-side S_more lists go back to the
+// propagation as walks, and its in-side S_last list as a chain of removals.
+// (Its out-side S_last members are its own tree's, removed by the same
+// rounds.)
+static_assert(kJumpItems >= 3, "a two-sided removal hands back up to three lists");
+struct TwoSidedKill {
+    int* hout;
+    int* hin;
+    __device__ __forceinline__ void operator()(int v, uint32_t (&item)[kJumpItems]) const {
+        const int2 o = xchg2_dev(hout + 2 * v, kDead, kDead);
+        const int2 i = xchg2_dev(hin + 2 * v, kDead, kDead);
+        if (o.x >= 0) item[0] = titem(kTMoreOut, o.x);
+        if (i.x >= 0) item[1] = titem(kTMoreIn, i.x);
+        if (i.y >= 0) item[2] = titem(kTLastIn, i.y);
+    }
+};
 
 // Live bitmap by ballot, plus the checks the live vertices made, read off
 // their final cursors: a live vertex's supports end at its first finally-live
@@ -363,7 +503,14 @@ hipError_t ac6_two_csr_preset(const trim_csr_t& gc, const Work& w, const Work2& 
         {
             Timed t(lc, "ac6t_sweep");
             hipLaunchKernelGGL(ac6t_sweep, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n, chunk,
-                               dead0, x.q, w.ctr, worker_edges, P, w.part, lc.schedule);
+                               dead0, x.q, w.ctr, worker_edges, P, w.part, lc.schedule,
+                               lc.forest ? w.jp : nullptr, lc.forest ? w.e : nullptr);
+        }
+        if (lc.forest) {
+            Timed t(lc, "ac6t_jump");
+            hipLaunchKernelGGL(ac6_jump<TwoSidedKill>, dim3(phase_blocks(n, lc.cus)), dim3(256), 0,
+                               lc.stream, TwoSidedKill{g.hout, g.hin}, w.jp, w.e, w.e + n, x.q,
+                               w.ctr, jump_rounds(n), lc.budget);
         }
         {
             Timed t(lc, "ac6t_propagate");

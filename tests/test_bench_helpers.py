@@ -38,7 +38,7 @@ def test_two_sided_sweep_counts_by_loop(gen):
         rro, rcol = gen.transpose(g)
         deg, indeg = np.diff(g.row_off), np.diff(rro)
         alive0 = (deg > 0) & (indeg > 0)
-        checks = joins = cas = 0
+        checks = joins = cas = members = 0
         for v in range(g.n):
             if not alive0[v]:
                 continue
@@ -58,7 +58,9 @@ def test_two_sided_sweep_counts_by_loop(gen):
                 continue
             checks += k2 + 1
             joins += 1
-        assert bench.two_sided_sweep_counts(g, rro, rcol) == (checks, joins, cas)
+            members += k == out.size - 1
+        assert bench.two_sided_sweep_counts(g, rro, rcol) == (checks, joins, cas, members,
+                                                               int(alive0.sum()))
 
 
 def test_step_stats():

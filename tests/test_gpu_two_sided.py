@@ -6,8 +6,11 @@ AC-4: the edge total equals the closed form sum over removed v of
 (out-degree + in-degree).  AC-6: the live vertices' checks do not depend on
 the schedule and must equal oracle.counts2 T6live exactly (stats.edges_live,
 read off the final cursors), the removed vertices' checks lie between the
-oracle's bounds, and stats.closes counts the vertices removed after the
-start (those that had a successor and a predecessor).  AC-3: the total equals
+oracle's bounds, stats.closes + stats.forest counts the vertices removed
+after the start (those that had a successor and a predecessor), and
+stats.forest the vertices of the out-side last-successor trees whose root
+the first sweep removed (both forms run: the forest collapse and
+TRIM_FLAG_STEPWISE).  AC-3: the total equals
 the oracle's closed form of the two-sided rounds (oracle.counts3two) and the
 rounds number alpha + 1 of two-sided peeling.
 """
@@ -50,12 +53,62 @@ def expected_two(g):
     return r, c, oracle.bitmap(r.live), n_dead0, t3
 
 
-def check_two(ctx, g, algos=(6, 4, 3), opts=None, name="", dev=None, exp=None):
+def _first_live(row_off, adj, dead0):
+    """Per vertex, the position of its first neighbour outside dead0 in its
+    list [row_off[v], row_off[v+1]), or -1."""
+    n = row_off.size - 1
+    start = row_off[:-1].astype(np.int64)
+    ok = np.flatnonzero(~dead0[adj])
+    j = np.searchsorted(ok, start)
+    first = np.full(n, -1, np.int64)
+    inb = j < ok.size
+    first[inb] = ok[j[inb]]
+    first[(first < start) | (first >= row_off[1:])] = -1
+    return first
+
+
+def forest_count2(g):
+    """Vertices the two-sided forest collapse removes: the vertices the first
+    sweep leaves without a live successor or a live predecessor (live: outside
+    the start-removed set of vertices without either), plus every vertex whose
+    out-support is its last successor and whose chain of such supports ends at
+    one of them (a chain into a cycle never does)."""
+    n = g.n
+    if n == 0 or g.m == 0:
+        return 0
+    rro, rcol = gg.transpose(g)
+    deg = np.diff(g.row_off.astype(np.int64))
+    indeg = np.diff(rro.astype(np.int64))
+    dead0 = (deg == 0) | (indeg == 0)
+    fo = _first_live(g.row_off, g.col, dead0)
+    fi = _first_live(rro, rcol, dead0)
+    cas = ~dead0 & ((fo < 0) | (fi < 0))
+    last = ~dead0 & ~cas & (fo == g.row_off[1:] - 1)
+    par = np.arange(n, dtype=np.int64)
+    par[last] = g.col[fo[last]]
+    for _ in range(int(np.ceil(np.log2(max(n, 2)))) + 2):
+        par = par[par]
+    at_root = par[par] == par
+    return int(cas.sum() + (last & at_root & cas[par]).sum())
+
+
+def check_two(ctx, g, algos=(6, 4, 3), opts=None, name="", dev=None, exp=None, stepwise=True):
+    """Every algorithm in `algos` against the oracle; AC-6 also in its stepwise
+    form (TRIM_FLAG_STEPWISE) unless ``stepwise`` is False."""
+    import paper_2107_12720_amd as T
     r, c, bm, n_dead0, (t3, rounds3) = exp or expected_two(g)
     dev = dev or upload(g, with_reverse=True)
-    for a in algos:
-        say(f"  [{name}] two-sided AC-{a} n={g.n} m={g.m}")
-        got, edges, st = run_two(ctx, g, a, opts=opts, dev=dev)
+    runs = [(a, opts) for a in algos]
+    if stepwise and 6 in algos:
+        o = opts or T.make_opts()
+        runs.append((6, T.make_opts(block=o.block, workers=o.workers, chunk=o.chunk,
+                                    schedule=o.schedule, budget=o.budget,
+                                    flags=o.flags | T.FLAG_STEPWISE)))
+    want_forest = None
+    for a, op in runs:
+        step = bool(op and op.flags & T.FLAG_STEPWISE)
+        say(f"  [{name}] two-sided AC-{a}{' stepwise' if step else ''} n={g.n} m={g.m}")
+        got, edges, st = run_two(ctx, g, a, opts=op, dev=dev)
         assert np.array_equal(got, bm), f"two-sided AC-{a} bitmap differs on {name}"
         assert st["n_live"] == r.n_live and st["n_dead"] == g.n - r.n_live, st
         assert edges == st["edges_total"], st
@@ -68,7 +121,16 @@ def check_two(ctx, g, algos=(6, 4, 3), opts=None, name="", dev=None, exp=None):
             # the live vertices' checks, read off their final cursors, exactly
             assert st["edges_live"] == c.T6live, (st, c)
             assert c.T6live + c.dead_lo <= edges <= c.T6live + c.dead_hi, (edges, c)
-            assert st["closes"] == g.n - r.n_live - n_dead0, (st, n_dead0)
+            # every vertex removed after the start is removed once: by the
+            # forest collapse or by a close of the propagation
+            assert st["closes"] + st["forest"] == g.n - r.n_live - n_dead0, (st, n_dead0)
+            if step:
+                assert st["forest"] == 0 and st["jump_rounds"] == 0, st
+            else:
+                if want_forest is None:
+                    want_forest = forest_count2(g)
+                assert st["forest"] == want_forest, (st, want_forest)
+                assert want_forest == 0 or st["jump_rounds"] >= 1, st
             assert st["graph_edges"] == g.m, st
     return r, c
 
