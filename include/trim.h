@@ -295,11 +295,15 @@ int trim_csr_preset(trim_ctx *ctx, int algo, const trim_csr_t *g, const uint32_t
  * hold the transpose of (row_off, col); the in-side scans follow rcol's order.
  * opts.validate checks ranges and offsets of both, not that they are
  * transposes of each other.  Outputs as for trim_csr, with worker_edges
- * sized by trim_num_workers for the same algo.  Stats: closes (AC-6) counts
- * the vertices removed after the start, i.e. those that had a successor and
- * a predecessor; n_dead all removed vertices.  AC-6 and AC-3 use 48 bytes
- * per vertex of context memory beyond trim_csr (in-side lists and records, a
- * larger queue), allocated on the first call of either.
+ * sized by trim_num_workers for the same algo.  Stats: closes + forest (AC-6)
+ * count the vertices removed after the start, i.e. those that had a
+ * successor and a predecessor; forest those the forest collapse removed (as
+ * for the one-sided call, over the out-side last-successor links; 0 with
+ * TRIM_FLAG_STEPWISE); n_dead all removed vertices.  AC-6 and AC-3 use 48
+ * bytes per vertex of context memory beyond trim_csr (in-side lists and
+ * records, a larger queue), 60 for graphs of up to 2^25 vertices (whose
+ * out-side S_more lists are split as in the one-sided call), allocated on
+ * the first call of either.
  */
 int trim_csr_two_sided(trim_ctx *ctx, int algo, const trim_csr_t *g, const trim_opts_t *opts,
                        uint32_t *live_bitmap, uint64_t *worker_edges, trim_stats_t *stats,
@@ -342,7 +346,8 @@ typedef struct {
  * counts.  The rounds and search levels are driven from the host: the call
  * synchronises `stream` once per level and returns when the labels are final.
  * Uses 96 bytes per vertex of context memory (the two-sided trimming arrays,
- * SCC marks and colours, two search frontiers and their prefix sums).
+ * SCC marks and colours, two search frontiers and their prefix sums), 108
+ * for graphs of up to 2^25 vertices (see trim_csr_two_sided).
  * TRIM_E_STALLED if a round made no progress (a guard; the method always
  * progresses).
  */

@@ -55,6 +55,7 @@ struct TwoGraph {
     int* hin;
     uint64_t* rec_out;
     uint64_t* rec_in;
+    int* ext;   // out-side split S_more heads (ac6_support.h), or nullptr
 };
 
 // Sets dead0 bit v iff v has no successor, no predecessor, or is preset
@@ -71,6 +72,8 @@ __global__ void ac6t_init(TwoGraph g, int n, uint32_t* dead0, const uint32_t* pr
                        (preset && ((preset[v >> 5] >> (v & 31)) & 1u));
         const int h = d ? kDead : kEmpty;
         reinterpret_cast<int2*>(g.hout)[v] = make_int2(h, h);
+        if (g.ext)
+            for (int j = 0; j < kMoreLists - 1; ++j) g.ext[(kMoreLists - 1) * (long long)v + j] = h;
         reinterpret_cast<int2*>(g.hin)[v] = make_int2(h, h);
         const uint64_t m = ballot(d);
         if (lane_id() == 0) {
@@ -86,6 +89,15 @@ constexpr int kTSweepUnroll = 4;   // vertices per lane in flight in the first s
 // entries buffered in LDS before one shared append: room for one step of the
 // largest workgroup (1,024 lanes x kTSweepUnroll)
 constexpr int kCasBuf = 1024 * kTSweepUnroll;
+// In-side joins of one sweep step are combined per list in an LDS table
+// (open addressing, kJoinProbes probes): a G^T list in source order makes a
+// hub the first predecessor of many of its successors, and on R-MAT scale 22
+// one list would otherwise take about 96,000 exchanges, serialised at its
+// address.  A full table only sends a join to the list directly.
+constexpr int kJoinLog = 10;
+constexpr int kJoinTable = 1 << kJoinLog;
+constexpr int kJoinProbes = 8;
+constexpr int kNoChain = -0x7FFFFFFF - 1;   // first joiner of a chain (no LDS predecessor)
 
 // The first sweep: for every vertex v outside dead0, the first successor
 // outside dead0 (its out-support) and, only if there is one, the first
@@ -112,9 +124,14 @@ __global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, 
                            int* jp, uint32_t* jlist) {
     constexpr int U = kTSweepUnroll;
     __shared__ uint32_t cas[kCasBuf];
+    __shared__ int tkey[kJoinTable], thead[kJoinTable];
     __shared__ int s_chunk, s_ncas, s_base;
     __shared__ uint64_t red[16];
     if (threadIdx.x == 0) s_ncas = 0;
+    for (int i = threadIdx.x; i < kJoinTable; i += blockDim.x) {
+        tkey[i] = -1;
+        thead[i] = kNoChain;
+    }
     uint64_t edges = 0, degsum = 0;
     auto flush = [&]() {
         __syncthreads();
@@ -193,17 +210,67 @@ __global__ void ac6t_sweep(TwoGraph g, int n, int chunk, const uint32_t* dead0, 
                     oki[k] = pi[k] < re[k];
                 }
             }
-            int oldo[U], oldi[U];
+            int oldo[U], oldi[U], key[U], hs[U];
+            bool lead[U];
+            // out-side joins first: their round trips overlap the in-side
+            // combining below
 #pragma unroll
             for (int k = 0; k < U; ++k) {
-                const uint64_t salt = ((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k];
                 if (oko[k]) {
-                    if (sched & TRIM_SCHED_JITTER) jitter_nap(salt);
-                    oldo[k] = xchg_dev(g.hout + 2 * wo[k] + (po[k] + 1 == e[k]), v[k]);
+                    if (sched & TRIM_SCHED_JITTER)
+                        jitter_nap(((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k]);
+                    oldo[k] = xchg_dev(join_slot(g.hout, g.ext, wo[k], po[k] + 1 == e[k], v[k]),
+                                       v[k]);
                 }
+            }
+            // in-side joins, step 1: join the workgroup's chain for the list
+            // (a free or matching table entry within kJoinProbes probes; else
+            // the list directly)
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                hs[k] = -1;
+                lead[k] = false;
                 if (oko[k] && oki[k]) {
-                    if (sched & TRIM_SCHED_JITTER) jitter_nap(salt ^ 1);
-                    oldi[k] = xchg_dev(g.hin + 2 * wi[k] + (pi[k] + 1 == re[k]), v[k]);
+                    key[k] = 2 * wi[k] + (pi[k] + 1 == re[k]);
+                    uint32_t h = ((uint32_t)key[k] * 0x9E3779B1u) >> (32 - kJoinLog);
+                    for (int t = 0; t < kJoinProbes; ++t, h = (h + 1) & (kJoinTable - 1)) {
+                        const int cur = atomicCAS(&tkey[h], -1, key[k]);
+                        if (cur == -1 || cur == key[k]) {
+                            lead[k] = cur == -1;
+                            hs[k] = (int)h;
+                            oldi[k] = atomicExch(&thead[h], v[k]);
+                            break;
+                        }
+                    }
+                    if (hs[k] < 0) {
+                        if (sched & TRIM_SCHED_JITTER)
+                            jitter_nap((((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k]) ^ 1);
+                        oldi[k] = xchg_dev(g.hin + key[k], v[k]);
+                    }
+                }
+            }
+            __syncthreads();
+            // step 2: one exchange per list publishes the whole chain; the
+            // list's previous head goes where the chain's head was
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (lead[k]) {
+                    if (sched & TRIM_SCHED_JITTER)
+                        jitter_nap((((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k]) ^ 1);
+                    thead[hs[k]] = xchg_dev(g.hin + key[k], thead[hs[k]]);
+                }
+            }
+            __syncthreads();
+            // step 3: the chain's first joiner links to the previous head
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (hs[k] >= 0 && oldi[k] == kNoChain) oldi[k] = thead[hs[k]];
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (lead[k]) {
+                    tkey[hs[k]] = -1;
+                    thead[hs[k]] = kNoChain;
                 }
             }
 #pragma unroll
@@ -343,7 +410,7 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
                         stays = in ? resume(in_view, rx, rec_cursor(r) + 1, g.hin, g.rec_in, edges,
                                             sched)
                                    : resume(out_view, rx, rec_cursor(r) + 1, g.hout, g.rec_out,
-                                            edges, sched);
+                                            edges, sched, g.ext);
                         joins += stays;
                     }
                     if (stays) {
@@ -367,12 +434,13 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
             // load of its link, all in flight together; the next step's memory
             // operations are issued before this step's pushes.
             int link = side >= 0 ? ld_dev(rec_link(side ? g.rec_in : g.rec_out, cx)) : -1;
-            int2 o = xchg2_dev(g.hout + 2 * cx, kDead, kDead);
+            ClosedLists o = close_lists(g.hout, g.ext, cx);
             int2 i = xchg2_dev(g.hin + 2 * cx, kDead, kDead);
             int fill = 0;
             for (int hop = 0;; ++hop) {
-                closes += (o.x != kDead);   // the out-pair's exchange counts the removal
-                const int ao = o.x, bo = o.y, ai = i.x, bi = i.y;
+                closes += (o.more[0] != kDead);   // the out-pair's exchange counts the removal
+                const ClosedLists co = o;
+                const int bo = co.last, ai = i.x, bi = i.y;
                 const int sib = side >= 0 ? link : -1;
                 int next = sib, nside = side;
                 if (bo >= 0) {
@@ -387,10 +455,12 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
                 if (go) {
                     if (sched & TRIM_SCHED_JITTER) jitter_nap(((uint64_t)next << 8) ^ hop);
                     link = ld_dev(rec_link(nside ? g.rec_in : g.rec_out, next));
-                    o = xchg2_dev(g.hout + 2 * next, kDead, kDead);
+                    o = close_lists(g.hout, g.ext, next);
                     i = xchg2_dev(g.hin + 2 * next, kDead, kDead);
                 }
-                if (ao >= 0) wq.push1(titem(kTMoreOut, ao));
+#pragma unroll
+                for (int j = 0; j < kMoreLists; ++j)
+                    if (co.more[j] >= 0) wq.push1(titem(kTMoreOut, co.more[j]));
                 if (ai >= 0) wq.push1(titem(kTMoreIn, ai));
                 if (bo >= 0 && bi >= 0) wq.push1(titem(kTLastIn, bi));
                 if ((bo >= 0 || bi >= 0) && sib >= 0) wq.push1(titem(last_kind(side), sib));
@@ -419,21 +489,25 @@ __global__ __launch_bounds__(256) void ac6t_propagate(TwoGraph g, uint32_t* q, i
     }
 }
 
-// The forest collapse's removal (forest_jump.h): both pairs of v exchanged
-// with kDead; its out-side and in-side S_more lists go back to the
+// The forest collapse's removal (forest_jump.h): every list head of v
+// exchanged with kDead; its out-side and in-side S_more lists go back to the
 // propagation as walks, and its in-side S_last list as a chain of removals.
 // (Its out-side S_last members are its own tree's, removed by the same
 // rounds.)
-static_assert(kJumpItems >= 3, "a two-sided removal hands back up to three lists");
+static_assert(kJumpItems >= kMoreLists + 2, "a two-sided removal hands back its S_more lists "
+                                            "and both in-side lists");
 struct TwoSidedKill {
     int* hout;
     int* hin;
+    int* ext;
     __device__ __forceinline__ void operator()(int v, uint32_t (&item)[kJumpItems]) const {
-        const int2 o = xchg2_dev(hout + 2 * v, kDead, kDead);
+        const ClosedLists o = close_lists(hout, ext, v);
         const int2 i = xchg2_dev(hin + 2 * v, kDead, kDead);
-        if (o.x >= 0) item[0] = titem(kTMoreOut, o.x);
-        if (i.x >= 0) item[1] = titem(kTMoreIn, i.x);
-        if (i.y >= 0) item[2] = titem(kTLastIn, i.y);
+#pragma unroll
+        for (int j = 0; j < kMoreLists; ++j)
+            if (o.more[j] >= 0) item[j] = titem(kTMoreOut, o.more[j]);
+        if (i.x >= 0) item[kMoreLists] = titem(kTMoreIn, i.x);
+        if (i.y >= 0) item[kMoreLists + 1] = titem(kTLastIn, i.y);
     }
 };
 
@@ -489,7 +563,12 @@ hipError_t ac6_two_csr_preset(const trim_csr_t& gc, const Work& w, const Work2& 
                               const LaunchCfg& lc, uint32_t* bitmap, uint64_t* worker_edges,
                               trim_stats_t* stats, const uint32_t* preset) {
     const int n = gc.n, P = lc.workers, B = lc.block;
-    TwoGraph g{gc.row_off, gc.col, gc.rrow_off, gc.rcol, w.a, x.hin, w.b, x.rec_in};
+    // split out-side S_more lists where their heads exist and the shared
+    // queue has room for the items a close then hands back
+    const bool split = w.ext && n <= kSplitMaxN &&
+                       x.qwords >= (long long)kQueuePerVertexTwoSplit * n + kQueueSlots;
+    TwoGraph g{gc.row_off, gc.col, gc.rrow_off, gc.rcol, w.a, x.hin, w.b, x.rec_in,
+               split ? w.ext : nullptr};
     uint32_t* dead0 = reinterpret_cast<uint32_t*>(w.c);
     int sweep_blocks = 0, pack_blocks = 0;
     {
@@ -509,7 +588,7 @@ hipError_t ac6_two_csr_preset(const trim_csr_t& gc, const Work& w, const Work2& 
         if (lc.forest) {
             Timed t(lc, "ac6t_jump");
             hipLaunchKernelGGL(ac6_jump<TwoSidedKill>, dim3(phase_blocks(n, lc.cus)), dim3(256), 0,
-                               lc.stream, TwoSidedKill{g.hout, g.hin}, w.jp, w.e, w.e + n, x.q,
+                               lc.stream, TwoSidedKill{g.hout, g.hin, g.ext}, w.jp, w.e, w.e + n, x.q,
                                w.ctr, jump_rounds(n), lc.budget);
         }
         {

@@ -38,8 +38,9 @@ constexpr int kJumpUnroll = 2;
 // spans kJumpHops * d after the round (2 is classic pointer doubling).
 constexpr int kJumpHops = 8;
 // Work items a removed vertex may hand back (its lists that are not members of
-// its own tree).
-constexpr int kJumpItems = kMoreLists;
+// its own tree): its S_more lists, plus the two in-side lists of the
+// two-sided kernels.
+constexpr int kJumpItems = kMoreLists + 2;
 
 // Items of one round step buffered in LDS: up to kJumpItems per removed vertex,
 // kJumpUnroll vertices per thread, plus what is left from before.

@@ -148,15 +148,17 @@ void free_work2(trim_ctx* c) {
     c->cap_n2 = 0;
 }
 
-// Two-sided AC-6 queues at most 7 items per vertex: one close, one S_last
-// member per side, one S_more list head per side and one failed scan per
-// side.  8n slots cover that.
+// Two-sided AC-6 queue: kQueuePerVertexTwo slots per vertex, or
+// kQueuePerVertexTwoSplit where the out-side S_more lists are split (graphs
+// up to kSplitMaxN vertices).
 int ensure2(trim_ctx* c, int64_t n) {
     size_t need = (size_t)(n > 0 ? n : 1);
     if (need <= c->cap_n2) return TRIM_OK;
     free_work2(c);
     size_t cap = need + need / 8 + 64;
-    const size_t qbytes = cap * 32 + (size_t)trim::kQueueSlots * 4;
+    const size_t per = (long long)need <= trim::kSplitMaxN ? trim::kQueuePerVertexTwoSplit
+                                                            : trim::kQueuePerVertexTwo;
+    const size_t qbytes = (cap * per + (size_t)trim::kQueueSlots) * 4;
     if (dmalloc(c, &c->w2.hin, cap * 8) != hipSuccess ||
         dmalloc(c, &c->w2.rec_in, cap * 8) != hipSuccess ||
         dmalloc(c, &c->w2.q, qbytes) != hipSuccess ||
@@ -167,7 +169,7 @@ int ensure2(trim_ctx* c, int64_t n) {
                     (long long)n);
     }
     c->cap_n2 = cap;
-    c->w2.qwords = (long long)cap * 8 + trim::kQueueSlots;
+    c->w2.qwords = (long long)(cap * per) + trim::kQueueSlots;
     return TRIM_OK;
 }
 

@@ -59,7 +59,8 @@ struct Work {
 struct Work2 {
     int* hin = nullptr;         // 2n int32: in-side list heads
     uint64_t* rec_in = nullptr; // n uint64: in-side (next, cursor) records
-    uint32_t* q = nullptr;      // 8n shared-queue slots (+ kQueueSlots), kNone between calls
+    uint32_t* q = nullptr;      // kQueuePerVertexTwo(Split) n shared-queue slots (+ kQueueSlots),
+                                //   kNone between calls
     long long qwords = 0;       // size of q in words
 };
 constexpr int kMaxWorkers = 16384;
@@ -69,6 +70,12 @@ constexpr int kMaxWorkers = 16384;
 constexpr int kMoreLists = 4;
 constexpr long long kSplitMaxN = 1LL << 25;
 constexpr int kQueuePerVertexSplit = 2 + kMoreLists;
+// Two-sided AC-6 queues at most 7 items per vertex with one S_more list per
+// side (one close, one S_last member per side, one S_more list head per side,
+// one failed scan per side), kMoreLists - 1 more with split out-side lists;
+// one slot per vertex more is kept as a margin.
+constexpr int kQueuePerVertexTwo = 8;
+constexpr int kQueuePerVertexTwoSplit = kQueuePerVertexTwo + kMoreLists - 1;
 // shared-queue slack beyond 3n slots: outstanding tickets, 64 per wavefront
 constexpr int kQueueSlots = 64 * 4 * kMaxWorkers;
 constexpr int kPartStride = 16384;   // >= workers, sweep blocks and pack blocks
