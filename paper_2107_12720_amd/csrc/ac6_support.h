@@ -8,12 +8,16 @@ namespace trim {
 
 // Split S_more lists: with `ext` (kMoreLists - 1 ints per vertex), S_more(w)
 // is kMoreLists lists -- head[2w] and ext[(kMoreLists - 1) w ..] -- and
-// joiner u goes to list u % kMoreLists, so a closed hub's supporters come
-// back as that many chains, walked side by side.  S_last(w) stays one list
-// (head[2w+1]).  ext == nullptr: one list.
+// joiner u goes to the list its id hashes to, so a closed hub's supporters
+// come back as that many chains, walked side by side.  The hash (the top
+// bits of a multiplicative one) and not the low bits of u: on R-MAT graphs
+// the low id bits follow the generator's quadrant choices, and u mod 4 put
+// up to 459 of one hub's 1,282 supporters in one list where the hash puts
+// about a quarter.  S_last(w) stays one list (head[2w+1]).  ext == nullptr:
+// one list.
 __device__ __forceinline__ int* join_slot(int* head, int* ext, int w, bool last, int u) {
     if (last) return head + 2 * w + 1;
-    const int s = u & (kMoreLists - 1);
+    const int s = (int)(((uint32_t)u * 0x9E3779B1u) >> (32 - kMoreListsLog));
     return (s == 0 || !ext) ? head + 2 * w : ext + (kMoreLists - 1) * w + (s - 1);
 }
 // The heads of a closed vertex's lists: more[] (kEmpty = none), last.

@@ -67,7 +67,8 @@ constexpr int kMaxWorkers = 16384;
 // AC-6 splits S_more lists kMoreLists ways for graphs up to kSplitMaxN
 // vertices; a close can then queue up to kMoreLists S_more heads, so the
 // shared queue needs room for 2 + kMoreLists items per vertex instead of 3.
-constexpr int kMoreLists = 4;
+constexpr int kMoreListsLog = 2;
+constexpr int kMoreLists = 1 << kMoreListsLog;
 constexpr long long kSplitMaxN = 1LL << 25;
 constexpr int kQueuePerVertexSplit = 2 + kMoreLists;
 // Two-sided AC-6 queues at most 7 items per vertex with one S_more list per
