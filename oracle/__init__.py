@@ -109,6 +109,11 @@ def load(path: str):
     L.or_ac3_jacobi2.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
     L.or_counts3two.restype = ctypes.c_int64
     L.or_counts3two.argtypes = [ctypes.c_int32, i32p, i32p, i32p, i32p, u8p, i32p, i64p]
+    L.or_ac6_deferred.restype = ctypes.c_int64
+    L.or_ac6_deferred.argtypes = [ctypes.c_int32, i32p, i32p, ctypes.c_int32, u8p, i64p]
+    L.or_counts_deferred.restype = ctypes.c_int64
+    L.or_counts_deferred.argtypes = [ctypes.c_int32, i32p, i32p, u8p, i32p, ctypes.c_int32,
+                                     ctypes.c_int32, i64p]
     L.or_num_threads.restype = ctypes.c_int
     L.or_fin64.restype = ctypes.c_uint64
     L.or_fin64.argtypes = [ctypes.c_uint64]
@@ -284,6 +289,38 @@ def ac3(g, jacobi: bool = True):
     if f(g.n, ro, col, live, st) < 0:
         raise MemoryError("oracle ac3: allocation failed")
     return live, int(st[0]), int(st[1])
+
+
+@dataclass
+class Deferred:
+    live: np.ndarray      # uint8[n], 1 = LIVE
+    edges: int            # traversed edges, cursor re-checks included
+    rounds: int           # rounds run (the last one registers supports unless the
+                          # fixed point came first)
+    rechecks: int         # cursor re-checks of rounds 2..
+
+
+def ac6_deferred(g, rounds: int) -> Deferred:
+    """AC-3 rounds with cursor for up to ``rounds - 1`` repetitions, then AC-6
+    from the vertices still live, run literally (oracle.c or_ac6_deferred)."""
+    ro, col = _csr(g)
+    live = np.empty(g.n, np.uint8)
+    st = np.zeros(4, np.int64)
+    if lib().or_ac6_deferred(g.n, ro, col, int(rounds), live, st) < 0:
+        raise MemoryError("oracle ac6_deferred: allocation failed")
+    return Deferred(live, int(st[0]), int(st[1]), int(st[3]))
+
+
+def counts_deferred(g, res: PeelResult, rounds: int):
+    """(total, rounds, rechecks) of :func:`ac6_deferred` in closed form from the
+    peeling levels (rounds >= 2)."""
+    ro, col = _csr(g)
+    out = np.zeros(3, np.int64)
+    rc = lib().or_counts_deferred(g.n, ro, col, res.live, res.level, res.alpha, int(rounds),
+                                  out)
+    if rc != 0:
+        raise ValueError(f"oracle counts: live vertex {-rc - 1} has no live successor")
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def bitmap(live: np.ndarray) -> np.ndarray:

@@ -24,6 +24,9 @@
  *                  at the start of each repetition (round).
  *   or_ac3_inplace the same with statuses updated in place during a sweep
  *                  (the literal sequential schedule, vertices in id order).
+ *   or_ac6_deferred  AC-3 rounds first, then AC-6 from the vertices still
+ *                  LIVE (supporting sets registered only for them), run
+ *                  literally; or_counts_deferred its totals in closed form.
  *   or_counts      closed forms of the traversed-edge totals for AC-6,
  *                  AC-4 (with and without the * initialisation) and AC-3.
  *   or_implicit_csr  materialises the hash-generated graph (Section 2.1,
@@ -248,6 +251,133 @@ int64_t or_ac3_inplace(int32_t n, const int32_t *row_off, const int32_t *col, ui
     return ac3_run(n, row_off, col, live, stats, 0);
 }
 
+/* ------------------------------------------- AC-6, supports registered late */
+/*
+ * A combination of the two algorithms above, for graphs that are shallow
+ * (small alpha): the first R-1 repetitions are AC-3 rounds with the
+ * edge_index cursor (statuses as at the start of each round, as in
+ * or_ac3_jacobi), in which no vertex joins a supporting set.  If a round
+ * removes nothing, the fixed point is reached and the run stops there.
+ * Otherwise round R is one more such round in which every vertex still LIVE
+ * re-checks its cursor, scans on past successors removed before round R, and
+ * joins the supporting set of the successor it stops at (Section 6.1) -- or
+ * becomes DEAD and enters Q if there is none.  From then on the AC-6
+ * propagation runs as in or_ac6_seq: every w taken from Q hands the members
+ * of w.S back to DoPost, which resumes after their cursor.  R <= 1 is the
+ * plain AC-6 algorithm.
+ *
+ * stats[0] = traversed edges (every status check of a successor, the
+ * cursor re-checks of rounds 2.. included), stats[1] = rounds run,
+ * stats[2] = n_live, stats[3] = cursor re-checks = entries of the live lists
+ * of rounds 2.. (vertices still LIVE at the start of such a round).
+ */
+int64_t or_ac6_deferred(int32_t n, const int32_t *row_off, const int32_t *col, int32_t R,
+                        uint8_t *live, int64_t *stats) {
+    int64_t *cur = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int64_t *dround = (int64_t *)malloc(((size_t)n + 1) * sizeof(int64_t));
+    int32_t *sh = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *sn = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    int32_t *Q = (int32_t *)malloc(((size_t)n + 1) * sizeof(int32_t));
+    if (!cur || !dround || !sh || !sn || !Q) {
+        free(cur); free(dround); free(sh); free(sn); free(Q);
+        return -1;
+    }
+    const int64_t NEVER = INT64_MAX;
+    for (int32_t v = 0; v < n; ++v) {
+        live[v] = 1;
+        cur[v] = row_off[v];
+        dround[v] = NEVER;
+        sh[v] = -1;
+    }
+    if (R < 1) R = 1;
+    int64_t edges = 0, rechecks = 0, rounds = 0, n_live = n;
+    int change = 1;
+    /* rounds 1 .. R-1: no supporting sets */
+    while (change && rounds < R - 1) {
+        change = 0;
+        rounds += 1;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!live[v]) continue;
+            if (rounds > 1) rechecks += 1;
+            int64_t end = row_off[v + 1];
+            int found = 0;
+            while (cur[v] < end) {
+                edges += 1;
+                if (dround[col[cur[v]]] >= rounds) { found = 1; break; }
+                cur[v] += 1;
+            }
+            if (!found) {
+                live[v] = 0;
+                dround[v] = rounds;
+                n_live -= 1;
+                change = 1;
+            }
+        }
+    }
+    if (change) {
+        /* round R: the same check, and the survivors join */
+        rounds += 1;
+        int64_t qh = 0, qt = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (!live[v]) continue;
+            if (rounds > 1) rechecks += 1;
+            int64_t end = row_off[v + 1];
+            int found = 0;
+            while (cur[v] < end) {
+                int32_t w = col[cur[v]];
+                edges += 1;
+                if (dround[w] >= rounds) {
+                    sn[v] = sh[w];
+                    sh[w] = v;
+                    found = 1;
+                    break;
+                }
+                cur[v] += 1;
+            }
+            if (!found) Q[qt++] = v;   /* removed in round R */
+        }
+        /* statuses of round R's removals change only now, so that round R
+           read those of its start */
+        for (int64_t i = 0; i < qt; ++i) {
+            live[Q[i]] = 0;
+            dround[Q[i]] = rounds;
+            n_live -= 1;
+        }
+        /* the AC-6 propagation: a member handed back resumes after its
+           cursor with the current statuses */
+        while (qh < qt) {
+            int32_t w = Q[qh++];
+            while (sh[w] >= 0) {
+                int32_t u = sh[w];
+                sh[w] = sn[u];
+                int64_t end = row_off[u + 1];
+                int found = 0;
+                for (cur[u] += 1; cur[u] < end; cur[u] += 1) {
+                    int32_t x = col[cur[u]];
+                    edges += 1;
+                    if (live[x]) {
+                        sn[u] = sh[x];
+                        sh[x] = u;
+                        found = 1;
+                        break;
+                    }
+                }
+                if (!found) {
+                    live[u] = 0;
+                    n_live -= 1;
+                    Q[qt++] = u;
+                }
+            }
+        }
+    }
+    stats[0] = edges;
+    stats[1] = rounds;
+    stats[2] = n_live;
+    stats[3] = rechecks;
+    free(cur); free(dround); free(sh); free(sn); free(Q);
+    return edges;
+}
+
 /* --------------------------------------------------------- closed forms */
 /*
  * Traversed-edge totals from the final live set and the peeling levels
@@ -295,6 +425,47 @@ int64_t or_counts(int32_t n, const int32_t *row_off, const int32_t *col, const u
     out[6] = m;
     out[7] = n_live;
     free(indeg);
+    return 0;
+}
+
+/*
+ * Closed form of or_ac6_deferred's totals for R >= 2, from the final live
+ * set and the peeling levels.  In round r a vertex's cursor moves past the
+ * successors of level < r, so a vertex removed at level l <= R checks
+ * deg(v) + l - 1 edges (as in AC-3), one removed later checks its cursor in
+ * each of the R rounds and every other edge once: deg(v) + R - 1, and a live
+ * one fl(v) + 1 plus one re-check per round after the first:
+ *   out[0] T = sum_dead (deg(v) + min(R, level(v)) - 1)
+ *              + sum_live (fl(v) + min(R, alpha + 1))
+ *   out[1] rounds = min(R, alpha + 1)
+ *   out[2] re-checks = sum_dead (min(R, level(v)) - 1)
+ *                      + sum_live (min(R, alpha + 1) - 1)
+ * so that T - re-checks is the AC-6 total T6.
+ * Returns 0, or -(v+1) for a live vertex without a live successor.
+ */
+int64_t or_counts_deferred(int32_t n, const int32_t *row_off, const int32_t *col,
+                           const uint8_t *live, const int32_t *level, int32_t alpha, int32_t R,
+                           int64_t *out) {
+    const int64_t rounds = (int64_t)alpha + 1 < R ? (int64_t)alpha + 1 : R;
+    int64_t t = 0, re = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        int64_t b = row_off[v], e = row_off[v + 1];
+        if (live[v]) {
+            int64_t fl = -1;
+            for (int64_t k = b; k < e; ++k)
+                if (live[col[k]]) { fl = k - b; break; }
+            if (fl < 0) return -((int64_t)v + 1);
+            t += fl + rounds;
+            re += rounds - 1;
+        } else {
+            int64_t l = level[v] < R ? level[v] : R;
+            t += (e - b) + l - 1;
+            re += l - 1;
+        }
+    }
+    out[0] = t;
+    out[1] = rounds;
+    out[2] = re;
     return 0;
 }
 
