@@ -256,8 +256,11 @@ int64_t or_ac3_inplace(int32_t n, const int32_t *row_off, const int32_t *col, ui
  * A combination of the two algorithms above, for graphs that are shallow
  * (small alpha): the first R-1 repetitions are AC-3 rounds with the
  * edge_index cursor (statuses as at the start of each round, as in
- * or_ac3_jacobi), in which no vertex joins a supporting set.  If a round
- * removes nothing, the fixed point is reached and the run stops there.
+ * or_ac3_jacobi), in which no vertex joins a supporting set.  Vertices
+ * without successors are DEAD before the first round (as during the first
+ * DoPost sweep of the AC-6 algorithm, which the first round is), so a vertex
+ * of peeling level l >= 2 is removed in round l - 1.  If a round removes
+ * nothing, the fixed point is reached and the run stops there.
  * Otherwise round R is one more such round in which every vertex still LIVE
  * re-checks its cursor, scans on past successors removed before round R, and
  * joins the supporting set of the successor it stops at (Section 6.1) -- or
@@ -283,14 +286,19 @@ int64_t or_ac6_deferred(int32_t n, const int32_t *row_off, const int32_t *col, i
         return -1;
     }
     const int64_t NEVER = INT64_MAX;
+    int64_t edges = 0, rechecks = 0, rounds = 0, n_live = n;
     for (int32_t v = 0; v < n; ++v) {
         live[v] = 1;
         cur[v] = row_off[v];
         dround[v] = NEVER;
         sh[v] = -1;
+        if (row_off[v + 1] == row_off[v]) {   /* removed before round 1 */
+            live[v] = 0;
+            dround[v] = 0;
+            n_live -= 1;
+        }
     }
     if (R < 1) R = 1;
-    int64_t edges = 0, rechecks = 0, rounds = 0, n_live = n;
     int change = 1;
     /* rounds 1 .. R-1: no supporting sets */
     while (change && rounds < R - 1) {
@@ -430,23 +438,24 @@ int64_t or_counts(int32_t n, const int32_t *row_off, const int32_t *col, const u
 
 /*
  * Closed form of or_ac6_deferred's totals for R >= 2, from the final live
- * set and the peeling levels.  In round r a vertex's cursor moves past the
- * successors of level < r, so a vertex removed at level l <= R checks
- * deg(v) + l - 1 edges (as in AC-3), one removed later checks its cursor in
- * each of the R rounds and every other edge once: deg(v) + R - 1, and a live
- * one fl(v) + 1 plus one re-check per round after the first:
- *   out[0] T = sum_dead (deg(v) + min(R, level(v)) - 1)
- *              + sum_live (fl(v) + min(R, alpha + 1))
- *   out[1] rounds = min(R, alpha + 1)
- *   out[2] re-checks = sum_dead (min(R, level(v)) - 1)
- *                      + sum_live (min(R, alpha + 1) - 1)
+ * set and the peeling levels.  Vertices without successors (level 1) are
+ * removed before round 1 and check nothing.  In round r a vertex's cursor
+ * moves past the successors of level <= r, so a vertex of level l >= 2 takes
+ * part in k(v) = min(R, l - 1) rounds: it checks its cursor edge once in
+ * each and every other edge once, deg(v) + k(v) - 1 edges; a live one takes
+ * part in all rounds run, K = min(R, max(alpha, 1)), and checks
+ * fl(v) + K edges:
+ *   out[0] T = sum_{dead, deg > 0} (deg(v) + k(v) - 1) + sum_live (fl(v) + K)
+ *   out[1] rounds = K
+ *   out[2] re-checks = sum_{dead, deg > 0} (k(v) - 1) + sum_live (K - 1)
  * so that T - re-checks is the AC-6 total T6.
  * Returns 0, or -(v+1) for a live vertex without a live successor.
  */
 int64_t or_counts_deferred(int32_t n, const int32_t *row_off, const int32_t *col,
                            const uint8_t *live, const int32_t *level, int32_t alpha, int32_t R,
                            int64_t *out) {
-    const int64_t rounds = (int64_t)alpha + 1 < R ? (int64_t)alpha + 1 : R;
+    const int64_t a = alpha > 1 ? alpha : 1;
+    const int64_t rounds = a < R ? a : R;
     int64_t t = 0, re = 0;
     for (int32_t v = 0; v < n; ++v) {
         int64_t b = row_off[v], e = row_off[v + 1];
@@ -457,10 +466,10 @@ int64_t or_counts_deferred(int32_t n, const int32_t *row_off, const int32_t *col
             if (fl < 0) return -((int64_t)v + 1);
             t += fl + rounds;
             re += rounds - 1;
-        } else {
-            int64_t l = level[v] < R ? level[v] : R;
-            t += (e - b) + l - 1;
-            re += l - 1;
+        } else if (e > b) {
+            int64_t k = (int64_t)level[v] - 1 < R ? (int64_t)level[v] - 1 : R;
+            t += (e - b) + k - 1;
+            re += k - 1;
         }
     }
     out[0] = t;
