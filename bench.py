@@ -620,7 +620,18 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
     st3 = res3.stats_dict()
     bits3 = np.unpackbits(res3.bitmap_numpy().view(np.uint8), bitorder="little")[:n]
     b3i = 4 * st3["edges_total"] + 12 * st3["work_items"] + n // 8
-    log(f"implicit: AC-6 {ms6:.2f} ms, AC-3 {ms3:.2f} ms ({st3['rounds']} rounds)")
+    dcheck, dout = bench_deferred(ctx, T, n, lambda o: ctx.trim_implicit(
+        T.AC6, log2n, imp.seed, imp.zero_thr, table, live_bitmap=lb, worker_edges=we,
+        stats=st, opts=o), reps, (4, 8))
+    for R, d in dcheck.items():
+        # the full oracle runs in the GPU test suite; here: the same live set
+        # as plain AC-6 and the same T6 once the re-checks are taken out
+        bitsR = np.unpackbits(d["bitmap"].view(np.uint8), bitorder="little")[:n]
+        dout["by_rounds"][str(R)]["parity"] = None
+        dout["by_rounds"][str(R)]["same_live_set_and_T6_as_ac6"] = bool(
+            np.array_equal(bitsR, bits) and d["edges"] - d["rechecks"] == t6)
+    log(f"implicit: AC-6 {ms6:.2f} ms, AC-3 {ms3:.2f} ms ({st3['rounds']} rounds), "
+        f"deferred AC-6 {dout['fastest_ms']:.2f} ms (R = {dout['fastest_rounds']})")
     return {"implicit": imp, "bits": bits}, {
         "workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
         "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": t6,
@@ -632,6 +643,7 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
                 "roofline": roof(b3i, ms3),
                 "same_live_set_as_ac6": bool(np.array_equal(bits3, bits))},
         "ac6_speedup_vs_ac3": ms3 / ms6,
+        "deferred": dout,
         "full_parity": "the full bitmap, T6, T3J and AC-3's rounds are compared with the "
                        "oracle in the GPU test suite (test_implicit_2_28_full); here: the "
                        "fixed-point property on 20,000 sampled vertices",
@@ -660,6 +672,41 @@ def ac3_bytes(n, st):
 def roof(b, ms):
     return {"algorithmic_bytes": int(b), "GBs": b / (ms / 1e3) / 1e9,
             "frac": b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+
+
+def bench_deferred(ctx, T, n, call, reps, rounds):
+    """AC-6 with late support registration (opts.rounds = R): AC-3 rounds with
+    the cursor first, supports registered in round R only for the vertices
+    still live.  Per R: time per trim, the traversed edges with and without the
+    cursor re-checks (edges_total - rechecks is the plain AC-6 total T6), the
+    rounds run, and the plain path's algorithmic bytes B6 = 8 T6 + 20 n + n/8
+    over this time (the same work as plain AC-6, so the two fractions compare
+    directly).  `call(opts)` runs one trim."""
+    import numpy as np
+    out, check = {}, {}
+    for R in rounds:
+        ms, kt, res = time_gpu(ctx, lambda o=T.make_opts(rounds=R): call(o), reps, 1)
+        st = res.stats_dict()
+        check[R] = {"bitmap": res.bitmap_numpy().copy(), "edges": st["edges_total"],
+                    "rounds": st["rounds"], "rechecks": st["rechecks"]}
+        t6 = st["edges_total"] - st["rechecks"]
+        out[str(R)] = {"ms": ms, "edges_total": st["edges_total"], "rechecks": st["rechecks"],
+                       "T6": t6, "rounds": st["rounds"], "joins": st["joins"],
+                       "kernels_ms": {k: float(np.mean(v)) for k, v in kt.items()},
+                       "path_B6": roof(8 * t6 + 20 * n + n // 8, ms), "parity": None}
+    best = min(out, key=lambda k: out[k]["ms"])
+    return check, {"by_rounds": out, "fastest_rounds": int(best), "fastest_ms": out[best]["ms"]}
+
+
+def deferred_parity(orc, g, r, bm, c, dc, do):
+    """CPU leg of bench_deferred: bitmap, total, rounds and re-checks against
+    the oracle's closed form, and total - re-checks against T6."""
+    import numpy as np
+    for R, got in dc.items():
+        tot, rounds, re = orc.counts_deferred(g, r, R)
+        do["by_rounds"][str(R)]["parity"] = bool(
+            np.array_equal(got["bitmap"], bm) and got["edges"] == tot
+            and got["rounds"] == rounds and got["rechecks"] == re and tot - re == c.T6)
 
 
 def bench_cfg0(ctx, T, gg, steps=50):
@@ -693,8 +740,13 @@ def bench_cfg0(ctx, T, gg, steps=50):
                      "parity": None}
         if name == "ac3":
             out[name]["rounds"] = st["rounds"]
+    check["deferred"], out["deferred"] = bench_deferred(
+        ctx, T, n, lambda o: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=lb,
+                                          worker_edges=we[:ctx.num_workers(T.AC6)], stats=st_t,
+                                          opts=o), steps, (4, 16, 32, 64))
     log(f"cfg0: AC-6 {out['ac6']['us']:.1f} us, AC-4 {out['ac4']['us']:.1f} us, "
-        f"AC-3 {out['ac3']['us']:.1f} us")
+        f"AC-3 {out['ac3']['us']:.1f} us, deferred AC-6 "
+        f"{out['deferred']['fastest_ms'] * 1e3:.1f} us (R = {out['deferred']['fastest_rounds']})")
     return check, out
 
 
@@ -741,6 +793,11 @@ def bench_explicit26(ctx, T, gg, reps):
                     "frac": path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
            "parity": None}
     check = {"graph": g, "ac6": {"bitmap": bm6, "edges": st["edges_total"]}}
+    check["deferred"], out["deferred"] = bench_deferred(
+        ctx, T, n, lambda o: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=lb, worker_edges=we[:P],
+                                          stats=st_t, opts=o), reps, (2, 4, 8))
+    log(f"explicit26: deferred AC-6 {out['deferred']['fastest_ms']:.3f} ms "
+        f"(R = {out['deferred']['fastest_rounds']})")
     # the baselines on the same graph; AC-4 takes G^T as an input (built here,
     # outside any timed region, as the paper treats it)
     log("explicit: G^T for AC-4 ...")
@@ -917,6 +974,8 @@ def oracle_leg(g, checks, cpu_seconds, out):
                                      f"the sequential peel, mean {tm:.3f} s",
                            "host_cores": os.cpu_count()}
     want_bm = oracle.bitmap(r.live)
+    if "deferred" in checks:
+        deferred_parity(oracle, g, r, want_bm, c, checks["deferred"], out["deferred"])
     a6 = checks["ac6"]
     out["parity"] = bool(np.array_equal(a6["bitmap"], want_bm) and a6["edges"] == c.T6)
     out["config"].update({"alpha": r.alpha, "n_live": r.n_live, "T6": c.T6, "T6min": c.T6min})
@@ -1016,6 +1075,8 @@ def oracle_leg(g, checks, cpu_seconds, out):
                                       and (name != "ac3" or cc[name]["rounds"] == c0.rounds3))
         co.update({"T6": c0.T6, "T4star": c0.T4s, "T3J": c0.T3J, "alpha": r0.alpha,
                    "n_live": r0.n_live})
+        if "deferred" in cc:
+            deferred_parity(oracle, cc["graph"], r0, bm0, c0, cc["deferred"], co["deferred"])
     if "explicit26" in checks:
         ec, eo = checks["explicit26"], out["explicit26"]
         g26 = ec["graph"]
@@ -1033,6 +1094,8 @@ def oracle_leg(g, checks, cpu_seconds, out):
                                    and ec["ac3"]["edges"] == c26.T3J
                                    and ec["ac3"]["rounds"] == c26.rounds3)
         eo.update({"alpha": r26.alpha, "T6min": c26.T6min})
+        if "deferred" in ec:
+            deferred_parity(oracle, g26, r26, bm26, c26, ec["deferred"], eo["deferred"])
     if "implicit" in checks:
         imp, bits = checks["implicit"]["implicit"], checks["implicit"]["bits"]
         rng = np.random.default_rng(0)
@@ -1160,6 +1223,12 @@ def main():
                  "frac": path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS},
         "stats": st,
     }
+
+    checks["deferred"], out["deferred"] = bench_deferred(
+        ctx, T, n, lambda o: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=bm, worker_edges=we,
+                                          stats=st_t, opts=o), 10, (2, 8))
+    log(f"deferred AC-6 {out['deferred']['fastest_ms']:.3f} ms "
+        f"(R = {out['deferred']['fastest_rounds']})")
 
     gt = None   # G^T on the host, built once when a section needs it
     if not args.no_baselines:

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define TRIM_ABI_VERSION 2
+#define TRIM_ABI_VERSION 3
 
 typedef enum { TRIM_AC3 = 3, TRIM_AC4 = 4, TRIM_AC6 = 6 } trim_algo_t;
 
@@ -115,7 +115,34 @@ typedef struct {
                            0 = TRIM_DEFAULT_BUDGET (a run that legitimately needs more
                            than that is longer than any workload here by over 10x). */
     int32_t flags;      /* TRIM_FLAG_* bits (0 = defaults) */
+    int32_t rounds;     /* AC-6 on trim_csr and trim_implicit: register supports late
+                           (see below).  0 or 1 = the plain algorithm;
+                           2 .. TRIM_MAX_ROUNDS = R rounds; other calls and algorithms
+                           take 0 or 1 only (TRIM_E_INVAL otherwise). */
 } trim_opts_t;
+
+/*
+ * Late support registration (opts.rounds = R >= 2, AC-6 only).  On a shallow
+ * graph (small alpha) most vertices keep the first successor they find, and
+ * the supporting sets (Section 6.1) they join are never handed back: their
+ * registration is the largest cost of the first sweep.  With R >= 2 the first
+ * R - 1 repetitions are instead rounds of the AC-3-based algorithm with the
+ * edge_index cursor (Sections 4.1 and 8), statuses read as they were at the
+ * start of each round, and vertices without successors removed before round
+ * 1 (as in the plain first sweep), so a vertex of peeling level l >= 2 goes
+ * in round l - 1.  If a round removes nothing, that is the fixed point and
+ * the call ends.  Otherwise round R re-checks every cursor the same way and
+ * registers each vertex still live in the supporting set of the successor it
+ * stops at, and the AC-6 propagation finishes from there.  The live set is
+ * the same as without it.  Traversed edges count every cursor re-check:
+ *   edges_total = sum_{dead, deg > 0} (deg + min(R, level - 1) - 1)
+ *               + sum_live (fl + K),   K = min(R, max(alpha, 1)),
+ * and stats.rechecks (the entries of the round lists from round 2 on) is the
+ * excess over the plain AC-6 total, so edges_total - rechecks = T6.
+ * stats.rounds = rounds run = K.  Working memory: 8 more bytes per vertex
+ * (the round list), allocated on the first such call.
+ */
+#define TRIM_MAX_ROUNDS 64
 
 /*
  * AC-6 (trim_csr, trim_csr_preset, trim_implicit, trim_batch,
@@ -150,7 +177,8 @@ typedef struct {
                               reverse edges traversed (AC-4) */
     uint64_t n_live;       /* popcount of the live bitmap */
     uint64_t n_dead;       /* vertices removed */
-    uint64_t rounds;       /* AC-3: sweeps run (alpha + 1); 0 otherwise */
+    uint64_t rounds;       /* AC-3: sweeps run (alpha + 1); AC-6 with opts.rounds >= 2:
+                              rounds run (see above); 0 otherwise */
     uint64_t queued;       /* AC-6/AC-4: work items that went through the shared queue */
     uint64_t edges_sweep;  /* AC-6: successor checks made by the first sweep */
     uint64_t closes;       /* AC-6: removed vertices whose support lists the propagation
@@ -176,7 +204,9 @@ typedef struct {
                               AC-3: live-list entries processed over all rounds */
     uint64_t phases;       /* AC-6: level-synchronous phases of the propagation before its
                               asynchronous tail */
-    uint64_t reserved;
+    uint64_t rechecks;     /* AC-6 with opts.rounds >= 2: cursor re-checks of rounds 2 ..
+                              (counted in edges_total; edges_total - rechecks is the plain
+                              AC-6 total); 0 otherwise */
 } trim_stats_t;   /* 18 words */
 
 /*

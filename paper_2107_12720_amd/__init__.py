@@ -40,9 +40,10 @@ EXPORTS = ("trim_version", "trim_last_error", "trim_ctx_create", "trim_ctx_destr
 MLP_PARAMS = 1377
 STATS_FIELDS = ("edges_total", "n_live", "n_dead", "rounds", "queued", "edges_sweep", "closes",
                 "joins", "visited", "graph_edges", "q_highwater", "edges_live", "stalled",
-                "forest", "jump_rounds", "work_items", "phases")
+                "forest", "jump_rounds", "work_items", "phases", "rechecks")
 STATS_WORDS = 18
-ABI_VERSION = 2
+ABI_VERSION = 3
+MAX_ROUNDS = 64
 DEFAULT_BUDGET = 1 << 22
 
 
@@ -56,7 +57,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("workers", ctypes.c_int32),
                 ("chunk", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("budget", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("budget", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("rounds", ctypes.c_int32)]
 
 
 class CsrDesc(ctypes.Structure):
@@ -160,9 +162,9 @@ FLAG_FOREST = 4
 
 
 def make_opts(block=0, workers=0, chunk=0, validate=False, graph=False, schedule=0,
-              budget=0, flags=0) -> Opts:
+              budget=0, flags=0, rounds=0) -> Opts:
     return Opts(block, workers, chunk, int(bool(validate)), int(bool(graph)), int(schedule),
-                int(budget), int(flags))
+                int(budget), int(flags), int(rounds))
 
 
 def _dev_ptr(t, dtype, name, allow_none=False):

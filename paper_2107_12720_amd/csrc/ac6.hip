@@ -110,33 +110,52 @@ struct ShareEvery<ImplicitView> {
 // covers 64 consecutive ids (blockDim and the grid stride are multiples of
 // 64); the last wavefront may write one word past ceil(n/32), which the
 // buffer has.
+//
+// With late support registration (opts.rounds >= 2, sinks2 != NULL) the heads
+// are left for ac6_heads, and the bitmap is written twice: the round bitmaps
+// start equal (see ac6_round).
 template <class View>
-__global__ void ac6_init(View g, int n, int* head, int* ext, uint32_t* sinks,
+__global__ void ac6_init(View g, int n, int* head, int* ext, uint32_t* sinks, uint32_t* sinks2,
                          const uint32_t* preset, int* ctr, uint64_t* worker_edges, int P,
                          trim_stats_t* stats) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     Stage<View>::apply(g, lds);
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid < kCtrInts) ctr[tid] = 0;
+    if (tid < kCtrInts) ctr[tid] = (tid == kHyRounds && sinks2) ? 1 : 0;
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
         const bool sink =
             g.end(v) == g.begin(v) || (preset && ((preset[v >> 5] >> (v & 31)) & 1u));
         const int h = sink ? kDead : kEmpty;
-        reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
-        if (ext)
-            for (int j = 0; j < kMoreLists - 1; ++j) ext[(kMoreLists - 1) * (long long)v + j] = h;
+        if (head) {
+            reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
+            if (ext)
+                for (int j = 0; j < kMoreLists - 1; ++j)
+                    ext[(kMoreLists - 1) * (long long)v + j] = h;
+        }
         const uint64_t m = ballot(sink);
         if (lane_id() == 0) {
             sinks[v >> 5] = (uint32_t)m;
             sinks[(v >> 5) + 1] = (uint32_t)(m >> 32);
+            if (sinks2) {
+                sinks2[v >> 5] = (uint32_t)m;
+                sinks2[(v >> 5) + 1] = (uint32_t)(m >> 32);
+            }
         }
     }
 }
 
 constexpr int kCasBuf = 4096;   // entries buffered in LDS before one shared-queue append
 constexpr int kSweepUnroll = 4; // vertices per lane in flight in the first sweep
+// Round-list entries (late support registration): (vertex, cursor target)
+// with flag bits on the target: the cursor is at the vertex's last successor;
+// the vertex was removed by a round (the entry is skipped from then on); the
+// cursor is still at the vertex's first successor (else it is in cur[v]).
+constexpr uint32_t kLastBit = 0x80000000u;
+constexpr uint32_t kGoneBit = 0x40000000u;
+constexpr uint32_t kFirstBit = 0x20000000u;
+constexpr uint32_t kTargetMask = 0x1FFFFFFFu;
 
 // With jp (the forest collapse): jp[v] = the target of v's support if that is
 // v's last successor (v is a tree member, listed in jlist), v itself if v has
@@ -152,19 +171,25 @@ constexpr int kSweepUnroll = 4; // vertices per lane in flight in the first swee
 // serial scan past sinks is the exception.  The join's exchange returns the
 // old head, which goes into the joiner's record: with several joins in flight
 // their round trips overlap instead of adding up.
-template <class View>
+//
+// kDefer (late support registration, the first of opts.rounds rounds): no
+// vertex joins a list.  A vertex with a live successor is appended to the
+// round-2 list with its cursor (see ac6_round); one without becomes a removal
+// of round 1, set in the round bitmap `ynext` and counted.
+template <class View, bool kDefer>
 __global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const uint32_t* sinks,
                           const uint32_t* preset, uint64_t* rec, uint32_t* q, int* ctr,
                           uint64_t* worker_edges, int P, uint64_t* part, int sched, int* jp,
-                          uint32_t* jlist) {
+                          uint32_t* jlist, uint32_t* ynext, int* lout, long long hcap,
+                          int* cur) {
     constexpr int U = kSweepUnroll;
     __shared__ uint64_t lds[Stage<View>::kWords];
-    __shared__ uint32_t cas[kCasBuf];
-    __shared__ int s_chunk, s_ncas, s_base;
+    __shared__ uint32_t cas[kDefer ? 1 : kCasBuf];
+    __shared__ int s_chunk, s_ncas, s_base, s_wave[1024 / kWave];
     __shared__ uint64_t red[16];
     Stage<View>::apply(g, lds);
     if (threadIdx.x == 0) s_ncas = 0;
-    uint64_t edges = 0, degsum = 0;
+    uint64_t edges = 0, degsum = 0, removed = 0;
     // move the buffered entries to the shared queue (close items) or to the
     // forest list, with one reservation
     auto flush = [&]() {
@@ -238,6 +263,29 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const u
                     ok[k] = p[k] < e[k];
                 }
             }
+            if constexpr (kDefer) {
+                int c = 0;
+#pragma unroll
+                for (int k = 0; k < U; ++k) c += ok[k];
+                int slot = block_append_base(c, ctr + kHyCnt0, nullptr, s_wave, &s_base);
+#pragma unroll
+                for (int k = 0; k < U; ++k) {
+                    if (ok[k]) {
+                        lout[slot] = v[k];
+                        lout[hcap + slot] = (int)((uint32_t)w[k] |
+                                                  (p[k] + 1 == e[k] ? kLastBit : 0u) |
+                                                  (p[k] == b[k] ? kFirstBit : 0u));
+                        if (p[k] != b[k]) cur[v[k]] = p[k];
+                        ++slot;
+                        edges += (uint64_t)(p[k] - b[k] + 1);
+                    } else if (b[k] < e[k]) {
+                        atomicOr(ynext + (v[k] >> 5), 1u << (v[k] & 31));
+                        removed += 1;
+                        edges += (uint64_t)(e[k] - b[k]);
+                    }
+                }
+                continue;
+            }
             int old[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
@@ -278,13 +326,239 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const u
             if (s_ncas > kCasBuf - U * (int)blockDim.x) flush();
         }
     }
-    flush();
+    if constexpr (!kDefer) flush();
     edges = block_sum(edges, red);
     degsum = block_sum(degsum, red);
+    if constexpr (kDefer) removed = block_sum(removed, red);
     if (threadIdx.x == 0) {
         if (edges) add_dev(worker_edges + (blockIdx.x % P), edges);
         part[kPartSweep * kPartStride + blockIdx.x] = edges;
         part[kPartDeg * kPartStride + blockIdx.x] = degsum;
+        if (kDefer && removed) add_dev(ctr + kHyDead0 + 1, (int)removed);
+    }
+}
+
+// ------------------------------------------ late support registration
+// With opts.rounds = R >= 2 the first R - 1 rounds are AC-3 rounds with the
+// edge_index cursor (Sections 4.1 and 8): no vertex joins a list.  Round 1 is
+// ac6_sweep<kDefer>, which, like the plain first sweep, finds the vertices
+// without successors removed already, so a vertex of peeling level l >= 2 is
+// removed in round l - 1.  Round r >= 2 (ac6_round) takes the list of the vertices
+// still live, each with its cursor target, and re-checks that target against
+// the removals of rounds before r; a removed target makes the vertex scan on.
+// If a round removes nothing the fixed point is reached: every later launch
+// returns at once and the live set is the complement of the round bitmap.
+// Otherwise round R (kJoin) does the same check and registers each surviving
+// vertex in the list of the target it stops at, exactly as the first sweep
+// does (a plain exchange: nothing is closed while it runs); from there the
+// forest collapse and the propagation run unchanged.  Every removal of a
+// round is certain (its successors were all removed before), so the
+// propagation starts from a state that a plain AC-6 run also passes through.
+//
+// Round bitmaps: two, y[0] and y[1].  Round r reads y[r & 1], which holds
+// every removal of the rounds before r, and builds y[(r + 1) & 1], which held
+// the removals before r - 1: it adds y[r & 1] word by word (the removals of
+// round r - 1) and its own removals bit by bit.  A round never reads the
+// bitmap it writes, so a removal of round r is seen from round r + 1 on,
+// whatever the order of the lanes: the rounds, the removals of each and the
+// number of successor checks are those of the sequential rounds.
+//
+// The round list: the vertices the first round left live, one entry each
+// (vertex, cursor target with the flag bits above), two arrays of hcap ints,
+// updated in place: an entry is written only when its cursor moves (the
+// cursor position goes to cur[v]) or its vertex is removed.  A round reads
+// every entry; removals are few after the first rounds, so rewriting the list
+// without them would cost more than skipping them.  The removal counts of the
+// rounds rotate over three control words.
+
+// True (and the stop word set) if round r need not run: a round before it
+// removed nothing.
+__device__ __forceinline__ bool deferred_done(int* ctr, int r) {
+    if (ld_dev(ctr + kHyStop)) return true;
+    if (ld_dev(ctr + kHyDead0 + (r - 1) % 3) == 0) {
+        if (threadIdx.x == 0) st_dev(ctr + kHyStop, 1);
+        return true;
+    }
+    return false;
+}
+
+constexpr int kRoundUnroll = 4;   // list entries per thread in flight
+
+template <class View, bool kJoin>
+__global__ __launch_bounds__(256) void ac6_round(View g, int r, const uint32_t* ycur,
+                                                 uint32_t* ynext, int nwords, int* lst,
+                                                 long long hcap, int* cur, int* head, int* ext,
+                                                 uint64_t* rec, int* jp, uint32_t* jlist,
+                                                 uint32_t* q, int* ctr, uint64_t* worker_edges,
+                                                 int P, int sched) {
+    constexpr int U = kRoundUnroll;
+    __shared__ uint64_t lds[Stage<View>::kWords];
+    __shared__ uint32_t buf[kJoin ? U * 256 : 1];
+    __shared__ int s_base, s_nbuf;
+    __shared__ uint64_t red[16];
+    if (deferred_done(ctr, r)) return;
+    Stage<View>::apply(g, lds);
+    const int cnt = ld_dev(ctr + kHyCnt0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st_dev(ctr + kHyDead0 + (r + 1) % 3, 0);
+        st_dev(ctr + kHyRounds, r);
+    }
+    const int stride = gridDim.x * blockDim.x;
+    if constexpr (!kJoin) {
+        // the removals of round r - 1 into the bitmap this round builds
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) {
+            const uint32_t b = ycur[i];
+            if (b && (b & ~ynext[i])) atomicOr(ynext + i, b);
+        }
+    } else {
+        if (threadIdx.x == 0) s_nbuf = 0;
+        __syncthreads();
+    }
+    int* lv = lst;
+    int* lt = lst + hcap;
+    uint64_t edges = 0, removed = 0, entries = 0;
+    for (int base = blockIdx.x * blockDim.x * U; base < cnt; base += stride * U) {
+        int v[U], p[U];
+        uint32_t t[U];
+        bool keep[U], gone[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = base + k * blockDim.x + threadIdx.x;
+            t[k] = kGoneBit;
+            if (i < cnt) t[k] = (uint32_t)__builtin_nontemporal_load(lt + i);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = base + k * blockDim.x + threadIdx.x;
+            v[k] = -1;
+            if (!(t[k] & kGoneBit)) v[k] = __builtin_nontemporal_load(lv + i);
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            keep[k] = gone[k] = false;
+            if (v[k] < 0) continue;
+            entries += 1;
+            const int w = (int)(t[k] & kTargetMask);
+            p[k] = -1;   // unchanged cursor (read only where needed)
+            if (!((ycur[w >> 5] >> (w & 31)) & 1u)) {   // the cursor edge, checked again
+                edges += 1;
+                keep[k] = true;
+                continue;
+            }
+            // the cursor target was removed before this round: scan on
+            const int p0 = (t[k] & kFirstBit) ? g.begin(v[k]) : cur[v[k]];
+            const int e1 = g.end(v[k]);
+            const int ctx = g.vctx(v[k]);
+            int pp = p0 + 1, x = 0;
+            for (; pp < e1; ++pp) {
+                x = g.target(v[k], pp, ctx);
+                if (!((ycur[x >> 5] >> (x & 31)) & 1u)) break;
+            }
+            const int i = base + k * blockDim.x + threadIdx.x;
+            if (pp < e1) {
+                edges += (uint64_t)(pp - p0 + 1);
+                t[k] = (uint32_t)x | (pp + 1 == e1 ? kLastBit : 0u);
+                p[k] = pp;
+                if constexpr (!kJoin) {
+                    cur[v[k]] = pp;
+                    lt[i] = (int)t[k];
+                }
+                keep[k] = true;
+            } else {
+                edges += (uint64_t)(e1 - p0);
+                gone[k] = true;
+                if constexpr (!kJoin) lt[i] = (int)(t[k] | kGoneBit);
+            }
+        }
+        if constexpr (!kJoin) {
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (gone[k]) {
+                    atomicOr(ynext + (v[k] >> 5), 1u << (v[k] & 31));
+                    removed += 1;
+                }
+            }
+        } else {
+            // register the survivors (the joins' round trips overlap), list the
+            // removed vertices and the tree members for the forest collapse
+            // (or queue the removed ones as close items without it)
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (keep[k] && p[k] < 0)
+                    p[k] = (t[k] & kFirstBit) ? g.begin(v[k]) : cur[v[k]];
+            int old[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                if (keep[k]) {
+                    if (sched & TRIM_SCHED_JITTER)
+                        jitter_nap(((uint64_t)blockIdx.x << 32) ^ (uint32_t)v[k]);
+                    const int w = (int)(t[k] & kTargetMask);
+                    old[k] = xchg_dev(join_slot(head, ext, w, (t[k] & kLastBit) != 0u, v[k]), v[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                bool member = false;
+                if (keep[k]) {
+                    rec[v[k]] = pack_rec(old[k], p[k]);
+                    member = (t[k] & kLastBit) != 0u;
+                    if (jp) jp[v[k]] = member ? (int)(t[k] & kTargetMask) : v[k];
+                } else if (gone[k] && jp) {
+                    jp[v[k]] = ~v[k];
+                }
+                const bool put = gone[k] || (jp && member);
+                const uint64_t mask = ballot(put);
+                if (mask) {
+                    int wbase = 0;
+                    if (lane_id() == 0) wbase = atomicAdd(&s_nbuf, popc(mask));
+                    wbase = __shfl(wbase, 0);
+                    if (put)
+                        buf[wbase + popc(mask & lanes_below())] =
+                            jp ? ((uint32_t)v[k] | (gone[k] ? kRootBit : 0u))
+                               : make_item(0, v[k]);
+                }
+            }
+            // one reservation per step for what the block buffered
+            __syncthreads();
+            const int nb = s_nbuf;
+            if (nb > 0) {
+                if (threadIdx.x == 0) {
+                    if (jp) {
+                        s_base = add_dev(ctr + kJCnt0, nb);
+                    } else {
+                        add_dev(ctr + kPending, nb);
+                        s_base = add_dev(ctr + kQTail, nb);
+                    }
+                }
+                __syncthreads();
+                uint32_t* dst = jp ? jlist : q;
+                for (int j = threadIdx.x; j < nb; j += blockDim.x) dst[s_base + j] = buf[j];
+                __syncthreads();
+                if (threadIdx.x == 0) s_nbuf = 0;
+            }
+            __syncthreads();
+        }
+    }
+    edges = block_sum(edges, red);
+    entries = block_sum(entries, red);
+    if constexpr (!kJoin) removed = block_sum(removed, red);
+    if (threadIdx.x == 0) {
+        if (edges) add_dev(worker_edges + (blockIdx.x % P), edges);
+        if (entries) add_dev(ctr + kHyWork, (int)entries);
+        if (!kJoin && removed) add_dev(ctr + kHyDead0 + r % 3, (int)removed);
+    }
+}
+
+// The list heads before round R registers supports: kDead (closed) for every
+// vertex removed so far -- the sinks, the preset vertices and the removals of
+// the rounds -- and kEmpty for the others.
+__global__ void ac6_heads(int n, int r, const uint32_t* y, int* head, int* ext, int* ctr) {
+    if (deferred_done(ctr, r)) return;
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const int h = ((y[v >> 5] >> (v & 31)) & 1u) ? kDead : kEmpty;
+        reinterpret_cast<int2*>(head)[v] = make_int2(h, h);
+        if (ext)
+            for (int j = 0; j < kMoreLists - 1; ++j) ext[(kMoreLists - 1) * (long long)v + j] = h;
     }
 }
 
@@ -318,6 +592,12 @@ __global__ __launch_bounds__(256) void ac6_propagate(View g, int* head, int* ext
     __shared__ uint32_t local_rings[256 / kWave][kLocalP];
     __shared__ int local_tail[256 / kWave];
     __shared__ uint64_t red[16];
+    if (ld_dev(ctr + kHyStop)) {   // the rounds reached the fixed point: nothing to do
+        if (threadIdx.x == 0)
+            for (int slot : {kPartCloses, kPartJoins, kPartVisited, kPartQhw})
+                part[slot * kPartStride + blockIdx.x] = 0;
+        return;
+    }
     Stage<View>::apply(g, lds);
     WaveQueue wq;
     const int wv = threadIdx.x / kWave;
@@ -463,6 +743,12 @@ __global__ __launch_bounds__(256) void ac6_levels(View g, int* head, int* ext, u
     __shared__ uint32_t stage[256 / kWave][kStage];
     __shared__ int stage_n[256 / kWave];
     __shared__ uint64_t red[16];
+    if (ld_dev(ctr + kHyStop)) {   // the rounds reached the fixed point: nothing to do
+        if (threadIdx.x == 0)
+            for (int slot : {kPartLvCloses, kPartLvJoins, kPartLvVisited})
+                part[slot * kPartStride + blockIdx.x] = 0;
+        return;
+    }
     Stage<View>::apply(g, lds);
     const int wv = threadIdx.x / kWave;
     if (lane_id() == 0) stage_n[wv] = 0;
@@ -615,6 +901,41 @@ struct Ac6Live {
     __device__ __forceinline__ bool operator()(int v) const { return head[2 * v] != kDead; }
 };
 
+// The live bitmap with late support registration: the complement of the
+// round bitmap when the rounds reached the fixed point (no support was
+// registered), else from the list heads as after a plain run.
+__global__ void ac6_pack_deferred(const int* head, const uint32_t* y, int n, uint32_t* bitmap,
+                                  uint64_t* part, const int* ctr, uint32_t* q, long long qwords) {
+    __shared__ uint64_t red[16];
+    clear_queue_if_stalled(ctr, q, qwords);
+    const int nwords = (n + 31) >> 5;
+    uint64_t live_cnt = 0;
+    if (ld_dev(ctr + kHyStop)) {
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords;
+             i += gridDim.x * blockDim.x) {
+            uint32_t wd = ~y[i];
+            if (i == nwords - 1 && (n & 31)) wd &= (1u << (n & 31)) - 1u;
+            bitmap[i] = wd;
+            live_cnt += (uint64_t)__popc(wd);
+        }
+    } else {
+        const int waves = (gridDim.x * blockDim.x) / kWave;
+        const int wid = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+        for (int base = wid * kWave; base < n; base += waves * kWave) {
+            const int v = base + lane_id();
+            const uint64_t b = ballot(v < n && head[2 * v] != kDead);
+            if (lane_id() == 0) {
+                const int w = base >> 5;
+                bitmap[w] = (uint32_t)b;
+                if (w + 1 < nwords) bitmap[w + 1] = (uint32_t)(b >> 32);
+                live_cnt += (uint64_t)popc(b);
+            }
+        }
+    }
+    live_cnt = block_sum(live_cnt, red);
+    if (threadIdx.x == 0) part[kPartLive * kPartStride + blockIdx.x] = live_cnt;
+}
+
 // Per-graph bitmaps: word wi of the packed output belongs to graph g with
 // bitmap_base[g] <= wi < bitmap_base[g+1] and covers local vertices
 // 32 * (wi - bitmap_base[g]) .. + 31 (bits past the graph's n are zero).
@@ -683,6 +1004,19 @@ inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
     return (int)b;
 }
 
+// Words from the first round bitmap to the second (both in w.c, which holds
+// n + n / 8 + 64 ints): room for ceil(n / 32) words plus the one past the end
+// that ac6_init may write, aligned to a cache line.
+inline long long round_bitmap_offset(long long n) { return ((n + 31) / 32 + 2 + 31) / 32 * 32; }
+// Workgroups of a round launch: about one per 1,024 list entries (a list
+// holds at most n), at most four per CU.
+inline int round_blocks(long long n, int cus) {
+    long long b = (n + 256 * kRoundUnroll - 1) / (256 * kRoundUnroll);
+    if (b < 1) b = 1;
+    if (b > 4LL * cus) b = 4LL * cus;
+    return (int)b;
+}
+
 template <class View>
 hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* bitmap,
                    uint64_t* worker_edges, trim_stats_t* stats, const int64_t* vbase = nullptr,
@@ -694,21 +1028,56 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     // split S_more lists for graphs up to kSplitMaxN vertices (their extra
     // heads exist only then)
     int* ext = (w.ext && n <= kSplitMaxN) ? w.ext : nullptr;
+    // late support registration: R rounds, two round bitmaps in w.c (y[1] is
+    // the sinks bitmap the first round reads), the round list in w.hl
+    const int R = (!bitmap_base && w.hl && w.hcap >= n) ? lc.rounds : 0;
+    const bool defer = R >= 2;
+    uint32_t* y[2];
+    y[1] = reinterpret_cast<uint32_t*>(w.c);
+    y[0] = y[1] + round_bitmap_offset(n);
+    const int nwords = (n + 31) / 32;
     {
         Timed t(lc, "ac6_init");
         hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           lc.stream, g, n, w.a, ext, reinterpret_cast<uint32_t*>(w.c), preset,
-                           w.ctr, worker_edges, P, stats);
+                           lc.stream, g, n, defer ? nullptr : w.a, ext, y[1],
+                           defer ? y[0] : nullptr, preset, w.ctr, worker_edges, P, stats);
     }
     if (n > 0) {
         const int chunk = sweep_chunk(lc, n, B);
         sweep_blocks = grid_for(n, chunk, lc.cus * 8);
-        {
+        if (!defer) {
             Timed t(lc, "ac6_sweep");
-            hipLaunchKernelGGL(ac6_sweep<View>, dim3(sweep_blocks), dim3(B), 0, lc.stream, g, n,
-                               chunk, w.a, ext, reinterpret_cast<const uint32_t*>(w.c), preset, w.b,
-                               w.q, w.ctr, worker_edges, P, w.part, lc.schedule,
-                               lc.forest ? w.jp : nullptr, lc.forest ? w.e : nullptr);
+            hipLaunchKernelGGL((ac6_sweep<View, false>), dim3(sweep_blocks), dim3(B), 0, lc.stream,
+                               g, n, chunk, w.a, ext, y[1], preset, w.b, w.q, w.ctr, worker_edges,
+                               P, w.part, lc.schedule, lc.forest ? w.jp : nullptr,
+                               lc.forest ? w.e : nullptr, nullptr, nullptr, 0LL, nullptr);
+        } else {
+            // the round list in w.hl, the moved cursors in w.d
+            {
+                Timed t(lc, "ac6_sweep");
+                hipLaunchKernelGGL((ac6_sweep<View, true>), dim3(sweep_blocks), dim3(B), 0,
+                                   lc.stream, g, n, chunk, nullptr, nullptr, y[1], preset, w.b,
+                                   w.q, w.ctr, worker_edges, P, w.part, lc.schedule, nullptr,
+                                   nullptr, y[0], w.hl, w.hcap, w.d);
+            }
+            const int rb = round_blocks(n, lc.cus);
+            if (R > 2) {
+                Timed t(lc, "ac6_rounds");
+                for (int r = 2; r < R; ++r)
+                    hipLaunchKernelGGL((ac6_round<View, false>), dim3(rb), dim3(256), 0,
+                                       lc.stream, g, r, y[r & 1], y[(r + 1) & 1], nwords, w.hl,
+                                       w.hcap, w.d, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, w.ctr, worker_edges, P, lc.schedule);
+            }
+            {
+                Timed t(lc, "ac6_register");
+                hipLaunchKernelGGL(ac6_heads, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
+                                   lc.stream, n, R, y[R & 1], w.a, ext, w.ctr);
+                hipLaunchKernelGGL((ac6_round<View, true>), dim3(rb), dim3(256), 0, lc.stream, g,
+                                   R, y[R & 1], nullptr, nwords, w.hl, w.hcap, w.d, w.a, ext, w.b,
+                                   lc.forest ? w.jp : nullptr, lc.forest ? w.e : nullptr, w.q,
+                                   w.ctr, worker_edges, P, lc.schedule);
+            }
         }
         if (lc.forest) {
             Timed t(lc, "ac6_jump");
@@ -731,8 +1100,13 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
         if (!bitmap_base) {
             Timed t(lc, "ac6_pack");
             pack_blocks = grid_for(n, 256, lc.cus * 4);
-            hipLaunchKernelGGL(pack_bitmap<Ac6Live>, dim3(pack_blocks), dim3(256), 0, lc.stream,
-                               Ac6Live{w.a}, n, bitmap, w.part, w.ctr, w.q, w.qwords);
+            if (defer)
+                hipLaunchKernelGGL(ac6_pack_deferred, dim3(pack_blocks), dim3(256), 0, lc.stream,
+                                   w.a, y[0], n, bitmap, w.part, w.ctr, w.q, w.qwords);
+            else
+                hipLaunchKernelGGL(pack_bitmap<Ac6Live>, dim3(pack_blocks), dim3(256), 0,
+                                   lc.stream, Ac6Live{w.a}, n, bitmap, w.part, w.ctr, w.q,
+                                   w.qwords);
         }
     }
     if (bitmap_base && n > 0) {

@@ -58,6 +58,7 @@ __global__ __launch_bounds__(256) void ac6_jump(Kill kill, int* jp, uint32_t* l0
     __shared__ uint32_t buf[kJumpBuf];   // hand-back items of removed vertices
     __shared__ int s_nbuf, s_base, s_wave[256 / kWave];
     __shared__ uint64_t red[16];
+    if (ld_dev(ctr + kHyStop)) return;   // AC-6 rounds reached the fixed point
     if (threadIdx.x == 0) s_nbuf = 0;
     __syncthreads();
     auto flush = [&]() {

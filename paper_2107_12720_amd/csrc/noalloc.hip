@@ -126,6 +126,8 @@ extern "C" int trim_csr_noalloc(const trim_csr_t* g, const trim_opts_t* o,
     if (g->n > 0 && !live_bitmap) return report_error(TRIM_E_INVAL, "live_bitmap is NULL");
     if (!worker_edges) return report_error(TRIM_E_INVAL, "worker_edges is NULL");
     int rc = check_options(o);
+    if (!rc && o && o->rounds > 1)
+        rc = report_error(TRIM_E_INVAL, "trim_csr_noalloc: opts.rounds must be 0 or 1");
     if (rc) return rc;
     if (o && o->graph) return report_error(TRIM_E_INVAL, "trim_csr_noalloc: opts.graph is 0");
     if (o && o->workers > TRIM_NOALLOC_WORKERS)

@@ -11,7 +11,7 @@
 #include "scc_internal.h"
 
 static_assert(sizeof(trim_stats_t) == 18 * sizeof(uint64_t), "trim_stats_t layout");
-static_assert(sizeof(trim_opts_t) == 8 * sizeof(int32_t), "trim_opts_t layout");
+static_assert(sizeof(trim_opts_t) == 9 * sizeof(int32_t), "trim_opts_t layout");
 
 struct trim_ctx {
     int device = 0;
@@ -98,6 +98,9 @@ void free_work(trim_ctx* c) {
     dfree(c, c->w.q);
     dfree(c, c->w.e);
     dfree(c, c->w.ext);
+    dfree(c, c->w.hl);
+    c->w.hl = nullptr;
+    c->w.hcap = 0;
     c->w.q = nullptr;
     c->w.e = nullptr;
     c->w.ext = nullptr;
@@ -137,6 +140,25 @@ int ensure(trim_ctx* c, int64_t n) {
     c->w.cap = (long long)cap;
     c->w.jp = reinterpret_cast<int*>(c->w.e + 2 * cap);   // after the two lists
     c->w.qwords = (long long)qslots;
+    return TRIM_OK;
+}
+
+// The round list of late support registration (2 ints per vertex), allocated
+// on first use.
+int ensure_rounds(trim_ctx* c, int64_t n) {
+    const long long need = n > 0 ? n : 1;
+    if (need <= c->w.hcap) return TRIM_OK;
+    dfree(c, c->w.hl);
+    c->w.hl = nullptr;
+    c->w.hcap = 0;
+    const long long cap = need + need / 8 + 64;
+    if (dmalloc(c, &c->w.hl, (size_t)cap * 2 * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->w.hl = nullptr;
+        return fail(TRIM_E_NOMEM, "cannot allocate the round lists for %lld vertices",
+                    (long long)n);
+    }
+    c->w.hcap = cap;
     return TRIM_OK;
 }
 
@@ -276,6 +298,17 @@ int check_opts(const trim_opts_t* o) {
     if (o->budget < 0) return fail(TRIM_E_INVAL, "opts.budget must be >= 0");
     if (o->flags & ~(TRIM_FLAG_STEPWISE | TRIM_FLAG_BATCH_UNION | TRIM_FLAG_FOREST))
         return fail(TRIM_E_INVAL, "opts.flags has unknown bits");
+    if (o->rounds < 0 || o->rounds > TRIM_MAX_ROUNDS)
+        return fail(TRIM_E_INVAL, "opts.rounds must be in [0, %d]", TRIM_MAX_ROUNDS);
+    return TRIM_OK;
+}
+
+// opts.rounds >= 2 (late support registration) is for one-sided AC-6 on one
+// graph only.
+int check_rounds(const trim_opts_t* o, int algo, bool allowed, const char* call) {
+    if (o && o->rounds > 1 && (!allowed || algo != TRIM_AC6))
+        return fail(TRIM_E_INVAL, "%s: opts.rounds = %d needs AC-6 on trim_csr or trim_implicit "
+                    "(0 or 1 here)", call, o->rounds);
     return TRIM_OK;
 }
 
@@ -287,6 +320,7 @@ trim::LaunchCfg launch_cfg(trim_ctx* c, int algo, const trim_opts_t* o, void* st
     lc.workers = workers_for(c, algo, o);
     lc.budget = (o && o->budget > 0) ? o->budget : TRIM_DEFAULT_BUDGET;
     lc.forest = !(o && (o->flags & TRIM_FLAG_STEPWISE));
+    lc.rounds = o ? o->rounds : 0;
     lc.cus = c->cus;
     lc.stream = (hipStream_t)stream;
     if (c->timer.keep > 0) lc.timer = c->timer.next();
@@ -462,10 +496,12 @@ int trim_csr(trim_ctx* c, int algo, const trim_csr_t* g, const trim_opts_t* o,
     if (algo == TRIM_AC4 && (!g->rrow_off || (g->m > 0 && !g->rcol)))
         return fail(TRIM_E_INVAL, "AC-4 needs the transposed graph (rrow_off, rcol)");
     int rc = check_opts(o);
+    if (!rc) rc = check_rounds(o, algo, true, "trim_csr");
     if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, g->n))) return rc;
+    if (algo == TRIM_AC6 && o && o->rounds > 1 && (rc = ensure_rounds(c, g->n))) return rc;
     trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
     if (o && o->validate && (rc = validate_graph(c, *g, lc.stream))) return rc;
     switch (algo) {
@@ -495,6 +531,7 @@ int trim_csr_preset(trim_ctx* c, int algo, const trim_csr_t* g, const uint32_t* 
     if (algo == TRIM_AC4 && (!g->rrow_off || (g->m > 0 && !g->rcol)))
         return fail(TRIM_E_INVAL, "AC-4 needs the transposed graph (rrow_off, rcol)");
     int rc = check_opts(o);
+    if (!rc) rc = check_rounds(o, algo, false, "trim_csr_preset");
     if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -526,6 +563,7 @@ int trim_scc(trim_ctx* c, const trim_csr_t* g, const trim_opts_t* o, int32_t* la
     if (g->m > 0 && (!g->col || !g->rcol)) return fail(TRIM_E_INVAL, "col or rcol is NULL");
     if (g->n > 0 && !label) return fail(TRIM_E_INVAL, "label is NULL");
     int rc = check_opts(o);
+    if (!rc) rc = check_rounds(o, TRIM_AC6, false, "trim_scc");
     if (rc || (rc = check_workers(c, TRIM_AC6, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -591,6 +629,7 @@ int trim_csr_two_sided(trim_ctx* c, int algo, const trim_csr_t* g, const trim_op
     if (g->n > 0 && !live_bitmap) return fail(TRIM_E_INVAL, "live_bitmap is NULL");
     if (!worker_edges) return fail(TRIM_E_INVAL, "worker_edges is NULL");
     int rc = check_opts(o);
+    if (!rc) rc = check_rounds(o, algo, false, "trim_csr_two_sided");
     if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -619,10 +658,14 @@ int trim_implicit(trim_ctx* c, int algo, const trim_implicit_t* g, const trim_op
     if (!g->deg_table) return fail(TRIM_E_INVAL, "deg_table is NULL");
     if (!live_bitmap || !worker_edges) return fail(TRIM_E_INVAL, "NULL output");
     int rc = check_opts(o);
+    if (!rc) rc = check_rounds(o, algo, true, "trim_implicit");
     if (rc || (rc = check_workers(c, algo, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     if ((rc = ensure(c, (int64_t)1 << g->log2n))) return rc;
+    if (algo == TRIM_AC6 && o && o->rounds > 1 &&
+        (rc = ensure_rounds(c, (int64_t)1 << g->log2n)))
+        return rc;
     trim::LaunchCfg lc = launch_cfg(c, algo, o, stream);
     // implicit graphs: the forest collapse only on request (see the header)
     lc.forest = o && (o->flags & TRIM_FLAG_FOREST) && !(o->flags & TRIM_FLAG_STEPWISE);
@@ -644,6 +687,7 @@ int trim_batch(trim_ctx* c, int32_t G, const int64_t* vbase, const int32_t* row_
         return fail(TRIM_E_INVAL, "batch sizes out of range");
     if (total_m > 0 && !col) return fail(TRIM_E_INVAL, "col is NULL");
     int rc = check_opts(o);
+    if (!rc) rc = check_rounds(o, TRIM_AC6, false, "trim_batch");
     if (rc || (rc = check_workers(c, TRIM_AC6, o))) return rc;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");

@@ -30,6 +30,14 @@ enum Ctr : int {
     kAcWork = 216,   // AC-3: live-list entries processed over all rounds
     kCnt0 = 224,     // AC-3 live-list sizes, rotating over 3 slots
     kStall = 240,    // watchdog: nonzero once a persistent kernel gave up (opts.budget)
+    // AC-6 with late support registration (opts.rounds): the round list's
+    // size, removals per round (rotating over 3 slots), the stop word (set
+    // once a round removed nothing), the rounds run and the cursor re-checks
+    kHyCnt0 = 4,
+    kHyDead0 = 36,
+    kHyStop = 100,
+    kHyRounds = 101,
+    kHyWork = 102,
     kCtrInts = 256
 };
 
@@ -54,6 +62,9 @@ struct Work {
     uint64_t* wedges = nullptr;  // per-worker counts when the caller has none (batches)
     uint64_t* part = nullptr;    // per-block partial sums (kPartSlots x kPartStride)
     long long cap = 0;           // vertices the per-vertex buffers hold
+    int* hl = nullptr;           // AC-6 with late support registration: the round list,
+                                 //   2 * hcap ints (vertex, cursor target and flags)
+    long long hcap = 0;
 };
 // Extra working memory of two-sided AC-6 (allocated on its first use).
 struct Work2 {
@@ -128,6 +139,7 @@ struct LaunchCfg {
     int workers = 0;          // persistent workgroups
     int budget = TRIM_DEFAULT_BUDGET;   // watchdog step budget (opts.budget)
     bool forest = true;       // AC-6: collapse the last-successor forest after the sweep
+    int rounds = 0;           // AC-6: rounds before supports are registered (opts.rounds)
     int cus = 256;
     hipStream_t stream = nullptr;
     Timer::Slot* timer = nullptr;   // non-null: record per-kernel events here

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_symbol():
     L = T.lib()
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert L.trim_version() == T.ABI_VERSION == 2
+    assert L.trim_version() == T.ABI_VERSION == 3
 
 
 def test_null_arguments_rejected():
@@ -63,15 +63,15 @@ def test_no_gpu_context_fails_cleanly():
 
 def test_opts_layout_matches_header():
     import paper_2107_12720_amd as T
-    assert ctypes.sizeof(T.Opts) == 32
+    assert ctypes.sizeof(T.Opts) == 36
     assert [f for f, _ in T.Opts._fields_] == ["block", "workers", "chunk", "validate", "graph",
-                                               "schedule", "budget", "flags"]
+                                               "schedule", "budget", "flags", "rounds"]
     # trim_stats_t: the header's uint64 words, the named fields first, in order
     text = open(os.path.join(ROOT, "include", "trim.h")).read()
     body = re.search(r"typedef struct \{([^}]*)\} trim_stats_t;", text).group(1)
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     fields = re.findall(r"uint64_t\s+(\w+)(?:\[(\d+)\])?;", body)
     assert sum(int(k or 1) for _, k in fields) == T.STATS_WORDS == 18
-    assert tuple(f for f, _ in fields if f != "reserved") == T.STATS_FIELDS
+    assert tuple(f for f, _ in fields) == T.STATS_FIELDS
     assert ctypes.sizeof(T.CsrDesc) == 48
     assert ctypes.sizeof(T.ImplicitDesc) == 32

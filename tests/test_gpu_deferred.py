@@ -1,0 +1,178 @@
+"""GPU parity of AC-6 with late support registration (opts.rounds = R >= 2).
+
+The first R - 1 repetitions are AC-3 rounds with the edge_index cursor
+(Sections 4.1 and 8), round R registers the supports of the vertices still
+live (Section 6.1), and the AC-6 propagation finishes.  Against the oracle:
+the live bitmap bit for bit; the traversed-edge total, the rounds run and the
+cursor re-checks equal to or_counts_deferred's closed form (itself pinned
+against the literal run in tests/test_oracle_deferred.py); and total minus
+re-checks equal to the plain AC-6 total T6.  Both with the forest collapse
+(the default on explicit graphs) and stepwise.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_common import expected, run_csr, say, sweep_counts
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2107_12720_amd as T
+    c = T.Context(0)
+    yield c
+    c.close()
+
+
+def check(ctx, g, R, name, flags=0, workers=0, schedule=0, chunk=0):
+    import paper_2107_12720_amd as T
+    r, c, bm = expected(g)
+    say(f"  [{name}] R={R} flags={flags} n={g.n} m={g.m}")
+    opts = T.make_opts(rounds=R, flags=flags, workers=workers, schedule=schedule, chunk=chunk)
+    got, edges, st = run_csr(ctx, g, 6, opts=opts)
+    assert np.array_equal(got, bm), f"bitmap differs on {name} R={R}"
+    total, rounds, re = oracle.counts_deferred(g, r, R)
+    assert edges == st["edges_total"] == total, (name, R, edges, total, st)
+    assert st["rounds"] == rounds and st["rechecks"] == re, (name, R, rounds, re, st)
+    assert edges - st["rechecks"] == c.T6
+    assert st["n_live"] == r.n_live and st["n_dead"] == g.n - r.n_live, st
+    assert st["edges_sweep"] == sweep_counts(g)[0], st
+    assert st["stalled"] == 0
+    return r, st
+
+
+HAND = [[1], [2], [], [3], [0, 3]]
+
+
+@pytest.mark.parametrize("R", [2, 3, 4, 5, 64])
+def test_hand_example(ctx, R):
+    # worked by hand in tests/test_oracle_deferred.py
+    _, st = check(ctx, gg.from_adjacency(HAND), R, "hand")
+    want = {2: (8, 2, 3), 3: (10, 3, 5), 4: (10, 3, 5), 5: (10, 3, 5), 64: (10, 3, 5)}[R]
+    assert (st["edges_total"], st["rounds"], st["rechecks"]) == want
+
+
+@pytest.mark.parametrize("adj,name", [
+    ([], "empty"),
+    ([[], [], []], "edgeless"),
+    ([[0]], "self-loop"),
+    ([[1], [0]], "2-cycle"),
+    ([[1], [2], [2], [0], []], "loop+tail"),
+    ([[1, 1, 1], []], "duplicates"),
+    ([[1], [0], [0], [4], []], "cycle-in-out"),
+    ([[1], [2], [3], [4], []], "path"),
+])
+@pytest.mark.parametrize("R", [2, 3, 8])
+def test_special_cases(ctx, adj, name, R):
+    import paper_2107_12720_amd as T
+    g = gg.from_adjacency(adj)
+    check(ctx, g, R, name)
+    check(ctx, g, R, name, flags=T.FLAG_STEPWISE)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_graphs(ctx, seed):
+    import paper_2107_12720_amd as T
+    rng = np.random.default_rng(2000 + seed)
+    for n, dens in ((97, 0.8), (1000, 1.2), (5000, 1.0), (20000, 2.5), (70001, 1.05)):
+        g = gg.uniform(n, int(dens * n), seed=seed * 17 + n, drop_self=bool(rng.integers(2)))
+        for R in (2, 3, 5, 64):
+            check(ctx, g, R, f"uniform n={n} seed={seed}")
+        check(ctx, g, 3, f"uniform n={n} seed={seed}", flags=T.FLAG_STEPWISE)
+
+
+def test_chain_deeper_than_the_rounds(ctx):
+    """A 30,000-vertex chain under an R-MAT core: the rounds stop at R and the
+    propagation (forest collapse, phases, asynchronous tail) removes the rest."""
+    import paper_2107_12720_amd as T
+    g = gg.rmat(16, 8, seed=3, chain=30000)
+    for R in (2, 4, 16):
+        r, st = check(ctx, g, R, "rmat16+chain")
+        assert st["rounds"] == R and r.alpha >= 30000
+    check(ctx, g, 4, "rmat16+chain", flags=T.FLAG_STEPWISE)
+
+
+def test_config0(ctx):
+    g = gg.config0()
+    r, _ = check(ctx, g, 4, "core+tail n=65536")
+    assert r.alpha > 4
+    _, st = check(ctx, g, 64, "core+tail n=65536")
+    assert st["rounds"] == r.alpha <= 64   # reached by the rounds alone
+
+
+def test_shallow_rmat_reaches_the_fixed_point_in_rounds(ctx):
+    g = gg.rmat(20, 16, seed=1)
+    r, st = check(ctx, g, 8, "rmat20")
+    assert r.alpha <= 8 and st["rounds"] == max(r.alpha, 1)
+    assert st["joins"] == 0 and st["closes"] == 0 and st["forest"] == 0
+
+
+def test_schedule_perturbation(ctx):
+    import paper_2107_12720_amd as T
+    g = gg.rmat(17, 8, seed=5, chain=2000)
+    for k, sched in enumerate((T.SCHED_REVERSE, T.SCHED_JITTER,
+                               T.SCHED_REVERSE | T.SCHED_JITTER)):
+        check(ctx, g, 3, f"rmat17+chain sched={sched}", schedule=sched,
+              workers=(0, 37, 1)[k], chunk=(0, 64, 4096)[k])
+
+
+def test_implicit(ctx):
+    """The hash-generated graph at 2^20 vertices (alpha in the tens): stepwise
+    (the implicit default) and with the forest collapse, R below and above
+    alpha + 1."""
+    import torch
+    import paper_2107_12720_amd as T
+    imp = gg.implicit(log2n=20, seed=4)
+    ro, col = oracle.implicit_csr(imp)
+    g = gg.CSR(imp.n, ro, col)
+    r, c, bm = expected(g)
+    table = T.to_device(imp.table)
+    for R, flags in ((4, 0), (4, T.FLAG_FOREST), (64, 0)):
+        say(f"  implicit 2^20 R={R} flags={flags}")
+        res = ctx.trim_implicit(6, 20, imp.seed, imp.zero_thr, table,
+                                opts=T.make_opts(rounds=R, flags=flags))
+        torch.cuda.synchronize()
+        st = res.stats_dict()
+        assert np.array_equal(res.bitmap_numpy()[: bm.shape[0]], bm)
+        total, rounds, re = oracle.counts_deferred(g, r, R)
+        assert st["edges_total"] == total and st["rounds"] == rounds and st["rechecks"] == re
+        assert total - re == c.T6 and st["graph_edges"] == g.m
+
+
+def test_plain_calls_unchanged_between_deferred_ones(ctx):
+    """A context alternating plain and deferred calls gives each its own exact
+    result (the round state of one call never leaks into the next)."""
+    g = gg.rmat(15, 8, seed=7, chain=500)
+    r, c, bm = expected(g)
+    for R in (0, 5, 1, 2, 0, 64, 0):
+        import paper_2107_12720_amd as T
+        got, edges, st = run_csr(ctx, g, 6, opts=T.make_opts(rounds=R))
+        assert np.array_equal(got, bm)
+        if R <= 1:
+            assert edges == c.T6 and st["rechecks"] == 0 and st["rounds"] == 0
+        else:
+            assert edges == oracle.counts_deferred(g, r, R)[0]
+
+
+def test_errors(ctx):
+    import torch
+    import paper_2107_12720_amd as T
+    g = gg.from_adjacency([[1], [0]])
+    ro, col, rro, rc = __import__("gpu_common").upload(g, with_reverse=True)
+    for algo in (3, 4):
+        with pytest.raises(T.TrimError):
+            ctx.trim_csr(algo, g.n, ro, col, rro, rc, opts=T.make_opts(rounds=2))
+    with pytest.raises(T.TrimError):
+        ctx.trim_csr(6, g.n, ro, col, opts=T.make_opts(rounds=T.MAX_ROUNDS + 1))
+    with pytest.raises(T.TrimError):
+        ctx.trim_csr_two_sided(6, g.n, ro, col, rro, rc, opts=T.make_opts(rounds=2))
+    pre = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(T.TrimError):
+        ctx.trim_csr_preset(6, g.n, ro, col, pre, opts=T.make_opts(rounds=2))
+    # the context still serves a valid call: the 2-cycle loses nothing in
+    # round 1, so that is the only round
+    got, edges, st = run_csr(ctx, g, 6, opts=T.make_opts(rounds=2))
+    assert got[0] == 3 and (edges, st["rounds"], st["rechecks"]) == (2, 1, 0)
