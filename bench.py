@@ -744,9 +744,27 @@ def bench_cfg0(ctx, T, gg, steps=50):
         ctx, T, n, lambda o: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=lb,
                                           worker_edges=we[:ctx.num_workers(T.AC6)], stats=st_t,
                                           opts=o), steps, (4, 16, 32, 64))
+    # the same graph as a batch of one: one workgroup trims it start to finish
+    # (statuses in an LDS bitmap, workgroup barriers between phases instead of
+    # device-wide ones)
+    vb = T.to_device(np.array([0, n], np.int64))
+    bbase = T.to_device(np.array([0, (n + 31) // 32], np.int64))
+    ge = torch.empty(1, dtype=torch.int64, device="cuda")
+    per = []
+    ms_o, kt_o, res_o = time_gpu(ctx, lambda: ctx.trim_batch(
+        vb, ro, col, bbase, n, m, live_bitmaps=lb, graph_edges=ge, stats=st_t,
+        opts=T.make_opts(block=1024)), steps, 3, per)
+    check["owned"] = {"bitmap": res_o.bitmap_numpy()[: (n + 31) // 32].copy(),
+                      "edges": int(res_o.worker_edges[0].item())}
+    out["ac6_one_workgroup"] = {"us": ms_o * 1e3, "median_us": float(np.median(per)) * 1e3,
+                                "edges_total": check["owned"]["edges"],
+                                "kernels_us": {k: float(np.mean(v)) * 1e3 for k, v in kt_o.items()},
+                                "call": "trim_batch with one graph, block 1024",
+                                "parity": None}
     log(f"cfg0: AC-6 {out['ac6']['us']:.1f} us, AC-4 {out['ac4']['us']:.1f} us, "
         f"AC-3 {out['ac3']['us']:.1f} us, deferred AC-6 "
-        f"{out['deferred']['fastest_ms'] * 1e3:.1f} us (R = {out['deferred']['fastest_rounds']})")
+        f"{out['deferred']['fastest_ms'] * 1e3:.1f} us (R = {out['deferred']['fastest_rounds']}), "
+        f"one-workgroup AC-6 {out['ac6_one_workgroup']['us']:.1f} us")
     return check, out
 
 
@@ -1077,6 +1095,9 @@ def oracle_leg(g, checks, cpu_seconds, out):
                    "n_live": r0.n_live})
         if "deferred" in cc:
             deferred_parity(oracle, cc["graph"], r0, bm0, c0, cc["deferred"], co["deferred"])
+        if "owned" in cc:
+            co["ac6_one_workgroup"]["parity"] = bool(
+                np.array_equal(cc["owned"]["bitmap"], bm0) and cc["owned"]["edges"] == c0.T6)
     if "explicit26" in checks:
         ec, eo = checks["explicit26"], out["explicit26"]
         g26 = ec["graph"]

@@ -97,7 +97,7 @@ def check_all(ctx, g, algos=(6, 4, 3), opts=None, name="", stepwise=True):
     if stepwise and 6 in algos:
         o = opts or T.make_opts()
         o2 = T.make_opts(block=o.block, workers=o.workers, chunk=o.chunk, schedule=o.schedule,
-                         budget=o.budget, flags=o.flags | T.FLAG_STEPWISE)
+                         budget=o.budget, flags=o.flags | T.FLAG_STEPWISE, rounds=o.rounds)
         _check_all(ctx, g, (6,), o2, name + " stepwise")
     return r, c
 

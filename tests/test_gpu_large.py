@@ -24,7 +24,22 @@ def test_config2_explicit_full(ctx):
     say("  generating R-MAT scale 26 ...")
     g = gg.config2_explicit()
     say(f"  rmat26 n={g.n} m={g.m}; oracle and AC-6 ...")
-    check_all(ctx, g, algos=(6,), name="rmat26")
+    r, c = check_all(ctx, g, algos=(6,), name="rmat26")
+    # late support registration, in the configuration the benchmark times
+    # fastest (R = 8: the rounds reach the fixed point) and with a register
+    # round (R = 2)
+    import numpy as np
+    import oracle
+    import paper_2107_12720_amd as T
+    from gpu_common import run_csr
+    bm = oracle.bitmap(r.live)
+    for R in (2, 8):
+        say(f"  rmat26 deferred R={R} ...")
+        got, edges, st = run_csr(ctx, g, 6, opts=T.make_opts(rounds=R))
+        assert np.array_equal(got, bm), R
+        total, rounds, re = oracle.counts_deferred(g, r, R)
+        assert (edges, st["rounds"], st["rechecks"]) == (total, rounds, re), (R, st)
+        assert total - re == c.T6
 
 
 @pytest.mark.timeout(1200)
@@ -44,10 +59,11 @@ def test_implicit_2_28_full(ctx):
     got = {}
     # the default (stepwise AC-6, as the benchmark runs it), the forest
     # collapse on request, and AC-3
-    for key, a, flags in (("6", 6, 0), ("6f", 6, T.FLAG_FOREST), ("3", 3, 0)):
-        say(f"  implicit 2^28: AC-{a} flags={flags} ...")
+    for key, a, flags, R in (("6", 6, 0, 0), ("6f", 6, T.FLAG_FOREST, 0), ("3", 3, 0, 0),
+                             ("6d", 6, 0, 8)):
+        say(f"  implicit 2^28: AC-{a} flags={flags} rounds={R} ...")
         res = ctx.trim_implicit(a, 28, imp.seed, imp.zero_thr, table,
-                                opts=T.make_opts(flags=flags))
+                                opts=T.make_opts(flags=flags, rounds=R))
         assert ctx.status() == 0
         torch.cuda.synchronize()
         got[key] = (res.bitmap_numpy().copy(), res.stats_dict(),
@@ -62,6 +78,11 @@ def test_implicit_2_28_full(ctx):
     c = oracle.counts(g, r)
     bm = oracle.bitmap(r.live)
     say(f"  oracle: T6={c.T6} T3J={c.T3J}")
+    bits, st, edges = got["6d"]
+    total, rounds, re = oracle.counts_deferred(g, r, 8)
+    assert np.array_equal(bits[: bm.shape[0]], bm), "deferred AC-6 bitmap differs at 2^28"
+    assert (edges, st["rounds"], st["rechecks"]) == (total, rounds, re), st
+    assert total - re == c.T6
     for key, a, want in (("6", 6, c.T6), ("6f", 6, c.T6), ("3", 3, c.T3J)):
         bits, st, edges = got[key]
         assert np.array_equal(bits[: bm.shape[0]], bm), f"AC-{a} bitmap differs at 2^28"
