@@ -581,7 +581,7 @@ def bench_batch(ctx, T, gg, reps):
             "speedup_vs_union": ms_union / ms_b}
 
 
-def bench_implicit(ctx, T, gg, reps, log2n=28):
+def bench_implicit(ctx, T, gg, reps, log2n=28, deferred=True):
     """AC-6 on the hash-generated graph G = (V, POST) with n = 2^28: successors
     are generated on the fly.  Checked at full size on sampled vertices: a live
     vertex has a live successor, a removed one has none."""
@@ -622,7 +622,7 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
     b3i = 4 * st3["edges_total"] + 12 * st3["work_items"] + n // 8
     dcheck, dout = bench_deferred(ctx, T, n, lambda o: ctx.trim_implicit(
         T.AC6, log2n, imp.seed, imp.zero_thr, table, live_bitmap=lb, worker_edges=we,
-        stats=st, opts=o), reps, (4, 8))
+        stats=st, opts=o), reps, (4, 8) if deferred else ())
     for R, d in dcheck.items():
         # the full oracle runs in the GPU test suite; here: the same live set
         # as plain AC-6 and the same T6 once the re-checks are taken out
@@ -630,8 +630,9 @@ def bench_implicit(ctx, T, gg, reps, log2n=28):
         dout["by_rounds"][str(R)]["parity"] = None
         dout["by_rounds"][str(R)]["same_live_set_and_T6_as_ac6"] = bool(
             np.array_equal(bitsR, bits) and d["edges"] - d["rechecks"] == t6)
-    log(f"implicit: AC-6 {ms6:.2f} ms, AC-3 {ms3:.2f} ms ({st3['rounds']} rounds), "
-        f"deferred AC-6 {dout['fastest_ms']:.2f} ms (R = {dout['fastest_rounds']})")
+    log(f"implicit: AC-6 {ms6:.2f} ms, AC-3 {ms3:.2f} ms ({st3['rounds']} rounds)"
+        + (f", deferred AC-6 {dout['fastest_ms']:.2f} ms (R = {dout['fastest_rounds']})"
+           if dout else ""))
     return {"implicit": imp, "bits": bits}, {
         "workload": "implicit_2^28_zipf2.1_cap256_zero0.2", "n": n, "m": m,
         "ms": ms6, "edges_per_s": m / (ms6 / 1e3), "T6": t6,
@@ -694,6 +695,8 @@ def bench_deferred(ctx, T, n, call, reps, rounds):
                        "T6": t6, "rounds": st["rounds"], "joins": st["joins"],
                        "kernels_ms": {k: float(np.mean(v)) for k, v in kt.items()},
                        "path_B6": roof(8 * t6 + 20 * n + n // 8, ms), "parity": None}
+    if not out:
+        return check, None
     best = min(out, key=lambda k: out[k]["ms"])
     return check, {"by_rounds": out, "fastest_rounds": int(best), "fastest_ms": out[best]["ms"]}
 
@@ -816,6 +819,21 @@ def bench_explicit26(ctx, T, gg, reps):
                                           stats=st_t, opts=o), reps, (2, 4, 8))
     log(f"explicit26: deferred AC-6 {out['deferred']['fastest_ms']:.3f} ms "
         f"(R = {out['deferred']['fastest_rounds']})")
+    # the dominant kernel of the fastest late-registration run: the first
+    # round without joins.  Algorithmic bytes: 4 B of offsets per vertex, 4 B
+    # per check (the target id; its status is a bit of the cache-resident
+    # sinks bitmap), 8 B per round-list entry written, the bitmap of removals.
+    fr = out["deferred"]["by_rounds"][str(out["deferred"]["fastest_rounds"])]
+    dsw_ms = fr["kernels_ms"].get("ac6_sweep")
+    if dsw_ms:
+        dsw = 4 * (n + 1) + 4 * sw[0] + 8 * sw[1] + n // 8
+        dtr = measured_traffic("ac6_sweep_deferred", "rmat26")
+        out["deferred"]["sweep_roofline"] = {
+            "kernel": "ac6_sweep (round 1, no joins)", "algorithmic_bytes": dsw, "avg_ms": dsw_ms,
+            "achieved_GBs": dsw / (dsw_ms / 1e3) / 1e9,
+            "frac": dsw / (dsw_ms / 1e3) / 1e9 / HBM_PEAK_GBS, "traffic": dtr,
+            "traffic_GBs": dtr / (dsw_ms / 1e3) / 1e9 if dtr else None,
+            "amplification": dtr / dsw if dtr else None}
     # the baselines on the same graph; AC-4 takes G^T as an input (built here,
     # outside any timed region, as the paper treats it)
     log("explicit: G^T for AC-4 ...")
@@ -1151,6 +1169,9 @@ def main():
                     help="skip the edge / vertex sampling sweep (R-MAT scale 22)")
     ap.add_argument("--no-scc", action="store_true",
                     help="skip the SCC decomposition (R-MAT scale 22 with and without chain)")
+    ap.add_argument("--no-deferred", action="store_true",
+                    help="skip the late-support-registration runs (opts.rounds) on cfg1 and "
+                         "the implicit graph (R-MAT 26 and cfg0 keep theirs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size "
@@ -1245,11 +1266,12 @@ def main():
         "stats": st,
     }
 
-    checks["deferred"], out["deferred"] = bench_deferred(
-        ctx, T, n, lambda o: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=bm, worker_edges=we,
-                                          stats=st_t, opts=o), 10, (2, 8))
-    log(f"deferred AC-6 {out['deferred']['fastest_ms']:.3f} ms "
-        f"(R = {out['deferred']['fastest_rounds']})")
+    if not args.no_deferred:
+        checks["deferred"], out["deferred"] = bench_deferred(
+            ctx, T, n, lambda o: ctx.trim_csr(T.AC6, n, ro, col, live_bitmap=bm, worker_edges=we,
+                                              stats=st_t, opts=o), 10, (2, 8))
+        log(f"deferred AC-6 {out['deferred']['fastest_ms']:.3f} ms "
+            f"(R = {out['deferred']['fastest_rounds']})")
 
     gt = None   # G^T on the host, built once when a section needs it
     if not args.no_baselines:
@@ -1317,7 +1339,8 @@ def main():
         checks["explicit26"], out["explicit26"] = bench_explicit26(ctx, T, gg, 3)
         log(f"explicit26: {out['explicit26']['edges_per_s']:.3e} edges/s")
     if not args.no_implicit:
-        checks["implicit"], out["implicit"] = bench_implicit(ctx, T, gg, 3)
+        checks["implicit"], out["implicit"] = bench_implicit(ctx, T, gg, 3,
+                                                             deferred=not args.no_deferred)
         log(f"implicit: {out['implicit']['edges_per_s']:.3e} edges/s")
     if not args.no_learned:
         out["learned"] = bench_learned(ctx, T, gg, use_oracle=not args.no_cpu)

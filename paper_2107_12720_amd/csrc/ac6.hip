@@ -427,22 +427,30 @@ __global__ __launch_bounds__(256) void ac6_round(View g, int r, const uint32_t* 
             t[k] = kGoneBit;
             if (i < cnt) t[k] = (uint32_t)__builtin_nontemporal_load(lt + i);
         }
+        // the cursor targets' bits; a registering round needs every entry's
+        // vertex, the others only the vertices whose target was removed
+        bool moved[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int w = (int)(t[k] & kTargetMask);
+            moved[k] = !(t[k] & kGoneBit) && ((ycur[w >> 5] >> (w & 31)) & 1u);
+        }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int i = base + k * blockDim.x + threadIdx.x;
             v[k] = -1;
-            if (!(t[k] & kGoneBit)) v[k] = __builtin_nontemporal_load(lv + i);
+            if (!(t[k] & kGoneBit) && (kJoin || moved[k]))
+                v[k] = __builtin_nontemporal_load(lv + i);
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             keep[k] = gone[k] = false;
-            if (v[k] < 0) continue;
+            if (t[k] & kGoneBit) continue;
             entries += 1;
-            const int w = (int)(t[k] & kTargetMask);
             p[k] = -1;   // unchanged cursor (read only where needed)
-            if (!((ycur[w >> 5] >> (w & 31)) & 1u)) {   // the cursor edge, checked again
+            if (!moved[k]) {   // the cursor edge, checked again: its target is live
                 edges += 1;
-                keep[k] = true;
+                keep[k] = kJoin;
                 continue;
             }
             // the cursor target was removed before this round: scan on
