@@ -442,7 +442,8 @@ int trim_batch(trim_ctx *ctx, int32_t G, const int64_t *vbase, const int32_t *ro
  * as for trim_csr; worker_edges needs opts.workers entries, or
  * TRIM_NOALLOC_WORKERS when opts.workers is 0.  g->rrow_off / g->rcol are
  * ignored.  TRIM_E_INVAL for n > TRIM_NOALLOC_MAX_N, opts.workers >
- * TRIM_NOALLOC_WORKERS or opts.graph != 0.  Every call on one GPU shares that
+ * TRIM_NOALLOC_WORKERS, opts.graph != 0 or opts.rounds > 1 (late support
+ * registration needs a round list it would have to allocate).  Every call on one GPU shares that
  * GPU's array: calls that overlap on one GPU (two streams, two threads) race
  * and must be serialised by the caller.  The watchdog (opts.budget) works as
  * for trim_csr; a stall shows in stats.stalled (no context to query).

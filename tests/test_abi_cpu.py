@@ -75,3 +75,22 @@ def test_opts_layout_matches_header():
     assert tuple(f for f, _ in fields) == T.STATS_FIELDS
     assert ctypes.sizeof(T.CsrDesc) == 48
     assert ctypes.sizeof(T.ImplicitDesc) == 32
+
+
+def test_noalloc_refuses_late_registration_before_any_gpu_call():
+    """trim_csr_noalloc takes opts.rounds 0 or 1 only; the refusal comes from
+    the argument checks, before the device is touched (host stand-ins for the
+    pointers are never dereferenced)."""
+    import paper_2107_12720_amd as T
+    L = T.lib()
+    dummy = (ctypes.c_int32 * 4)()
+    g = T.CsrDesc(1, 0, ctypes.cast(dummy, ctypes.c_void_p), None, None, None)
+    o = T.make_opts(rounds=2)
+    rc = L.trim_csr_noalloc(ctypes.byref(g), ctypes.byref(o), ctypes.cast(dummy, ctypes.c_void_p),
+                            ctypes.cast(dummy, ctypes.c_void_p), None, None)
+    assert rc == -1 and "rounds" in T.last_error()
+    o = T.make_opts(rounds=T.MAX_ROUNDS + 1)
+    rc = L.trim_csr_noalloc(ctypes.byref(g), ctypes.byref(o), ctypes.cast(dummy, ctypes.c_void_p),
+                            ctypes.cast(dummy, ctypes.c_void_p), None, None)
+    assert rc == -1 and "rounds" in T.last_error()
+
