@@ -104,6 +104,23 @@ struct ShareEvery<ImplicitView> {
     static constexpr int value = 64;
 };
 
+// A filter of the removals of one round: 2^log2 bits, vertex v at a
+// multiplicative hash of its id (R-MAT ids carry the generator's quadrant
+// choices in their low bits), three slots used in rotation (see ac6_round).
+struct RoundFilter {
+    uint32_t* f = nullptr;   // 3 slots of 2^(log2 - 5) words
+    int log2 = 5;
+    __device__ __forceinline__ int words() const { return 1 << (log2 - 5); }
+    __device__ __forceinline__ uint32_t* slot(int r) const { return f + (r % 3) * words(); }
+    __device__ __forceinline__ uint32_t hash(int v) const {
+        return ((uint32_t)v * 0x9E3779B1u) >> (32 - log2);
+    }
+    __device__ __forceinline__ void add(int r, int v) const {
+        const uint32_t h = hash(v);
+        atomicOr(slot(r) + (h >> 5), 1u << (h & 31));
+    }
+};
+
 // Also writes sinks[]: bit v set iff v has no successor or is preset.  During
 // the first sweep these are the only removed vertices, so the sweep tests this
 // small, cache-resident bitmap instead of a list head in HBM.  Each wavefront
@@ -117,11 +134,15 @@ struct ShareEvery<ImplicitView> {
 template <class View>
 __global__ void ac6_init(View g, int n, int* head, int* ext, uint32_t* sinks, uint32_t* sinks2,
                          const uint32_t* preset, int* ctr, uint64_t* worker_edges, int P,
-                         trim_stats_t* stats) {
+                         trim_stats_t* stats, RoundFilter flt) {
     __shared__ uint64_t lds[Stage<View>::kWords];
     Stage<View>::apply(g, lds);
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     if (tid < kCtrInts) ctr[tid] = (tid == kHyRounds && sinks2) ? 1 : 0;
+    // the filter slots rounds 1 and 2 write
+    if (flt.f)
+        for (int i = tid; i < 2 * flt.words(); i += gridDim.x * blockDim.x)
+            flt.slot(1)[i] = 0;
     for (int p = tid; p < P; p += gridDim.x * blockDim.x) worker_edges[p] = 0;
     if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
     for (int v = tid; v < n; v += gridDim.x * blockDim.x) {
@@ -148,6 +169,7 @@ __global__ void ac6_init(View g, int n, int* head, int* ext, uint32_t* sinks, ui
 
 constexpr int kCasBuf = 4096;   // entries buffered in LDS before one shared-queue append
 constexpr int kSweepUnroll = 4; // vertices per lane in flight in the first sweep
+constexpr int kSweepUnrollDefer = 8;   // the same without joins (late registration)
 // Round-list entries (late support registration): (vertex, cursor target)
 // with flag bits on the target: the cursor is at the vertex's last successor;
 // the vertex was removed by a round (the entry is skipped from then on); the
@@ -156,6 +178,7 @@ constexpr uint32_t kLastBit = 0x80000000u;
 constexpr uint32_t kGoneBit = 0x40000000u;
 constexpr uint32_t kFirstBit = 0x20000000u;
 constexpr uint32_t kTargetMask = 0x1FFFFFFFu;
+
 
 // With jp (the forest collapse): jp[v] = the target of v's support if that is
 // v's last successor (v is a tree member, listed in jlist), v itself if v has
@@ -181,8 +204,8 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const u
                           const uint32_t* preset, uint64_t* rec, uint32_t* q, int* ctr,
                           uint64_t* worker_edges, int P, uint64_t* part, int sched, int* jp,
                           uint32_t* jlist, uint32_t* ynext, int* lout, long long hcap,
-                          int* cur) {
-    constexpr int U = kSweepUnroll;
+                          int* cur, RoundFilter flt) {
+    constexpr int U = kDefer ? kSweepUnrollDefer : kSweepUnroll;
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t cas[kDefer ? 1 : kCasBuf];
     __shared__ int s_chunk, s_ncas, s_base, s_wave[1024 / kWave];
@@ -280,6 +303,7 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const u
                         edges += (uint64_t)(p[k] - b[k] + 1);
                     } else if (b[k] < e[k]) {
                         atomicOr(ynext + (v[k] >> 5), 1u << (v[k] & 31));
+                        flt.add(1, v[k]);
                         removed += 1;
                         edges += (uint64_t)(e[k] - b[k]);
                     }
@@ -387,13 +411,14 @@ constexpr int kRoundUnroll = 4;   // list entries per thread in flight
 template <class View, bool kJoin>
 __global__ __launch_bounds__(256) void ac6_round(View g, int r, const uint32_t* ycur,
                                                  uint32_t* ynext, int nwords, int* lst,
-                                                 long long hcap, int* cur, int* head, int* ext,
-                                                 uint64_t* rec, int* jp, uint32_t* jlist,
-                                                 uint32_t* q, int* ctr, uint64_t* worker_edges,
-                                                 int P, int sched) {
+                                                 long long hcap, int* cur, RoundFilter flt,
+                                                 int* head, int* ext, uint64_t* rec, int* jp,
+                                                 uint32_t* jlist, uint32_t* q, int* ctr,
+                                                 uint64_t* worker_edges, int P, int sched) {
     constexpr int U = kRoundUnroll;
     __shared__ uint64_t lds[Stage<View>::kWords];
     __shared__ uint32_t buf[kJoin ? U * 256 : 1];
+    __shared__ uint32_t sflt[1 << (kRoundFilterMaxLog2 - 5)];   // round r - 1's filter
     __shared__ int s_base, s_nbuf;
     __shared__ uint64_t red[16];
     if (deferred_done(ctr, r)) return;
@@ -404,12 +429,27 @@ __global__ __launch_bounds__(256) void ac6_round(View g, int r, const uint32_t* 
         st_dev(ctr + kHyRounds, r);
     }
     const int stride = gridDim.x * blockDim.x;
+    // Every live entry's target was found live against the removals before
+    // round r - 1, so it is removed before round r iff round r - 1 removed
+    // it: while those removals are few, their filter (L2-resident) answers
+    // most checks and only its hits read the round bitmap.
+    const bool use_flt =
+        flt.f && ld_dev(ctr + kHyDead0 + (r - 1) % 3) <= (1 << flt.log2) / 8;
+    if (use_flt) {   // staged in LDS: the checks then leave L2 alone
+        const uint32_t* fs = flt.slot(r - 1);
+        for (int i = threadIdx.x; i < flt.words(); i += blockDim.x) sflt[i] = fs[i];
+        __syncthreads();
+    }
     if constexpr (!kJoin) {
-        // the removals of round r - 1 into the bitmap this round builds
+        // the removals of round r - 1 into the bitmap this round builds, and
+        // the filter slot round r + 1 writes cleared
         for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) {
             const uint32_t b = ycur[i];
             if (b && (b & ~ynext[i])) atomicOr(ynext + i, b);
         }
+        if (flt.f)
+            for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < flt.words(); i += stride)
+                flt.slot(r + 1)[i] = 0;
     } else {
         if (threadIdx.x == 0) s_nbuf = 0;
         __syncthreads();
@@ -433,7 +473,12 @@ __global__ __launch_bounds__(256) void ac6_round(View g, int r, const uint32_t* 
 #pragma unroll
         for (int k = 0; k < U; ++k) {
             const int w = (int)(t[k] & kTargetMask);
-            moved[k] = !(t[k] & kGoneBit) && ((ycur[w >> 5] >> (w & 31)) & 1u);
+            bool hit = true;
+            if (use_flt) {
+                const uint32_t h = flt.hash(w);
+                hit = (sflt[h >> 5] >> (h & 31)) & 1u;
+            }
+            moved[k] = !(t[k] & kGoneBit) && hit && ((ycur[w >> 5] >> (w & 31)) & 1u);
         }
 #pragma unroll
         for (int k = 0; k < U; ++k) {
@@ -483,6 +528,7 @@ __global__ __launch_bounds__(256) void ac6_round(View g, int r, const uint32_t* 
             for (int k = 0; k < U; ++k) {
                 if (gone[k]) {
                     atomicOr(ynext + (v[k] >> 5), 1u << (v[k] & 31));
+                    if (flt.f) flt.add(r, v[k]);
                     removed += 1;
                 }
             }
@@ -552,7 +598,7 @@ __global__ __launch_bounds__(256) void ac6_round(View g, int r, const uint32_t* 
     if constexpr (!kJoin) removed = block_sum(removed, red);
     if (threadIdx.x == 0) {
         if (edges) add_dev(worker_edges + (blockIdx.x % P), edges);
-        if (entries) add_dev(ctr + kHyWork, (int)entries);
+        if (entries) add_dev(reinterpret_cast<uint64_t*>(ctr + kHyWork), entries);
         if (!kJoin && removed) add_dev(ctr + kHyDead0 + r % 3, (int)removed);
     }
 }
@@ -1017,7 +1063,9 @@ inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
 // that ac6_init may write, aligned to a cache line.
 inline long long round_bitmap_offset(long long n) { return ((n + 31) / 32 + 2 + 31) / 32 * 32; }
 // Workgroups of a round launch: about one per 1,024 list entries (a list
-// holds at most n), at most four per CU.
+// holds at most n), at most four per CU
+// (more workgroups measured slower: every round launch after the fixed point
+// still starts them all).
 inline int round_blocks(long long n, int cus) {
     long long b = (n + 256 * kRoundUnroll - 1) / (256 * kRoundUnroll);
     if (b < 1) b = 1;
@@ -1044,11 +1092,20 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     y[1] = reinterpret_cast<uint32_t*>(w.c);
     y[0] = y[1] + round_bitmap_offset(n);
     const int nwords = (n + 31) / 32;
+    // the round filters follow the round list in w.hl: 2^flog bits each, about
+    // n / 8 bits (at least 32, at most kRoundFilterMaxLog2)
+    RoundFilter flt;
+    if (defer) {
+        flt.f = reinterpret_cast<uint32_t*>(w.hl + 2 * w.hcap);
+        int flog = 5;
+        while (flog < kRoundFilterMaxLog2 && (1LL << (flog + 3)) < (long long)n) ++flog;
+        flt.log2 = flog;
+    }
     {
         Timed t(lc, "ac6_init");
         hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
                            lc.stream, g, n, defer ? nullptr : w.a, ext, y[1],
-                           defer ? y[0] : nullptr, preset, w.ctr, worker_edges, P, stats);
+                           defer ? y[0] : nullptr, preset, w.ctr, worker_edges, P, stats, flt);
     }
     if (n > 0) {
         const int chunk = sweep_chunk(lc, n, B);
@@ -1058,7 +1115,7 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
             hipLaunchKernelGGL((ac6_sweep<View, false>), dim3(sweep_blocks), dim3(B), 0, lc.stream,
                                g, n, chunk, w.a, ext, y[1], preset, w.b, w.q, w.ctr, worker_edges,
                                P, w.part, lc.schedule, lc.forest ? w.jp : nullptr,
-                               lc.forest ? w.e : nullptr, nullptr, nullptr, 0LL, nullptr);
+                               lc.forest ? w.e : nullptr, nullptr, nullptr, 0LL, nullptr, flt);
         } else {
             // the round list in w.hl, the moved cursors in w.d
             {
@@ -1066,7 +1123,7 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
                 hipLaunchKernelGGL((ac6_sweep<View, true>), dim3(sweep_blocks), dim3(B), 0,
                                    lc.stream, g, n, chunk, nullptr, nullptr, y[1], preset, w.b,
                                    w.q, w.ctr, worker_edges, P, w.part, lc.schedule, nullptr,
-                                   nullptr, y[0], w.hl, w.hcap, w.d);
+                                   nullptr, y[0], w.hl, w.hcap, w.d, flt);
             }
             const int rb = round_blocks(n, lc.cus);
             if (R > 2) {
@@ -1074,17 +1131,17 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
                 for (int r = 2; r < R; ++r)
                     hipLaunchKernelGGL((ac6_round<View, false>), dim3(rb), dim3(256), 0,
                                        lc.stream, g, r, y[r & 1], y[(r + 1) & 1], nwords, w.hl,
-                                       w.hcap, w.d, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                       nullptr, w.ctr, worker_edges, P, lc.schedule);
+                                       w.hcap, w.d, flt, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr, w.ctr, worker_edges, P, lc.schedule);
             }
             {
                 Timed t(lc, "ac6_register");
                 hipLaunchKernelGGL(ac6_heads, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
                                    lc.stream, n, R, y[R & 1], w.a, ext, w.ctr);
                 hipLaunchKernelGGL((ac6_round<View, true>), dim3(rb), dim3(256), 0, lc.stream, g,
-                                   R, y[R & 1], nullptr, nwords, w.hl, w.hcap, w.d, w.a, ext, w.b,
-                                   lc.forest ? w.jp : nullptr, lc.forest ? w.e : nullptr, w.q,
-                                   w.ctr, worker_edges, P, lc.schedule);
+                                   R, y[R & 1], nullptr, nwords, w.hl, w.hcap, w.d, flt, w.a, ext,
+                                   w.b, lc.forest ? w.jp : nullptr, lc.forest ? w.e : nullptr,
+                                   w.q, w.ctr, worker_edges, P, lc.schedule);
             }
         }
         if (lc.forest) {

@@ -143,8 +143,8 @@ int ensure(trim_ctx* c, int64_t n) {
     return TRIM_OK;
 }
 
-// The round list of late support registration (2 ints per vertex), allocated
-// on first use.
+// The round list of late support registration (2 ints per vertex) and its
+// three round filters, allocated on first use.
 int ensure_rounds(trim_ctx* c, int64_t n) {
     const long long need = n > 0 ? n : 1;
     if (need <= c->w.hcap) return TRIM_OK;
@@ -152,7 +152,8 @@ int ensure_rounds(trim_ctx* c, int64_t n) {
     c->w.hl = nullptr;
     c->w.hcap = 0;
     const long long cap = need + need / 8 + 64;
-    if (dmalloc(c, &c->w.hl, (size_t)cap * 2 * sizeof(int)) != hipSuccess) {
+    const size_t filters = 3 * ((size_t)1 << (trim::kRoundFilterMaxLog2 - 5));
+    if (dmalloc(c, &c->w.hl, ((size_t)cap * 2 + filters) * sizeof(int)) != hipSuccess) {
         (void)hipGetLastError();
         c->w.hl = nullptr;
         return fail(TRIM_E_NOMEM, "cannot allocate the round lists for %lld vertices",

@@ -37,9 +37,11 @@ enum Ctr : int {
     kHyDead0 = 36,
     kHyStop = 100,
     kHyRounds = 101,
-    kHyWork = 102,
+    kHyWork = 102,   // uint64 (words 102 and 103, 8-byte aligned)
     kCtrInts = 256
 };
+
+static_assert(kHyWork % 2 == 0, "the 64-bit re-check counter needs an 8-byte aligned word");
 
 // Working memory of one call, sized for n vertices (owned by trim_ctx).
 struct Work {
@@ -63,7 +65,8 @@ struct Work {
     uint64_t* part = nullptr;    // per-block partial sums (kPartSlots x kPartStride)
     long long cap = 0;           // vertices the per-vertex buffers hold
     int* hl = nullptr;           // AC-6 with late support registration: the round list,
-                                 //   2 * hcap ints (vertex, cursor target and flags)
+                                 //   2 * hcap ints (vertex, cursor target and flags), then
+                                 //   3 round filters of up to 2^kRoundFilterMaxLog2 bits
     long long hcap = 0;
 };
 // Extra working memory of two-sided AC-6 (allocated on its first use).
@@ -75,6 +78,9 @@ struct Work2 {
     long long qwords = 0;       // size of q in words
 };
 constexpr int kMaxWorkers = 16384;
+// Round filters of late support registration: at most 2^18 bits (32 KB) each,
+// so that a round workgroup can hold one in LDS.
+constexpr int kRoundFilterMaxLog2 = 18;
 // AC-6 splits S_more lists kMoreLists ways for graphs up to kSplitMaxN
 // vertices; a close can then queue up to kMoreLists S_more heads, so the
 // shared queue needs room for 2 + kMoreLists items per vertex instead of 3.

@@ -115,7 +115,7 @@ __global__ void finalize_stats(int n, int P, int n_sweep, int n_prop, int n_pack
         stats->work_items = (uint64_t)(uint32_t)ld_dev(ctr + kJWork) +
                             (uint64_t)(uint32_t)ld_dev(ctr + kAcWork);
         stats->phases = (uint64_t)ld_dev(ctr + kLvPhases);
-        stats->rechecks = (uint64_t)(uint32_t)ld_dev(ctr + kHyWork);
+        stats->rechecks = ld_dev(reinterpret_cast<const uint64_t*>(ctr + kHyWork));
         if (ld_dev(ctr + kHyRounds)) stats->rounds = (uint64_t)ld_dev(ctr + kHyRounds);
         if (n == 0 && empty_rounds) stats->rounds = (uint64_t)empty_rounds;
     }
