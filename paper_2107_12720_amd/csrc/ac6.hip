@@ -167,6 +167,54 @@ __global__ void ac6_init(View g, int n, int* head, int* ext, uint32_t* sinks, ui
     }
 }
 
+// The init of late registration on an explicit graph: no list heads, only
+// the two round bitmaps of the sinks.  A lane takes four consecutive vertices
+// from one 16-byte load of the offsets (and the next offset), a wavefront 256
+// vertices, whose eight bitmap words it assembles by shuffles.  Offsets that
+// are not 16-byte aligned take the one-vertex-per-lane path of ac6_init.
+__global__ void ac6_init_bits(const int* row_off, int n, uint32_t* y1, uint32_t* y0, int* ctr,
+                              uint64_t* worker_edges, int P, trim_stats_t* stats,
+                              RoundFilter flt) {
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    if (tid < kCtrInts) ctr[tid] = tid == kHyRounds ? 1 : 0;
+    for (int p = tid; p < P; p += stride) worker_edges[p] = 0;
+    if (stats && tid < (int)(sizeof(trim_stats_t) / 8)) ((uint64_t*)stats)[tid] = 0;
+    if (flt.f)
+        for (int i = tid; i < 2 * flt.words(); i += stride) flt.slot(1)[i] = 0;
+    const int ngroups = (n + 3) >> 2;   // groups of four vertices
+    const int nwords = (n + 31) >> 5;
+    const int lane = lane_id();
+    const int waves = stride / kWave;
+    for (int g0 = (tid / kWave) * kWave; g0 < ngroups; g0 += waves * kWave) {
+        const int gi = g0 + lane;
+        uint32_t nib = 0;
+        if (gi < ngroups) {
+            const int v = gi << 2;
+            if (v + 4 <= n) {
+                typedef int v4i __attribute__((ext_vector_type(4)));
+                const v4i a = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(row_off) + gi);
+                const int e4 = __builtin_nontemporal_load(row_off + v + 4);
+                nib = (uint32_t)(a.x == a.y) | ((uint32_t)(a.y == a.z) << 1) |
+                      ((uint32_t)(a.z == a.w) << 2) | ((uint32_t)(a.w == e4) << 3);
+            } else {
+                for (int j = 0; v + j < n; ++j)
+                    nib |= (uint32_t)(row_off[v + j] == row_off[v + j + 1]) << j;
+            }
+        }
+        // word (g0 / 8 + lane / 8) holds the nibbles of lanes 8k .. 8k + 7
+        uint32_t word = nib << (4 * (lane & 7));
+        word |= __shfl_xor(word, 1);
+        word |= __shfl_xor(word, 2);
+        word |= __shfl_xor(word, 4);
+        const int wi = (g0 >> 3) + (lane >> 3);
+        if ((lane & 7) == 0 && wi < nwords) {
+            y1[wi] = word;
+            y0[wi] = word;
+        }
+    }
+}
+
 constexpr int kCasBuf = 4096;   // entries buffered in LDS before one shared-queue append
 constexpr int kSweepUnroll = 4; // vertices per lane in flight in the first sweep
 constexpr int kSweepUnrollDefer = 8;   // the same without joins (late registration)
@@ -396,11 +444,13 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const u
 // rounds rotate over three control words.
 
 // True (and the stop word set) if round r need not run: a round before it
-// removed nothing.
+// removed nothing.  Every workgroup decides from the same count, which no one
+// changes while this kernel runs; only workgroup 0 writes the stop word (a
+// store from each of thousands of workgroups to one word queues them all).
 __device__ __forceinline__ bool deferred_done(int* ctr, int r) {
     if (ld_dev(ctr + kHyStop)) return true;
     if (ld_dev(ctr + kHyDead0 + (r - 1) % 3) == 0) {
-        if (threadIdx.x == 0) st_dev(ctr + kHyStop, 1);
+        if (blockIdx.x == 0 && threadIdx.x == 0) st_dev(ctr + kHyStop, 1);
         return true;
     }
     return false;
@@ -1058,6 +1108,19 @@ inline int grid_for(long long n, int block, int max_blocks = 1 << 20) {
     return (int)b;
 }
 
+// Which views take ac6_init_bits: explicit graphs whose offsets are 16-byte
+// aligned (the caller's pointer; torch allocations are).
+template <class View>
+struct InitBits {
+    static bool ok(const View&) { return false; }
+    static const int* row_off(const View&) { return nullptr; }
+};
+template <>
+struct InitBits<ExplicitView> {
+    static bool ok(const ExplicitView& g) { return ((uintptr_t)g.row_off & 15) == 0; }
+    static const int* row_off(const ExplicitView& g) { return g.row_off; }
+};
+
 // Words from the first round bitmap to the second (both in w.c, which holds
 // n + n / 8 + 64 ints): room for ceil(n / 32) words plus the one past the end
 // that ac6_init may write, aligned to a cache line.
@@ -1103,9 +1166,15 @@ hipError_t ac6_run(View g, int n, const Work& w, const LaunchCfg& lc, uint32_t* 
     }
     {
         Timed t(lc, "ac6_init");
-        hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
-                           lc.stream, g, n, defer ? nullptr : w.a, ext, y[1],
-                           defer ? y[0] : nullptr, preset, w.ctr, worker_edges, P, stats, flt);
+        if (defer && InitBits<View>::ok(g))
+            hipLaunchKernelGGL(ac6_init_bits, dim3(grid_for((n + 3) / 4, 256, 16384)), dim3(256),
+                               0, lc.stream, InitBits<View>::row_off(g), n, y[1], y[0], w.ctr,
+                               worker_edges, P, stats, flt);
+        else
+            hipLaunchKernelGGL(ac6_init<View>, dim3(grid_for(n, 256, 16384)), dim3(256), 0,
+                               lc.stream, g, n, defer ? nullptr : w.a, ext, y[1],
+                               defer ? y[0] : nullptr, preset, w.ctr, worker_edges, P, stats,
+                               flt);
     }
     if (n > 0) {
         const int chunk = sweep_chunk(lc, n, B);
