@@ -157,6 +157,30 @@ def test_plain_calls_unchanged_between_deferred_ones(ctx):
             assert edges == oracle.counts_deferred(g, r, R)[0]
 
 
+def test_unaligned_offsets(ctx):
+    """Offsets that are not 16-byte aligned (a view one int into a buffer)
+    take the one-vertex-per-lane init; aligned ones the four-per-lane init.
+    Both give the oracle's bitmap and counts, with n both a multiple of 4 and
+    not."""
+    import torch
+    import paper_2107_12720_amd as T
+    for n in (4096, 4099):
+        g = gg.uniform(n, 3 * n, seed=n, drop_self=False)
+        r, c, bm = expected(g)
+        buf = torch.zeros(n + 2, dtype=torch.int32, device="cuda")
+        buf[1:] = T.to_device(g.row_off)
+        ro = buf[1:]
+        assert ro.data_ptr() % 16 != 0
+        col = T.to_device(g.col)
+        for rows in (ro, T.to_device(g.row_off)):
+            res = ctx.trim_csr(6, n, rows, col, opts=T.make_opts(rounds=3))
+            torch.cuda.synchronize()
+            st = res.stats_dict()
+            assert np.array_equal(res.bitmap_numpy()[: bm.shape[0]], bm), n
+            total, rounds, re = oracle.counts_deferred(g, r, 3)
+            assert (st["edges_total"], st["rounds"], st["rechecks"]) == (total, rounds, re)
+
+
 def test_errors(ctx):
     import torch
     import paper_2107_12720_amd as T
