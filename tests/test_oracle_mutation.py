@@ -18,6 +18,7 @@ import pytest
 
 import oracle
 import test_oracle as P
+import test_oracle_deferred as D
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -45,6 +46,21 @@ C_MUTANTS = [
      "two-sided live checks without the in-side support"),
     ("or_peel_preset", "            live[v] = 0;\n            q[qt++] = v;\n        }",
      "            live[v] = 0;\n        }", "preset removal not propagated"),
+    ("or_counts_deferred", "t += fl + rounds;", "t += fl + rounds - 1;",
+     "late registration: live vertex without its first check"),
+    ("or_counts_deferred", "int64_t k = (int64_t)level[v] - 1 < R ? (int64_t)level[v] - 1 : R;",
+     "int64_t k = (int64_t)level[v] < R ? (int64_t)level[v] : R;",
+     "late registration: rounds of a removed vertex from its level, not level - 1"),
+    ("or_counts_deferred", "const int64_t a = alpha > 1 ? alpha : 1;",
+     "const int64_t a = alpha + 1;", "late registration: alpha + 1 rounds as in AC-3"),
+    ("or_ac6_deferred", "if (dround[col[cur[v]]] >= rounds) { found = 1; break; }",
+     "if (dround[col[cur[v]]] > rounds) { found = 1; break; }",
+     "late registration: a round reading its own removals"),
+    ("or_ac6_deferred", "if (row_off[v + 1] == row_off[v]) {",
+     "if (0) {", "late registration: vertices without successors not removed up front"),
+    ("or_ac6_deferred", "for (cur[u] += 1; cur[u] < end; cur[u] += 1) {",
+     "for (; cur[u] < end; cur[u] += 1) {",
+     "late registration: a handed-back vertex re-checks its old support"),
 ]
 
 # (original text, planted mistake, what the mistake is) in oracle/mlp_ref.py
@@ -75,6 +91,10 @@ def c_pins(orc, gen):
         ("two_sided_ac3", lambda: P.test_two_sided_ac3_hand_example(orc, gen)),
         ("preset_exhaustive", lambda: P.test_preset_exhaustive_three_vertices(orc, gen)),
         ("preset_totals", lambda: P.test_preset_totals_by_literal_runs(orc, gen, 0)),
+        ("deferred_hand", lambda: [D.test_hand_example(orc, gen, R) for R in (2, 3, 4)]),
+        ("deferred_literal",
+         lambda: D.test_literal_run_against_closed_form_and_other_algorithms(orc, gen, 3)),
+        ("deferred_small", lambda: D.test_no_removal_and_empty(orc, gen)),
     ]
 
 
