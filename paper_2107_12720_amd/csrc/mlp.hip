@@ -25,6 +25,11 @@
 // in lane j + 32*((i/4)%2), register 4*(i/8) + i%4.  A 32-edge tile is
 // computed transposed (hidden units x edges), so layer 1's output registers
 // 4j..4j+3 are exactly the B operand of layer 2's k-block j.
+// Contractions over 32 (layer 2 and its backward pass, the weight gradients
+// over a tile's edges) use gfx950's double-K form v_mfma_f32_32x32x16 bf16:
+// 8 items per lane, A[i][k] in lane i%32 + 32*(k/8), item k%8, the same D.
+// Where its operands are two 8-deep blocks side by side (cat), both operands
+// see the same order of k, and a sum over k does not depend on that order.
 #include "trim_device.h"
 #include "trim_internal.h"
 
@@ -50,6 +55,15 @@ __device__ __forceinline__ float rbf(float f) { return bf2f(f2bf(f)); }
 __device__ __forceinline__ int drow(int r, int l) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
 __device__ __forceinline__ f32x16 mfma(bf16x4 a, bf16x4 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, a),
+                                                   __builtin_bit_cast(bf16v8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 cat(bf16x4 lo, bf16x4 hi) {
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 struct Graph {
@@ -141,8 +155,8 @@ __device__ __forceinline__ float forward(const Weights& W, const float f[4], f32
         z1[r] += W.b1[r];
         h1[r >> 2][r & 3] = f2bf(fmaxf(z1[r], 0.f));
     }
-    z2 = zero;
-    for (int j = 0; j < 4; ++j) z2 = mfma(W.w2[j], h1[j], z2);
+    z2 = mfma16(cat(W.w2[0], W.w2[1]), cat(h1[0], h1[1]), zero);
+    z2 = mfma16(cat(W.w2[2], W.w2[3]), cat(h1[2], h1[3]), z2);
     float s = 0.f;
     for (int r = 0; r < 16; ++r) {
         z2[r] += W.b2[r];
@@ -218,8 +232,8 @@ __global__ __launch_bounds__(256) void mlp_grad(Graph g, const uint32_t* live, c
             dz2b[r >> 2][r & 3] = f2bf(dz2[r]);
         }
         // dH1 = W2^T dZ2 (dZ2 registers 4j..4j+3 are the B operand of k-block j)
-        f32x16 dh1 = zero;
-        for (int j = 0; j < 4; ++j) dh1 = mfma(W.w2t[j], dz2b[j], dh1);
+        f32x16 dh1 = mfma16(cat(W.w2t[0], W.w2t[1]), cat(dz2b[0], dz2b[1]), zero);
+        dh1 = mfma16(cat(W.w2t[2], W.w2t[3]), cat(dz2b[2], dz2b[3]), dh1);
         // stage dZ2, H1 and X for the weight gradients (contraction over edges)
         for (int r = 0; r < 16; ++r) {
             T.a[drow(r, l)][col] = bf2f(dz2b[r >> 2][r & 3]);
@@ -228,14 +242,14 @@ __global__ __launch_bounds__(256) void mlp_grad(Graph g, const uint32_t* live, c
         for (int t4 = 0; t4 < 4; ++t4) T.x[col][4 * half + t4] = rbf(f[t4]);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int j = 0; j < 4; ++j) {
-            bf16x4 a, b;
-            for (int t4 = 0; t4 < 4; ++t4) {
-                const int e = 8 * j + 4 * half + t4;
-                a[t4] = f2bf(T.a[col][e]);
-                b[t4] = f2bf(T.b[col][e]);
+        for (int j = 0; j < 2; ++j) {
+            bf16x8 a, b;
+            for (int t8 = 0; t8 < 8; ++t8) {
+                const int e = 16 * j + 8 * half + t8;
+                a[t8] = f2bf(T.a[col][e]);
+                b[t8] = f2bf(T.b[col][e]);
             }
-            gw2 = mfma(a, b, gw2);   // dW2[h_out][h_in] += sum_e dZ2[h_out][e] H1[h_in][e]
+            gw2 = mfma16(a, b, gw2);   // dW2[h_out][h_in] += sum_e dZ2[h_out][e] H1[h_in][e]
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -247,14 +261,14 @@ __global__ __launch_bounds__(256) void mlp_grad(Graph g, const uint32_t* live, c
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int j = 0; j < 4; ++j) {
-            bf16x4 a, b;
-            for (int t4 = 0; t4 < 4; ++t4) {
-                const int e = 8 * j + 4 * half + t4;
-                a[t4] = f2bf(T.a[col][e]);
-                b[t4] = col < 8 ? f2bf(T.x[e][col]) : (short)0;
+        for (int j = 0; j < 2; ++j) {
+            bf16x8 a, b;
+            for (int t8 = 0; t8 < 8; ++t8) {
+                const int e = 16 * j + 8 * half + t8;
+                a[t8] = f2bf(T.a[col][e]);
+                b[t8] = col < 8 ? f2bf(T.x[e][col]) : (short)0;
             }
-            gw1 = mfma(a, b, gw1);   // dW1[h][f] += sum_e dZ1[h][e] X[e][f]
+            gw1 = mfma16(a, b, gw1);   // dW1[h][f] += sum_e dZ1[h][e] X[e][f]
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
