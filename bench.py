@@ -712,7 +712,7 @@ def deferred_parity(orc, g, r, bm, c, dc, do):
             and got["rounds"] == rounds and got["rechecks"] == re and tot - re == c.T6)
 
 
-def bench_cfg0(ctx, T, gg, steps=50):
+def bench_coretail(ctx, T, gg, steps=50):
     """The small core+tail graph (n = 65,536): microseconds per trim of AC-6,
     AC-4* and AC-3J and their traversed-edge totals (the oracle's closed forms
     are compared in the CPU leg)."""
@@ -764,7 +764,7 @@ def bench_cfg0(ctx, T, gg, steps=50):
                                 "kernels_us": {k: float(np.mean(v)) * 1e3 for k, v in kt_o.items()},
                                 "call": "trim_batch with one graph, block 1024",
                                 "parity": None}
-    log(f"cfg0: AC-6 {out['ac6']['us']:.1f} us, AC-4 {out['ac4']['us']:.1f} us, "
+    log(f"core+tail n=65536: AC-6 {out['ac6']['us']:.1f} us, AC-4 {out['ac4']['us']:.1f} us, "
         f"AC-3 {out['ac3']['us']:.1f} us, deferred AC-6 "
         f"{out['deferred']['fastest_ms'] * 1e3:.1f} us (R = {out['deferred']['fastest_rounds']}), "
         f"one-workgroup AC-6 {out['ac6_one_workgroup']['us']:.1f} us")
@@ -1100,8 +1100,8 @@ def oracle_leg(g, checks, cpu_seconds, out):
                 ok = False
                 break
         out["batch"]["parity"] = bool(ok)
-    if "cfg0" in checks:
-        cc, co = checks["cfg0"], out["cfg0"]
+    if "coretail65536" in checks:
+        cc, co = checks["coretail65536"], out["coretail65536"]
         r0 = oracle.peel(cc["graph"])
         c0 = oracle.counts(cc["graph"], r0)
         bm0 = oracle.bitmap(r0.live)
@@ -1161,7 +1161,7 @@ def main():
     ap.add_argument("--no-explicit26", action="store_true",
                     help="skip the explicit R-MAT scale-26 graph")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-order section")
-    ap.add_argument("--no-cfg0", action="store_true",
+    ap.add_argument("--no-coretail", action="store_true",
                     help="skip the small core+tail graph (n = 65,536)")
     ap.add_argument("--no-two-sided", action="store_true",
                     help="skip two-sided trimming (AC-6 and AC-4) of the same graph")
@@ -1170,8 +1170,9 @@ def main():
     ap.add_argument("--no-scc", action="store_true",
                     help="skip the SCC decomposition (R-MAT scale 22 with and without chain)")
     ap.add_argument("--no-deferred", action="store_true",
-                    help="skip the late-support-registration runs (opts.rounds) on cfg1 and "
-                         "the implicit graph (R-MAT 26 and cfg0 keep theirs)")
+                    help="skip the late-support-registration runs (opts.rounds) on the chain "
+                         "graph and the implicit graph (R-MAT 26 and the core+tail graph keep "
+                         "theirs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size "
@@ -1333,8 +1334,8 @@ def main():
     if not args.no_batch:
         checks["batch"], out["batch"] = bench_batch(ctx, T, gg, 10)
         log(f"batch: {out['batch']['graphs_per_s']:.0f} graphs/s")
-    if not args.no_cfg0:
-        checks["cfg0"], out["cfg0"] = bench_cfg0(ctx, T, gg)
+    if not args.no_coretail:
+        checks["coretail65536"], out["coretail65536"] = bench_coretail(ctx, T, gg)
     if not args.no_explicit26:
         checks["explicit26"], out["explicit26"] = bench_explicit26(ctx, T, gg, 3)
         log(f"explicit26: {out['explicit26']['edges_per_s']:.3e} edges/s")

@@ -265,7 +265,7 @@ def test_config4_full(ctx):
     import paper_2107_12720_amd as T
     from paper_2107_12720_amd import learned
     from oracle import mlp_ref
-    say("  cfg4: 16 training graphs (R-MAT 20) with oracle labels ...")
+    say("  learned order: 16 training graphs (R-MAT 20) with oracle labels ...")
     train = []
     for seed in range(1, 17):
         g = gg.rmat(20, 16, seed=seed)
