@@ -439,9 +439,16 @@ __global__ void ac6_sweep(View g, int n, int chunk, int* head, int* ext, const u
 // (vertex, cursor target with the flag bits above), two arrays of hcap ints,
 // updated in place: an entry is written only when its cursor moves (the
 // cursor position goes to cur[v]) or its vertex is removed.  A round reads
-// every entry; removals are few after the first rounds, so rewriting the list
-// without them would cost more than skipping them.  The removal counts of the
-// rounds rotate over three control words.
+// every entry's target, and the vertex only where the target was removed;
+// removals are few after the first rounds, so rewriting the list without
+// them would cost more than skipping them.  The removal counts of the rounds
+// rotate over three control words.
+//
+// Removal filters: a target found live in round r - 1 is removed before
+// round r iff round r - 1 removed it, so each round also sets its removals
+// in a hashed filter (RoundFilter, three slots in rotation) and the next
+// round, while those removals are few, checks the filter (staged in LDS)
+// first and the round bitmap only on a hit.
 
 // True (and the stop word set) if round r need not run: a round before it
 // removed nothing.  Every workgroup decides from the same count, which no one
